@@ -1,0 +1,314 @@
+"""Pins of the oracle's Krylov solvers (CPU only)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spl
+
+from oracle import operators as O, transfer as T, bicgstab as B, gmres as G, gmresdr as DR
+from oracle import deflation as D, adjoint as ADJ
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------- rticyc ---
+
+def test_cycle_tolerance_hand_values():
+    """Sec. 4.1 step 3 b) with ncyc = 4, rtol = 1e-8, ||r0|| = 1."""
+    tau, nu0, ncyc = 1e-8, 1.0, 4
+    t, br = B.cycle_tolerance(1.0, nu0, tau, 1, ncyc)
+    assert np.isclose(t, 1e-2) and br == 1            # both criteria give 1e-2
+    t, br = B.cycle_tolerance(1e-2, nu0, tau, 2, ncyc)  # on schedule: tie
+    assert np.isclose(t, 1e-2)
+    # residual jumped up to 1e-1 during the projection: the second criterion
+    # (at least icyc/ncyc of the way) asks for more and is enforced
+    t, br = B.cycle_tolerance(1e-1, nu0, tau, 2, ncyc)
+    assert br == 2 and np.isclose(t * 1e-1, 1e-4)
+    assert np.isclose((1e-8 / 1e-1) ** (1 / 3), 4.641588833612782e-3)
+    # last cycle asks for the final tolerance under both criteria
+    t, _ = B.cycle_tolerance(3e-5, nu0, tau, 4, ncyc)
+    assert np.isclose(t * 3e-5, tau)
+
+
+def test_cycle_tolerance_geometric_schedule():
+    """If every cycle meets its target exactly, the residual reaches tau at
+    exactly cycle ncyc, shrinking by the same factor each cycle."""
+    tau, nu0, ncyc = 1e-10 * 3.0, 3.0, 7
+    nu = nu0
+    factors = []
+    for icyc in range(1, ncyc + 1):
+        t, _ = B.cycle_tolerance(nu, nu0, tau, icyc, ncyc)
+        factors.append(t)
+        nu *= t
+    assert np.isclose(nu, tau, rtol=1e-12)
+    assert np.allclose(factors, factors[0], rtol=1e-12)
+
+
+# -------------------------------------------------------------- BiCGStab ---
+
+def test_inner_bicgstab_matches_scipy_iterates():
+    """The inner solver is textbook Bi-CGSTAB: its iterates equal scipy's
+    (which implements the same recurrences) iteration by iteration."""
+    op = O.const_cd((21, 17), (60.0, 25.0))
+    A = O.to_csr(op)
+    b = W.rhs(op.n, 31)
+    xs = []
+    spl.bicgstab(A, b, rtol=1e-30, maxiter=8, callback=lambda xk: xs.append(xk.copy()))
+    for it in range(1, 9):
+        res = B.bicgstab_inner(lambda z: O.apply(op, z), b, 0.0, it)
+        np.testing.assert_allclose(res.e, xs[it - 1], rtol=0, atol=1e-12 * np.linalg.norm(xs[it - 1]))
+
+
+def test_inner_bicgstab_invariants():
+    """r^ . s = 0 after each half step and t . r = 0 after each full step
+    (alpha and omega are the defining Petrov-Galerkin / minimal-residual
+    choices), and the recursive residual equals r0 - A e."""
+    op = O.const_cd((19, 13), (50.0, 0.0))
+    mv = lambda z: O.apply(op, z)
+    r0 = W.rhs(op.n, 5)
+    res = B.bicgstab_inner(mv, r0, 0.0, 6)
+    rho, alpha, omega = res.scalars[0]
+    assert np.isclose(rho, r0 @ r0)
+    s = r0 - alpha * mv(r0)
+    assert abs(r0 @ s) < 1e-12 * np.linalg.norm(r0) * np.linalg.norm(s)
+    t = mv(s)
+    r1 = s - omega * t
+    assert abs(t @ r1) < 1e-12 * np.linalg.norm(t) * np.linalg.norm(r1)
+    # true vs recursive residual after 6 iterations
+    e = res.e
+    full = B.bicgstab_inner(mv, r0, 0.0, 6)
+    assert np.allclose(full.e, e)
+
+
+def test_bicgstab_scalar_operator_one_half_step():
+    """A = c I: the first half step is exact."""
+    op = O.StencilOp((5, 4), {"C": 3.0, "W": 0.0, "E": 0.0, "S": 0.0, "N": 0.0})
+    r0 = W.rhs(op.n, 2)
+    res = B.bicgstab_inner(lambda z: O.apply(op, z), r0, 1e-12, 10)
+    assert res.status == "half" and res.iters == 1
+    np.testing.assert_allclose(res.e, r0 / 3.0, rtol=1e-15)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_bicgstab_proj_reaches_direct_solution(precision):
+    c = W.CONFIGS["C1"]
+    op = O.const_cd(c["n"], c["beta"])
+    b = W.rhs(op.n, c["seed"])
+    xstar = spl.spsolve(O.to_csr(op).tocsc(), b)
+    x, rep = B.bicgstab_proj(op, b, rtol=1e-11, ncyc=20, precision=precision)
+    assert rep.status == 0
+    assert rep.relres_true <= 1e-11
+    assert np.linalg.norm(x - xstar) / np.linalg.norm(xstar) < 1e-7
+
+
+def test_table_4_2_soft_band():
+    """Sec. 4.2, Table 4.2: restarted BiCGStab without deflation on the
+    Example 1 operator at 127^2 with a random right-hand side.  BiCGStab
+    counts depend on rounding and MATLAB's exit rules, so the band is soft:
+    mvps within 25 %, cycles actually used within 15 %."""
+    g = json.load(open(os.path.join(GOLDEN, "table_4_2_example3.json")))
+    op = O.example1_operator(g["n"])
+    b = W.rhs(op.n, 11)
+    for ncyc in (1, 50, 400):
+        i = g["ncyc"].index(ncyc)
+        x, rep = B.bicgstab_proj(op, b, rtol=g["rtol"], ncyc=ncyc, max_extra=0 if ncyc == 1 else None)
+        assert rep.status == 0 and rep.relres_true <= g["rtol"]
+        assert abs(rep.mvp_inner - g["mvps"][i]) <= 0.25 * g["mvps"][i], (ncyc, rep.mvp_inner)
+        assert abs(rep.cycles - g["cycles_used"][i]) <= 0.15 * g["cycles_used"][i] + 0.5, (ncyc, rep.cycles)
+
+
+def test_bicgstab_breakdown_on_skew_operator():
+    """Pure centred convection with no diffusion is skew-symmetric, so
+    r^T A r = 0 and the first step breaks down: the solve must stop with
+    status breakdown instead of looping."""
+    h = 1 / 9
+    op = O.StencilOp((8, 8), {"C": 0.0, "W": -10 / (2 * h), "E": 10 / (2 * h), "S": 0.0, "N": 0.0})
+    b = W.rhs(op.n, 3)
+    x, rep = B.bicgstab_proj(op, b, rtol=1e-8, ncyc=5)
+    assert rep.status == B.BREAKDOWN
+
+
+def test_bicgstab_not_converged_status():
+    op = O.const_cd((31, 31), (40.0, 0.0))
+    b = W.rhs(op.n, 8)
+    x, rep = B.bicgstab_proj(op, b, rtol=1e-12, ncyc=3, max_extra=0, maxit_cycle=5)
+    assert rep.status == B.NOT_CONVERGED and rep.cycles == 3
+    assert rep.relres_true < 1.0
+
+
+# ----------------------------------------------------------------- GMRES ---
+
+def test_gmres_cycle_is_minimal_residual():
+    """One GMRES(m) cycle minimises ||r - A e|| over the Krylov space:
+    compare with least squares over an explicit (QR-orthonormalised) power
+    basis."""
+    op = O.const_cd((9, 8), (30.0, 10.0))
+    mv = lambda z: O.apply(op, z)
+    r = W.rhs(op.n, 4)
+    m = 8
+    K = [r / np.linalg.norm(r)]
+    for _ in range(m - 1):
+        K.append(mv(K[-1]))
+        K[-1] /= np.linalg.norm(K[-1])
+    Q, _ = np.linalg.qr(np.stack(K, axis=1))
+    AQ = O.apply(op, Q)
+    z, *_ = np.linalg.lstsq(AQ, r, rcond=None)
+    e_ref = Q @ z
+    e, lsq, steps = G.gmres_cycle(mv, r, m)
+    assert steps == m
+    np.testing.assert_allclose(e, e_ref, atol=1e-8 * np.linalg.norm(e_ref))
+    assert np.isclose(lsq, np.linalg.norm(r - mv(e)), rtol=1e-10)
+
+
+def test_gmres_restarted_matches_scipy():
+    op = O.const_cd((15, 15), (40.0, 0.0))
+    A = O.to_csr(op)
+    b = W.rhs(op.n, 9)
+    xs = []
+    spl.gmres(A, b, restart=10, maxiter=3, rtol=1e-30, callback=lambda xk: xs.append(xk.copy()),
+              callback_type="x")
+    x, rep = G.gmres_proj(op, b, rtol=1e-30, m=10, maxcyc=3)
+    np.testing.assert_allclose(x, xs[-1], atol=1e-9 * np.linalg.norm(x))
+
+
+def test_gmres_proj_deflation_helps():
+    """Sec. 3, Table 3.1: deflating with coarse-grid eigenvectors converges in
+    far fewer fine cycles than no deflation."""
+    op = O.example1_operator(63)
+    b = W.rhs(op.n, 1)
+    opc = O.coarsen(op)
+    xc, Wc, _ = DR.gmres_dr(opc, T.restrict(b, op.dims), 30, 10, maxcyc=80)
+    V, H = D.deflation_space(op, Wc, opc.dims)
+    _, r0 = G.gmres_proj(op, b, rtol=1e-8, m=20, maxcyc=1000)
+    _, r1 = G.gmres_proj(op, b, x0=T.prolongate(xc, opc.dims), V=V, H=H, rtol=1e-8, m=20, maxcyc=1000)
+    assert r1.status == 0 and r1.relres_true <= 1e-8
+    assert r1.cycles < 0.75 * r0.cycles
+
+
+# -------------------------------------------------------------- GMRES-DR ---
+
+def test_harmonic_ritz_definition():
+    """theta, y = V_m g are harmonic Ritz pairs iff (A - theta) y is
+    orthogonal to A range(V_m): Hbar^T Hbar g = theta H_m^T g."""
+    op = O.const_cd((11, 9), (30.0, 5.0))
+    V, Hbar, j = G.arnoldi(lambda z: O.apply(op, z), W.rhs(op.n, 1), 12)
+    theta, Gm = DR.harmonic_ritz(Hbar, 12)
+    ref = sla.eig(Hbar.T @ Hbar, Hbar[:12, :12].T, right=False)
+    for t in theta:
+        assert np.min(np.abs(ref - t)) <= 1e-9 * abs(t)
+    for t in ref:
+        assert np.min(np.abs(theta - t)) <= 1e-9 * abs(t)
+
+
+def test_gmres_dr_finds_closed_form_eigenvalues():
+    """Coarse grid of the small workload: 31^2, beta = 40.  The kept harmonic
+    Ritz values converge to the closed-form smallest eigenvalues."""
+    op = O.const_cd((31, 31), (40.0, 0.0))
+    h = 1 / 32
+    lx = 2 / h**2 - 2 * np.sqrt(1 / h**4 - 40.0**2 / (4 * h * h)) * np.cos(np.arange(1, 32) * np.pi * h)
+    ly = 2 / h**2 - 2 / h**2 * np.cos(np.arange(1, 32) * np.pi * h)
+    exact = np.sort((lx[:, None] + ly[None, :]).reshape(-1))[:6]
+    b = W.rhs(op.n, 1)
+    x, Wc, rep = DR.gmres_dr(op, b, 30, 10, nev=6, rtolev=1e-10, rtol=1e-10, maxcyc=200)
+    assert rep.nconv >= 6
+    got = np.sort(rep.theta.real)[:6]
+    np.testing.assert_allclose(got, exact, rtol=2e-6)
+    assert rep.relres <= 1e-9
+    assert np.linalg.norm(Wc.T @ Wc - np.eye(Wc.shape[1])) < 1e-12
+    # the span of W contains the converged eigenvectors: A W ~= W (W^T A W)
+    AW = O.apply(op, Wc)
+    th, Gm = np.linalg.eig(Wc.T @ AW)
+    order = np.argsort(np.abs(th))[:6]
+    for i in order:
+        y = Wc @ Gm[:, i]
+        assert np.linalg.norm(AW @ Gm[:, i] - th[i] * y) / np.linalg.norm(y) < 1e-6 * O.norm1(op)
+
+
+def test_gmres_dr_first_cycle_is_gmres():
+    op = O.const_cd((15, 13), (20.0, 0.0))
+    b = W.rhs(op.n, 2)
+    x, Wc, rep = DR.gmres_dr(op, b, 20, 5, maxcyc=1)
+    e, _, _ = G.gmres_cycle(lambda z: O.apply(op, z), b, 20)
+    np.testing.assert_allclose(x, e, atol=1e-10 * np.linalg.norm(e))
+
+
+def test_gmres_dr_complex_pairs():
+    """Cell Peclet > 1 gives a complex spectrum: kept pairs enter W as real
+    and imaginary parts (k = 8 grows to 9 when a pair straddles position k),
+    converged values match the dense eigenvalues, and each converged complex
+    eigenvector lies in span(W)."""
+    op = O.const_cd((9, 7), (40.0, 0.0))
+    evals, evecs = np.linalg.eig(O.to_csr(op).toarray())
+    assert np.abs(evals.imag).max() > 1.0
+    b = W.rhs(op.n, 6)
+    x, Wc, rep = DR.gmres_dr(op, b, 20, 8, nev=4, rtolev=1e-11, rtol=1e-12, maxcyc=300)
+    assert rep.nconv >= 4
+    assert np.linalg.norm(Wc.T @ Wc - np.eye(Wc.shape[1])) < 1e-12
+    assert np.any(np.abs(rep.theta.imag) > 1.0)
+    for t in rep.theta[:4]:
+        i = np.argmin(np.abs(evals - t))
+        assert abs(evals[i] - t) <= 1e-9 * abs(t)
+        v = evecs[:, i]
+        assert np.linalg.norm(v - Wc @ (Wc.T @ v)) < 1e-8
+
+
+# --------------------------------------------------------------- adjoint ---
+
+def _dense_solve(op, b, transpose=False):
+    A = O.to_csr(op).toarray()
+    return np.linalg.solve(A.T if transpose else A, b)
+
+
+def test_grad_k_matches_finite_differences():
+    dims = (9, 7)
+    k = W.kfield(dims, 5)
+    beta = (60.0, 0.0)
+    b = W.rhs(63, 7)
+    ustar = W.rhs(63, 6)
+
+    def L(kk):
+        return ADJ.loss(_dense_solve(O.div_k(dims, kk, beta), b), ustar)
+
+    op = O.div_k(dims, k, beta)
+    u = _dense_solve(op, b)
+    lam = _dense_solve(op, u - ustar, transpose=True)
+    g = ADJ.grad_k(lam, u, dims)
+    rng = np.random.default_rng(0)
+    for _ in range(12):
+        cj, ci = rng.integers(0, dims[1] + 1), rng.integers(0, dims[0] + 1)
+        eps = 1e-4 * k[cj, ci]
+        kp, km = k.copy(), k.copy()
+        kp[cj, ci] += eps
+        km[cj, ci] -= eps
+        fd = (L(kp) - L(km)) / (2 * eps)
+        assert abs(fd - g[cj, ci]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max())
+
+
+def test_grad_k_equals_derivative_matrix_form():
+    """dL/dk_c = -lambda^T (dA/dk_c) u with dA/dk_c from assembling the
+    operator with k = unit cell minus k = 0 (the operator is affine in k)."""
+    dims = (6, 5)
+    rng = np.random.default_rng(1)
+    lam, u = rng.standard_normal(30), rng.standard_normal(30)
+    g = ADJ.grad_k(lam, u, dims)
+    A0 = O.to_csr(O.div_k(dims, np.zeros((6, 7)), (20.0, 0.0)))
+    for cj, ci in [(0, 0), (2, 3), (5, 6), (3, 0)]:
+        e = np.zeros((6, 7))
+        e[cj, ci] = 1.0
+        dA = O.to_csr(O.div_k(dims, e, (20.0, 0.0))) - A0
+        assert np.isclose(g[cj, ci], -lam @ (dA @ u), rtol=1e-12, atol=1e-12)
+
+
+def test_grad_b_is_adjoint_solution():
+    dims = (7, 7)
+    op = O.div_k(dims, W.kfield(dims, 2), (60.0, 0.0))
+    b, ustar = W.rhs(49, 3), W.rhs(49, 4)
+    u = _dense_solve(op, b)
+    lam = _dense_solve(op, u - ustar, transpose=True)
+    d = W.rhs(49, 8)
+    eps = 1e-6
+    fd = (ADJ.loss(_dense_solve(op, b + eps * d), ustar) - ADJ.loss(_dense_solve(op, b - eps * d), ustar)) / (2 * eps)
+    assert np.isclose(fd, lam @ d, rtol=1e-6)

@@ -1,0 +1,66 @@
+"""Seeded synthetic inputs and workload definitions.
+
+This module is shared by the oracle-based tests and by the GPU path's tests
+and benchmark.  It holds NO arithmetic of the method: only random draws
+(``numpy.random.Generator(PCG64(seed))``) and the sizes, coefficients and
+solver parameters of each workload.  The paper's experiments use synthetic
+PDE matrices with random or analytic right-hand sides; these workloads are
+stand-ins of the same kind (no dataset is involved).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def rhs(n, seed):
+    """``b ~ N(0, 1)`` of length n, float64, lexicographic order."""
+    return rng(seed).standard_normal(n)
+
+
+def rhs_block(n, seeds):
+    """Column block (n, len(seeds)) of N(0,1) right-hand sides."""
+    return np.stack([rhs(n, s) for s in seeds], axis=1)
+
+
+def kfield(dims, seed, scale=0.5):
+    """Per-cell coefficient ``k = exp(scale * z)``, ``z ~ N(0,1)``, shape
+    ``(n_y + 1, n_x + 1)`` for an ``n_x x n_y`` interior grid."""
+    nx, ny = dims
+    return np.exp(scale * rng(seed).standard_normal((ny + 1, nx + 1)))
+
+
+def integer_field(shape, seed, lo=-8, hi=8):
+    """Small integers as float64 (sums and products of them are exact)."""
+    return rng(seed).integers(lo, hi + 1, size=shape).astype(np.float64)
+
+
+def uneven_instances():
+    """Sixteen uneven 2-D instances: ``N_i = 127 + 2 round(192 i / 15)``
+    interior points per side and convection ``beta_i = 10 + 190 i / 15``."""
+    out = []
+    for i in range(16):
+        N = 127 + 2 * int(round(192 * i / 15))
+        if N % 2 == 0:
+            N += 1
+        out.append({"N": N, "beta": 10.0 + 190.0 * i / 15.0, "seed": 200 + i})
+    return out
+
+
+# Workload table.  "C1" is the small case the oracle finishes in seconds;
+# "C2" is the headline single-GPU configuration.
+CONFIGS = {
+    "C1": dict(dim=2, n=(63, 63), beta=(40.0, 0.0), sigma=0.0, seed=1,
+               m=30, k=10, nev=10, rtolev=1e-8, ncyc=20, rtol=1e-8),
+    "C2": dict(dim=2, n=(1023, 1023), beta=(100.0, 0.0), sigma=0.0, seed=2,
+               m=80, k=30, nev=30, rtolev=1e-8, ncyc=20, rtol=1e-8, m3=50),
+    "C3": dict(dim=3, n=(255, 255, 255), beta=(50.0, 20.0, 10.0), sigma=0.0, seed=3,
+               m=90, k=40, nev=40, rtolev=1e-8, ncyc=20, rtol=1e-8),
+    "C4": dict(dim=2, n=(511, 511), beta=(100.0, 0.0), sigma=0.0, seeds=list(range(100, 132)),
+               m=80, k=30, nev=30, rtolev=1e-8, ncyc=20, rtol=1e-8),
+    "C5": dict(dim=2, n=(1023, 1023), beta=(60.0, 0.0), sigma=0.0, kseed=5, bstar_seed=6,
+               bseed=7, dir_seed=8, m=80, k=30, nev=30, rtolev=1e-8, ncyc=20, rtol=1e-8),
+}
