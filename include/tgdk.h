@@ -1,0 +1,260 @@
+/*
+ * tgdk -- two-grid deflated Krylov solvers for gfx950 (MI355X).
+ *
+ * C-ABI of the fine-grid hot path of the two-grid deflated Krylov method of
+ * Morgan, Whyte, Wilcox and Yang, "Two-grid deflated Krylov methods for linear
+ * equations" (arXiv 2005.03070).  The library solves A x = b (Sec. 1) for a
+ * finite-difference PDE operator A on a fine grid, using approximate
+ * eigenvectors computed on a coarse grid with GMRES-DR (Sec. 2.1) and moved to
+ * the fine grid (Sec. 3), a Galerkin projection over them (Sec. 2.2), and
+ * restarted BiCGStab with a projection before every cycle (Sec. 4.1,
+ * "BiCGStab(ncyc)-Proj(k)") or GMRES(m)-Proj(k) (Sec. 2.2).
+ *
+ * Conventions for every entry point:
+ *  - Vectors are caller-owned DEVICE memory (e.g. torch tensors), contiguous.
+ *    A block of several vectors is column-major: vector j starts at
+ *    ptr + j * n.  Right-hand sides and solutions are always float64.
+ *  - Grid ordering is lexicographic with x fastest: point (i, j, l), 0-based,
+ *    is element (l * n_y + j) * n_x + i.
+ *  - Every call is ordered on the context's HIP stream.  Calls that return
+ *    scalars or reports (solvers, setup) block the host until their work is
+ *    complete; the others only enqueue work.
+ *  - Return value: 0 OK; negative = hard error (outputs undefined, see
+ *    tgdk_last_error()); positive = soft outcome, outputs valid (see the
+ *    report).  Handles own their internal device workspaces.
+ *    *_destroy(NULL) is a no-op.  Handles are not thread-safe.
+ */
+#ifndef TGDK_H
+#define TGDK_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define TGDK_OK             0
+#define TGDK_E_INVALID     -1   /* bad argument (sizes, pointers, kinds) */
+#define TGDK_E_NOMEM       -2   /* device or host allocation failed */
+#define TGDK_E_HIP         -3   /* a HIP runtime call failed */
+#define TGDK_E_SINGULAR    -4   /* singular small matrix (H, Gram, Hessenberg) */
+#define TGDK_E_NONFINITE   -5   /* NaN/Inf in an input or a residual */
+#define TGDK_NOT_CONVERGED  1   /* tolerance not reached in the allowed cycles */
+#define TGDK_BREAKDOWN      2   /* a Krylov breakdown stopped all progress */
+
+/* element types */
+#define TGDK_F64 0
+#define TGDK_F32 1
+
+/* operator kinds */
+#define TGDK_CONST_CD    0  /* -Lap(u) + beta.grad(u) + sigma u, constant beta  */
+#define TGDK_VAR_STENCIL 1  /* per-row coefficients C,W,E,S,N(,D,U) given       */
+#define TGDK_DIV_K       2  /* 2-D -div(k grad u) + beta.grad(u) + sigma u,
+                               k per primal cell                              */
+
+/* solver methods and precisions */
+#define TGDK_BICGSTAB_PROJ 0
+#define TGDK_GMRES_PROJ    1
+#define TGDK_FP64          0
+#define TGDK_FP32_IR       1
+
+#define TGDK_MAX_DEFL 128   /* largest deflation space (k) and GMRES m */
+#define TGDK_NHIST    8     /* recorded BiCGStab scalars of the first cycle */
+
+/* Text of the last non-OK return on the calling thread ("" if none). */
+const char* tgdk_last_error(void);
+
+typedef struct tgdk_ctx_s*  tgdk_ctx;
+typedef struct tgdk_op_s*   tgdk_op;
+typedef struct tgdk_defl_s* tgdk_defl;
+
+/* Context: a device and a HIP stream (hipStream_t passed as void*, e.g.
+ * torch.cuda.current_stream().cuda_stream; NULL = the null stream).  The
+ * stream is borrowed, not owned. */
+int tgdk_ctx_create(tgdk_ctx* out, int device, void* hip_stream);
+int tgdk_ctx_destroy(tgdk_ctx ctx);
+/* Number of compute units of the context's device (for launch sizing). */
+int tgdk_ctx_num_cus(tgdk_ctx ctx);
+
+/* ---------------------------------------------------------------- operators
+ * The discretised operator of Sec. 1 / Sec. 3 Example 1: centred finite
+ * differences on the interior grid n[0] x n[1] (x n[2]) of the unit square
+ * (cube) with zero Dirichlet data, h_a = 1/(n[a]+1), matrix not scaled by h^2.
+ * Row p of A x is C_p x_p + sum over neighbours q of c_{q-p}(p) x_q; neighbours
+ * outside the domain are dropped.
+ *  - CONST_CD: C = sum_a 2/h_a^2 + sigma; along axis a the lower neighbour
+ *    has -1/h_a^2 - beta[a]/(2h_a), the upper -1/h_a^2 + beta[a]/(2h_a).
+ *  - VAR_STENCIL: coef is a device array of (2*dim+1)*n float64, the arrays
+ *    C, W, E, S, N (, D, U) one after the other (W/E = x-1/x+1, S/N = y-1/y+1,
+ *    D/U = z-1/z+1).  Copied.
+ *  - DIV_K (dim 2 only): coef is a device array of (n[0]+1)*(n[1]+1) float64
+ *    per-cell k, cell (cj, ci) at coef[cj*(n[0]+1) + ci] between node columns
+ *    ci, ci+1 and node rows cj, cj+1 (boundary nodes numbered 0 and n+1).  A
+ *    grid edge takes the mean of the two cells sharing it; centre
+ *    sum_e k_e/h^2 + sigma, neighbour -k_e/h^2 plus centred convection.  Copied.
+ * tgdk_op_create fails with TGDK_E_INVALID for n[a] < 1, dim not 2 or 3, or a
+ * NULL coef where one is needed. */
+typedef struct {
+    int dim;
+    int n[3];
+    int kind;
+    double beta[3];
+    double sigma;
+    const double* coef;
+} tgdk_op_desc;
+
+int tgdk_op_create(tgdk_ctx ctx, const tgdk_op_desc* desc, tgdk_op* out);
+/* The same PDE on the coarse grid h_c = 2 h_f (n_c = (n_f - 1)/2 per axis;
+ * every n_f must be odd and >= 3).  CONST_CD keeps beta and sigma; DIV_K takes
+ * the geometric mean of the 2x2 (2x2x2) fine cells; VAR_STENCIL cannot be
+ * coarsened (TGDK_E_INVALID). */
+int tgdk_op_coarsen(tgdk_op fine, tgdk_op* coarse);
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1) for nrhs column
+ * vectors; x and y device arrays of nrhs*n elements of type dtype
+ * (TGDK_F64/TGDK_F32); x and y must not overlap.  Enqueue only. */
+int tgdk_op_apply(tgdk_op op, int transpose, int dtype, const void* x, void* y, int nrhs);
+/* Number of unknowns n and dimensions of an operator. */
+int tgdk_op_info(tgdk_op op, int* dim, int* n_per_axis /* [3] */, long long* n);
+int tgdk_op_destroy(tgdk_op op);
+
+/* ----------------------------------------------------------- grid transfer
+ * Coarse-to-fine transfer of Sec. 3 ("spline interpolation or
+ * prolongation"), read as the linear spline: vf = P vc with bilinear
+ * (trilinear) weights 1, 1/2, 1/4 (, 1/8) on nested grids n_f = 2 n_c + 1.
+ * Restriction is full weighting vc = P^T vf / 2^dim.  Both apply the 1-D
+ * operator along x, then y, then z, adding contributors in increasing index
+ * order, so results are reproducible to the bit.  ncols column vectors of
+ * float64 (dtype must be TGDK_F64).  Enqueue only. */
+int tgdk_prolongate(tgdk_op coarse, tgdk_op fine, int dtype, const void* vc, void* vf, int ncols);
+int tgdk_restrict(tgdk_op fine, tgdk_op coarse, int dtype, const void* vf, void* vc, int ncols);
+
+/* ------------------------------------------------------ coarse GMRES-DR(m,k)
+ * Phase 1 of the Sec. 3 algorithm: GMRES-DR(m,k) (Sec. 2.1) on the coarse
+ * grid solves A_c x_c = b_c (or A_c^T x_c = b_c if transpose) and computes the
+ * k harmonic Ritz vectors with smallest |theta|.  It stops when
+ * ||b_c - A_c x_c|| <= rtol ||b_c|| and the nev smallest pairs have relative
+ * eigen-residual ||A y - rho y|| / ||A||_1 <= rtolev (checked at cycle ends),
+ * or after maxcyc cycles (returns TGDK_NOT_CONVERGED, outputs valid).
+ * b_c, x_c: device float64, n_c elements; x_c is overwritten (start 0).
+ * *coarse_space receives an orthonormal basis of the final harmonic Ritz
+ * vectors (k, or k+1 when a complex pair straddles position k).
+ * Requirements: 1 <= k < m <= TGDK_MAX_DEFL, nev <= k. */
+typedef struct {
+    int m, k, nev, maxcyc, transpose;
+    double rtolev, rtol;
+} tgdk_gmresdr_params;
+
+typedef struct {
+    int cycles, nconv, k_out;
+    long long mvps;
+    double relres;                       /* true ||b - A x|| / ||b|| at exit */
+    double theta_re[TGDK_MAX_DEFL + 1];  /* kept harmonic Ritz values */
+    double theta_im[TGDK_MAX_DEFL + 1];
+    double eigres[TGDK_MAX_DEFL + 1];    /* relative eigen-residuals */
+    double seconds;
+} tgdk_gmresdr_report;
+
+int tgdk_coarse_setup(tgdk_op coarse, const double* b_c, double* x_c,
+                      const tgdk_gmresdr_params* params, tgdk_defl* coarse_space,
+                      tgdk_gmresdr_report* report);
+
+/* ------------------------------------------------------- deflation spaces
+ * A deflation space holds an orthonormal V (n x k, device, stored float64 or
+ * float32) and H = V^T A V with its LU factors (Sec. 2.2 projection box,
+ * steps 1-2).  It belongs to one operator (and to A^T when transpose = 1).
+ *
+ * tgdk_defl_prolongate: V = Q of the thin QR (positive diagonal) of P W_c,
+ * where W_c is the basis of a coarse space; then H.  Errors with
+ * TGDK_E_SINGULAR if P W_c is rank deficient.
+ * tgdk_defl_from_basis: the same from a caller basis W (device float64, n x k
+ * column-major, not modified) on the operator's own grid.
+ * store_dtype: TGDK_F64 or TGDK_F32 (float32 storage: V is rounded once and
+ * H formed from the rounded V, so the projection stays exact for that basis).
+ */
+int tgdk_defl_prolongate(tgdk_defl coarse_space, tgdk_op fine, int store_dtype, tgdk_defl* fine_space);
+int tgdk_defl_from_basis(tgdk_op op, const double* W, int k, int transpose, int store_dtype,
+                         tgdk_defl* out);
+/* k and the store type of a space. */
+int tgdk_defl_info(tgdk_defl defl, int* k, int* store_dtype, long long* n);
+/* Copy V out as float64 (device, n x k) and H (host, k x k row-major); either
+ * pointer may be NULL. */
+int tgdk_defl_copy(tgdk_defl defl, double* V_out, double* H_out);
+int tgdk_defl_destroy(tgdk_defl defl);
+
+/* ------------------------------------------------------------ fine solve
+ * BiCGStab(ncyc)-Proj(k) (Sec. 4.1 algorithm box, step 3 a-d) or
+ * GMRES(m3)-Proj(k) (Sec. 2.2 box) on A x = b (A^T x = b if transpose).
+ *  - defl may be NULL (k = 0: plain restarted BiCGStab / GMRES(m3)).
+ *  - b, x: device float64, nrhs columns of n; x is the initial guess when
+ *    x0_given = 1, otherwise it is zeroed first.  The nrhs systems share A,
+ *    V and H and advance cycle by cycle together; each keeps its own scalars
+ *    and stops on its own.
+ *  - The overall tolerance is tau = rtol * min(||b||, ||b - A x0||) on the
+ *    true residual, recomputed in float64 after every cycle.
+ *  - Cycle tolerance (BiCGStab): the smaller of
+ *    (tau/||r||)^(1/(ncyc-icyc+1)) and (||r0||/||r||)(tau/||r0||)^(icyc/ncyc),
+ *    relative to the residual after the projection; after ncyc cycles
+ *    tau/||r|| for up to max_extra_cycles more cycles, then
+ *    TGDK_NOT_CONVERGED.
+ *  - precision TGDK_FP32_IR: the inner BiCGStab runs in float32 on the
+ *    correction system, its relative tolerance floored at fp32_floor; the
+ *    projection, x and the true residual stay float64.  (BiCGStab only.)
+ *  - maxit_cycle bounds the iterations of one inner cycle.
+ * reports: host array of nrhs reports.  Returns the worst status over the
+ * right-hand sides. */
+typedef struct {
+    int method;            /* TGDK_BICGSTAB_PROJ or TGDK_GMRES_PROJ */
+    int ncyc;              /* BiCGStab: requested cycles (>= 1) */
+    int m3;                /* GMRES: cycle length m (1..TGDK_MAX_DEFL) */
+    int precision;         /* TGDK_FP64 or TGDK_FP32_IR */
+    int x0_given;
+    int transpose;
+    int maxit_cycle;
+    int max_extra_cycles;  /* BiCGStab: cycles allowed past ncyc; GMRES: max cycles */
+    double rtol;
+    double fp32_floor;
+} tgdk_solve_params;
+
+typedef struct {
+    int status, cycles;
+    long long iters_inner, mvp_inner, mvp_boundary;
+    double relres_true;    /* ||b - A x|| / ||b|| at exit (float64) */
+    double seconds;        /* host wall time of the call */
+    int branch[4];         /* cycles whose tolerance came from criterion 1, 2, past-ncyc */
+    int n_first;           /* recorded first-cycle BiCGStab scalars */
+    double first_rho[TGDK_NHIST], first_alpha[TGDK_NHIST], first_omega[TGDK_NHIST];
+} tgdk_solve_report;
+
+int tgdk_solve(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int nrhs,
+               const tgdk_solve_params* params, tgdk_solve_report* reports);
+
+/* Several independent instances (each its own operator, deflation space or
+ * NULL, right-hand side and solution, all on one context and of one
+ * dimension) solved together: every kernel launch covers the tiles of all
+ * instances, so small and uneven grids fill the device in one launch per
+ * step.  Same parameters and reports (one per instance) as tgdk_solve. */
+int tgdk_solve_instances(int ninst, const tgdk_op* ops, const tgdk_defl* defls,
+                         const double* const* b, double* const* x,
+                         const tgdk_solve_params* params, tgdk_solve_report* reports);
+
+/* --------------------------------------------------------------- adjoint
+ * Gradient of L(u) = 1/2 ||u - u*||^2 with u = A(k)^{-1} b for a DIV_K
+ * operator, given u and lambda = A^{-T}(u - u*):
+ *   dL/dk_c = -sum over the four sides e = (p, q) of cell c of
+ *             (1/2) h^-2 (lambda_p - lambda_q)(u_p - u_q),
+ * with u = lambda = 0 on boundary nodes (dL/db = lambda needs no call).
+ * lambda, u: device float64 (n); grad_k: device float64 ((n_x+1)(n_y+1)).
+ * TGDK_E_INVALID unless the operator is 2-D DIV_K.  Enqueue only. */
+int tgdk_adjoint_grad_k(tgdk_op fine, const double* lambda, const double* u, double* grad_k);
+
+/* ------------------------------------------------------------- autotune
+ * Times the candidate tile heights of the stencil-shaped kernels for this
+ * operator and element type and keeps the fastest for later launches on
+ * operators of the same shape.  Results are cached in the file named by the
+ * environment variable TGDK_TUNE_CACHE (if set).  Returns the chosen tile
+ * height in *tile_y (may be NULL). */
+int tgdk_tune(tgdk_op op, int dtype, int nrhs, int* tile_y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TGDK_H */

@@ -1,0 +1,300 @@
+"""Python binding of the tgdk C-ABI.
+
+Tensors are torch CUDA(HIP) tensors; this module only checks shapes and
+dtypes and passes device pointers and the current stream to libtgdk.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import check, lib
+
+_CTX = {}
+
+
+def _stream_ptr(device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def context(device=None):
+    """The tgdk context for a device and its current torch stream."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else torch.device(device).index or 0)
+    key = (dev.index, _stream_ptr(dev))
+    if key not in _CTX:
+        h = C.c_void_p()
+        check(lib().tgdk_ctx_create(C.byref(h), dev.index, C.c_void_p(key[1])))
+        _CTX[key] = (h, dev)
+    return _CTX[key]
+
+
+def _ptr(t, dtype=torch.float64, numel=None, what="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what} has {t.numel()} elements, expected {numel}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Operator:
+    """A discretised operator (see include/tgdk.h, tgdk_op_desc)."""
+
+    def __init__(self, dims, kind=L.CONST_CD, beta=(0.0, 0.0, 0.0), sigma=0.0, coef=None, device=None,
+                 _handle=None):
+        self.ctx, self.device = context(device)
+        self.dims = tuple(int(d) for d in dims)
+        self.dim = len(self.dims)
+        self.n = int(np.prod(self.dims))
+        self.kind = kind
+        self.beta = tuple(float(b) for b in beta) + (0.0,) * (3 - len(beta))
+        self.sigma = float(sigma)
+        self._keep = coef
+        if _handle is not None:
+            self.h = _handle
+            return
+        d = L.OpDesc()
+        d.dim = self.dim
+        for a in range(3):
+            d.n[a] = self.dims[a] if a < self.dim else 1
+            d.beta[a] = self.beta[a]
+        d.kind = kind
+        d.sigma = self.sigma
+        d.coef = None
+        if coef is not None:
+            d.coef = _ptr(coef, what="coef")
+        h = C.c_void_p()
+        check(lib().tgdk_op_create(self.ctx, C.byref(d), C.byref(h)))
+        self.h = h
+
+    @classmethod
+    def const_cd(cls, dims, beta=(0.0, 0.0, 0.0), sigma=0.0, device=None):
+        return cls(dims, L.CONST_CD, beta, sigma, None, device)
+
+    @classmethod
+    def div_k(cls, dims, kcell, beta=(0.0, 0.0), sigma=0.0):
+        kcell = kcell.contiguous()
+        if tuple(kcell.shape) != (dims[1] + 1, dims[0] + 1):
+            raise ValueError("kcell must have shape (n_y + 1, n_x + 1)")
+        return cls(dims, L.DIV_K, beta, sigma, kcell, kcell.device)
+
+    @classmethod
+    def var_stencil(cls, dims, coef):
+        """coef: (2*dim+1, n) tensor, rows C, W, E, S, N(, D, U)."""
+        coef = coef.contiguous()
+        return cls(dims, L.VAR_STENCIL, (0.0, 0.0, 0.0), 0.0, coef, coef.device)
+
+    def coarsen(self):
+        h = C.c_void_p()
+        check(lib().tgdk_op_coarsen(self.h, C.byref(h)))
+        cd = tuple((d - 1) // 2 for d in self.dims)
+        return Operator(cd, self.kind, self.beta, self.sigma, None, self.device, _handle=h)
+
+    def apply(self, x, transpose=False):
+        """y = A x (or A^T x) for x of shape (n,) or (nrhs, n)."""
+        dt = L.F64 if x.dtype == torch.float64 else L.F32
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        _ptr(x, x.dtype, self.n * nrhs, "x")
+        y = torch.empty_like(x)
+        check(lib().tgdk_op_apply(self.h, int(transpose), dt, C.c_void_p(x.data_ptr()),
+                                  C.c_void_p(y.data_ptr()), nrhs))
+        return y
+
+    def tune(self, dtype=torch.float64, nrhs=1):
+        ty = C.c_int()
+        check(lib().tgdk_tune(self.h, L.F64 if dtype == torch.float64 else L.F32, nrhs, C.byref(ty)))
+        return ty.value
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None and _lib._lib is not None:
+                lib().tgdk_op_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def prolongate(coarse, fine, vc):
+    ncols = 1 if vc.dim() == 1 else vc.shape[0]
+    _ptr(vc, numel=coarse.n * ncols, what="vc")
+    vf = torch.empty((fine.n,) if vc.dim() == 1 else (ncols, fine.n), dtype=torch.float64, device=vc.device)
+    check(lib().tgdk_prolongate(coarse.h, fine.h, L.F64, C.c_void_p(vc.data_ptr()), C.c_void_p(vf.data_ptr()),
+                                ncols))
+    return vf
+
+
+def restrict(fine, coarse, vf):
+    ncols = 1 if vf.dim() == 1 else vf.shape[0]
+    _ptr(vf, numel=fine.n * ncols, what="vf")
+    vc = torch.empty((coarse.n,) if vf.dim() == 1 else (ncols, coarse.n), dtype=torch.float64, device=vf.device)
+    check(lib().tgdk_restrict(fine.h, coarse.h, L.F64, C.c_void_p(vf.data_ptr()), C.c_void_p(vc.data_ptr()),
+                              ncols))
+    return vc
+
+
+class DeflationSpace:
+    def __init__(self, handle, op, transpose):
+        self.h = handle
+        self.op = op
+        self.transpose = transpose
+        k, st, n = C.c_int(), C.c_int(), C.c_longlong()
+        check(lib().tgdk_defl_info(handle, C.byref(k), C.byref(st), C.byref(n)))
+        self.k, self.store, self.n = k.value, st.value, n.value
+
+    def basis(self):
+        """(V as a (k, n) float64 tensor, H as a k x k numpy array)."""
+        V = torch.empty((self.k, self.n), dtype=torch.float64, device=self.op.device)
+        H = np.zeros((self.k, self.k))
+        check(lib().tgdk_defl_copy(self.h, C.c_void_p(V.data_ptr()), H.ctypes.data_as(L.DP)))
+        return V, H
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None and _lib._lib is not None:
+                lib().tgdk_defl_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+@dataclass
+class SetupReport:
+    status: int
+    cycles: int
+    nconv: int
+    k_out: int
+    mvps: int
+    relres: float
+    theta: np.ndarray
+    eigres: np.ndarray
+    seconds: float
+
+
+def coarse_setup(coarse, b_c, m, k, nev=None, rtolev=1e-8, rtol=1e-8, maxcyc=300, transpose=False):
+    """GMRES-DR(m,k) on the coarse grid: returns (x_c, space, SetupReport)."""
+    _ptr(b_c, numel=coarse.n, what="b_c")
+    x_c = torch.empty_like(b_c)
+    p = L.GmresDrParams(m, k, k if nev is None else nev, maxcyc, int(transpose), rtolev, rtol)
+    rep = L.GmresDrReport()
+    h = C.c_void_p()
+    rc = check(lib().tgdk_coarse_setup(coarse.h, C.c_void_p(b_c.data_ptr()), C.c_void_p(x_c.data_ptr()),
+                                       C.byref(p), C.byref(h), C.byref(rep)))
+    kk = rep.k_out
+    theta = np.array(rep.theta_re[:kk]) + 1j * np.array(rep.theta_im[:kk])
+    sr = SetupReport(rc, rep.cycles, rep.nconv, kk, rep.mvps, rep.relres, theta, np.array(rep.eigres[:kk]),
+                     rep.seconds)
+    return x_c, DeflationSpace(h, coarse, transpose), sr
+
+
+def defl_prolongate(space, fine, store=torch.float64):
+    h = C.c_void_p()
+    check(lib().tgdk_defl_prolongate(space.h, fine.h, L.F64 if store == torch.float64 else L.F32, C.byref(h)))
+    return DeflationSpace(h, fine, space.transpose)
+
+
+def defl_from_basis(op, W, transpose=False, store=torch.float64):
+    """W: (k, n) float64 tensor (k basis vectors, each contiguous)."""
+    W = W.contiguous()
+    k = W.shape[0]
+    _ptr(W, numel=k * op.n, what="W")
+    h = C.c_void_p()
+    check(lib().tgdk_defl_from_basis(op.h, C.c_void_p(W.data_ptr()), k, int(transpose),
+                                     L.F64 if store == torch.float64 else L.F32, C.byref(h)))
+    return DeflationSpace(h, op, transpose)
+
+
+@dataclass
+class Report:
+    status: int
+    cycles: int
+    iters_inner: int
+    mvp_inner: int
+    mvp_boundary: int
+    relres_true: float
+    seconds: float
+    branch: list = field(default_factory=list)
+    first_scalars: list = field(default_factory=list)
+
+    @property
+    def status_name(self):
+        return L.STATUS_NAMES.get(self.status, str(self.status))
+
+
+def _params(method, ncyc, m3, precision, x0_given, transpose, maxit_cycle, max_extra, rtol, fp32_floor):
+    p = L.SolveParams()
+    p.method = L.GMRES_PROJ if method == "gmres" else L.BICGSTAB_PROJ
+    p.ncyc = ncyc
+    p.m3 = m3
+    p.precision = L.FP32_IR if precision == "fp32_ir" else L.FP64
+    p.x0_given = int(x0_given)
+    p.transpose = int(transpose)
+    p.maxit_cycle = maxit_cycle
+    if max_extra is None:
+        max_extra = ncyc if method != "gmres" else 1000
+    p.max_extra_cycles = max_extra
+    p.rtol = rtol
+    p.fp32_floor = fp32_floor
+    return p
+
+
+def _reports(reps):
+    out = []
+    for r in reps:
+        fs = [(r.first_rho[i], r.first_alpha[i], r.first_omega[i]) for i in range(r.n_first)]
+        out.append(Report(r.status, r.cycles, r.iters_inner, r.mvp_inner, r.mvp_boundary, r.relres_true,
+                          r.seconds, list(r.branch), fs))
+    return out
+
+
+def solve(op, b, x0=None, defl=None, method="bicgstab", ncyc=20, m3=50, precision="fp64", rtol=1e-8,
+          transpose=False, maxit_cycle=100000, max_extra=None, fp32_floor=1e-4, out=None):
+    """Fine solve of A x = b (A^T x = b if transpose).  b: (n,) or (nrhs, n)
+    float64.  Returns (x, [Report per right-hand side])."""
+    nrhs = 1 if b.dim() == 1 else b.shape[0]
+    _ptr(b, numel=op.n * nrhs, what="b")
+    if out is None:
+        out = torch.empty_like(b)
+    _ptr(out, numel=op.n * nrhs, what="x")
+    if x0 is not None:
+        out.copy_(x0)
+    p = _params(method, ncyc, m3, precision, x0 is not None, transpose, maxit_cycle, max_extra, rtol, fp32_floor)
+    reps = (L.SolveReport * nrhs)()
+    check(lib().tgdk_solve(op.h, defl.h if defl is not None else None, C.c_void_p(b.data_ptr()),
+                           C.c_void_p(out.data_ptr()), nrhs, C.byref(p), reps))
+    return out, _reports(reps)
+
+
+def solve_instances(ops, defls, bs, x0s=None, ncyc=20, precision="fp64", rtol=1e-8, maxit_cycle=100000,
+                    max_extra=None, fp32_floor=1e-4, outs=None):
+    """Independent instances solved together (one launch per step covers all)."""
+    ni = len(ops)
+    if outs is None:
+        outs = [torch.empty_like(b) for b in bs]
+    for j in range(ni):
+        _ptr(bs[j], numel=ops[j].n, what="b")
+        if x0s is not None:
+            outs[j].copy_(x0s[j])
+    p = _params("bicgstab", ncyc, 0, precision, x0s is not None, False, maxit_cycle, max_extra, rtol, fp32_floor)
+    oph = (C.c_void_p * ni)(*[o.h.value for o in ops])
+    dh = (C.c_void_p * ni)(*[(d.h.value if d is not None else None) for d in defls]) if defls else None
+    bp = (C.c_void_p * ni)(*[b.data_ptr() for b in bs])
+    xp = (C.c_void_p * ni)(*[x.data_ptr() for x in outs])
+    reps = (L.SolveReport * ni)()
+    check(lib().tgdk_solve_instances(ni, oph, dh, bp, xp, C.byref(p), reps))
+    return outs, _reports(reps)
+
+
+def grad_k(op, lam, u):
+    _ptr(lam, numel=op.n, what="lambda")
+    _ptr(u, numel=op.n, what="u")
+    g = torch.empty((op.dims[1] + 1, op.dims[0] + 1), dtype=torch.float64, device=u.device)
+    check(lib().tgdk_adjoint_grad_k(op.h, C.c_void_p(lam.data_ptr()), C.c_void_p(u.data_ptr()),
+                                    C.c_void_p(g.data_ptr())))
+    return g

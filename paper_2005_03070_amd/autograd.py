@@ -1,0 +1,81 @@
+"""Two-grid solver object and a differentiable solve.
+
+``TwoGridSolver`` strings the phases of the two-grid algorithm together
+(Sec. 3 algorithm box, phase 1 and phase 3; Sec. 4.1 for BiCGStab): the
+coarse operator, GMRES-DR on the coarse grid, moving its vectors and solution
+to the fine grid, and the deflated fine solve.  With ``transpose=True`` every
+phase uses ``A^T``: GMRES-DR on ``A_c^T`` yields left eigenvectors of
+``A_c``, which deflate the adjoint system.
+
+``DeflatedSolve`` is a ``torch.autograd.Function`` for
+``u = A(k)^{-1} b`` with ``A(k)`` the divergence-form operator built from the
+per-cell coefficient ``k``: the backward pass solves ``A^T lambda = dL/du``
+with the same two-grid method on the transpose and returns
+``dL/db = lambda`` and ``dL/dk`` from the edge formula (libtgdk's
+tgdk_adjoint_grad_k).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import api
+
+
+class TwoGridSolver:
+    def __init__(self, op, m=30, k=10, nev=None, rtolev=1e-8, coarse_rtol=1e-8, maxcyc=300,
+                 store=torch.float64, transpose=False):
+        self.op = op
+        self.coarse = op.coarsen()
+        self.m, self.k, self.nev = m, k, (k if nev is None else nev)
+        self.rtolev, self.coarse_rtol, self.maxcyc = rtolev, coarse_rtol, maxcyc
+        self.store = store
+        self.transpose = transpose
+        self.defl = None
+        self.setup_report = None
+
+    def setup(self, b):
+        """Phase 1: GMRES-DR on the restricted right-hand side; returns the
+        prolongated coarse solution (the fine initial guess)."""
+        bc = api.restrict(self.op, self.coarse, b)
+        xc, space, rep = api.coarse_setup(self.coarse, bc, self.m, self.k, self.nev, self.rtolev,
+                                          self.coarse_rtol, self.maxcyc, self.transpose)
+        self.setup_report = rep
+        self.defl = api.defl_prolongate(space, self.op, self.store)
+        return api.prolongate(self.coarse, self.op, xc)
+
+    def solve(self, b, x0=None, **kw):
+        """Phase 3 with the current deflation space (set up on the first call)."""
+        if self.defl is None:
+            x0 = self.setup(b)
+        kw.setdefault("transpose", self.transpose)
+        return api.solve(self.op, b, x0=x0, defl=self.defl, **kw)
+
+
+class DeflatedSolve(torch.autograd.Function):
+    """u = A(k)^{-1} b for the 2-D operator -div(k grad u) + beta.grad(u)."""
+
+    @staticmethod
+    def forward(ctx, b, kcell, dims, beta, cfg):
+        cfg = dict(cfg or {})
+        solve_kw = cfg.pop("solve", {})
+        op = api.Operator.div_k(tuple(dims), kcell.detach(), tuple(beta))
+        fwd = TwoGridSolver(op, **cfg)
+        u, reps = fwd.solve(b.detach().contiguous(), **solve_kw)
+        if reps[0].status != 0:
+            raise RuntimeError(f"forward solve ended with status {reps[0].status_name}")
+        ctx.op = op
+        ctx.cfg = cfg
+        ctx.solve_kw = solve_kw
+        ctx.reports = {"forward": reps[0], "forward_setup": fwd.setup_report}
+        ctx.save_for_backward(u)
+        return u
+
+    @staticmethod
+    def backward(ctx, g):
+        (u,) = ctx.saved_tensors
+        adj = TwoGridSolver(ctx.op, transpose=True, **ctx.cfg)
+        lam, reps = adj.solve(g.detach().contiguous(), **ctx.solve_kw)
+        if reps[0].status != 0:
+            raise RuntimeError(f"adjoint solve ended with status {reps[0].status_name}")
+        gk = api.grad_k(ctx.op, lam, u)
+        return lam, gk, None, None, None

@@ -1,0 +1,214 @@
+// Device-side building blocks shared by the tgdk kernels (gfx950, wave64).
+//
+// * Tile geometry: every grid-shaped kernel gives one 256-thread workgroup a
+//   64 (x) by TY (y) by TZ (z) tile.  x rows of 64 elements keep global
+//   accesses coalesced; stencil kernels stage the tile plus a one-point halo
+//   in LDS.
+// * XCD-aware tile order: consecutive workgroup ids are dispatched round-robin
+//   over the 8 XCDs, each with its own L2.  xcd_remap() gives every XCD a
+//   contiguous range of tiles so the halo rows a tile shares with its
+//   neighbours are read through the same L2.
+// * Deterministic reductions: wave butterflies, a fixed LDS combine and a
+//   "last workgroup" epilogue that sums per-tile partials in tile order.  No
+//   floating-point atomics, so reruns are bitwise identical.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tgdk_shared.h"
+
+namespace tgdk {
+
+constexpr int NT = 256;         // threads per workgroup of the tile kernels
+constexpr int NWAVE = NT / 64;
+constexpr int NXCD = 8;         // XCDs on MI355X
+
+template <int DIM, int TY_, int TZ_>
+struct Tile {
+    static constexpr int TX = 64, TY = TY_, TZ = TZ_;
+    static constexpr int HZ = (DIM == 3) ? 1 : 0;
+    static constexpr int BX = TX + 2, BY = TY + 2, BZ = TZ + 2 * HZ;
+    static constexpr int BOX = BX * BY * BZ;
+    static constexpr int PTS = TX * TY * TZ;
+    static constexpr int PPT = PTS / NT;
+    static_assert(PTS % NT == 0, "tile must be a multiple of the workgroup");
+};
+
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+    const int q = G / NXCD, rem = G % NXCD;
+    const int xcd = b % NXCD, local = b / NXCD;
+    return xcd * q + (xcd < rem ? xcd : rem) + local;
+}
+
+// Position of a tile inside its problem.
+struct TilePos {
+    int x0, y0, z0;
+};
+
+template <class Cfg>
+__device__ __forceinline__ TilePos tile_pos(int t, int tx, int ty) {
+    TilePos p;
+    const int ix = t % tx;
+    const int rest = t / tx;
+    p.x0 = ix * Cfg::TX;
+    p.y0 = (rest % ty) * Cfg::TY;
+    p.z0 = (rest / ty) * Cfg::TZ;
+    return p;
+}
+
+template <class T>
+__device__ __forceinline__ const T* coef_ptr(const DevOp& op);
+template <>
+__device__ __forceinline__ const double* coef_ptr<double>(const DevOp& op) { return op.coef64; }
+template <>
+__device__ __forceinline__ const float* coef_ptr<float>(const DevOp& op) { return op.coef32; }
+
+// Stencil row at global point g whose value sits at LDS index c of a halo box
+// with x stride 1, y stride BX and z stride BX*BY.  Terms are added in the
+// fixed order C, W, E, S, N, D, U.
+template <class Cfg, int DIM, class T>
+__device__ __forceinline__ T stencil_row(const DevOp& op, const T* __restrict__ L, int c, long long g) {
+    T cC, cW, cE, cS, cN, cD = 0, cU = 0;
+    if (op.var) {
+        const T* cf = coef_ptr<T>(op);
+        const long long n = op.n;
+        cC = cf[g];
+        cW = cf[n + g];
+        cE = cf[2 * n + g];
+        cS = cf[3 * n + g];
+        cN = cf[4 * n + g];
+        if (DIM == 3) {
+            cD = cf[5 * n + g];
+            cU = cf[6 * n + g];
+        }
+    } else {
+        cC = (T)op.cc[0];
+        cW = (T)op.cc[1];
+        cE = (T)op.cc[2];
+        cS = (T)op.cc[3];
+        cN = (T)op.cc[4];
+        if (DIM == 3) {
+            cD = (T)op.cc[5];
+            cU = (T)op.cc[6];
+        }
+    }
+    T y = cC * L[c];
+    y += cW * L[c - 1];
+    y += cE * L[c + 1];
+    y += cS * L[c - Cfg::BX];
+    y += cN * L[c + Cfg::BX];
+    if (DIM == 3) {
+        y += cD * L[c - Cfg::BX * Cfg::BY];
+        y += cU * L[c + Cfg::BX * Cfg::BY];
+    }
+    return y;
+}
+
+// Halo-box index h -> global coordinates.
+template <class Cfg>
+__device__ __forceinline__ void box_coords(int h, const TilePos& tp, int& gx, int& gy, int& gz) {
+    const int hx = h % Cfg::BX;
+    const int hy = (h / Cfg::BX) % Cfg::BY;
+    const int hz = h / (Cfg::BX * Cfg::BY);
+    gx = tp.x0 + hx - 1;
+    gy = tp.y0 + hy - 1;
+    gz = tp.z0 + hz - Cfg::HZ;
+}
+
+// Interior point q of this thread -> global coordinates and LDS centre index.
+template <class Cfg>
+__device__ __forceinline__ void point_coords(int q, const TilePos& tp, int& gx, int& gy, int& gz, int& c) {
+    const int l = threadIdx.x + q * NT;
+    const int lx = l % Cfg::TX;
+    const int ly = (l / Cfg::TX) % Cfg::TY;
+    const int lz = l / (Cfg::TX * Cfg::TY);
+    gx = tp.x0 + lx;
+    gy = tp.y0 + ly;
+    gz = tp.z0 + lz;
+    c = ((lz + Cfg::HZ) * Cfg::BY + (ly + 1)) * Cfg::BX + (lx + 1);
+}
+
+__device__ __forceinline__ bool inside(const DevOp& op, int gx, int gy, int gz) {
+    return gx >= 0 && gx < op.nx && gy >= 0 && gy < op.ny && gz >= 0 && gz < op.nz;
+}
+
+__device__ __forceinline__ long long gidx(const DevOp& op, int gx, int gy, int gz) {
+    return ((long long)gz * op.ny + gy) * op.nx + gx;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sums a[0..NR) over the workgroup; the totals land in out[0..NR) of thread
+// i < NR (other threads' out is undefined).  sh needs NWAVE*NR doubles.
+template <int NR>
+__device__ __forceinline__ void block_sum(const double (&a)[NR], double* sh, double& out) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const double s = wave_sum(a[i]);
+        if (lane == 0) sh[w * NR + i] = s;
+    }
+    __syncthreads();
+    out = 0.0;
+    if (threadIdx.x < NR) {
+        double s = sh[threadIdx.x];
+        for (int w2 = 1; w2 < NWAVE; ++w2) s += sh[w2 * NR + threadIdx.x];
+        out = s;
+    }
+    __syncthreads();
+}
+
+// Runtime-width variant: a[i] for i < nr held in shared memory rows; used
+// by the projection kernels.  vals[t * stride + i] contains thread t's value i.
+__device__ __forceinline__ double block_sum_one(double v, double* sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = sh[0];
+    for (int w2 = 1; w2 < NWAVE; ++w2) s += sh[w2];
+    __syncthreads();
+    return s;
+}
+
+// Every workgroup of a problem calls this once after writing its partials.
+// Returns true in exactly one workgroup -- the last to arrive -- which may
+// then read all partials of that problem.  The counter is reset for the next
+// launch by that workgroup.
+__device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned total) {
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned prev =
+            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = (prev == total - 1) ? 1 : 0;
+        if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const bool is_last = last != 0;
+    if (is_last) __threadfence();
+    return is_last;
+}
+
+// In the last workgroup: sums column i of partial[t * stride + i] over
+// t = 0..ntiles-1 in a fixed order; result valid in every thread.
+__device__ __forceinline__ double sum_partials(const double* partial, int ntiles, int stride, int i, double* sh) {
+    double s = 0.0;
+    for (int t = threadIdx.x; t < ntiles; t += NT) s += partial[(long long)t * stride + i];
+    return block_sum_one(s, sh);
+}
+
+// Problem lookup for grouped launches (linear scan; groups are small).
+__device__ __forceinline__ int find_prob(const DevProb* probs, int nprob, int tile) {
+    int j = 0;
+    while (j + 1 < nprob && tile >= probs[j + 1].tile_begin) ++j;
+    return j;
+}
+
+}  // namespace tgdk

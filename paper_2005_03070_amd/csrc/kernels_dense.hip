@@ -1,0 +1,231 @@
+// Tall-skinny kernels: Gram products A^T B, V Y products, and the classical
+// Gram-Schmidt steps of the Arnoldi process.  All reductions over the long
+// dimension are deterministic (per-block partials summed in block order by the
+// last block).
+#include "device_common.h"
+#include "launch.h"
+
+namespace tgdk {
+
+constexpr int GS_ROWS_PER_BLOCK = 1024;
+
+int gs_blocks(long long n) {
+    long long b = (n + GS_ROWS_PER_BLOCK - 1) / GS_ROWS_PER_BLOCK;
+    if (b > 1024) b = 1024;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+template <class T>
+__device__ __forceinline__ double ld(const void* p, long long i) {
+    return (double)reinterpret_cast<const T*>(p)[i];
+}
+
+// ------------------------------------------------------------- Gram A^T B
+// Each block walks chunks of 64 rows (grid-stride), stages them in LDS and
+// accumulates its share of the p x q outputs; thread t owns outputs
+// t, t+256, ... of the row-major p x q result.
+constexpr int GRAM_MAX = 64;
+constexpr int GRAM_CHUNK = 32;
+
+int gram_blocks(long long n) {
+    long long b = (n + 4 * GRAM_CHUNK - 1) / (4 * GRAM_CHUNK);
+    if (b > 512) b = 512;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+template <class TA, class TB>
+__global__ __launch_bounds__(NT) void k_gram(const void* A, long long lda, int p, const void* B, long long ldb,
+                                             int q, long long n, double* G, double* partial, unsigned* counter) {
+    __shared__ double As[GRAM_CHUNK][GRAM_MAX + 1];
+    __shared__ double Bs[GRAM_CHUNK][GRAM_MAX + 1];
+    __shared__ double sh[NWAVE];
+    const int npair = p * q;
+    constexpr int MAXPT = GRAM_MAX * GRAM_MAX / NT;
+    double acc[MAXPT];
+#pragma unroll
+    for (int i = 0; i < MAXPT; ++i) acc[i] = 0.0;
+    const long long nchunk = (n + GRAM_CHUNK - 1) / GRAM_CHUNK;
+    for (long long ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        const long long r0 = ch * GRAM_CHUNK;
+        for (int idx = threadIdx.x; idx < GRAM_CHUNK * p; idx += NT) {
+            const int rr = idx % GRAM_CHUNK, col = idx / GRAM_CHUNK;
+            const long long g = r0 + rr;
+            As[rr][col] = g < n ? ld<TA>(A, col * lda + g) : 0.0;
+        }
+        for (int idx = threadIdx.x; idx < GRAM_CHUNK * q; idx += NT) {
+            const int rr = idx % GRAM_CHUNK, col = idx / GRAM_CHUNK;
+            const long long g = r0 + rr;
+            Bs[rr][col] = g < n ? ld<TB>(B, col * ldb + g) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < MAXPT; ++s) {
+            const int pr = threadIdx.x + s * NT;
+            if (pr < npair) {
+                const int i = pr / q, j = pr % q;
+                double a = acc[s];
+                for (int rr = 0; rr < GRAM_CHUNK; ++rr) a += As[rr][i] * Bs[rr][j];
+                acc[s] = a;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < MAXPT; ++s) {
+        const int pr = threadIdx.x + s * NT;
+        if (pr < npair) partial[(long long)blockIdx.x * npair + pr] = acc[s];
+    }
+    if (!arrive_last(counter, gridDim.x)) return;
+    for (int pr = threadIdx.x; pr < npair; pr += NT) {
+        double s = 0.0;
+        for (int b = 0; b < (int)gridDim.x; ++b) s += partial[(long long)b * npair + pr];
+        G[pr] = s;
+    }
+    (void)sh;
+}
+
+void launch_gram(const void* A, int atype, long long lda, int p, const void* B, int btype, long long ldb, int q,
+                 long long n, double* G, double* partial, unsigned* counter, hipStream_t s) {
+    const int nb = gram_blocks(n);
+    if (atype == 0 && btype == 0)
+        hipLaunchKernelGGL((k_gram<double, double>), dim3(nb), dim3(NT), 0, s, A, lda, p, B, ldb, q, n, G, partial,
+                           counter);
+    else if (atype == 1 && btype == 1)
+        hipLaunchKernelGGL((k_gram<float, float>), dim3(nb), dim3(NT), 0, s, A, lda, p, B, ldb, q, n, G, partial,
+                           counter);
+    else if (atype == 1 && btype == 0)
+        hipLaunchKernelGGL((k_gram<float, double>), dim3(nb), dim3(NT), 0, s, A, lda, p, B, ldb, q, n, G, partial,
+                           counter);
+    else
+        hipLaunchKernelGGL((k_gram<double, float>), dim3(nb), dim3(NT), 0, s, A, lda, p, B, ldb, q, n, G, partial,
+                           counter);
+}
+
+// ---------------------------------------------------------------- V * Y
+__global__ __launch_bounds__(NT) void k_vmul(const double* __restrict__ V, long long ldv, int p,
+                                             const double* __restrict__ Y, int q, double* __restrict__ Out,
+                                             long long ldo, long long n) {
+    // Y is tiny and read uniformly by all lanes (scalar loads).
+    for (long long g = blockIdx.x * (long long)NT + threadIdx.x; g < n; g += (long long)gridDim.x * NT) {
+        for (int c = 0; c < q; ++c) {
+            double a = 0.0;
+            for (int i = 0; i < p; ++i) a += V[i * ldv + g] * Y[(long long)c * p + i];
+            Out[c * ldo + g] = a;
+        }
+    }
+}
+
+void launch_vmul(const double* V, long long ldv, int p, const double* Y, int q, double* Out, long long ldo,
+                 long long n, hipStream_t s) {
+    long long nb = (n + NT - 1) / NT;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_vmul, dim3((int)nb), dim3(NT), 0, s, V, ldv, p, Y, q, Out, ldo, n);
+}
+
+__global__ __launch_bounds__(NT) void k_vmul_add(const double* __restrict__ V, long long ldv, int p,
+                                                 const double* __restrict__ y, double* __restrict__ x, long long n) {
+    __shared__ double ys[MAXK + 1];
+    for (int i = threadIdx.x; i < p; i += NT) ys[i] = y[i];
+    __syncthreads();
+    for (long long g = blockIdx.x * (long long)NT + threadIdx.x; g < n; g += (long long)gridDim.x * NT) {
+        double a = 0.0;
+        for (int i = 0; i < p; ++i) a += V[i * ldv + g] * ys[i];
+        x[g] += a;
+    }
+}
+
+void launch_vmul_add(const double* V, long long ldv, int p, const double* y, double* x, long long n,
+                     hipStream_t s) {
+    long long nb = (n + NT - 1) / NT;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_vmul_add, dim3((int)nb), dim3(NT), 0, s, V, ldv, p, y, x, n);
+}
+
+// ------------------------------------------------- Gram-Schmidt (Arnoldi)
+// MODE 0: hout = V^T w.  MODE 1: w -= V h, then hout = V^T w.
+// MODE 2: w -= V h, then hout[0] = ||w||.
+template <int MODE>
+__global__ __launch_bounds__(NT) void k_gs(const double* __restrict__ V, long long ldv, int p, double* w,
+                                           const double* __restrict__ h, long long n, double* hout,
+                                           double* partial, unsigned* counter) {
+    __shared__ double sh[NWAVE * 16];
+    __shared__ double hs[MAXK + 1];
+    const long long stride = (long long)gridDim.x * NT;
+    const long long g0 = blockIdx.x * (long long)NT + threadIdx.x;
+    if (MODE >= 1 && p > 0) {
+        for (int i = threadIdx.x; i < p; i += NT) hs[i] = h[i];
+        __syncthreads();
+        for (long long g = g0; g < n; g += stride) {
+            double a = w[g];
+            for (int i = 0; i < p; ++i) a -= V[i * ldv + g] * hs[i];
+            w[g] = a;
+        }
+    }
+    if (MODE <= 1) {
+        const int pstride = MAXK + 1;
+        for (int c0 = 0; c0 < p; c0 += 16) {
+            double acc[16];
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
+            for (long long g = g0; g < n; g += stride) {
+                const double wv = w[g];
+#pragma unroll
+                for (int jj = 0; jj < 16; ++jj)
+                    if (c0 + jj < p) acc[jj] += V[(c0 + jj) * ldv + g] * wv;
+            }
+            double tot;
+            block_sum<16>(acc, sh, tot);
+            if (threadIdx.x < 16 && c0 + threadIdx.x < p)
+                partial[(long long)blockIdx.x * pstride + c0 + threadIdx.x] = tot;
+        }
+        if (!arrive_last(counter, gridDim.x)) return;
+        for (int i = 0; i < p; ++i) {
+            const double s = sum_partials(partial, gridDim.x, pstride, i, sh);
+            if (threadIdx.x == 0) hout[i] = s;
+        }
+    } else {
+        double acc[1] = {0.0};
+        for (long long g = g0; g < n; g += stride) acc[0] += w[g] * w[g];
+        double tot;
+        block_sum<1>(acc, sh, tot);
+        if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+        if (!arrive_last(counter, gridDim.x)) return;
+        const double s = sum_partials(partial, gridDim.x, 1, 0, sh);
+        if (threadIdx.x == 0) hout[0] = sqrt(s);
+    }
+}
+
+void launch_gs_dot(const double* V, long long ldv, int p, const double* w, long long n, double* hout,
+                   double* partial, unsigned* counter, hipStream_t s) {
+    hipLaunchKernelGGL((k_gs<0>), dim3(gs_blocks(n)), dim3(NT), 0, s, V, ldv, p, const_cast<double*>(w),
+                       (const double*)nullptr, n, hout, partial, counter);
+}
+void launch_gs_update_dot(const double* V, long long ldv, int p, double* w, const double* h, long long n,
+                          double* hout, double* partial, unsigned* counter, hipStream_t s) {
+    hipLaunchKernelGGL((k_gs<1>), dim3(gs_blocks(n)), dim3(NT), 0, s, V, ldv, p, w, h, n, hout, partial, counter);
+}
+void launch_gs_update_norm(const double* V, long long ldv, int p, double* w, const double* h, long long n,
+                           double* nrm, double* partial, unsigned* counter, hipStream_t s) {
+    hipLaunchKernelGGL((k_gs<2>), dim3(gs_blocks(n)), dim3(NT), 0, s, V, ldv, p, w, h, n, nrm, partial, counter);
+}
+void launch_norm2(const double* w, long long n, double* out, double* partial, unsigned* counter, hipStream_t s) {
+    hipLaunchKernelGGL((k_gs<2>), dim3(gs_blocks(n)), dim3(NT), 0, s, (const double*)nullptr, 0LL, 0,
+                       const_cast<double*>(w), (const double*)nullptr, n, out, partial, counter);
+}
+
+__global__ void k_scale(const double* w, double* v, const double* __restrict__ nrm,
+                        long long n) {
+    const double s = *nrm;
+    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < n;
+         g += (long long)gridDim.x * blockDim.x)
+        v[g] = s > 0.0 ? w[g] / s : 0.0;
+}
+void launch_scale(const double* w, double* v, const double* nrm, long long n, hipStream_t s) {
+    long long nb = (n + 255) / 256;
+    if (nb > 8192) nb = 8192;
+    hipLaunchKernelGGL(k_scale, dim3((int)nb), dim3(256), 0, s, w, v, nrm, n);
+}
+
+}  // namespace tgdk

@@ -1,0 +1,314 @@
+// Grid kernels: stencil application, operator construction, grid transfer and
+// the adjoint coefficient gradient.
+#include "device_common.h"
+#include "launch.h"
+
+namespace tgdk {
+
+// ------------------------------------------------------------------ y = A x
+// One workgroup per tile (blockIdx.x, XCD-remapped) and right-hand side
+// (blockIdx.y).  x is staged with its halo in LDS, so every x element is read
+// from global memory once per tile plus the halo.
+template <class Cfg, int DIM, class T>
+__global__ __launch_bounds__(NT) void k_apply(DevOp op, const T* __restrict__ x, T* __restrict__ y,
+                                              int tx, int ty) {
+    __shared__ T L[Cfg::BOX];
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const TilePos tp = tile_pos<Cfg>(tile, tx, ty);
+    const long long off = (long long)blockIdx.y * op.n;
+    x += off;
+    y += off;
+    for (int h = threadIdx.x; h < Cfg::BOX; h += NT) {
+        int gx, gy, gz;
+        box_coords<Cfg>(h, tp, gx, gy, gz);
+        L[h] = inside(op, gx, gy, gz) ? x[gidx(op, gx, gy, gz)] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Cfg::PPT; ++q) {
+        int gx, gy, gz, c;
+        point_coords<Cfg>(q, tp, gx, gy, gz, c);
+        if (inside(op, gx, gy, gz)) {
+            const long long g = gidx(op, gx, gy, gz);
+            y[g] = stencil_row<Cfg, DIM, T>(op, L, c, g);
+        }
+    }
+}
+
+template <class Cfg, int DIM, class T>
+static void apply_cfg(const DevOp& op, const T* x, T* y, int nrhs, hipStream_t s) {
+    const int tx = (op.nx + Cfg::TX - 1) / Cfg::TX;
+    const int ty = (op.ny + Cfg::TY - 1) / Cfg::TY;
+    const int tz = (op.nz + Cfg::TZ - 1) / Cfg::TZ;
+    dim3 grid(tx * ty * tz, nrhs);
+    hipLaunchKernelGGL((k_apply<Cfg, DIM, T>), grid, dim3(NT), 0, s, op, x, y, tx, ty);
+}
+
+template <class T>
+void launch_apply(const DevOp& op, const T* x, T* y, int nrhs, int tile_id, hipStream_t s) {
+    if (op.dim == 2) {
+        switch (tile_id) {
+            case 1: apply_cfg<Tile<2, 8, 1>, 2, T>(op, x, y, nrhs, s); break;
+            case 2: apply_cfg<Tile<2, 4, 1>, 2, T>(op, x, y, nrhs, s); break;
+            default: apply_cfg<Tile<2, 16, 1>, 2, T>(op, x, y, nrhs, s); break;
+        }
+    } else {
+        switch (tile_id) {
+            case 1: apply_cfg<Tile<3, 8, 4>, 3, T>(op, x, y, nrhs, s); break;
+            case 2: apply_cfg<Tile<3, 4, 8>, 3, T>(op, x, y, nrhs, s); break;
+            default: apply_cfg<Tile<3, 4, 4>, 3, T>(op, x, y, nrhs, s); break;
+        }
+    }
+}
+template void launch_apply<double>(const DevOp&, const double*, double*, int, int, hipStream_t);
+template void launch_apply<float>(const DevOp&, const float*, float*, int, int, hipStream_t);
+
+// ------------------------------------------------- operator construction
+// 2-D -div(k grad u) + beta.grad(u) + sigma u from per-cell k (cells
+// (n_y+1) x (n_x+1)); an edge takes the mean of the two cells sharing it.
+__global__ void k_build_divk(int nx, int ny, const double* __restrict__ kc, double hx, double hy,
+                             double bx, double by, double sigma, double* __restrict__ coef) {
+    const long long n = (long long)nx * ny;
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(p % nx), j = (int)(p / nx);   // interior node (i+1, j+1) in 0..n+1 numbering
+        const int kw = nx + 1;
+        const double k_sw = kc[(long long)j * kw + i];
+        const double k_se = kc[(long long)j * kw + i + 1];
+        const double k_nw = kc[(long long)(j + 1) * kw + i];
+        const double k_ne = kc[(long long)(j + 1) * kw + i + 1];
+        const double ke_e = 0.5 * (k_se + k_ne);
+        const double ke_w = 0.5 * (k_sw + k_nw);
+        const double ke_n = 0.5 * (k_nw + k_ne);
+        const double ke_s = 0.5 * (k_sw + k_se);
+        const double ix2 = 1.0 / (hx * hx), iy2 = 1.0 / (hy * hy);
+        coef[p] = (ke_e + ke_w) * ix2 + (ke_n + ke_s) * iy2 + sigma;
+        coef[n + p] = -ke_w * ix2 - bx / (2.0 * hx);
+        coef[2 * n + p] = -ke_e * ix2 + bx / (2.0 * hx);
+        coef[3 * n + p] = -ke_s * iy2 - by / (2.0 * hy);
+        coef[4 * n + p] = -ke_n * iy2 + by / (2.0 * hy);
+    }
+}
+
+void launch_build_divk(int nx, int ny, const double* kc, double bx, double by, double sigma, double* coef,
+                       hipStream_t s) {
+    const long long n = (long long)nx * ny;
+    const int blocks = (int)((n + 255) / 256 < 65535 ? (n + 255) / 256 : 65535);
+    hipLaunchKernelGGL(k_build_divk, dim3(blocks), dim3(256), 0, s, nx, ny, kc, 1.0 / (nx + 1),
+                       1.0 / (ny + 1), bx, by, sigma, coef);
+}
+
+// Transposed coefficients: (A^T)_{p,p+o} = A_{p+o,p}, i.e. the coefficient of
+// row p+o toward offset -o.  Out-of-domain entries are set to zero.
+__global__ void k_transpose_coef(int dim, int nx, int ny, int nz, const double* __restrict__ c,
+                                 double* __restrict__ ct) {
+    const long long n = (long long)nx * ny * nz;
+    const long long sy = nx, sz = (long long)nx * ny;
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(p % nx), j = (int)((p / nx) % ny), l = (int)(p / sz);
+        ct[p] = c[p];
+        ct[n + p] = (i > 0) ? c[2 * n + p - 1] : 0.0;            // W^T(p) = E(p-1)
+        ct[2 * n + p] = (i < nx - 1) ? c[n + p + 1] : 0.0;       // E^T(p) = W(p+1)
+        ct[3 * n + p] = (j > 0) ? c[4 * n + p - sy] : 0.0;       // S^T(p) = N(p-nx)
+        ct[4 * n + p] = (j < ny - 1) ? c[3 * n + p + sy] : 0.0;  // N^T(p) = S(p+nx)
+        if (dim == 3) {
+            ct[5 * n + p] = (l > 0) ? c[6 * n + p - sz] : 0.0;       // D^T(p) = U(p-nxny)
+            ct[6 * n + p] = (l < nz - 1) ? c[5 * n + p + sz] : 0.0;  // U^T(p) = D(p+nxny)
+        }
+    }
+}
+
+void launch_transpose_coef(int dim, int nx, int ny, int nz, const double* c, double* ct, hipStream_t s) {
+    const long long n = (long long)nx * ny * nz;
+    const int blocks = (int)((n + 255) / 256 < 65535 ? (n + 255) / 256 : 65535);
+    hipLaunchKernelGGL(k_transpose_coef, dim3(blocks), dim3(256), 0, s, dim, nx, ny, nz, c, ct);
+}
+
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, long long n) {
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x)
+        b[p] = (float)a[p];
+}
+__global__ void k_to_f64(const float* __restrict__ a, double* __restrict__ b, long long n) {
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x)
+        b[p] = (double)a[p];
+}
+
+void launch_to_f32(const double* a, float* b, long long n, hipStream_t s) {
+    const int blocks = (int)((n + 255) / 256 < 65535 ? (n + 255) / 256 : 65535);
+    hipLaunchKernelGGL(k_to_f32, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, a, b, n);
+}
+void launch_to_f64(const float* a, double* b, long long n, hipStream_t s) {
+    const int blocks = (int)((n + 255) / 256 < 65535 ? (n + 255) / 256 : 65535);
+    hipLaunchKernelGGL(k_to_f64, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, a, b, n);
+}
+
+// Coarse cell coefficient: geometric mean of the 2x2 fine cells.
+__global__ void k_coarsen_kcell(int ncx, int ncy, const double* __restrict__ kf, double* __restrict__ kc) {
+    const int cw = ncx + 1, fw = 2 * (ncx + 1);
+    const long long nc = (long long)(ncx + 1) * (ncy + 1);
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nc;
+         p += (long long)gridDim.x * blockDim.x) {
+        const int ci = (int)(p % cw), cj = (int)(p / cw);
+        const double a = log(kf[(long long)(2 * cj) * fw + 2 * ci]);
+        const double b = log(kf[(long long)(2 * cj) * fw + 2 * ci + 1]);
+        const double c = log(kf[(long long)(2 * cj + 1) * fw + 2 * ci]);
+        const double d = log(kf[(long long)(2 * cj + 1) * fw + 2 * ci + 1]);
+        kc[p] = exp(0.25 * (a + b + c + d));
+    }
+}
+
+void launch_coarsen_kcell(int ncx, int ncy, const double* kf, double* kc, hipStream_t s) {
+    const long long nc = (long long)(ncx + 1) * (ncy + 1);
+    const int blocks = (int)((nc + 255) / 256 < 65535 ? (nc + 255) / 256 : 65535);
+    hipLaunchKernelGGL(k_coarsen_kcell, dim3(blocks), dim3(256), 0, s, ncx, ncy, kf, kc);
+}
+
+// ------------------------------------------------------------ grid transfer
+// Linear-spline prolongation, applied as x-pass, then y-pass, then z-pass;
+// each 1-D pass copies a coinciding coarse value or averages the two
+// neighbours (zero outside).  Every product has weight 1/2, so the result is
+// exact up to the single rounding of each two-term sum.
+__device__ __forceinline__ double pr_x(const double* vc, int ncx, int ncy, int fi, int J, int K) {
+    if (J < 0 || J >= ncy) return 0.0;
+    const double* row = vc + ((long long)K * ncy + J) * ncx;
+    if (fi & 1) return row[(fi - 1) >> 1];
+    const int I = fi >> 1;  // neighbours I-1 and I
+    const double a = (I - 1 >= 0) ? row[I - 1] : 0.0;
+    const double b = (I < ncx) ? row[I] : 0.0;
+    return 0.5 * a + 0.5 * b;
+}
+__device__ __forceinline__ double pr_xy(const double* vc, int ncx, int ncy, int fi, int fj, int K) {
+    if (fj & 1) return pr_x(vc, ncx, ncy, fi, (fj - 1) >> 1, K);
+    const int J = fj >> 1;
+    return 0.5 * pr_x(vc, ncx, ncy, fi, J - 1, K) + 0.5 * pr_x(vc, ncx, ncy, fi, J, K);
+}
+
+__global__ void k_prolong(int dim, int ncx, int ncy, int ncz, const double* __restrict__ vc,
+                          double* __restrict__ vf) {
+    const int nfx = 2 * ncx + 1, nfy = 2 * ncy + 1, nfz = dim == 3 ? 2 * ncz + 1 : 1;
+    const long long nf = (long long)nfx * nfy * nfz, ncn = (long long)ncx * ncy * ncz;
+    vc += blockIdx.y * ncn;
+    vf += blockIdx.y * nf;
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nf;
+         p += (long long)gridDim.x * blockDim.x) {
+        const int fi = (int)(p % nfx), fj = (int)((p / nfx) % nfy), fk = (int)(p / ((long long)nfx * nfy));
+        double out;
+        if (dim == 2) {
+            out = pr_xy(vc, ncx, ncy, fi, fj, 0);
+        } else if (fk & 1) {
+            out = pr_xy(vc, ncx, ncy, fi, fj, (fk - 1) >> 1);
+        } else {
+            const int K = fk >> 1;
+            const double a = (K - 1 >= 0) ? pr_xy(vc, ncx, ncy, fi, fj, K - 1) : 0.0;
+            const double b = (K < ncz) ? pr_xy(vc, ncx, ncy, fi, fj, K) : 0.0;
+            out = 0.5 * a + 0.5 * b;
+        }
+        vf[p] = out;
+    }
+}
+
+void launch_prolong(int dim, int ncx, int ncy, int ncz, const double* vc, double* vf, int ncols, hipStream_t s) {
+    const long long nf = (long long)(2 * ncx + 1) * (2 * ncy + 1) * (dim == 3 ? 2 * ncz + 1 : 1);
+    const int blocks = (int)((nf + 255) / 256 < 16384 ? (nf + 255) / 256 : 16384);
+    hipLaunchKernelGGL(k_prolong, dim3(blocks, ncols), dim3(256), 0, s, dim, ncx, ncy, ncz, vc, vf);
+}
+
+// Full weighting: 1/4, 1/2, 1/4 along x, then y, then z (added in that order).
+__device__ __forceinline__ double rs_x(const double* vf, int nfx, int nfy, int I, int fj, int fk) {
+    const double* row = vf + ((long long)fk * nfy + fj) * nfx;
+    const double t = 0.25 * row[2 * I] + 0.5 * row[2 * I + 1];
+    return t + 0.25 * row[2 * I + 2];
+}
+__device__ __forceinline__ double rs_xy(const double* vf, int nfx, int nfy, int I, int J, int fk) {
+    const double t = 0.25 * rs_x(vf, nfx, nfy, I, 2 * J, fk) + 0.5 * rs_x(vf, nfx, nfy, I, 2 * J + 1, fk);
+    return t + 0.25 * rs_x(vf, nfx, nfy, I, 2 * J + 2, fk);
+}
+
+__global__ void k_restrict(int dim, int ncx, int ncy, int ncz, const double* __restrict__ vf,
+                           double* __restrict__ vc) {
+    const int nfx = 2 * ncx + 1, nfy = 2 * ncy + 1, nfz = dim == 3 ? 2 * ncz + 1 : 1;
+    const long long nf = (long long)nfx * nfy * nfz, ncn = (long long)ncx * ncy * (dim == 3 ? ncz : 1);
+    vc += blockIdx.y * ncn;
+    vf += blockIdx.y * nf;
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < ncn;
+         p += (long long)gridDim.x * blockDim.x) {
+        const int I = (int)(p % ncx), J = (int)((p / ncx) % ncy), K = (int)(p / ((long long)ncx * ncy));
+        double out;
+        if (dim == 2) {
+            out = rs_xy(vf, nfx, nfy, I, J, 0);
+        } else {
+            const double t = 0.25 * rs_xy(vf, nfx, nfy, I, J, 2 * K) + 0.5 * rs_xy(vf, nfx, nfy, I, J, 2 * K + 1);
+            out = t + 0.25 * rs_xy(vf, nfx, nfy, I, J, 2 * K + 2);
+        }
+        vc[p] = out;
+    }
+}
+
+void launch_restrict(int dim, int ncx, int ncy, int ncz, const double* vf, double* vc, int ncols, hipStream_t s) {
+    const long long ncn = (long long)ncx * ncy * (dim == 3 ? ncz : 1);
+    const int blocks = (int)((ncn + 255) / 256 < 16384 ? (ncn + 255) / 256 : 16384);
+    hipLaunchKernelGGL(k_restrict, dim3(blocks > 0 ? blocks : 1, ncols), dim3(256), 0, s, dim, ncx, ncy,
+                       dim == 3 ? ncz : 1, vf, vc);
+}
+
+// ----------------------------------------------------- adjoint gradient
+// dL/dk_c = -1/2 (sum of (lam_p - lam_q)(u_p - u_q)/h^2 over the four sides of
+// cell c), boundary nodes carrying zero.
+__device__ __forceinline__ double node_val(const double* v, int nx, int ny, int i, int j) {
+    // i, j in 0..n+1 numbering (0 and n+1 are boundary)
+    if (i < 1 || i > nx || j < 1 || j > ny) return 0.0;
+    return v[(long long)(j - 1) * nx + (i - 1)];
+}
+
+__global__ void k_grad_k(int nx, int ny, const double* __restrict__ lam, const double* __restrict__ u,
+                         double* __restrict__ g) {
+    const double hx = 1.0 / (nx + 1), hy = 1.0 / (ny + 1);
+    const long long nc = (long long)(nx + 1) * (ny + 1);
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nc;
+         p += (long long)gridDim.x * blockDim.x) {
+        const int ci = (int)(p % (nx + 1)), cj = (int)(p / (nx + 1));
+        // corners (ci, cj), (ci+1, cj), (ci, cj+1), (ci+1, cj+1)
+        const double l00 = node_val(lam, nx, ny, ci, cj), l10 = node_val(lam, nx, ny, ci + 1, cj);
+        const double l01 = node_val(lam, nx, ny, ci, cj + 1), l11 = node_val(lam, nx, ny, ci + 1, cj + 1);
+        const double u00 = node_val(u, nx, ny, ci, cj), u10 = node_val(u, nx, ny, ci + 1, cj);
+        const double u01 = node_val(u, nx, ny, ci, cj + 1), u11 = node_val(u, nx, ny, ci + 1, cj + 1);
+        const double exb = (l10 - l00) * (u10 - u00) / (hx * hx);  // bottom side
+        const double ext = (l11 - l01) * (u11 - u01) / (hx * hx);  // top side
+        const double eyl = (l01 - l00) * (u01 - u00) / (hy * hy);  // left side
+        const double eyr = (l11 - l10) * (u11 - u10) / (hy * hy);  // right side
+        g[p] = -0.5 * (((exb + ext) + eyl) + eyr);
+    }
+}
+
+void launch_grad_k(int nx, int ny, const double* lam, const double* u, double* g, hipStream_t s) {
+    const long long nc = (long long)(nx + 1) * (ny + 1);
+    const int blocks = (int)((nc + 255) / 256 < 16384 ? (nc + 255) / 256 : 16384);
+    hipLaunchKernelGGL(k_grad_k, dim3(blocks), dim3(256), 0, s, nx, ny, lam, u, g);
+}
+
+// ----------------------------------------------------- simple vector ops
+__global__ void k_fill(double* __restrict__ a, double v, long long n) {
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x)
+        a[p] = v;
+}
+void launch_fill(double* a, double v, long long n, hipStream_t s) {
+    const int blocks = (int)((n + 255) / 256 < 16384 ? (n + 255) / 256 : 16384);
+    hipLaunchKernelGGL(k_fill, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, a, v, n);
+}
+
+// Copy kernel of known size: the bandwidth ceiling used to scale counters.
+__global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, long long n) {
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x)
+        b[p] = a[p];
+}
+void launch_copy(const double* a, double* b, long long n, hipStream_t s) {
+    const int blocks = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    hipLaunchKernelGGL(k_copy, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, a, b, n);
+}
+
+}  // namespace tgdk

@@ -1,0 +1,600 @@
+// Fused kernels of the fine solve: true residual, Galerkin projection,
+// restarted BiCGStab and the end-of-cycle update.  All of them take a group
+// of problems (one or more right-hand sides or grid instances); one launch
+// covers every tile of every problem.  The scalar recurrences run on the
+// device in the epilogue of the last workgroup of each problem, so the host
+// never waits inside a cycle.
+//
+// BiCGStab (van der Vorst; Sec. 4.1 of the paper runs it restarted) is
+// evaluated in two launches per iteration:
+//
+//   phase A (iteration i):  r_i = s_{i-1} - w t_{i-1};  e += a p_{i-1} + w s_{i-1};
+//                           p_i = r_i + beta (p_{i-1} - w v_{i-1});  v_i = A p_i;
+//                           partial r^.v_i
+//   epilogue:               alpha = rho_i / (r^.v_i)
+//   phase B:                s_i = r_i - alpha v_i;  t_i = A s_i;
+//                           partials s.s, t.s, t.t, r^.s, r^.t
+//   epilogue:               omega = t.s / t.t;  ||r_{i+1}||^2 = s.s - 2 w t.s + w^2 t.t;
+//                           rho_{i+1} = r^.s - w r^.t (no separate pass over r_{i+1})
+//
+// Each phase recomputes its stencil input (p_i or s_i) on the tile halo from
+// the previous vectors, so the update and the stencil share one pass.
+#include "device_common.h"
+#include "launch.h"
+
+namespace tgdk {
+
+enum : int { SV_NONFINITE = 4 };
+
+template <class T>
+__device__ __forceinline__ T* vp(void* p) { return reinterpret_cast<T*>(p); }
+
+__device__ __forceinline__ void mirror_out(const DevProb& P, const SolveState* st) {
+    if (P.mirror) {
+        P.mirror->solve_state = st->solve_state;
+        P.mirror->inner_state = st->inner_state;
+        P.mirror->icyc = st->icyc;
+        P.mirror->iter = st->iter;
+        __threadfence_system();
+    }
+}
+
+// Sec. 4.1 step 3 b): tolerance of the cycle that starts with residual nu.
+__device__ void start_cycle(SolveState* st, double nu, double rho0) {
+    double rt;
+    int branch;
+    if (st->icyc > st->ncyc) {
+        rt = st->tau / nu;
+        branch = 3;
+    } else {
+        const double t1 = pow(st->tau / nu, 1.0 / (double)(st->ncyc - st->icyc + 1));
+        const double t2 = (st->nu0 / nu) * pow(st->tau / st->nu0, (double)st->icyc / (double)st->ncyc);
+        if (t1 <= t2) {
+            rt = t1;
+            branch = 1;
+        } else {
+            rt = t2;
+            branch = 2;
+        }
+    }
+    if (st->precision == 1 && rt < st->fp32_floor) rt = st->fp32_floor;
+    st->rt = rt;
+    st->target2 = (rt * nu) * (rt * nu);
+    st->branch[branch] += 1;
+    st->rho = rho0;
+    st->rho_old = 1.0;
+    st->alpha = 1.0;
+    st->omega = 1.0;
+    st->iter = 0;
+    st->inner_state = IN_RUNNING;
+}
+
+// ---------------------------------------------------------- true residual
+// r = b - A x (float64).  first != 0 on the first call of a solve (also sums
+// ||b||^2).  Without deflation vectors (k = 0) a BiCGStab cycle starts here:
+// the inner residual and shadow vector are written in the inner type.
+template <class Cfg, int DIM, class TI>
+__global__ __launch_bounds__(NT) void k_residual(const DevProb* __restrict__ probs, int nprob, int first) {
+    __shared__ double L[Cfg::BOX];
+    __shared__ double sh[NWAVE * 3];
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const DevProb& P = probs[find_prob(probs, nprob, t)];
+    SolveState* st = P.st;
+    if (first != 2 && st->solve_state != SV_RUNNING) return;
+    const TilePos tp = tile_pos<Cfg>(t - P.tile_begin, P.tx, P.ty);
+    const DevOp& op = P.op;
+    const double* x = P.x;
+    for (int h = threadIdx.x; h < Cfg::BOX; h += NT) {
+        int gx, gy, gz;
+        box_coords<Cfg>(h, tp, gx, gy, gz);
+        L[h] = inside(op, gx, gy, gz) ? x[gidx(op, gx, gy, gz)] : 0.0;
+    }
+    __syncthreads();
+    const bool start = (P.k == 0) && (st->method == METHOD_BICGSTAB) && first != 2;
+    TI* rin = vp<TI>(P.rin);
+    TI* rhat = vp<TI>(P.rhat);
+    const bool sep = (void*)rin != (void*)P.r;
+    double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < Cfg::PPT; ++q) {
+        int gx, gy, gz, c;
+        point_coords<Cfg>(q, tp, gx, gy, gz, c);
+        if (!inside(op, gx, gy, gz)) continue;
+        const long long g = gidx(op, gx, gy, gz);
+        const double bv = P.b[g];
+        const double rv = bv - stencil_row<Cfg, DIM, double>(op, L, c, g);
+        P.r[g] = rv;
+        acc[0] += rv * rv;
+        acc[1] += bv * bv;
+        if (start) {
+            const TI ri = (TI)rv;
+            if (sep) rin[g] = ri;
+            rhat[g] = ri;
+            acc[2] += (double)ri * (double)ri;
+        }
+    }
+    double tot;
+    block_sum<3>(acc, sh, tot);
+    const int lt = t - P.tile_begin;
+    if (threadIdx.x < 3) P.partial[(long long)lt * P.pstride + threadIdx.x] = tot;
+    if (!arrive_last(P.counter, P.ntiles)) return;
+    const double rr = sum_partials(P.partial, P.ntiles, P.pstride, 0, sh);
+    const double bb = sum_partials(P.partial, P.ntiles, P.pstride, 1, sh);
+    const double ri = sum_partials(P.partial, P.ntiles, P.pstride, 2, sh);
+    if (threadIdx.x != 0) return;
+    if (first == 2) {
+        st->nu_final = sqrt(rr);
+        return;
+    }
+    st->mvp_boundary += 1;
+    const double nu = sqrt(rr);
+    st->nu = nu;
+    if (first) {
+        st->bnorm = sqrt(bb);
+        st->nu0 = nu;
+        st->tau = st->rtol * fmin(st->bnorm, nu);
+        if (!isfinite(nu))
+            st->solve_state = SV_NONFINITE;
+        else if (nu <= st->tau || nu == 0.0)
+            st->solve_state = SV_CONVERGED;
+    } else {
+        const bool broke = (st->inner_state == IN_BREAK_NOUPD || st->inner_state == IN_BREAK_FULL);
+        if (!isfinite(nu))
+            st->solve_state = SV_NONFINITE;
+        else if (nu <= st->tau)
+            st->solve_state = SV_CONVERGED;
+        else if (st->method == METHOD_BICGSTAB && broke && st->iter == 0)
+            st->solve_state = SV_BREAKDOWN;
+        else if (st->icyc >= st->ncyc + st->max_extra)
+            st->solve_state = SV_NOT_CONVERGED;
+    }
+    if (st->solve_state == SV_RUNNING) {
+        st->icyc += 1;
+        if (start) start_cycle(st, nu, ri);
+    }
+    mirror_out(P, st);
+}
+
+// ------------------------------------------------- projection: c = V^T r
+// Partials of c over the tile, then (last workgroup) c summed in tile order
+// and H d = c solved with the LU factors of H (Sec. 2.2 box, steps 2-3).
+template <class Cfg, class TV>
+__global__ __launch_bounds__(NT) void k_proj_dot(const DevProb* __restrict__ probs, int nprob) {
+    __shared__ double sh[NWAVE * 16];
+    __shared__ double y[MAXK + 1];
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const DevProb& P = probs[find_prob(probs, nprob, t)];
+    SolveState* st = P.st;
+    if (st->solve_state != SV_RUNNING || P.k == 0) return;
+    const int lt = t - P.tile_begin;
+    const TilePos tp = tile_pos<Cfg>(lt, P.tx, P.ty);
+    const DevOp& op = P.op;
+    const TV* V = reinterpret_cast<const TV*>(P.V);
+    const int k = P.k;
+    double rv[Cfg::PPT];
+    long long gq[Cfg::PPT];
+#pragma unroll
+    for (int q = 0; q < Cfg::PPT; ++q) {
+        int gx, gy, gz, c;
+        point_coords<Cfg>(q, tp, gx, gy, gz, c);
+        const bool ok = inside(op, gx, gy, gz);
+        gq[q] = ok ? gidx(op, gx, gy, gz) : -1;
+        rv[q] = ok ? P.r[gq[q]] : 0.0;
+    }
+    for (int c0 = 0; c0 < k; c0 += 16) {
+        double acc[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
+#pragma unroll
+        for (int q = 0; q < Cfg::PPT; ++q) {
+            if (gq[q] < 0) continue;
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj)
+                if (c0 + jj < k) acc[jj] += (double)V[(long long)(c0 + jj) * P.ldv + gq[q]] * rv[q];
+        }
+        double tot;
+        block_sum<16>(acc, sh, tot);
+        if (threadIdx.x < 16 && c0 + threadIdx.x < k)
+            P.partial[(long long)lt * P.pstride + c0 + threadIdx.x] = tot;
+    }
+    if (!arrive_last(P.counter, P.ntiles)) return;
+    for (int i = 0; i < k; ++i) {
+        const double ci = sum_partials(P.partial, P.ntiles, P.pstride, i, sh);
+        if (threadIdx.x == 0) y[i] = ci;
+    }
+    __syncthreads();
+    // LU solve: row interchanges, then L (unit lower) and U (upper), row-major.
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < k; ++i) st->cvec[i] = y[i];
+        for (int i = 0; i < k; ++i) {
+            const int pi = P.piv[i];
+            if (pi != i) {
+                const double tmp = y[i];
+                y[i] = y[pi];
+                y[pi] = tmp;
+            }
+        }
+    }
+    __syncthreads();
+    const double* LU = P.lu;
+    for (int j = 0; j < k; ++j) {
+        const double yj = y[j];
+        __syncthreads();
+        for (int i = j + 1 + threadIdx.x; i < k; i += NT) y[i] -= LU[i * k + j] * yj;
+        __syncthreads();
+    }
+    for (int j = k - 1; j >= 0; --j) {
+        if (threadIdx.x == 0) y[j] = y[j] / LU[j * k + j];
+        __syncthreads();
+        const double yj = y[j];
+        for (int i = threadIdx.x; i < j; i += NT) y[i] -= LU[i * k + j] * yj;
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < k; i += NT) st->d[i] = y[i];
+}
+
+// ---------------------------------- projection: x += V d, r -= A (V d)
+// w = V d is formed on the tile halo in LDS; then x += w and r -= A w on the
+// tile.  Starts the BiCGStab cycle (inner residual, shadow vector, rticyc).
+template <class Cfg, int DIM, class TV, class TI>
+__global__ __launch_bounds__(NT) void k_proj_apply(const DevProb* __restrict__ probs, int nprob) {
+    __shared__ double L[Cfg::BOX];
+    __shared__ double dsh[MAXK + 1];
+    __shared__ double sh[NWAVE * 2];
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const DevProb& P = probs[find_prob(probs, nprob, t)];
+    SolveState* st = P.st;
+    if (st->solve_state != SV_RUNNING || P.k == 0) return;
+    const int lt = t - P.tile_begin;
+    const TilePos tp = tile_pos<Cfg>(lt, P.tx, P.ty);
+    const DevOp& op = P.op;
+    const TV* V = reinterpret_cast<const TV*>(P.V);
+    const int k = P.k;
+    for (int i = threadIdx.x; i < k; i += NT) dsh[i] = st->d[i];
+    __syncthreads();
+    for (int h = threadIdx.x; h < Cfg::BOX; h += NT) {
+        int gx, gy, gz;
+        box_coords<Cfg>(h, tp, gx, gy, gz);
+        double w = 0.0;
+        if (inside(op, gx, gy, gz)) {
+            const long long g = gidx(op, gx, gy, gz);
+            for (int j = 0; j < k; ++j) w += (double)V[(long long)j * P.ldv + g] * dsh[j];
+        }
+        L[h] = w;
+    }
+    __syncthreads();
+    const bool start = st->method == METHOD_BICGSTAB;
+    TI* rin = vp<TI>(P.rin);
+    TI* rhat = vp<TI>(P.rhat);
+    const bool sep = (void*)rin != (void*)P.r;
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < Cfg::PPT; ++q) {
+        int gx, gy, gz, c;
+        point_coords<Cfg>(q, tp, gx, gy, gz, c);
+        if (!inside(op, gx, gy, gz)) continue;
+        const long long g = gidx(op, gx, gy, gz);
+        P.x[g] += L[c];
+        const double rv = P.r[g] - stencil_row<Cfg, DIM, double>(op, L, c, g);
+        P.r[g] = rv;
+        acc[0] += rv * rv;
+        if (start) {
+            const TI ri = (TI)rv;
+            if (sep) rin[g] = ri;
+            rhat[g] = ri;
+            acc[1] += (double)ri * (double)ri;
+        }
+    }
+    double tot;
+    block_sum<2>(acc, sh, tot);
+    if (threadIdx.x < 2) P.partial[(long long)lt * P.pstride + threadIdx.x] = tot;
+    if (!arrive_last(P.counter, P.ntiles)) return;
+    const double rr = sum_partials(P.partial, P.ntiles, P.pstride, 0, sh);
+    const double ri = sum_partials(P.partial, P.ntiles, P.pstride, 1, sh);
+    if (threadIdx.x != 0) return;
+    st->mvp_boundary += 1;
+    const double nu = sqrt(rr);
+    st->nu = nu;
+    if (!isfinite(nu))
+        st->solve_state = SV_NONFINITE;
+    else if (nu <= st->tau)
+        st->solve_state = SV_CONVERGED;
+    else if (start)
+        start_cycle(st, nu, ri);
+    mirror_out(P, st);
+}
+
+// ----------------------------------------------------- BiCGStab phase A
+template <class Cfg, int DIM, class TI>
+__global__ __launch_bounds__(NT) void k_bicg_a(const DevProb* __restrict__ probs, int nprob) {
+    __shared__ TI L[Cfg::BOX];
+    __shared__ double sh[NWAVE * 2];
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const DevProb& P = probs[find_prob(probs, nprob, t)];
+    SolveState* st = P.st;
+    if (st->solve_state != SV_RUNNING || st->inner_state != IN_RUNNING) return;
+    const int lt = t - P.tile_begin;
+    const TilePos tp = tile_pos<Cfg>(lt, P.tx, P.ty);
+    const DevOp& op = P.op;
+    const int iter = st->iter;
+    const bool first = iter == 0;
+    const int cur = iter & 1, prv = cur ^ 1;
+    TI* pnew = vp<TI>(P.p[cur]);
+    const TI* pold = vp<TI>(P.p[prv]);
+    TI* vnew = vp<TI>(P.v[cur]);
+    const TI* vold = vp<TI>(P.v[prv]);
+    TI* rin = vp<TI>(P.rin);
+    const TI* rhat = vp<TI>(P.rhat);
+    const TI* sv_ = vp<TI>(P.s);
+    const TI* tv_ = vp<TI>(P.t);
+    TI* e = vp<TI>(P.e);
+    const TI alpha = (TI)st->alpha, omega = (TI)st->omega;
+    const TI beta = first ? TI(0) : (TI)((st->rho / st->rho_old) * (st->alpha / st->omega));
+    for (int h = threadIdx.x; h < Cfg::BOX; h += NT) {
+        int gx, gy, gz;
+        box_coords<Cfg>(h, tp, gx, gy, gz);
+        TI pv = TI(0);
+        if (inside(op, gx, gy, gz)) {
+            const long long g = gidx(op, gx, gy, gz);
+            if (first) {
+                pv = rin[g];
+            } else {
+                const TI rv = sv_[g] - omega * tv_[g];
+                pv = rv + beta * (pold[g] - omega * vold[g]);
+            }
+        }
+        L[h] = pv;
+    }
+    __syncthreads();
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < Cfg::PPT; ++q) {
+        int gx, gy, gz, c;
+        point_coords<Cfg>(q, tp, gx, gy, gz, c);
+        if (!inside(op, gx, gy, gz)) continue;
+        const long long g = gidx(op, gx, gy, gz);
+        const TI vv = stencil_row<Cfg, DIM, TI>(op, L, c, g);
+        pnew[g] = L[c];
+        vnew[g] = vv;
+        TI rv;
+        if (first) {
+            rv = rin[g];
+            e[g] = TI(0);
+        } else {
+            const TI sv = sv_[g];
+            rv = sv - omega * tv_[g];
+            rin[g] = rv;
+            e[g] = e[g] + alpha * pold[g] + omega * sv;
+        }
+        acc[0] += (double)rhat[g] * (double)vv;
+        acc[1] += (double)rv * (double)rv;
+    }
+    double tot;
+    block_sum<2>(acc, sh, tot);
+    if (threadIdx.x < 2) P.partial[(long long)lt * P.pstride + threadIdx.x] = tot;
+    if (!arrive_last(P.counter, P.ntiles)) return;
+    const double sig = sum_partials(P.partial, P.ntiles, P.pstride, 0, sh);
+    const double rr = sum_partials(P.partial, P.ntiles, P.pstride, 1, sh);
+    if (threadIdx.x != 0) return;
+    st->mvp_inner += 1;
+    st->sigma = sig;
+    st->rr_last = rr;
+    st->pbuf = cur;
+    if (sig == 0.0 || !isfinite(sig)) {
+        st->inner_state = IN_BREAK_NOUPD;
+        mirror_out(P, st);
+    } else {
+        st->alpha = st->rho / sig;
+    }
+}
+
+// ----------------------------------------------------- BiCGStab phase B
+template <class Cfg, int DIM, class TI>
+__global__ __launch_bounds__(NT) void k_bicg_b(const DevProb* __restrict__ probs, int nprob) {
+    __shared__ TI L[Cfg::BOX];
+    __shared__ double sh[NWAVE * 5];
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const DevProb& P = probs[find_prob(probs, nprob, t)];
+    SolveState* st = P.st;
+    if (st->solve_state != SV_RUNNING || st->inner_state != IN_RUNNING) return;
+    const int lt = t - P.tile_begin;
+    const TilePos tp = tile_pos<Cfg>(lt, P.tx, P.ty);
+    const DevOp& op = P.op;
+    const int cur = st->iter & 1;
+    const TI* v = vp<TI>(P.v[cur]);
+    const TI* rin = vp<TI>(P.rin);
+    const TI* rhat = vp<TI>(P.rhat);
+    TI* s = vp<TI>(P.s);
+    TI* tt_ = vp<TI>(P.t);
+    const TI alpha = (TI)st->alpha;
+    for (int h = threadIdx.x; h < Cfg::BOX; h += NT) {
+        int gx, gy, gz;
+        box_coords<Cfg>(h, tp, gx, gy, gz);
+        TI sv = TI(0);
+        if (inside(op, gx, gy, gz)) {
+            const long long g = gidx(op, gx, gy, gz);
+            sv = rin[g] - alpha * v[g];
+        }
+        L[h] = sv;
+    }
+    __syncthreads();
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < Cfg::PPT; ++q) {
+        int gx, gy, gz, c;
+        point_coords<Cfg>(q, tp, gx, gy, gz, c);
+        if (!inside(op, gx, gy, gz)) continue;
+        const long long g = gidx(op, gx, gy, gz);
+        const TI sv = L[c];
+        const TI tv = stencil_row<Cfg, DIM, TI>(op, L, c, g);
+        s[g] = sv;
+        tt_[g] = tv;
+        const double rh = (double)rhat[g];
+        const double sd = (double)sv, td = (double)tv;
+        acc[0] += sd * sd;
+        acc[1] += td * sd;
+        acc[2] += td * td;
+        acc[3] += rh * sd;
+        acc[4] += rh * td;
+    }
+    double tot;
+    block_sum<5>(acc, sh, tot);
+    if (threadIdx.x < 5) P.partial[(long long)lt * P.pstride + threadIdx.x] = tot;
+    if (!arrive_last(P.counter, P.ntiles)) return;
+    double sums[5];
+    for (int i = 0; i < 5; ++i) sums[i] = sum_partials(P.partial, P.ntiles, P.pstride, i, sh);
+    if (threadIdx.x != 0) return;
+    const double ss = sums[0], ts = sums[1], tt = sums[2], rs = sums[3], rt = sums[4];
+    st->mvp_inner += 1;
+    st->iter += 1;
+    st->iters_total += 1;
+    const int hi = st->nhist;
+    if (ss <= st->target2) {
+        if (st->icyc == 1 && hi < NHIST) {
+            st->hist[3 * hi] = st->rho;
+            st->hist[3 * hi + 1] = st->alpha;
+            st->hist[3 * hi + 2] = __builtin_nan("");
+            st->nhist = hi + 1;
+        }
+        st->inner_state = IN_HALF;
+        mirror_out(P, st);
+        return;
+    }
+    const double omega = (tt != 0.0) ? ts / tt : 0.0;
+    st->omega = omega;
+    if (st->icyc == 1 && hi < NHIST) {
+        st->hist[3 * hi] = st->rho;
+        st->hist[3 * hi + 1] = st->alpha;
+        st->hist[3 * hi + 2] = omega;
+        st->nhist = hi + 1;
+    }
+    if (omega == 0.0 || !isfinite(omega)) {
+        st->inner_state = IN_BREAK_FULL;
+    } else {
+        double rr = ss - 2.0 * omega * ts + omega * omega * tt;
+        if (rr < 0.0) rr = 0.0;
+        const double rho_new = rs - omega * rt;
+        if (rr <= st->target2)
+            st->inner_state = IN_CONVERGED;
+        else if (rho_new == 0.0 || !isfinite(rho_new))
+            st->inner_state = IN_BREAK_FULL;
+        else if (st->iter >= st->maxit)
+            st->inner_state = IN_MAXIT;
+        else {
+            st->rho_old = st->rho;
+            st->rho = rho_new;
+        }
+    }
+    if (st->inner_state != IN_RUNNING) mirror_out(P, st);
+}
+
+// ------------------------------------------------ end of an inner cycle
+// x += e + (pending update of the last iteration), in float64.
+template <class Cfg, class TI>
+__global__ __launch_bounds__(NT) void k_finalize(const DevProb* __restrict__ probs, int nprob) {
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const DevProb& P = probs[find_prob(probs, nprob, t)];
+    const SolveState* st = P.st;
+    if (st->solve_state != SV_RUNNING) return;
+    const int lt = t - P.tile_begin;
+    const TilePos tp = tile_pos<Cfg>(lt, P.tx, P.ty);
+    const DevOp& op = P.op;
+    const int is = st->inner_state;
+    const double a = (is == IN_BREAK_NOUPD) ? 0.0 : st->alpha;
+    const double w = (is == IN_CONVERGED || is == IN_BREAK_FULL || is == IN_MAXIT) ? st->omega : 0.0;
+    const TI* p = vp<TI>(P.p[st->pbuf]);
+    const TI* s = vp<TI>(P.s);
+    const TI* e = vp<TI>(P.e);
+    const bool any_iter = !(is == IN_BREAK_NOUPD && st->iter == 0);
+#pragma unroll
+    for (int q = 0; q < Cfg::PPT; ++q) {
+        int gx, gy, gz, c;
+        point_coords<Cfg>(q, tp, gx, gy, gz, c);
+        if (!inside(op, gx, gy, gz)) continue;
+        const long long g = gidx(op, gx, gy, gz);
+        if (!any_iter) continue;
+        double upd = (double)e[g];
+        if (a != 0.0) upd += a * (double)p[g];
+        if (w != 0.0) upd += w * (double)s[g];
+        P.x[g] += upd;
+    }
+}
+
+// ------------------------------------------------------------ launchers
+template <class Cfg, int DIM, class TI>
+static void solve_launch_cfg(int which, const DevProb* probs, int nprob, int total_tiles, int flag, int vtype,
+                             hipStream_t s) {
+    dim3 grid(total_tiles), block(NT);
+    switch (which) {
+        case K_RESIDUAL:
+            hipLaunchKernelGGL((k_residual<Cfg, DIM, TI>), grid, block, 0, s, probs, nprob, flag);
+            break;
+        case K_PROJ_DOT:
+            if (vtype == 0)
+                hipLaunchKernelGGL((k_proj_dot<Cfg, double>), grid, block, 0, s, probs, nprob);
+            else
+                hipLaunchKernelGGL((k_proj_dot<Cfg, float>), grid, block, 0, s, probs, nprob);
+            break;
+        case K_PROJ_APPLY:
+            if (vtype == 0)
+                hipLaunchKernelGGL((k_proj_apply<Cfg, DIM, double, TI>), grid, block, 0, s, probs, nprob);
+            else
+                hipLaunchKernelGGL((k_proj_apply<Cfg, DIM, float, TI>), grid, block, 0, s, probs, nprob);
+            break;
+        case K_BICG_A:
+            hipLaunchKernelGGL((k_bicg_a<Cfg, DIM, TI>), grid, block, 0, s, probs, nprob);
+            break;
+        case K_BICG_B:
+            hipLaunchKernelGGL((k_bicg_b<Cfg, DIM, TI>), grid, block, 0, s, probs, nprob);
+            break;
+        case K_FINALIZE:
+            hipLaunchKernelGGL((k_finalize<Cfg, TI>), grid, block, 0, s, probs, nprob);
+            break;
+    }
+}
+
+template <int DIM, class TI>
+static void solve_launch_dim(int which, const DevProb* probs, int nprob, int total_tiles, int flag, int vtype,
+                             int tile_id, hipStream_t s) {
+    if (DIM == 2) {
+        switch (tile_id) {
+            case 1: solve_launch_cfg<Tile<2, 8, 1>, 2, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
+            case 2: solve_launch_cfg<Tile<2, 4, 1>, 2, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
+            default: solve_launch_cfg<Tile<2, 16, 1>, 2, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
+        }
+    } else {
+        switch (tile_id) {
+            case 1: solve_launch_cfg<Tile<3, 8, 4>, 3, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
+            case 2: solve_launch_cfg<Tile<3, 4, 8>, 3, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
+            default: solve_launch_cfg<Tile<3, 4, 4>, 3, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
+        }
+    }
+}
+
+void launch_solve_kernel(int which, int dim, int inner_f32, int vtype, int tile_id, const DevProb* probs,
+                         int nprob, int total_tiles, int flag, hipStream_t s) {
+    if (total_tiles <= 0) return;
+    if (dim == 2) {
+        if (inner_f32)
+            solve_launch_dim<2, float>(which, probs, nprob, total_tiles, flag, vtype, tile_id, s);
+        else
+            solve_launch_dim<2, double>(which, probs, nprob, total_tiles, flag, vtype, tile_id, s);
+    } else {
+        if (inner_f32)
+            solve_launch_dim<3, float>(which, probs, nprob, total_tiles, flag, vtype, tile_id, s);
+        else
+            solve_launch_dim<3, double>(which, probs, nprob, total_tiles, flag, vtype, tile_id, s);
+    }
+}
+
+void tile_shape(int dim, int tile_id, int* ty, int* tz) {
+    if (dim == 2) {
+        *tz = 1;
+        *ty = tile_id == 1 ? 8 : (tile_id == 2 ? 4 : 16);
+    } else {
+        *ty = tile_id == 1 ? 8 : 4;
+        *tz = tile_id == 2 ? 8 : 4;
+    }
+}
+
+}  // namespace tgdk

@@ -1,0 +1,60 @@
+// Host-callable kernel launchers (defined in the .hip files).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "tgdk_shared.h"
+
+namespace tgdk {
+
+enum : int { K_RESIDUAL = 0, K_PROJ_DOT = 1, K_PROJ_APPLY = 2, K_BICG_A = 3, K_BICG_B = 4, K_FINALIZE = 5 };
+
+// grid kernels
+template <class T>
+void launch_apply(const DevOp& op, const T* x, T* y, int nrhs, int tile_id, hipStream_t s);
+void launch_build_divk(int nx, int ny, const double* kc, double bx, double by, double sigma, double* coef,
+                       hipStream_t s);
+void launch_transpose_coef(int dim, int nx, int ny, int nz, const double* c, double* ct, hipStream_t s);
+void launch_to_f32(const double* a, float* b, long long n, hipStream_t s);
+void launch_to_f64(const float* a, double* b, long long n, hipStream_t s);
+void launch_coarsen_kcell(int ncx, int ncy, const double* kf, double* kc, hipStream_t s);
+void launch_prolong(int dim, int ncx, int ncy, int ncz, const double* vc, double* vf, int ncols, hipStream_t s);
+void launch_restrict(int dim, int ncx, int ncy, int ncz, const double* vf, double* vc, int ncols, hipStream_t s);
+void launch_grad_k(int nx, int ny, const double* lam, const double* u, double* g, hipStream_t s);
+void launch_fill(double* a, double v, long long n, hipStream_t s);
+void launch_copy(const double* a, double* b, long long n, hipStream_t s);
+
+// fused solve kernels over a problem group
+void launch_solve_kernel(int which, int dim, int inner_f32, int vtype, int tile_id, const DevProb* probs,
+                         int nprob, int total_tiles, int flag, hipStream_t s);
+void tile_shape(int dim, int tile_id, int* ty, int* tz);
+
+// tall-skinny products (column-major blocks, leading dimensions in elements)
+// G (p x q, row-major, device) = A^T B, A: n x p, B: n x q; partial workspace
+// of gram_partial_size(n) doubles * p*q and one counter.
+int gram_blocks(long long n);
+void launch_gram(const void* A, int atype, long long lda, int p, const void* B, int btype, long long ldb, int q,
+                 long long n, double* G, double* partial, unsigned* counter, hipStream_t s);
+// Out (n x q, col-major, ldo) = V (n x p, ldv) * Y (p x q, col-major, device)
+void launch_vmul(const double* V, long long ldv, int p, const double* Y, int q, double* Out, long long ldo,
+                 long long n, hipStream_t s);
+// x += V y  (V n x p float64, y device p-vector)
+void launch_vmul_add(const double* V, long long ldv, int p, const double* y, double* x, long long n,
+                     hipStream_t s);
+
+// classical Gram-Schmidt steps of the Arnoldi process (one problem)
+int gs_blocks(long long n);
+// hout[i] = V_i . w, i < p
+void launch_gs_dot(const double* V, long long ldv, int p, const double* w, long long n, double* hout,
+                   double* partial, unsigned* counter, hipStream_t s);
+// w -= V h; then hout[i] = V_i . w
+void launch_gs_update_dot(const double* V, long long ldv, int p, double* w, const double* h, long long n,
+                          double* hout, double* partial, unsigned* counter, hipStream_t s);
+// w -= V h; *nrm = ||w||; then v = w / ||w|| (zero if ||w|| = 0)
+void launch_gs_update_norm(const double* V, long long ldv, int p, double* w, const double* h, long long n,
+                           double* nrm, double* partial, unsigned* counter, hipStream_t s);
+void launch_scale(const double* w, double* v, const double* nrm, long long n, hipStream_t s);
+// sum of squares of a vector -> *out (deterministic)
+void launch_norm2(const double* w, long long n, double* out, double* partial, unsigned* counter, hipStream_t s);
+
+}  // namespace tgdk

@@ -1,0 +1,491 @@
+// Fine-solve drivers: BiCGStab(ncyc)-Proj(k) over a group of problems
+// (right-hand sides sharing an operator, or independent grid instances) and
+// GMRES(m)-Proj(k) for one right-hand side.
+//
+// The host only enqueues: every scalar decision (alpha, omega, cycle
+// tolerance, convergence, breakdown) is taken on the device by the kernels'
+// epilogues.  Inner iterations are enqueued in batches; the host watches a
+// host-mapped status mirror one batch behind, so the GPU queue never drains
+// while the host decides whether a cycle has ended.  Launches that follow the
+// end of a cycle find the problem finished and return at once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dense.h"
+#include "host.h"
+
+namespace tgdk {
+
+enum : int { SV_NONFINITE_H = 4 };
+
+struct ProbSpec {
+    tgdk_op op;
+    tgdk_defl defl;
+    const double* b;
+    double* x;
+};
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static int status_of(const SolveState& st) {
+    switch (st.solve_state) {
+        case SV_CONVERGED: return TGDK_OK;
+        case SV_BREAKDOWN: return TGDK_BREAKDOWN;
+        case SV_NOT_CONVERGED: return TGDK_NOT_CONVERGED;
+        case SV_NONFINITE_H: return TGDK_E_NONFINITE;
+        default: return TGDK_NOT_CONVERGED;
+    }
+}
+
+static int worst(int a, int b) {
+    if (a < 0 || b < 0) return std::min(a, b);
+    return std::max(a, b);
+}
+
+static int ensure_mirror(tgdk_ctx ctx, int n) {
+    if (ctx->mirror_cap >= n) return TGDK_OK;
+    if (ctx->mirror) (void)hipHostFree(ctx->mirror);
+    ctx->mirror = nullptr;
+    ctx->mirror_cap = 0;
+    TGDK_HIP(hipHostMalloc((void**)&ctx->mirror, sizeof(Mirror) * n, hipHostMallocMapped));
+    ctx->mirror_cap = n;
+    return TGDK_OK;
+}
+
+static int ensure_events(tgdk_ctx ctx, int n) {
+    while ((int)ctx->events.size() < n) {
+        hipEvent_t e;
+        TGDK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->events.push_back(e);
+    }
+    return TGDK_OK;
+}
+
+struct Group {
+    tgdk_ctx ctx = nullptr;
+    int dim = 2, inner_f32 = 0, vtype = 0, tile_id = 0;
+    int nprob = 0, total_tiles = 0;
+    DevProb* d_probs = nullptr;
+    SolveState* d_states = nullptr;
+    std::vector<DevProb> probs;
+    std::vector<SolveState> states;
+    Mirror* mirror = nullptr;
+};
+
+static void launch(const Group& g, int which, int flag = 0) {
+    launch_solve_kernel(which, g.dim, g.inner_f32, g.vtype, g.tile_id, g.d_probs, g.nprob, g.total_tiles, flag,
+                        g.ctx->stream);
+}
+
+// Host-mapped mirror values are written by the device; read them volatile.
+static Mirror read_mirror(const Group& g, int j) {
+    volatile Mirror* m = g.mirror + j;
+    Mirror r;
+    r.solve_state = m->solve_state;
+    r.inner_state = m->inner_state;
+    r.icyc = m->icyc;
+    r.iter = m->iter;
+    return r;
+}
+
+static int wait_event(hipEvent_t e) {
+    // spin on the event (low latency), yielding to the runtime
+    for (;;) {
+        hipError_t q = hipEventQuery(e);
+        if (q == hipSuccess) return TGDK_OK;
+        if (q != hipErrorNotReady) return fail(TGDK_E_HIP, std::string("kernel failed: ") + hipGetErrorString(q));
+    }
+}
+
+// Allocates and fills the device-side group description and workspaces.
+static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk_solve_params* prm, Group& g) {
+    g.ctx = ctx;
+    g.nprob = (int)ps.size();
+    g.dim = ps[0].op->dim;
+    g.inner_f32 = prm->precision == TGDK_FP32_IR ? 1 : 0;
+    g.tile_id = ps[0].op->tile_id[g.inner_f32];
+    int vtype = -1;
+    for (const auto& p : ps)
+        if (p.defl) {
+            const int t = p.defl->store == TGDK_F32 ? 1 : 0;
+            if (vtype >= 0 && vtype != t) return fail(TGDK_E_INVALID, "mixed deflation storage types in one group");
+            vtype = t;
+        }
+    g.vtype = vtype < 0 ? 0 : vtype;
+    int ty, tz;
+    tile_shape(g.dim, g.tile_id, &ty, &tz);
+    const size_t ies = g.inner_f32 ? 4 : 8;
+    // layout
+    size_t off = 0;
+    const size_t off_probs = off;
+    off += align256(sizeof(DevProb) * g.nprob);
+    const size_t off_states = off;
+    off += align256(sizeof(SolveState) * g.nprob);
+    const size_t off_counters = off;
+    off += align256(sizeof(unsigned) * g.nprob);
+    std::vector<size_t> off_vec(g.nprob), off_part(g.nprob);
+    std::vector<int> pstride(g.nprob);
+    g.probs.assign(g.nprob, DevProb());
+    int tiles = 0;
+    for (int j = 0; j < g.nprob; ++j) {
+        const tgdk_op op = ps[j].op;
+        DevProb& P = g.probs[j];
+        memset(&P, 0, sizeof(P));
+        P.op = make_devop(op, prm->transpose);
+        P.tx = (op->n[0] + 63) / 64;
+        P.ty = (op->n[1] + ty - 1) / ty;
+        P.tz = g.dim == 3 ? (op->n[2] + tz - 1) / tz : 1;
+        P.ntiles = P.tx * P.ty * P.tz;
+        P.tile_begin = tiles;
+        tiles += P.ntiles;
+        P.k = ps[j].defl ? ps[j].defl->k : 0;
+        pstride[j] = std::max(8, P.k);
+        P.pstride = pstride[j];
+        off_vec[j] = off;
+        const size_t n = (size_t)op->N;
+        off += align256(n * 8);                     // r (float64)
+        off += (g.inner_f32 ? 9 : 8) * align256(n * ies);  // inner vectors
+        off_part[j] = off;
+        off += align256((size_t)P.ntiles * pstride[j] * 8);
+    }
+    g.total_tiles = tiles;
+    int rc = ctx->solve_ws.ensure(off);
+    if (rc) return rc;
+    rc = ensure_mirror(ctx, g.nprob);
+    if (rc) return rc;
+    char* base = (char*)ctx->solve_ws.p;
+    g.d_probs = (DevProb*)(base + off_probs);
+    g.d_states = (SolveState*)(base + off_states);
+    unsigned* counters = (unsigned*)(base + off_counters);
+    g.mirror = ctx->mirror;
+    g.states.assign(g.nprob, SolveState());
+    for (int j = 0; j < g.nprob; ++j) {
+        DevProb& P = g.probs[j];
+        const size_t n = (size_t)ps[j].op->N;
+        char* v = base + off_vec[j];
+        P.b = ps[j].b;
+        P.x = ps[j].x;
+        P.r = (double*)v;
+        v += align256(n * 8);
+        void* vecs[9];
+        const int nv = g.inner_f32 ? 9 : 8;
+        for (int i = 0; i < nv; ++i) {
+            vecs[i] = v;
+            v += align256(n * ies);
+        }
+        int i = 0;
+        P.rin = g.inner_f32 ? vecs[i++] : (void*)P.r;
+        P.rhat = vecs[i++];
+        P.p[0] = vecs[i++];
+        P.p[1] = vecs[i++];
+        P.v[0] = vecs[i++];
+        P.v[1] = vecs[i++];
+        P.s = vecs[i++];
+        P.t = vecs[i++];
+        P.e = vecs[i++];
+        if (ps[j].defl) {
+            P.V = ps[j].defl->V;
+            P.ldv = ps[j].defl->n;
+            P.lu = ps[j].defl->d_lu;
+            P.piv = ps[j].defl->d_piv;
+        }
+        P.st = g.d_states + j;
+        P.partial = (double*)(base + off_part[j]);
+        P.counter = counters + j;
+        P.mirror = g.mirror + j;
+        SolveState& S = g.states[j];
+        memset(&S, 0, sizeof(S));
+        S.rtol = prm->rtol;
+        S.fp32_floor = prm->fp32_floor > 0 ? prm->fp32_floor : 1e-4;
+        S.method = prm->method == TGDK_GMRES_PROJ ? METHOD_GMRES : METHOD_BICGSTAB;
+        if (S.method == METHOD_BICGSTAB) {
+            S.ncyc = prm->ncyc;
+            S.max_extra = prm->max_extra_cycles >= 0 ? prm->max_extra_cycles : prm->ncyc;
+        } else {
+            S.ncyc = 0;
+            S.max_extra = prm->max_extra_cycles > 0 ? prm->max_extra_cycles : 1000;
+        }
+        S.maxit = prm->maxit_cycle > 0 ? prm->maxit_cycle : 100000;
+        S.k = P.k;
+        S.precision = g.inner_f32;
+        S.solve_state = SV_RUNNING;
+        S.inner_state = IN_CONVERGED;
+        g.mirror[j].solve_state = SV_RUNNING;
+        g.mirror[j].inner_state = IN_RUNNING;
+        g.mirror[j].icyc = 0;
+        g.mirror[j].iter = 0;
+    }
+    hipStream_t s = ctx->stream;
+    TGDK_HIP(hipMemcpyAsync(g.d_probs, g.probs.data(), sizeof(DevProb) * g.nprob, hipMemcpyHostToDevice, s));
+    TGDK_HIP(hipMemcpyAsync(g.d_states, g.states.data(), sizeof(SolveState) * g.nprob, hipMemcpyHostToDevice, s));
+    TGDK_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned) * g.nprob, s));
+    if (!prm->x0_given)
+        for (int j = 0; j < g.nprob; ++j)
+            TGDK_HIP(hipMemsetAsync(ps[j].x, 0, sizeof(double) * ps[j].op->N, s));
+    return TGDK_OK;
+}
+
+static int finish_group(Group& g, const std::vector<ProbSpec>& ps, tgdk_solve_report* reps, double secs,
+                        const std::vector<long long>* extra_inner) {
+    hipStream_t s = g.ctx->stream;
+    launch(g, K_RESIDUAL, 2);
+    TGDK_HIP(hipGetLastError());
+    TGDK_HIP(hipMemcpyAsync(g.states.data(), g.d_states, sizeof(SolveState) * g.nprob, hipMemcpyDeviceToHost, s));
+    TGDK_HIP(hipStreamSynchronize(s));
+    int rc = TGDK_OK;
+    for (int j = 0; j < g.nprob; ++j) {
+        const SolveState& S = g.states[j];
+        tgdk_solve_report& R = reps[j];
+        memset(&R, 0, sizeof(R));
+        R.status = status_of(S);
+        R.cycles = S.icyc;
+        R.iters_inner = S.iters_total;
+        R.mvp_inner = S.mvp_inner + (extra_inner ? (*extra_inner)[j] : 0);
+        R.mvp_boundary = S.mvp_boundary;
+        R.relres_true = S.bnorm > 0 ? S.nu_final / S.bnorm : S.nu_final;
+        R.seconds = secs;
+        for (int i = 0; i < 4; ++i) R.branch[i] = S.branch[i];
+        R.n_first = S.nhist;
+        for (int i = 0; i < S.nhist && i < TGDK_NHIST; ++i) {
+            R.first_rho[i] = S.hist[3 * i];
+            R.first_alpha[i] = S.hist[3 * i + 1];
+            R.first_omega[i] = S.hist[3 * i + 2];
+        }
+        if (R.status == TGDK_E_NONFINITE) set_error("non-finite residual (check b, x0 and the operator)");
+        rc = worst(rc, R.status);
+    }
+    (void)ps;
+    return rc;
+}
+
+static bool all_inner_done(const Group& g) {
+    for (int j = 0; j < g.nprob; ++j) {
+        const Mirror m = read_mirror(g, j);
+        if (m.solve_state == SV_RUNNING && m.inner_state == IN_RUNNING) return false;
+    }
+    return true;
+}
+
+static bool all_solved(const Group& g) {
+    for (int j = 0; j < g.nprob; ++j)
+        if (read_mirror(g, j).solve_state == SV_RUNNING) return false;
+    return true;
+}
+
+static int bicgstab_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk_solve_params* prm,
+                          tgdk_solve_report* reps) {
+    const auto t0 = std::chrono::steady_clock::now();
+    Group g;
+    int rc = build_group(ctx, ps, prm, g);
+    if (rc) return rc;
+    bool any_defl = false;
+    for (const auto& p : ps) any_defl |= (p.defl != nullptr);
+    const int B = 8;  // iterations per enqueued batch
+    const int max_cycles = prm->ncyc + (prm->max_extra_cycles >= 0 ? prm->max_extra_cycles : prm->ncyc) + 2;
+    const int maxit = prm->maxit_cycle > 0 ? prm->maxit_cycle : 100000;
+    rc = ensure_events(ctx, 3);
+    if (rc) return rc;
+    hipStream_t s = ctx->stream;
+    launch(g, K_RESIDUAL, 1);
+    TGDK_HIP(hipGetLastError());
+    for (int cyc = 0; cyc < max_cycles; ++cyc) {
+        if (any_defl) {
+            launch(g, K_PROJ_DOT);
+            launch(g, K_PROJ_APPLY);
+        }
+        // inner iterations, one batch ahead of the status check
+        int batches = 0;
+        const int max_batches = maxit / B + 2;
+        for (;;) {
+            for (int i = 0; i < B; ++i) {
+                launch(g, K_BICG_A);
+                launch(g, K_BICG_B);
+            }
+            TGDK_HIP(hipEventRecord(ctx->events[batches & 1], s));
+            ++batches;
+            if (batches >= 2) {
+                if ((rc = wait_event(ctx->events[batches & 1]))) return rc;  // the batch before the last
+                if (all_inner_done(g)) break;
+            }
+            if (batches > max_batches) break;
+        }
+        launch(g, K_FINALIZE);
+        launch(g, K_RESIDUAL, 0);
+        TGDK_HIP(hipGetLastError());
+        TGDK_HIP(hipEventRecord(ctx->events[2], s));
+        if ((rc = wait_event(ctx->events[2]))) return rc;
+        if (all_solved(g)) break;
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return finish_group(g, ps, reps, secs, nullptr);
+}
+
+// GMRES(m)-Proj(k): one right-hand side.  Arnoldi with classical
+// Gram-Schmidt and one full re-orthogonalisation (CGS2), Hessenberg
+// least squares on the host at the end of each cycle.
+static int gmres_single(tgdk_ctx ctx, const ProbSpec& p, const tgdk_solve_params* prm, tgdk_solve_report* rep) {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<ProbSpec> ps{p};
+    Group g;
+    int rc = build_group(ctx, ps, prm, g);
+    if (rc) return rc;
+    hipStream_t s = ctx->stream;
+    const int m = prm->m3;
+    const long long n = p.op->N;
+    // Krylov basis, w, H columns
+    double *V = nullptr, *w = nullptr, *Hd = nullptr, *dy = nullptr;
+    const size_t hsz = (size_t)(m + 1) * m;
+    if (hipMalloc((void**)&V, sizeof(double) * n * (m + 1)) != hipSuccess)
+        return fail(TGDK_E_NOMEM, "GMRES basis allocation failed");
+    if (hipMalloc((void**)&w, sizeof(double) * n) != hipSuccess ||
+        hipMalloc((void**)&Hd, sizeof(double) * (2 * hsz + m + 8)) != hipSuccess ||
+        hipMalloc((void**)&dy, sizeof(double) * (m + 1)) != hipSuccess) {
+        (void)hipFree(V);
+        if (w) (void)hipFree(w);
+        if (Hd) (void)hipFree(Hd);
+        return fail(TGDK_E_NOMEM, "GMRES workspace allocation failed");
+    }
+    double* H1 = Hd;
+    double* H2 = Hd + hsz;
+    double* Nd = Hd + 2 * hsz;
+    rc = ctx->partial.ensure((size_t)gs_blocks(n) * (MAXK + 1) * sizeof(double));
+    std::vector<long long> extra(1, 0);
+    const DevOp op = make_devop(p.op, prm->transpose);
+    const int maxcyc = prm->max_extra_cycles > 0 ? prm->max_extra_cycles : 1000;
+    std::vector<double> h1(hsz), h2(hsz), nrm(m), Hbar(hsz), rhs(m + 1), y(m), res(m + 1);
+    SolveState S;
+    double* d_nu = &g.d_states[0].nu;
+    if (!rc) {
+        launch(g, K_RESIDUAL, 1);
+        TGDK_HIP(hipStreamSynchronize(s));
+    }
+    for (int cyc = 0; cyc < maxcyc && !rc; ++cyc) {
+        if (all_solved(g)) break;
+        if (p.defl) {
+            launch(g, K_PROJ_DOT);
+            launch(g, K_PROJ_APPLY);
+            TGDK_HIP(hipStreamSynchronize(s));
+            if (all_solved(g)) break;
+        }
+        launch_scale(g.probs[0].r, V, d_nu, n, s);
+        int steps = m;
+        for (int j = 0; j < m; ++j) {
+            launch_apply<double>(op, V + (size_t)j * n, w, 1, p.op->tile_id[0], s);
+            launch_gs_dot(V, n, j + 1, w, n, H1 + (size_t)j * (m + 1), (double*)ctx->partial.p, ctx->counters, s);
+            launch_gs_update_dot(V, n, j + 1, w, H1 + (size_t)j * (m + 1), n, H2 + (size_t)j * (m + 1),
+                                 (double*)ctx->partial.p, ctx->counters, s);
+            launch_gs_update_norm(V, n, j + 1, w, H2 + (size_t)j * (m + 1), n, Nd + j, (double*)ctx->partial.p,
+                                  ctx->counters, s);
+            launch_scale(w, V + (size_t)(j + 1) * n, Nd + j, n, s);
+        }
+        TGDK_HIP(hipGetLastError());
+        TGDK_HIP(hipMemcpyAsync(h1.data(), H1, sizeof(double) * hsz, hipMemcpyDeviceToHost, s));
+        TGDK_HIP(hipMemcpyAsync(h2.data(), H2, sizeof(double) * hsz, hipMemcpyDeviceToHost, s));
+        TGDK_HIP(hipMemcpyAsync(nrm.data(), Nd, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+        TGDK_HIP(hipMemcpyAsync(&S, g.d_states, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+        TGDK_HIP(hipStreamSynchronize(s));
+        // Hbar (row-major (m+1) x m); stop at an exact zero subdiagonal
+        std::fill(Hbar.begin(), Hbar.end(), 0.0);
+        for (int j = 0; j < m; ++j) {
+            for (int i = 0; i <= j; ++i) Hbar[(size_t)i * m + j] = h1[(size_t)j * (m + 1) + i] + h2[(size_t)j * (m + 1) + i];
+            Hbar[(size_t)(j + 1) * m + j] = nrm[j];
+            if (nrm[j] == 0.0) {
+                steps = j + 1;
+                break;
+            }
+        }
+        std::vector<double> Hs((size_t)(steps + 1) * steps);
+        for (int i = 0; i <= steps; ++i)
+            for (int j = 0; j < steps; ++j) Hs[(size_t)i * steps + j] = Hbar[(size_t)i * m + j];
+        std::fill(rhs.begin(), rhs.end(), 0.0);
+        rhs[0] = S.nu;
+        lstsq(steps + 1, steps, Hs.data(), rhs.data(), y.data(), res.data());
+        TGDK_HIP(hipMemcpyAsync(dy, y.data(), sizeof(double) * steps, hipMemcpyHostToDevice, s));
+        launch_vmul_add(V, n, steps, dy, p.x, n, s);
+        extra[0] += steps;
+        launch(g, K_RESIDUAL, 0);
+        TGDK_HIP(hipGetLastError());
+        TGDK_HIP(hipStreamSynchronize(s));
+    }
+    (void)hipFree(V);
+    (void)hipFree(w);
+    (void)hipFree(Hd);
+    (void)hipFree(dy);
+    if (rc) return rc;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return finish_group(g, ps, rep, secs, &extra);
+}
+
+static int check_params(const tgdk_solve_params* prm) {
+    if (!prm) return fail(TGDK_E_INVALID, "params is NULL");
+    if (prm->method == TGDK_BICGSTAB_PROJ) {
+        if (prm->ncyc < 1) return fail(TGDK_E_INVALID, "ncyc must be >= 1");
+    } else if (prm->method == TGDK_GMRES_PROJ) {
+        if (prm->m3 < 1 || prm->m3 > MAXK) return fail(TGDK_E_INVALID, "m3 out of range");
+        if (prm->precision != TGDK_FP64) return fail(TGDK_E_INVALID, "GMRES-Proj runs in float64 only");
+    } else {
+        return fail(TGDK_E_INVALID, "unknown method");
+    }
+    if (prm->precision != TGDK_FP64 && prm->precision != TGDK_FP32_IR) return fail(TGDK_E_INVALID, "precision");
+    if (!(prm->rtol > 0.0)) return fail(TGDK_E_INVALID, "rtol must be > 0");
+    return TGDK_OK;
+}
+
+static int check_defl(tgdk_op op, tgdk_defl d, const tgdk_solve_params* prm) {
+    if (!d) return TGDK_OK;
+    if (d->n != op->N || d->op->dim != op->dim) return fail(TGDK_E_INVALID, "deflation space size does not match the operator");
+    for (int a = 0; a < op->dim; ++a)
+        if (d->op->n[a] != op->n[a]) return fail(TGDK_E_INVALID, "deflation space grid does not match the operator");
+    if (d->transpose != (prm->transpose ? 1 : 0))
+        return fail(TGDK_E_INVALID, "deflation space was built for the other orientation (A vs A^T)");
+    return TGDK_OK;
+}
+
+}  // namespace tgdk
+
+using namespace tgdk;
+
+extern "C" {
+
+int tgdk_solve(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int nrhs, const tgdk_solve_params* prm,
+               tgdk_solve_report* reports) {
+    if (!fine || !b || !x || nrhs < 1 || !reports) return fail(TGDK_E_INVALID, "bad argument");
+    int rc = check_params(prm);
+    if (rc) return rc;
+    if ((rc = check_defl(fine, defl, prm))) return rc;
+    TGDK_HIP(hipSetDevice(fine->ctx->device));
+    std::vector<ProbSpec> ps(nrhs);
+    for (int j = 0; j < nrhs; ++j) ps[j] = ProbSpec{fine, defl, b + (size_t)j * fine->N, x + (size_t)j * fine->N};
+    if (prm->method == TGDK_GMRES_PROJ) {
+        if (nrhs != 1) return fail(TGDK_E_INVALID, "GMRES-Proj takes one right-hand side");
+        return gmres_single(fine->ctx, ps[0], prm, reports);
+    }
+    return bicgstab_group(fine->ctx, ps, prm, reports);
+}
+
+int tgdk_solve_instances(int ninst, const tgdk_op* ops, const tgdk_defl* defls, const double* const* b,
+                         double* const* x, const tgdk_solve_params* prm, tgdk_solve_report* reports) {
+    if (ninst < 1 || !ops || !b || !x || !reports) return fail(TGDK_E_INVALID, "bad argument");
+    int rc = check_params(prm);
+    if (rc) return rc;
+    if (prm->method != TGDK_BICGSTAB_PROJ) return fail(TGDK_E_INVALID, "instances use BiCGStab-Proj");
+    std::vector<ProbSpec> ps(ninst);
+    for (int j = 0; j < ninst; ++j) {
+        if (!ops[j] || !b[j] || !x[j]) return fail(TGDK_E_INVALID, "NULL instance");
+        if (ops[j]->ctx != ops[0]->ctx || ops[j]->dim != ops[0]->dim)
+            return fail(TGDK_E_INVALID, "instances must share a context and a dimension");
+        tgdk_defl d = defls ? defls[j] : nullptr;
+        if ((rc = check_defl(ops[j], d, prm))) return rc;
+        ps[j] = ProbSpec{ops[j], d, b[j], x[j]};
+    }
+    TGDK_HIP(hipSetDevice(ops[0]->ctx->device));
+    return bicgstab_group(ops[0]->ctx, ps, prm, reports);
+}
+
+}  // extern "C"
