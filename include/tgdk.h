@@ -58,7 +58,7 @@ extern "C" {
 #define TGDK_FP32_IR       1
 
 #define TGDK_MAX_DEFL 128   /* largest deflation space (k) and GMRES m */
-#define TGDK_NHIST    8     /* recorded BiCGStab scalars of the first cycle */
+#define TGDK_NHIST    8     /* recorded BiCGStab scalars of the first iterations */
 
 /* Text of the last non-OK return on the calling thread ("" if none). */
 const char* tgdk_last_error(void);
@@ -220,7 +220,7 @@ typedef struct {
     double relres_true;    /* ||b - A x|| / ||b|| at exit (float64) */
     double seconds;        /* host wall time of the call */
     int branch[4];         /* cycles whose tolerance came from criterion 1, 2, past-ncyc */
-    int n_first;           /* recorded first-cycle BiCGStab scalars */
+    int n_first;           /* recorded (rho, alpha, omega) of the first inner iterations */
     double first_rho[TGDK_NHIST], first_alpha[TGDK_NHIST], first_omega[TGDK_NHIST];
 } tgdk_solve_report;
 

@@ -139,7 +139,7 @@ class SolveReport:
     nu_hist: list = field(default_factory=list)   # ||r|| after each cycle's true residual
     branches: list = field(default_factory=list)  # rticyc branch per cycle
     inner_iters: list = field(default_factory=list)
-    first_scalars: list = field(default_factory=list)  # inner scalars of cycle 1
+    first_scalars: list = field(default_factory=list)  # first 8 inner (rho, alpha, omega), across cycles
 
 
 def bicgstab_proj(op, b, x0=None, V=None, H=None, rtol=1e-8, ncyc=20,
@@ -180,8 +180,8 @@ def bicgstab_proj(op, b, x0=None, V=None, H=None, rtol=1e-8, ncyc=20,
         rep.mvp_inner += inner.mvps
         rep.branches.append(branch)
         rep.inner_iters.append(inner.iters)
-        if icyc == 1:
-            rep.first_scalars = inner.scalars
+        if len(rep.first_scalars) < 8:
+            rep.first_scalars += inner.scalars[: 8 - len(rep.first_scalars)]
         x = x + inner.e.astype(np.float64)
         r = b - mv(x)                                   # true residual, FP64
         rep.mvp_boundary += 1

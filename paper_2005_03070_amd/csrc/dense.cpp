@@ -103,24 +103,32 @@ void upper_inverse(int n, const double* R, double* Rinv) {
 void householder_qr(int m, int n, const double* A, double* Q, double* R) {
     // A row-major m x n (m >= n).  Q row-major m x n with orthonormal columns,
     // R row-major n x n upper triangular with R_ii >= 0.
+    // Reflectors are kept as unit vectors (beta = 2) and every norm is
+    // formed after scaling by the largest magnitude, so columns of any size
+    // (down to the subnormal range) neither overflow nor underflow.
     std::vector<double> W(A, A + (size_t)m * n);
     std::vector<std::vector<double>> vs;
     std::vector<double> betas;
     for (int j = 0; j < n; ++j) {
         std::vector<double> v(m, 0.0);
-        double nrm = 0.0;
-        for (int i = j; i < m; ++i) nrm += W[i * n + j] * W[i * n + j];
-        nrm = std::sqrt(nrm);
+        double amax = 0.0;
+        for (int i = j; i < m; ++i) amax = std::max(amax, std::fabs(W[i * n + j]));
         double beta = 0.0;
-        if (nrm > 0.0) {
-            const double a = W[j * n + j];
-            const double alpha = (a >= 0.0) ? -nrm : nrm;
-            for (int i = j; i < m; ++i) v[i] = W[i * n + j];
+        if (amax > 0.0 && std::isfinite(amax)) {
+            for (int i = j; i < m; ++i) v[i] = W[i * n + j] / amax;
+            double nrm = 0.0;
+            for (int i = j; i < m; ++i) nrm += v[i] * v[i];
+            nrm = std::sqrt(nrm);
+            const double alpha = (v[j] >= 0.0) ? -nrm : nrm;
             v[j] -= alpha;
+            double vmax = 0.0;
+            for (int i = j; i < m; ++i) vmax = std::max(vmax, std::fabs(v[i]));
             double vn = 0.0;
-            for (int i = j; i < m; ++i) vn += v[i] * v[i];
+            for (int i = j; i < m; ++i) vn += (v[i] / vmax) * (v[i] / vmax);
+            vn = vmax * std::sqrt(vn);
             if (vn > 0.0) {
-                beta = 2.0 / vn;
+                for (int i = j; i < m; ++i) v[i] /= vn;
+                beta = 2.0;
                 for (int c = j; c < n; ++c) {
                     double s = 0.0;
                     for (int i = j; i < m; ++i) s += v[i] * W[i * n + c];
@@ -332,6 +340,12 @@ int eig_real(int n, const double* A, cd* w, cd* X) {
             cd den = H[j * n + j] - w[i];
             if (std::abs(den) < small) den = small;
             y[j] = -s / den;
+            // keep the partial solution bounded (near-defective T can grow it
+            // by 1/eps per step); only the direction matters
+            const double a = std::abs(y[j]);
+            if (a > 1.0) {
+                for (int l2 = j; l2 <= i; ++l2) y[l2] /= a;
+            }
         }
         double nrm = 0.0;
         for (int r = 0; r < n; ++r) {
@@ -341,6 +355,7 @@ int eig_real(int n, const double* A, cd* w, cd* X) {
             nrm += std::norm(s);
         }
         nrm = std::sqrt(nrm);
+        if (!(nrm > 0.0) || !std::isfinite(nrm)) return 2;
         // phase: make the largest component real and positive
         int imax = 0;
         for (int r = 1; r < n; ++r)

@@ -8,9 +8,11 @@
 //   over the 8 XCDs, each with its own L2.  xcd_remap() gives every XCD a
 //   contiguous range of tiles so the halo rows a tile shares with its
 //   neighbours are read through the same L2.
-// * Deterministic reductions: wave butterflies, a fixed LDS combine and a
-//   "last workgroup" epilogue that sums per-tile partials in tile order.  No
-//   floating-point atomics, so reruns are bitwise identical.
+// * Deterministic reductions: wave butterflies and a fixed LDS combine give a
+//   per-tile partial; a one-workgroup epilogue launch sums the partials in
+//   tile order.  No atomics and no device-scope fences (on a multi-XCD part
+//   an agent-scope release writes back the L2, which would serialise
+//   thousands of workgroups); the kernel boundary makes the partials visible.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -176,28 +178,8 @@ __device__ __forceinline__ double block_sum_one(double v, double* sh) {
     return s;
 }
 
-// Every workgroup of a problem calls this once after writing its partials.
-// Returns true in exactly one workgroup -- the last to arrive -- which may
-// then read all partials of that problem.  The counter is reset for the next
-// launch by that workgroup.
-__device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned total) {
-    __shared__ int last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned prev =
-            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = (prev == total - 1) ? 1 : 0;
-        if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    const bool is_last = last != 0;
-    if (is_last) __threadfence();
-    return is_last;
-}
-
-// In the last workgroup: sums column i of partial[t * stride + i] over
-// t = 0..ntiles-1 in a fixed order; result valid in every thread.
+// Sums column i of partial[t * stride + i] over t = 0..ntiles-1 in a fixed
+// order (one workgroup); the result is valid in every thread.
 __device__ __forceinline__ double sum_partials(const double* partial, int ntiles, int stride, int i, double* sh) {
     double s = 0.0;
     for (int t = threadIdx.x; t < ntiles; t += NT) s += partial[(long long)t * stride + i];

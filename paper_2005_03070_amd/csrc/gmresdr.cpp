@@ -12,6 +12,8 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -37,7 +39,7 @@ static int harmonic_ritz(int m, const std::vector<double>& Hbar, Ritz& out) {
             HmT[(size_t)j * m + i] = Hbar[(size_t)i * m + j];
         }
     std::vector<int> piv(m);
-    if (lu_factor(m, HmT.data(), piv.data()) != 0) return TGDK_E_SINGULAR;
+    if (lu_factor(m, HmT.data(), piv.data()) != 0) return 1;
     std::vector<double> f(m, 0.0);
     f[m - 1] = 1.0;
     lu_solve(m, HmT.data(), piv.data(), f.data());
@@ -45,7 +47,7 @@ static int harmonic_ritz(int m, const std::vector<double>& Hbar, Ritz& out) {
     for (int i = 0; i < m; ++i) Hm[(size_t)i * m + (m - 1)] += h * h * f[i];
     out.theta.assign(m, 0.0);
     out.G.assign((size_t)m * m, 0.0);
-    if (eig_real(m, Hm.data(), out.theta.data(), out.G.data()) != 0) return TGDK_E_SINGULAR;
+    if (eig_real(m, Hm.data(), out.theta.data(), out.G.data()) != 0) return 2;
     return TGDK_OK;
 }
 
@@ -208,6 +210,7 @@ extern "C" int tgdk_coarse_setup(tgdk_op op, const double* b, double* x, const t
     long long mvps = m;
     int cyc = 0, nconv = 0, kk = 0;
     std::vector<int> chosen;
+    std::vector<double> dbg_prevH, dbg_prevQ, dbg_prevc;
     Ritz R;
     double lin = 0.0;
     double* W = nullptr;
@@ -219,8 +222,21 @@ extern "C" int tgdk_coarse_setup(tgdk_op op, const double* b, double* x, const t
         for (double v : q) lin += v * v;
         lin = std::sqrt(lin);
         if ((rc = harmonic_ritz(m, Hbar, R))) {
+            const char* dump = getenv("TGDK_DEBUG_DUMP");
+            if (dump) {
+                FILE* f = fopen(dump, "w");
+                if (f) {
+                    fprintf(f, "%d %d %d %d\n", m, cyc, rc, kk);
+                    for (double v : Hbar) fprintf(f, "%.17g\n", v);
+                    for (double v : dbg_prevH) fprintf(f, "%.17g\n", v);
+                    for (double v : dbg_prevQ) fprintf(f, "%.17g\n", v);
+                    for (double v : dbg_prevc) fprintf(f, "%.17g\n", v);
+                    fclose(f);
+                }
+            }
             cleanup();
-            return fail(rc, "harmonic Ritz eigenproblem failed");
+            return fail(TGDK_E_SINGULAR, rc == 1 ? "harmonic Ritz step: H_m is singular"
+                                                 : "harmonic Ritz step: QR iteration did not converge");
         }
         chosen = select_smallest(R.theta, k);
         nconv = 0;
@@ -250,8 +266,15 @@ extern "C" int tgdk_coarse_setup(tgdk_op op, const double* b, double* x, const t
         std::vector<double> P((size_t)(m + 1) * (kk + 1), 0.0), Q((size_t)(m + 1) * (kk + 1)), Rr((size_t)(kk + 1) * (kk + 1));
         for (int cidx = 0; cidx < kk; ++cidx)
             for (int r = 0; r < m; ++r) P[(size_t)r * (kk + 1) + cidx] = cols[cidx][r];
-        for (int r = 0; r <= m; ++r) P[(size_t)r * (kk + 1) + kk] = q[r];
+        // only the direction of q enters P_{k+1}; once the coarse system has
+        // converged q keeps shrinking toward the subnormal range, so scale it
+        double qmax = 0.0;
+        for (double v : q) qmax = std::max(qmax, std::fabs(v));
+        for (int r = 0; r <= m; ++r) P[(size_t)r * (kk + 1) + kk] = qmax > 0.0 ? q[r] / qmax : 0.0;
         householder_qr(m + 1, kk + 1, P.data(), Q.data(), Rr.data());
+        dbg_prevH = Hbar;
+        dbg_prevQ = Q;
+        dbg_prevc = c;
         std::vector<double> Qc((size_t)(m + 1) * (kk + 1));  // column-major for the device
         for (int r = 0; r <= m; ++r)
             for (int cidx = 0; cidx <= kk; ++cidx) Qc[(size_t)cidx * (m + 1) + r] = Q[(size_t)r * (kk + 1) + cidx];

@@ -77,13 +77,19 @@ __global__ __launch_bounds__(NT) void k_gram(const void* A, long long lda, int p
         const int pr = threadIdx.x + s * NT;
         if (pr < npair) partial[(long long)blockIdx.x * npair + pr] = acc[s];
     }
-    if (!arrive_last(counter, gridDim.x)) return;
-    for (int pr = threadIdx.x; pr < npair; pr += NT) {
+    (void)sh;
+    (void)counter;
+    (void)G;
+}
+
+// Sums the per-block Gram partials in block order.
+__global__ __launch_bounds__(NT) void k_gram_finish(const double* __restrict__ partial, int nblocks, int npair,
+                                                    double* __restrict__ G) {
+    for (int pr = blockIdx.x * NT + threadIdx.x; pr < npair; pr += gridDim.x * NT) {
         double s = 0.0;
-        for (int b = 0; b < (int)gridDim.x; ++b) s += partial[(long long)b * npair + pr];
+        for (int b = 0; b < nblocks; ++b) s += partial[(long long)b * npair + pr];
         G[pr] = s;
     }
-    (void)sh;
 }
 
 void launch_gram(const void* A, int atype, long long lda, int p, const void* B, int btype, long long ldb, int q,
@@ -101,6 +107,8 @@ void launch_gram(const void* A, int atype, long long lda, int p, const void* B, 
     else
         hipLaunchKernelGGL((k_gram<double, float>), dim3(nb), dim3(NT), 0, s, A, lda, p, B, ldb, q, n, G, partial,
                            counter);
+    const int npair = p * q;
+    hipLaunchKernelGGL(k_gram_finish, dim3((npair + NT - 1) / NT), dim3(NT), 0, s, partial, nb, npair, G);
 }
 
 // ---------------------------------------------------------------- V * Y
@@ -180,39 +188,58 @@ __global__ __launch_bounds__(NT) void k_gs(const double* __restrict__ V, long lo
             if (threadIdx.x < 16 && c0 + threadIdx.x < p)
                 partial[(long long)blockIdx.x * pstride + c0 + threadIdx.x] = tot;
         }
-        if (!arrive_last(counter, gridDim.x)) return;
-        for (int i = 0; i < p; ++i) {
-            const double s = sum_partials(partial, gridDim.x, pstride, i, sh);
-            if (threadIdx.x == 0) hout[i] = s;
-        }
     } else {
         double acc[1] = {0.0};
         for (long long g = g0; g < n; g += stride) acc[0] += w[g] * w[g];
         double tot;
         block_sum<1>(acc, sh, tot);
         if (threadIdx.x == 0) partial[blockIdx.x] = tot;
-        if (!arrive_last(counter, gridDim.x)) return;
-        const double s = sum_partials(partial, gridDim.x, 1, 0, sh);
+    }
+    (void)counter;
+    (void)hout;
+}
+
+// Sums the per-block partials in block order: hout[i] for i < p, or
+// hout[0] = sqrt(sum) for the norm (MODE 2).
+template <int MODE>
+__global__ __launch_bounds__(NT) void k_gs_finish(const double* __restrict__ partial, int nblocks, int p,
+                                                  double* __restrict__ hout) {
+    __shared__ double sh[NWAVE];
+    if (MODE <= 1) {
+        for (int i = 0; i < p; ++i) {
+            const double s = sum_partials(partial, nblocks, MAXK + 1, i, sh);
+            if (threadIdx.x == 0) hout[i] = s;
+        }
+    } else {
+        const double s = sum_partials(partial, nblocks, 1, 0, sh);
         if (threadIdx.x == 0) hout[0] = sqrt(s);
     }
 }
 
 void launch_gs_dot(const double* V, long long ldv, int p, const double* w, long long n, double* hout,
                    double* partial, unsigned* counter, hipStream_t s) {
-    hipLaunchKernelGGL((k_gs<0>), dim3(gs_blocks(n)), dim3(NT), 0, s, V, ldv, p, const_cast<double*>(w),
+    const int nb = gs_blocks(n);
+    hipLaunchKernelGGL((k_gs<0>), dim3(nb), dim3(NT), 0, s, V, ldv, p, const_cast<double*>(w),
                        (const double*)nullptr, n, hout, partial, counter);
+    hipLaunchKernelGGL((k_gs_finish<0>), dim3(1), dim3(NT), 0, s, partial, nb, p, hout);
 }
 void launch_gs_update_dot(const double* V, long long ldv, int p, double* w, const double* h, long long n,
                           double* hout, double* partial, unsigned* counter, hipStream_t s) {
-    hipLaunchKernelGGL((k_gs<1>), dim3(gs_blocks(n)), dim3(NT), 0, s, V, ldv, p, w, h, n, hout, partial, counter);
+    const int nb = gs_blocks(n);
+    hipLaunchKernelGGL((k_gs<1>), dim3(nb), dim3(NT), 0, s, V, ldv, p, w, h, n, hout, partial, counter);
+    hipLaunchKernelGGL((k_gs_finish<1>), dim3(1), dim3(NT), 0, s, partial, nb, p, hout);
 }
 void launch_gs_update_norm(const double* V, long long ldv, int p, double* w, const double* h, long long n,
                            double* nrm, double* partial, unsigned* counter, hipStream_t s) {
-    hipLaunchKernelGGL((k_gs<2>), dim3(gs_blocks(n)), dim3(NT), 0, s, V, ldv, p, w, h, n, nrm, partial, counter);
+    const int nb = gs_blocks(n);
+    hipLaunchKernelGGL((k_gs<2>), dim3(nb), dim3(NT), 0, s, V, ldv, p, w, h, n, nrm, partial, counter);
+    hipLaunchKernelGGL((k_gs_finish<2>), dim3(1), dim3(NT), 0, s, partial, nb, p, nrm);
 }
 void launch_norm2(const double* w, long long n, double* out, double* partial, unsigned* counter, hipStream_t s) {
-    hipLaunchKernelGGL((k_gs<2>), dim3(gs_blocks(n)), dim3(NT), 0, s, (const double*)nullptr, 0LL, 0,
+    const int nb = gs_blocks(n);
+    hipLaunchKernelGGL((k_gs<2>), dim3(nb), dim3(NT), 0, s, (const double*)nullptr, 0LL, 0,
                        const_cast<double*>(w), (const double*)nullptr, n, out, partial, counter);
+    hipLaunchKernelGGL((k_gs_finish<2>), dim3(1), dim3(NT), 0, s, partial, nb, 0, out);
 }
 
 __global__ void k_scale(const double* w, double* v, const double* __restrict__ nrm,

@@ -117,7 +117,15 @@ __global__ __launch_bounds__(NT) void k_residual(const DevProb* __restrict__ pro
     block_sum<3>(acc, sh, tot);
     const int lt = t - P.tile_begin;
     if (threadIdx.x < 3) P.partial[(long long)lt * P.pstride + threadIdx.x] = tot;
-    if (!arrive_last(P.counter, P.ntiles)) return;
+}
+
+// Epilogue of the true residual (one workgroup per problem).
+__global__ __launch_bounds__(NT) void k_epi_residual(const DevProb* __restrict__ probs, int first) {
+    __shared__ double sh[NWAVE];
+    const DevProb& P = probs[blockIdx.x];
+    SolveState* st = P.st;
+    if (first != 2 && st->solve_state != SV_RUNNING) return;
+    const bool start = (P.k == 0) && (st->method == METHOD_BICGSTAB) && first != 2;
     const double rr = sum_partials(P.partial, P.ntiles, P.pstride, 0, sh);
     const double bb = sum_partials(P.partial, P.ntiles, P.pstride, 1, sh);
     const double ri = sum_partials(P.partial, P.ntiles, P.pstride, 2, sh);
@@ -197,7 +205,16 @@ __global__ __launch_bounds__(NT) void k_proj_dot(const DevProb* __restrict__ pro
         if (threadIdx.x < 16 && c0 + threadIdx.x < k)
             P.partial[(long long)lt * P.pstride + c0 + threadIdx.x] = tot;
     }
-    if (!arrive_last(P.counter, P.ntiles)) return;
+}
+
+// c summed in tile order, then H d = c by the LU factors of H.
+__global__ __launch_bounds__(NT) void k_epi_proj_dot(const DevProb* __restrict__ probs) {
+    __shared__ double sh[NWAVE];
+    __shared__ double y[MAXK + 1];
+    const DevProb& P = probs[blockIdx.x];
+    SolveState* st = P.st;
+    if (st->solve_state != SV_RUNNING || P.k == 0) return;
+    const int k = P.k;
     for (int i = 0; i < k; ++i) {
         const double ci = sum_partials(P.partial, P.ntiles, P.pstride, i, sh);
         if (threadIdx.x == 0) y[i] = ci;
@@ -288,7 +305,14 @@ __global__ __launch_bounds__(NT) void k_proj_apply(const DevProb* __restrict__ p
     double tot;
     block_sum<2>(acc, sh, tot);
     if (threadIdx.x < 2) P.partial[(long long)lt * P.pstride + threadIdx.x] = tot;
-    if (!arrive_last(P.counter, P.ntiles)) return;
+}
+
+__global__ __launch_bounds__(NT) void k_epi_proj_apply(const DevProb* __restrict__ probs) {
+    __shared__ double sh[NWAVE];
+    const DevProb& P = probs[blockIdx.x];
+    SolveState* st = P.st;
+    if (st->solve_state != SV_RUNNING || P.k == 0) return;
+    const bool start = st->method == METHOD_BICGSTAB;
     const double rr = sum_partials(P.partial, P.ntiles, P.pstride, 0, sh);
     const double ri = sum_partials(P.partial, P.ntiles, P.pstride, 1, sh);
     if (threadIdx.x != 0) return;
@@ -372,14 +396,21 @@ __global__ __launch_bounds__(NT) void k_bicg_a(const DevProb* __restrict__ probs
     double tot;
     block_sum<2>(acc, sh, tot);
     if (threadIdx.x < 2) P.partial[(long long)lt * P.pstride + threadIdx.x] = tot;
-    if (!arrive_last(P.counter, P.ntiles)) return;
+}
+
+// alpha = rho / (r^.v); breakdown if r^.v vanishes.
+__global__ __launch_bounds__(NT) void k_epi_a(const DevProb* __restrict__ probs) {
+    __shared__ double sh[NWAVE];
+    const DevProb& P = probs[blockIdx.x];
+    SolveState* st = P.st;
+    if (st->solve_state != SV_RUNNING || st->inner_state != IN_RUNNING) return;
     const double sig = sum_partials(P.partial, P.ntiles, P.pstride, 0, sh);
     const double rr = sum_partials(P.partial, P.ntiles, P.pstride, 1, sh);
     if (threadIdx.x != 0) return;
     st->mvp_inner += 1;
     st->sigma = sig;
     st->rr_last = rr;
-    st->pbuf = cur;
+    st->pbuf = st->iter & 1;
     if (sig == 0.0 || !isfinite(sig)) {
         st->inner_state = IN_BREAK_NOUPD;
         mirror_out(P, st);
@@ -440,7 +471,14 @@ __global__ __launch_bounds__(NT) void k_bicg_b(const DevProb* __restrict__ probs
     double tot;
     block_sum<5>(acc, sh, tot);
     if (threadIdx.x < 5) P.partial[(long long)lt * P.pstride + threadIdx.x] = tot;
-    if (!arrive_last(P.counter, P.ntiles)) return;
+}
+
+// omega, the next rho and the exit tests of the iteration.
+__global__ __launch_bounds__(NT) void k_epi_b(const DevProb* __restrict__ probs) {
+    __shared__ double sh[NWAVE];
+    const DevProb& P = probs[blockIdx.x];
+    SolveState* st = P.st;
+    if (st->solve_state != SV_RUNNING || st->inner_state != IN_RUNNING) return;
     double sums[5];
     for (int i = 0; i < 5; ++i) sums[i] = sum_partials(P.partial, P.ntiles, P.pstride, i, sh);
     if (threadIdx.x != 0) return;
@@ -450,7 +488,7 @@ __global__ __launch_bounds__(NT) void k_bicg_b(const DevProb* __restrict__ probs
     st->iters_total += 1;
     const int hi = st->nhist;
     if (ss <= st->target2) {
-        if (st->icyc == 1 && hi < NHIST) {
+        if (hi < NHIST) {
             st->hist[3 * hi] = st->rho;
             st->hist[3 * hi + 1] = st->alpha;
             st->hist[3 * hi + 2] = __builtin_nan("");
@@ -462,7 +500,7 @@ __global__ __launch_bounds__(NT) void k_bicg_b(const DevProb* __restrict__ probs
     }
     const double omega = (tt != 0.0) ? ts / tt : 0.0;
     st->omega = omega;
-    if (st->icyc == 1 && hi < NHIST) {
+    if (hi < NHIST) {
         st->hist[3 * hi] = st->rho;
         st->hist[3 * hi + 1] = st->alpha;
         st->hist[3 * hi + 2] = omega;
@@ -528,24 +566,29 @@ static void solve_launch_cfg(int which, const DevProb* probs, int nprob, int tot
     switch (which) {
         case K_RESIDUAL:
             hipLaunchKernelGGL((k_residual<Cfg, DIM, TI>), grid, block, 0, s, probs, nprob, flag);
+            hipLaunchKernelGGL(k_epi_residual, dim3(nprob), block, 0, s, probs, flag);
             break;
         case K_PROJ_DOT:
             if (vtype == 0)
                 hipLaunchKernelGGL((k_proj_dot<Cfg, double>), grid, block, 0, s, probs, nprob);
             else
                 hipLaunchKernelGGL((k_proj_dot<Cfg, float>), grid, block, 0, s, probs, nprob);
+            hipLaunchKernelGGL(k_epi_proj_dot, dim3(nprob), block, 0, s, probs);
             break;
         case K_PROJ_APPLY:
             if (vtype == 0)
                 hipLaunchKernelGGL((k_proj_apply<Cfg, DIM, double, TI>), grid, block, 0, s, probs, nprob);
             else
                 hipLaunchKernelGGL((k_proj_apply<Cfg, DIM, float, TI>), grid, block, 0, s, probs, nprob);
+            hipLaunchKernelGGL(k_epi_proj_apply, dim3(nprob), block, 0, s, probs);
             break;
         case K_BICG_A:
             hipLaunchKernelGGL((k_bicg_a<Cfg, DIM, TI>), grid, block, 0, s, probs, nprob);
+            hipLaunchKernelGGL(k_epi_a, dim3(nprob), block, 0, s, probs);
             break;
         case K_BICG_B:
             hipLaunchKernelGGL((k_bicg_b<Cfg, DIM, TI>), grid, block, 0, s, probs, nprob);
+            hipLaunchKernelGGL(k_epi_b, dim3(nprob), block, 0, s, probs);
             break;
         case K_FINALIZE:
             hipLaunchKernelGGL((k_finalize<Cfg, TI>), grid, block, 0, s, probs, nprob);

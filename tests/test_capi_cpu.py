@@ -139,3 +139,41 @@ def test_host_lstsq_and_lu_and_qr():
     np.testing.assert_allclose(Q @ R, A, atol=1e-12)
     assert np.all(np.diag(R) >= 0) and np.allclose(np.tril(R, -1), 0)
     np.testing.assert_allclose(Q.T @ Q, np.eye(30), atol=1e-12)
+
+
+def test_host_eig_near_defective_stays_finite():
+    """Near-defective matrices (a Jordan-like chain of nearly equal
+    eigenvalues, as harmonic Ritz matrices become once pairs converge twice):
+    eigenvectors must stay finite and unit-norm."""
+    rng = np.random.default_rng(7)
+    for n in (12, 30, 60):
+        J = np.diag(np.full(n, 5.0) + 1e-13 * rng.standard_normal(n)) + np.diag(np.full(n - 1, 1e3), 1)
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        M = Q @ J @ Q.T
+        a, ap = _d(M)
+        wr, wrp = _d(np.zeros(n))
+        wi, wip = _d(np.zeros(n))
+        Xr, Xrp = _d(np.zeros(n * n))
+        Xi, Xip = _d(np.zeros(n * n))
+        assert _lib().lib().tgdk_host_eig(n, ap, wrp, wip, Xrp, Xip) == 0
+        X = (Xr + 1j * Xi).reshape(n, n)
+        assert np.all(np.isfinite(X))
+        assert np.allclose(np.linalg.norm(X, axis=1), 1.0)
+
+
+def test_host_qr_tiny_and_huge_columns():
+    """Columns scaled by 1e-160 and 1e+150 (the GMRES-DR least-squares
+    residual shrinks toward the subnormal range once the coarse system has
+    converged): Q stays finite and orthonormal, Q R reproduces A."""
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((31, 11))
+    A[:, 10] *= 1e-160
+    A[:, 3] *= 1e150
+    a, ap = _d(A)
+    Q, qp = _d(np.zeros((31, 11)))
+    R, rp = _d(np.zeros((11, 11)))
+    assert _lib().lib().tgdk_host_qr(31, 11, ap, qp, rp) == 0
+    assert np.all(np.isfinite(Q)) and np.all(np.isfinite(R))
+    np.testing.assert_allclose(Q.T @ Q, np.eye(11), atol=1e-12)
+    for j in range(11):
+        np.testing.assert_allclose(Q @ R[:, j], A[:, j], rtol=0, atol=1e-12 * np.abs(A[:, j]).max())

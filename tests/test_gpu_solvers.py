@@ -44,7 +44,7 @@ def _true_relres(oop, b, x, transpose=False):
 
 def test_bicgstab_k0_matches_oracle_scalars_and_solution():
     """Restarted BiCGStab without deflation on the small workload: the first
-    cycle's (rho, alpha, omega) agree with the oracle to 1e-12, the solution
+    iterations' (rho, alpha, omega) agree with the oracle to 1e-12, the solution
     with the direct solve, and the mvp count with the oracle's (soft)."""
     c, oop, b = _c1()
     op = tg().Operator.const_cd(c["n"], c["beta"])
