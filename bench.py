@@ -1,0 +1,255 @@
+"""Benchmark of the fine-grid hot path on one MI355X.
+
+Workload (the headline single-GPU configuration): 2-D convection-diffusion
+-u_xx - u_yy + 100 u_x on the unit square, 5-point centred differences, fine
+grid 1023 x 1023 (n = 1,046,529), coarse grid 511 x 511, b ~ N(0,1) (seed 2).
+Setup (untimed, reported separately): GMRES-DR(80,30) on the coarse grid until
+30 harmonic Ritz pairs have relative residual <= 1e-8, prolongation and
+orthonormalisation of the 30 vectors, H = V^T A V.  A step is one fine solve,
+BiCGStab(20)-Proj(30) in float64 from the prolongated coarse solution to true
+relative residual ||b - A x|| / ||b|| <= 1e-8, with every input already in
+device memory.
+
+Prints one JSON line.  `value` is seconds per fine solve (lower is better).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fine-solve time to rel.resid 1e-8 (s) + stencil HBM GB/s; FP32/batched vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("kernels_krylov.hip", "device_common.h", "tgdk_shared.h"):
+        with open(os.path.join(ROOT, "paper_2005_03070_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "bicg_phase_a_f64_1023sq_counters.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_hash") != kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU design is "
+              "documented but not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2005_03070_amd as tg
+    from paper_2005_03070_amd import _lib as L
+    from paper_2005_03070_amd.api import context
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    c = W.CONFIGS["C2"]
+    nx, ny = c["n"]
+    n = nx * ny
+    b_np = W.rhs(n, c["seed"])
+    b = torch.tensor(b_np, device=dev)
+    op = tg.Operator.const_cd((nx, ny), c["beta"])
+    ctx, _ = context(dev)
+    log = lambda *m: print("[bench]", *m, file=sys.stderr, flush=True)  # noqa: E731
+
+    # ---------------------------------------------------------------- setup
+    t0 = time.perf_counter()
+    coarse = op.coarsen()
+    bc = tg.restrict(op, coarse, b)
+    xc, cspace, srep = tg.coarse_setup(coarse, bc, c["m"], c["k"], c["nev"], c["rtolev"], 1e-8, 300)
+    space = tg.defl_prolongate(cspace, op)
+    x0 = tg.prolongate(coarse, op, xc)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"setup {setup_s:.2f}s: GMRES-DR cycles={srep.cycles} nconv={srep.nconv} mvps={srep.mvps}")
+
+    def fine_solve(**kw):
+        kw.setdefault("ncyc", c["ncyc"])
+        kw.setdefault("rtol", c["rtol"])
+        return tg.solve(op, b, x0=x0, defl=space, **kw)
+
+    def true_relres(x):
+        r = b - op.apply(x)
+        return float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
+
+    # ------------------------------------------------------- headline steps
+    for _ in range(a.warmup):
+        fine_solve()
+    torch.cuda.synchronize()
+    times = []
+    reps = None
+    t_start = time.perf_counter()
+    for _ in range(a.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, reps = fine_solve()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    total = time.perf_counter() - t_start
+    rr = true_relres(x)
+    assert reps[0].status == 0 and rr <= c["rtol"], (reps[0].status_name, rr)
+    sec = total / a.steps
+    log(f"fp64 BiCGStab(20)-Proj(30): {sec*1e3:.1f} ms/solve, mvps {reps[0].mvp_inner}, relres {rr:.2e}")
+    head = reps[0]
+
+    # ------------------------------------------- live kernel timing (roofline)
+    def timed_kernel(which, **kw):
+        L.check(L.lib().tgdk_ctx_time_kernel(ctx, which))
+        x, r = fine_solve(**kw)
+        ms = np.zeros(1)
+        cnt = np.zeros(1, dtype=np.int64)
+        import ctypes as C
+        L.check(L.lib().tgdk_ctx_kernel_time(ctx, ms.ctypes.data_as(L.DP), cnt.ctypes.data_as(C.POINTER(C.c_longlong))))
+        L.check(L.lib().tgdk_ctx_time_kernel(ctx, 0))
+        return float(ms[0]) / max(int(cnt[0]), 1), int(cnt[0])
+
+    a_ms, a_cnt = timed_kernel(1)
+    b_ms, b_cnt = timed_kernel(2)
+    bytes_a = 10 * 8 * n  # reads s, t, p, v, e, r^; writes r, e, p, v (float64)
+    bytes_b = 5 * 8 * n   # reads r, v, r^; writes s, t
+    ach_a = bytes_a / (a_ms * 1e-3) / 1e9
+    ach_b = bytes_b / (b_ms * 1e-3) / 1e9
+    log(f"phase A {a_ms*1e3:.1f} us x{a_cnt} -> {ach_a:.0f} GB/s; phase B {b_ms*1e3:.1f} us x{b_cnt} -> {ach_b:.0f} GB/s")
+
+    # ------------------------------------------------------------ variants
+    variants = {}
+    if not a.no_variants:
+        def run(name, steps, **kw):
+            fine_solve(**kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(steps):
+                xv, rv = fine_solve(**kw)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / steps
+            variants[name] = {"seconds": dt, "relres_true": true_relres(xv), "status": rv[0].status_name,
+                              "cycles": rv[0].cycles, "mvp_inner": rv[0].mvp_inner,
+                              "mvp_boundary": rv[0].mvp_boundary}
+            log(f"{name}: {dt*1e3:.1f} ms, mvps {rv[0].mvp_inner}, relres {variants[name]['relres_true']:.2e}")
+
+        run("fp32_inner_fp64_refinement", max(3, a.steps // 2), precision="fp32_ir")
+        run("gmres50_proj30_fp64", 2, method="gmres", m3=c["m3"])
+        # no deflation, from zero: the restarted BiCGStab baseline
+        t = time.perf_counter()
+        x_nd, r_nd = tg.solve(op, b, rtol=c["rtol"], ncyc=c["ncyc"], max_extra=40)
+        torch.cuda.synchronize()
+        variants["bicgstab20_no_deflation_fp64"] = {
+            "seconds": time.perf_counter() - t, "relres_true": true_relres(x_nd), "status": r_nd[0].status_name,
+            "cycles": r_nd[0].cycles, "mvp_inner": r_nd[0].mvp_inner}
+
+    # ------------------------------------------ standalone stencil bandwidth
+    def stencil_gbs(opx, dtype, rotate_bytes=2 << 30):
+        es = torch.tensor([], dtype=dtype).element_size()
+        per = 2 * opx.n * es
+        nbuf = max(2, int(rotate_bytes // per))
+        xs = [torch.randn(opx.n, dtype=dtype, device=dev) for _ in range(nbuf)]
+        ys = [torch.empty_like(xs[0]) for _ in range(nbuf)]
+        for i in range(nbuf):
+            ys[i] = opx.apply(xs[i])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps_ = 3 * nbuf
+        e0.record()
+        for i in range(reps_):
+            j = i % nbuf
+            ys[j] = opx.apply(xs[j])
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps_
+        del xs, ys
+        return per / (ms * 1e-3) / 1e9, ms * 1e3
+
+    st_c2, us_c2 = stencil_gbs(op, torch.float64)
+    op3 = tg.Operator.const_cd((255, 255, 255), (50.0, 20.0, 10.0))
+    st_c3, us_c3 = stencil_gbs(op3, torch.float32)
+    log(f"stencil 1023^2 f64 {st_c2:.0f} GB/s ({us_c2:.1f} us); 255^3 f32 {st_c3:.0f} GB/s ({us_c3:.1f} us)")
+
+    # -------------------------------------------------- oracle CPU baseline
+    cpu = None
+    if not a.no_cpu:
+        from oracle import bicgstab as OB, operators as OO
+        oop = OO.const_cd((nx, ny), c["beta"])
+        r0 = b_np - OO.apply(oop, x0.cpu().numpy())
+        t = time.perf_counter()
+        iters = 0
+        chunk = 20
+        while time.perf_counter() - t < a.cpu_seconds:
+            res = OB.bicgstab_inner(lambda z: OO.apply(oop, z), r0, 0.0, chunk)
+            iters += res.iters
+        dt = time.perf_counter() - t
+        per_mvp = dt / (2 * iters)
+        total_mvps = head.mvp_inner + head.mvp_boundary
+        cpu = {"value": per_mvp * total_mvps, "unit": "s", "cores": 1, "kind": "oracle",
+               "sample": (f"numpy float64 Bi-CGSTAB iterations of the oracle on the same 1023^2 operator: "
+                          f"{2 * iters} mvps in {dt:.1f} s ({per_mvp * 1e3:.2f} ms per mvp with its vector ops), "
+                          f"scaled to the GPU solve's {total_mvps} mvps; projection and setup not included; "
+                          f"single-threaded numpy on a host with {os.cpu_count()} cores")}
+        log(f"cpu oracle {per_mvp*1e3:.2f} ms/mvp -> {cpu['value']:.1f} s per solve")
+
+    out = {
+        "metric": METRIC,
+        "value": sec,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2-D conv-diff -Lap(u)+100u_x, 5-pt, fine 1023^2 (n=1,046,529), coarse 511^2, "
+                               "GMRES-DR(80,30) -> 30 vectors, BiCGStab(20)-Proj(30) fp64, rtol 1e-8 true residual",
+                   "n": n, "k": space.k, "ncyc": c["ncyc"], "seed": c["seed"]},
+        "roofline": {"bound": "hbm", "achieved": ach_a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach_a / HBM_PEAK_GBS, "traffic": traffic_from_profiles(),
+                     "kernel": "k_bicg_a (BiCGStab phase A: stencil + p/r/e updates + r^.v partials), f64",
+                     "algorithmic_bytes_per_launch": bytes_a, "avg_launch_us": a_ms * 1e3,
+                     "launches_timed": a_cnt},
+        "kernels": {"bicg_phase_b_f64": {"avg_launch_us": b_ms * 1e3, "achieved_GBs": ach_b,
+                                         "algorithmic_bytes_per_launch": bytes_b},
+                    "stencil_1023sq_f64_GBs": st_c2, "stencil_255cube_f32_GBs": st_c3},
+        "solve": {"relres_true": rr, "cycles": head.cycles, "mvp_inner": head.mvp_inner,
+                  "mvp_boundary": head.mvp_boundary, "min_s": min(times), "max_s": max(times)},
+        "setup": {"seconds": setup_s, "gmresdr_cycles": srep.cycles, "nconv": srep.nconv, "mvps": srep.mvps},
+        "variants": variants,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

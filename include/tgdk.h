@@ -57,7 +57,7 @@ extern "C" {
 #define TGDK_FP64          0
 #define TGDK_FP32_IR       1
 
-#define TGDK_MAX_DEFL 128   /* largest deflation space (k) and GMRES m */
+#define TGDK_MAX_DEFL 128   /* largest GMRES cycle length m (deflation spaces: k <= 64) */
 #define TGDK_NHIST    8     /* recorded BiCGStab scalars of the first iterations */
 
 /* Text of the last non-OK return on the calling thread ("" if none). */
@@ -74,6 +74,15 @@ int tgdk_ctx_create(tgdk_ctx* out, int device, void* hip_stream);
 int tgdk_ctx_destroy(tgdk_ctx ctx);
 /* Number of compute units of the context's device (for launch sizing). */
 int tgdk_ctx_num_cus(tgdk_ctx ctx);
+/* Measurement hook.  which = 1 (BiCGStab phase A: stencil fused with the
+ * p/r/e updates and the r^.v partials) or 2 (phase B: stencil fused with the
+ * s update and five dot-product partials); 0 switches timing off.  While on,
+ * each launch of that kernel inside tgdk_solve / tgdk_solve_instances is
+ * bracketed by HIP events on the context stream (this adds a little launch
+ * overhead).  tgdk_ctx_kernel_time returns the summed duration in ms and the
+ * number of launches that did work since the last call, then resets both. */
+int tgdk_ctx_time_kernel(tgdk_ctx ctx, int which);
+int tgdk_ctx_kernel_time(tgdk_ctx ctx, double* total_ms, long long* launches);
 
 /* ---------------------------------------------------------------- operators
  * The discretised operator of Sec. 1 / Sec. 3 Example 1: centred finite

@@ -269,11 +269,30 @@ int tgdk_ctx_destroy(tgdk_ctx c) {
     if (c->dscal) (void)hipFree(c->dscal);
     if (c->mirror) (void)hipHostFree(c->mirror);
     for (auto e : c->events) (void)hipEventDestroy(e);
+    for (auto e : c->tev) (void)hipEventDestroy(e);
     delete c;
     return TGDK_OK;
 }
 
 int tgdk_ctx_num_cus(tgdk_ctx c) { return c ? c->num_cus : 0; }
+
+int tgdk_ctx_time_kernel(tgdk_ctx c, int which) {
+    if (!c || which < 0 || which > 2) return fail(TGDK_E_INVALID, "bad argument");
+    c->time_which = which;
+    c->tev_used = 0;
+    c->time_ms = 0.0;
+    c->time_count = 0;
+    return TGDK_OK;
+}
+
+int tgdk_ctx_kernel_time(tgdk_ctx c, double* total_ms, long long* launches) {
+    if (!c) return fail(TGDK_E_INVALID, "NULL context");
+    if (total_ms) *total_ms = c->time_ms;
+    if (launches) *launches = c->time_count;
+    c->time_ms = 0.0;
+    c->time_count = 0;
+    return TGDK_OK;
+}
 
 int tgdk_op_create(tgdk_ctx ctx, const tgdk_op_desc* d, tgdk_op* out) {
     if (!ctx || !d || !out) return fail(TGDK_E_INVALID, "NULL argument");

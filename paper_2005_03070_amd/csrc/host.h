@@ -46,6 +46,13 @@ struct tgdk_ctx_s {
     tgdk::Mirror* mirror = nullptr;  // host-mapped
     int mirror_cap = 0;
     std::vector<hipEvent_t> events;
+    // kernel timing for measurement (0 off, 1 BiCGStab phase A, 2 phase B)
+    int time_which = 0;
+    std::vector<hipEvent_t> tev;        // event pairs
+    std::vector<int> tev_cyc, tev_iter;  // cycle and iteration of each timed launch
+    size_t tev_used = 0;
+    double time_ms = 0.0;
+    long long time_count = 0;
 };
 
 struct tgdk_op_s {

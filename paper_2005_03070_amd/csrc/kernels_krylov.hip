@@ -146,6 +146,10 @@ __global__ __launch_bounds__(NT) void k_epi_residual(const DevProb* __restrict__
         else if (nu <= st->tau || nu == 0.0)
             st->solve_state = SV_CONVERGED;
     } else {
+        if (st->icyc >= 1 && st->icyc <= NCYCLOG) {
+            st->cyc_iters[st->icyc - 1] = st->iter;
+            st->cyc_end[st->icyc - 1] = st->inner_state;
+        }
         const bool broke = (st->inner_state == IN_BREAK_NOUPD || st->inner_state == IN_BREAK_FULL);
         if (!isfinite(nu))
             st->solve_state = SV_NONFINITE;
@@ -561,8 +565,9 @@ __global__ __launch_bounds__(NT) void k_finalize(const DevProb* __restrict__ pro
 // ------------------------------------------------------------ launchers
 template <class Cfg, int DIM, class TI>
 static void solve_launch_cfg(int which, const DevProb* probs, int nprob, int total_tiles, int flag, int vtype,
-                             hipStream_t s) {
+                             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     dim3 grid(total_tiles), block(NT);
+    if (ev0) (void)hipEventRecord(ev0, s);
     switch (which) {
         case K_RESIDUAL:
             hipLaunchKernelGGL((k_residual<Cfg, DIM, TI>), grid, block, 0, s, probs, nprob, flag);
@@ -584,10 +589,12 @@ static void solve_launch_cfg(int which, const DevProb* probs, int nprob, int tot
             break;
         case K_BICG_A:
             hipLaunchKernelGGL((k_bicg_a<Cfg, DIM, TI>), grid, block, 0, s, probs, nprob);
+            if (ev1) (void)hipEventRecord(ev1, s);
             hipLaunchKernelGGL(k_epi_a, dim3(nprob), block, 0, s, probs);
             break;
         case K_BICG_B:
             hipLaunchKernelGGL((k_bicg_b<Cfg, DIM, TI>), grid, block, 0, s, probs, nprob);
+            if (ev1) (void)hipEventRecord(ev1, s);
             hipLaunchKernelGGL(k_epi_b, dim3(nprob), block, 0, s, probs);
             break;
         case K_FINALIZE:
@@ -598,35 +605,35 @@ static void solve_launch_cfg(int which, const DevProb* probs, int nprob, int tot
 
 template <int DIM, class TI>
 static void solve_launch_dim(int which, const DevProb* probs, int nprob, int total_tiles, int flag, int vtype,
-                             int tile_id, hipStream_t s) {
+                             int tile_id, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (DIM == 2) {
         switch (tile_id) {
-            case 1: solve_launch_cfg<Tile<2, 8, 1>, 2, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
-            case 2: solve_launch_cfg<Tile<2, 4, 1>, 2, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
-            default: solve_launch_cfg<Tile<2, 16, 1>, 2, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
+            case 1: solve_launch_cfg<Tile<2, 8, 1>, 2, TI>(which, probs, nprob, total_tiles, flag, vtype, s, e0, e1); break;
+            case 2: solve_launch_cfg<Tile<2, 4, 1>, 2, TI>(which, probs, nprob, total_tiles, flag, vtype, s, e0, e1); break;
+            default: solve_launch_cfg<Tile<2, 16, 1>, 2, TI>(which, probs, nprob, total_tiles, flag, vtype, s, e0, e1); break;
         }
     } else {
         switch (tile_id) {
-            case 1: solve_launch_cfg<Tile<3, 8, 4>, 3, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
-            case 2: solve_launch_cfg<Tile<3, 4, 8>, 3, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
-            default: solve_launch_cfg<Tile<3, 4, 4>, 3, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
+            case 1: solve_launch_cfg<Tile<3, 8, 4>, 3, TI>(which, probs, nprob, total_tiles, flag, vtype, s, e0, e1); break;
+            case 2: solve_launch_cfg<Tile<3, 4, 8>, 3, TI>(which, probs, nprob, total_tiles, flag, vtype, s, e0, e1); break;
+            default: solve_launch_cfg<Tile<3, 4, 4>, 3, TI>(which, probs, nprob, total_tiles, flag, vtype, s, e0, e1); break;
         }
     }
 }
 
 void launch_solve_kernel(int which, int dim, int inner_f32, int vtype, int tile_id, const DevProb* probs,
-                         int nprob, int total_tiles, int flag, hipStream_t s) {
+                         int nprob, int total_tiles, int flag, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (total_tiles <= 0) return;
     if (dim == 2) {
         if (inner_f32)
-            solve_launch_dim<2, float>(which, probs, nprob, total_tiles, flag, vtype, tile_id, s);
+            solve_launch_dim<2, float>(which, probs, nprob, total_tiles, flag, vtype, tile_id, s, e0, e1);
         else
-            solve_launch_dim<2, double>(which, probs, nprob, total_tiles, flag, vtype, tile_id, s);
+            solve_launch_dim<2, double>(which, probs, nprob, total_tiles, flag, vtype, tile_id, s, e0, e1);
     } else {
         if (inner_f32)
-            solve_launch_dim<3, float>(which, probs, nprob, total_tiles, flag, vtype, tile_id, s);
+            solve_launch_dim<3, float>(which, probs, nprob, total_tiles, flag, vtype, tile_id, s, e0, e1);
         else
-            solve_launch_dim<3, double>(which, probs, nprob, total_tiles, flag, vtype, tile_id, s);
+            solve_launch_dim<3, double>(which, probs, nprob, total_tiles, flag, vtype, tile_id, s, e0, e1);
     }
 }
 

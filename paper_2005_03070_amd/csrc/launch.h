@@ -25,8 +25,11 @@ void launch_fill(double* a, double v, long long n, hipStream_t s);
 void launch_copy(const double* a, double* b, long long n, hipStream_t s);
 
 // fused solve kernels over a problem group
+// e0/e1 (may be null): events recorded around the phase kernel (before its
+// epilogue launch) for measurement.
 void launch_solve_kernel(int which, int dim, int inner_f32, int vtype, int tile_id, const DevProb* probs,
-                         int nprob, int total_tiles, int flag, hipStream_t s);
+                         int nprob, int total_tiles, int flag, hipStream_t s, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
 void tile_shape(int dim, int tile_id, int* ty, int* tz);
 
 // tall-skinny products (column-major blocks, leading dimensions in elements)

@@ -83,6 +83,59 @@ static void launch(const Group& g, int which, int flag = 0) {
                         g.ctx->stream);
 }
 
+// A launch of the timed kernel: events around it, tagged with its cycle and
+// iteration so launches that found the cycle already finished can be told
+// apart afterwards.
+static int launch_timed(const Group& g, int which, int cyc, int it) {
+    tgdk_ctx ctx = g.ctx;
+    const bool timed = (ctx->time_which == 1 && which == K_BICG_A) || (ctx->time_which == 2 && which == K_BICG_B);
+    if (!timed) {
+        launch(g, which);
+        return TGDK_OK;
+    }
+    if (ctx->tev_used * 2 + 2 > ctx->tev.size()) {
+        for (int i = 0; i < 256; ++i) {
+            hipEvent_t e;
+            TGDK_HIP(hipEventCreate(&e));
+            ctx->tev.push_back(e);
+        }
+    }
+    const size_t k = ctx->tev_used++;
+    if (ctx->tev_cyc.size() <= k) {
+        ctx->tev_cyc.resize(k + 1);
+        ctx->tev_iter.resize(k + 1);
+    }
+    ctx->tev_cyc[k] = cyc;
+    ctx->tev_iter[k] = it;
+    launch_solve_kernel(which, g.dim, g.inner_f32, g.vtype, g.tile_id, g.d_probs, g.nprob, g.total_tiles, 0,
+                        ctx->stream, ctx->tev[2 * k], ctx->tev[2 * k + 1]);
+    return TGDK_OK;
+}
+
+// Adds the durations of the timed launches that did work (per the device's
+// per-cycle iteration log) to the context's totals.
+static void collect_timing(Group& g) {
+    tgdk_ctx ctx = g.ctx;
+    for (size_t k = 0; k < ctx->tev_used; ++k) {
+        const int c = ctx->tev_cyc[k], i = ctx->tev_iter[k];
+        int real = 0;
+        for (int j = 0; j < g.nprob; ++j) {
+            const SolveState& S = g.states[j];
+            if (c >= NCYCLOG || c >= S.icyc) continue;
+            int r = S.cyc_iters[c];
+            if (ctx->time_which == 1 && S.cyc_end[c] == IN_BREAK_NOUPD) r += 1;
+            real = std::max(real, r);
+        }
+        if (i >= real) continue;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ctx->tev[2 * k], ctx->tev[2 * k + 1]) == hipSuccess) {
+            ctx->time_ms += ms;
+            ctx->time_count += 1;
+        }
+    }
+    ctx->tev_used = 0;
+}
+
 // Host-mapped mirror values are written by the device; read them volatile.
 static Mirror read_mirror(const Group& g, int j) {
     volatile Mirror* m = g.mirror + j;
@@ -304,8 +357,8 @@ static int bicgstab_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const t
         const int max_batches = maxit / B + 2;
         for (;;) {
             for (int i = 0; i < B; ++i) {
-                launch(g, K_BICG_A);
-                launch(g, K_BICG_B);
+                if ((rc = launch_timed(g, K_BICG_A, cyc, batches * B + i))) return rc;
+                if ((rc = launch_timed(g, K_BICG_B, cyc, batches * B + i))) return rc;
             }
             TGDK_HIP(hipEventRecord(ctx->events[batches & 1], s));
             ++batches;
@@ -323,7 +376,9 @@ static int bicgstab_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const t
         if (all_solved(g)) break;
     }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    return finish_group(g, ps, reps, secs, nullptr);
+    rc = finish_group(g, ps, reps, secs, nullptr);
+    if (ctx->time_which) collect_timing(g);
+    return rc;
 }
 
 // GMRES(m)-Proj(k): one right-hand side.  Arnoldi with classical

@@ -6,7 +6,8 @@
 namespace tgdk {
 
 constexpr int MAXK = 128;   // largest deflation space / GMRES cycle length
-constexpr int NHIST = 8;    // recorded first-cycle BiCGStab scalars
+constexpr int NHIST = 8;    // recorded first BiCGStab scalars
+constexpr int NCYCLOG = 512;  // cycles whose inner iteration counts are logged
 
 // An operator as the kernels see it (passed by value or inside DevProb).
 struct DevOp {
@@ -51,6 +52,8 @@ struct SolveState {
     int branch[4];
     long long iters_total, mvp_inner, mvp_boundary;
     double hist[3 * NHIST];
+    int cyc_iters[NCYCLOG];  // inner iterations of each finished cycle
+    int cyc_end[NCYCLOG];    // inner state that ended it
     double d[MAXK + 1];      // projection coefficients (H d = c)
     double cvec[MAXK + 1];
 };
