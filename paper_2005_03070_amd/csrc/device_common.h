@@ -139,6 +139,49 @@ __device__ __forceinline__ long long gidx(const DevOp& op, int gx, int gy, int g
     return ((long long)gz * op.ny + gy) * op.nx + gx;
 }
 
+// Fills the halo of an LDS box (everything except the tile interior, which
+// the caller writes from its own points): the rows above/below the tile (and
+// the planes in front/behind it in 3-D), 64 wide and coalesced, then the two
+// halo columns of every box row.  val(g) gives the value at an in-domain
+// global index; out-of-domain points get zero.  Fixed trip counts, so the
+// loads of all iterations are in flight together.
+template <class Cfg, int DIM, class T, class F>
+__device__ __forceinline__ void fill_halo(T* L, const TilePos& tp, const DevOp& op, F&& val) {
+    constexpr int BX = Cfg::BX, BY = Cfg::BY, BZ = Cfg::BZ, TY = Cfg::TY, TZ = Cfg::TZ, HZ = Cfg::HZ;
+    constexpr int HR = (DIM == 3) ? (2 * TZ + 2 * BY) : 2;
+    constexpr int NHR = HR * 64;
+#pragma unroll
+    for (int k = 0; k < (NHR + NT - 1) / NT; ++k) {
+        const int e = threadIdx.x + k * NT;
+        if (e < NHR) {
+            const int hr = e >> 6, lane = e & 63;
+            int hy, hz;
+            if (hr < 2 * TZ) {
+                hz = (hr >> 1) + HZ;
+                hy = (hr & 1) ? TY + 1 : 0;
+            } else {
+                const int i2 = hr - 2 * TZ;
+                hz = (i2 >= BY) ? BZ - 1 : 0;
+                hy = i2 % BY;
+            }
+            const int gx = tp.x0 + lane, gy = tp.y0 + hy - 1, gz = tp.z0 + hz - HZ;
+            L[(hz * BY + hy) * BX + lane + 1] =
+                (gx < op.nx && gy >= 0 && gy < op.ny && gz >= 0 && gz < op.nz) ? val(gidx(op, gx, gy, gz)) : T(0);
+        }
+    }
+    constexpr int NHC = BY * BZ * 2;
+#pragma unroll
+    for (int k = 0; k < (NHC + NT - 1) / NT; ++k) {
+        const int e = threadIdx.x + k * NT;
+        if (e < NHC) {
+            const int br = e >> 1, side = e & 1;
+            const int hz = br / BY, hy = br % BY, hx = side ? BX - 1 : 0;
+            const int gx = tp.x0 + hx - 1, gy = tp.y0 + hy - 1, gz = tp.z0 + hz - HZ;
+            L[(hz * BY + hy) * BX + hx] = inside(op, gx, gy, gz) ? val(gidx(op, gx, gy, gz)) : T(0);
+        }
+    }
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -184,6 +227,58 @@ __device__ __forceinline__ double sum_partials(const double* partial, int ntiles
     double s = 0.0;
     for (int t = threadIdx.x; t < ntiles; t += NT) s += partial[(long long)t * stride + i];
     return block_sum_one(s, sh);
+}
+
+// Sums columns 0..NV-1 of partial[t * stride + v] over t = 0..ntiles-1 in a
+// fixed order, all columns in one pass (independent loads in flight); every
+// thread receives the totals.  sh needs NWAVE*NV doubles.
+template <int NV>
+__device__ __forceinline__ void sum_partials_multi(const double* __restrict__ partial, int ntiles, int stride,
+                                                   double (&out)[NV], double* sh) {
+    double a[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a[v] = 0.0;
+#pragma unroll 4
+    for (int t = threadIdx.x; t < ntiles; t += NT) {
+        const double* row = partial + (long long)t * stride;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a[v] += row[v];
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double s = wave_sum(a[v]);
+        if (lane == 0) sh[w * NV + v] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double s = sh[v];
+        for (int w2 = 1; w2 < NWAVE; ++w2) s += sh[w2 * NV + v];
+        out[v] = s;
+    }
+    __syncthreads();
+}
+
+// Sums ncols columns (ncols <= NT/4) of partial[t * stride + c] over
+// t = 0..ntiles-1 into out[c] (LDS or global), in a fixed order: thread
+// (part, c) sums tiles part, part + nparts, ...; then the parts are added in
+// order.  scratch needs NT doubles.
+__device__ __forceinline__ void sum_partial_columns(const double* __restrict__ partial, int ntiles, int stride,
+                                                    int ncols, double* out, double* scratch) {
+    const int nparts = NT / ncols;
+    const int c = threadIdx.x % ncols, part = threadIdx.x / ncols;
+    double a = 0.0;
+    if (part < nparts)
+        for (int t = part; t < ntiles; t += nparts) a += partial[(long long)t * stride + c];
+    scratch[threadIdx.x] = a;
+    __syncthreads();
+    if (threadIdx.x < ncols) {
+        double s = 0.0;
+        for (int q = 0; q < nparts; ++q) s += scratch[q * ncols + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
 }
 
 // Problem lookup for grouped launches (linear scan; groups are small).

@@ -22,62 +22,81 @@ __device__ __forceinline__ double ld(const void* p, long long i) {
 }
 
 // ------------------------------------------------------------- Gram A^T B
-// Each block walks chunks of 64 rows (grid-stride), stages them in LDS and
-// accumulates its share of the p x q outputs; thread t owns outputs
-// t, t+256, ... of the row-major p x q result.
-constexpr int GRAM_MAX = 64;
-constexpr int GRAM_CHUNK = 32;
+// Matrix-core (v_mfma_f64_16x16x4f64) Gram product G = A^T B, K = the long
+// dimension n.  Operand layout of the instruction on gfx950 (one wave):
+//   A-operand  lane l holds A[l % 16][l / 16]   (16 x 4)
+//   B-operand  lane l holds B[l / 16][l % 16]   (4 x 16)
+//   result     lane l, register r holds D[l / 16 + 4 r][l % 16]  (16 x 16)
+// Each workgroup stages 64-row chunks of A and B in LDS (coalesced column
+// loads, float32 inputs widened exactly), and its four waves accumulate the
+// 16 x 16 output tiles over the chunk; per-workgroup partial tiles are summed
+// in workgroup order by k_gram_finish.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+constexpr int GRAM_MAX = 64;   // p, q <= 64
+constexpr int GRAM_ROWS = 32;  // rows staged per chunk (two 32 x 65 float64 LDS tiles)
 
 int gram_blocks(long long n) {
-    long long b = (n + 4 * GRAM_CHUNK - 1) / (4 * GRAM_CHUNK);
-    if (b > 512) b = 512;
+    long long b = (n + 4 * GRAM_ROWS - 1) / (4 * GRAM_ROWS);
+    if (b > 1024) b = 1024;
     if (b < 1) b = 1;
     return (int)b;
 }
 
 template <class TA, class TB>
-__global__ __launch_bounds__(NT) void k_gram(const void* A, long long lda, int p, const void* B, long long ldb,
+__global__ __launch_bounds__(NT) void k_gram(const void* A_, long long lda, int p, const void* B_, long long ldb,
                                              int q, long long n, double* G, double* partial, unsigned* counter) {
-    __shared__ double As[GRAM_CHUNK][GRAM_MAX + 1];
-    __shared__ double Bs[GRAM_CHUNK][GRAM_MAX + 1];
-    __shared__ double sh[NWAVE];
-    const int npair = p * q;
-    constexpr int MAXPT = GRAM_MAX * GRAM_MAX / NT;
-    double acc[MAXPT];
+    __shared__ double As[GRAM_ROWS][GRAM_MAX + 1];
+    __shared__ double Bs[GRAM_ROWS][GRAM_MAX + 1];
+    const TA* A = reinterpret_cast<const TA*>(A_);
+    const TB* B = reinterpret_cast<const TB*>(B_);
+    const int pt = (p + 15) / 16, qt = (q + 15) / 16, ntile = pt * qt;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int MAXT = (GRAM_MAX / 16) * (GRAM_MAX / 16) / NWAVE;  // tiles per wave
+    d4_t acc[MAXT];
 #pragma unroll
-    for (int i = 0; i < MAXPT; ++i) acc[i] = 0.0;
-    const long long nchunk = (n + GRAM_CHUNK - 1) / GRAM_CHUNK;
+    for (int i = 0; i < MAXT; ++i) acc[i] = d4_t{0.0, 0.0, 0.0, 0.0};
+    const long long nchunk = (n + GRAM_ROWS - 1) / GRAM_ROWS;
     for (long long ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-        const long long r0 = ch * GRAM_CHUNK;
-        for (int idx = threadIdx.x; idx < GRAM_CHUNK * p; idx += NT) {
-            const int rr = idx % GRAM_CHUNK, col = idx / GRAM_CHUNK;
+        const long long r0 = ch * GRAM_ROWS;
+        for (int idx = threadIdx.x; idx < GRAM_ROWS * GRAM_MAX; idx += NT) {
+            const int rr = idx % GRAM_ROWS, col = idx / GRAM_ROWS;
             const long long g = r0 + rr;
-            As[rr][col] = g < n ? ld<TA>(A, col * lda + g) : 0.0;
-        }
-        for (int idx = threadIdx.x; idx < GRAM_CHUNK * q; idx += NT) {
-            const int rr = idx % GRAM_CHUNK, col = idx / GRAM_CHUNK;
-            const long long g = r0 + rr;
-            Bs[rr][col] = g < n ? ld<TB>(B, col * ldb + g) : 0.0;
+            As[rr][col] = (g < n && col < p) ? (double)A[col * lda + g] : 0.0;
+            Bs[rr][col] = (g < n && col < q) ? (double)B[col * ldb + g] : 0.0;
         }
         __syncthreads();
 #pragma unroll
-        for (int s = 0; s < MAXPT; ++s) {
-            const int pr = threadIdx.x + s * NT;
-            if (pr < npair) {
-                const int i = pr / q, j = pr % q;
-                double a = acc[s];
-                for (int rr = 0; rr < GRAM_CHUNK; ++rr) a += As[rr][i] * Bs[rr][j];
+        for (int s = 0; s < MAXT; ++s) {
+            const int tile = w + s * NWAVE;
+            if (tile < ntile) {
+                const int i0 = (tile / qt) * 16, j0 = (tile % qt) * 16;
+                d4_t a = acc[s];
+#pragma unroll
+                for (int k4 = 0; k4 < GRAM_ROWS; k4 += 4) {
+                    const double av = As[k4 + (lane >> 4)][i0 + (lane & 15)];
+                    const double bv = Bs[k4 + (lane >> 4)][j0 + (lane & 15)];
+                    a = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, a, 0, 0, 0);
+                }
                 acc[s] = a;
             }
         }
         __syncthreads();
     }
+    // per-workgroup partial, row-major p x q
+    const int npair = p * q;
 #pragma unroll
-    for (int s = 0; s < MAXPT; ++s) {
-        const int pr = threadIdx.x + s * NT;
-        if (pr < npair) partial[(long long)blockIdx.x * npair + pr] = acc[s];
+    for (int s = 0; s < MAXT; ++s) {
+        const int tile = w + s * NWAVE;
+        if (tile < ntile) {
+            const int i0 = (tile / qt) * 16, j0 = (tile % qt) * 16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + (lane >> 4) + 4 * r, j = j0 + (lane & 15);
+                if (i < p && j < q) partial[(long long)blockIdx.x * npair + i * q + j] = acc[s][r];
+            }
+        }
     }
-    (void)sh;
     (void)counter;
     (void)G;
 }
@@ -112,23 +131,57 @@ void launch_gram(const void* A, int atype, long long lda, int p, const void* B, 
 }
 
 // ---------------------------------------------------------------- V * Y
+// Out (n x q) = V (n x p) Y (p x q) on the matrix cores, computed as
+// Out^T = Y^T V^T so that each lane's V load is one of 16 consecutive rows of
+// a column (coalesced): B-operand lane l = V[r0 + l % 16][k0 + l / 16],
+// A-operand lane l = Y[k0 + l / 16][j0 + l % 16], result lane l, register r =
+// Out[r0 + l % 16][j0 + l / 16 + 4 r].  One wave owns 16 rows and all q
+// columns (q <= 144), loading V once.
+constexpr int VMUL_MAXQT = 9;
+
 __global__ __launch_bounds__(NT) void k_vmul(const double* __restrict__ V, long long ldv, int p,
                                              const double* __restrict__ Y, int q, double* __restrict__ Out,
                                              long long ldo, long long n) {
-    // Y is tiny and read uniformly by all lanes (scalar loads).
-    for (long long g = blockIdx.x * (long long)NT + threadIdx.x; g < n; g += (long long)gridDim.x * NT) {
-        for (int c = 0; c < q; ++c) {
-            double a = 0.0;
-            for (int i = 0; i < p; ++i) a += V[i * ldv + g] * Y[(long long)c * p + i];
-            Out[c * ldo + g] = a;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int qt = (q + 15) / 16;
+    const long long nrt = (n + 15) / 16;
+    for (long long rt = (long long)blockIdx.x * NWAVE + w; rt < nrt; rt += (long long)gridDim.x * NWAVE) {
+        const long long r0 = rt * 16;
+        const long long row = r0 + (lane & 15);
+        d4_t acc[VMUL_MAXQT];
+#pragma unroll
+        for (int t = 0; t < VMUL_MAXQT; ++t) acc[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < p; k0 += 4) {
+            const int kc = k0 + (lane >> 4);
+            const double bv = (row < n && kc < p) ? V[kc * ldv + row] : 0.0;
+#pragma unroll
+            for (int t = 0; t < VMUL_MAXQT; ++t) {
+                if (t < qt) {
+                    const int jc = t * 16 + (lane & 15);
+                    const double av = (kc < p && jc < q) ? Y[(long long)jc * p + kc] : 0.0;
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+                }
+            }
+        }
+        if (row < n) {
+#pragma unroll
+            for (int t = 0; t < VMUL_MAXQT; ++t) {
+                if (t < qt) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int jc = t * 16 + (lane >> 4) + 4 * r;
+                        if (jc < q) Out[jc * ldo + row] = acc[t][r];
+                    }
+                }
+            }
         }
     }
 }
 
 void launch_vmul(const double* V, long long ldv, int p, const double* Y, int q, double* Out, long long ldo,
                  long long n, hipStream_t s) {
-    long long nb = (n + NT - 1) / NT;
-    if (nb > 4096) nb = 4096;
+    long long nb = ((n + 15) / 16 + NWAVE - 1) / NWAVE;
+    if (nb > 8192) nb = 8192;
     hipLaunchKernelGGL(k_vmul, dim3((int)nb), dim3(NT), 0, s, V, ldv, p, Y, q, Out, ldo, n);
 }
 
@@ -206,9 +259,12 @@ __global__ __launch_bounds__(NT) void k_gs_finish(const double* __restrict__ par
                                                   double* __restrict__ hout) {
     __shared__ double sh[NWAVE];
     if (MODE <= 1) {
-        for (int i = 0; i < p; ++i) {
-            const double s = sum_partials(partial, nblocks, MAXK + 1, i, sh);
-            if (threadIdx.x == 0) hout[i] = s;
+        // one thread per value, blocks added in order (loads coalesced across values)
+        for (int i = threadIdx.x; i < p; i += NT) {
+            double s = 0.0;
+#pragma unroll 8
+            for (int b = 0; b < nblocks; ++b) s += partial[(long long)b * (MAXK + 1) + i];
+            hout[i] = s;
         }
     } else {
         const double s = sum_partials(partial, nblocks, 1, 0, sh);

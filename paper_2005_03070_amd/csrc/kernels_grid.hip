@@ -18,21 +18,22 @@ __global__ __launch_bounds__(NT) void k_apply(DevOp op, const T* __restrict__ x,
     const long long off = (long long)blockIdx.y * op.n;
     x += off;
     y += off;
-    for (int h = threadIdx.x; h < Cfg::BOX; h += NT) {
-        int gx, gy, gz;
-        box_coords<Cfg>(h, tp, gx, gy, gz);
-        L[h] = inside(op, gx, gy, gz) ? x[gidx(op, gx, gy, gz)] : T(0);
-    }
-    __syncthreads();
+    long long gq[Cfg::PPT];
+    int cq[Cfg::PPT];
+    bool okq[Cfg::PPT];
 #pragma unroll
     for (int q = 0; q < Cfg::PPT; ++q) {
-        int gx, gy, gz, c;
-        point_coords<Cfg>(q, tp, gx, gy, gz, c);
-        if (inside(op, gx, gy, gz)) {
-            const long long g = gidx(op, gx, gy, gz);
-            y[g] = stencil_row<Cfg, DIM, T>(op, L, c, g);
-        }
+        int gx, gy, gz;
+        point_coords<Cfg>(q, tp, gx, gy, gz, cq[q]);
+        okq[q] = inside(op, gx, gy, gz);
+        gq[q] = okq[q] ? gidx(op, gx, gy, gz) : 0;
+        L[cq[q]] = okq[q] ? x[gq[q]] : T(0);
     }
+    fill_halo<Cfg, DIM, T>(L, tp, op, [&](long long g) { return x[g]; });
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Cfg::PPT; ++q)
+        if (okq[q]) y[gq[q]] = stencil_row<Cfg, DIM, T>(op, L, cq[q], gq[q]);
 }
 
 template <class Cfg, int DIM, class T>

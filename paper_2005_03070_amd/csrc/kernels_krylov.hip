@@ -35,6 +35,7 @@ __device__ __forceinline__ void mirror_out(const DevProb& P, const SolveState* s
         P.mirror->inner_state = st->inner_state;
         P.mirror->icyc = st->icyc;
         P.mirror->iter = st->iter;
+        P.mirror->target2 = st->target2;
         __threadfence_system();
     }
 }
@@ -67,6 +68,7 @@ __device__ void start_cycle(SolveState* st, double nu, double rho0) {
     st->omega = 1.0;
     st->iter = 0;
     st->inner_state = IN_RUNNING;
+    st->rr_last = nu * nu;
 }
 
 // ---------------------------------------------------------- true residual
@@ -83,12 +85,22 @@ __global__ __launch_bounds__(NT) void k_residual(const DevProb* __restrict__ pro
     if (first != 2 && st->solve_state != SV_RUNNING) return;
     const TilePos tp = tile_pos<Cfg>(t - P.tile_begin, P.tx, P.ty);
     const DevOp& op = P.op;
-    const double* x = P.x;
-    for (int h = threadIdx.x; h < Cfg::BOX; h += NT) {
+    const double* __restrict__ x = P.x;
+    const double* __restrict__ b = P.b;
+    long long gq[Cfg::PPT];
+    int cq[Cfg::PPT];
+    bool okq[Cfg::PPT];
+    double bq[Cfg::PPT];
+#pragma unroll
+    for (int q = 0; q < Cfg::PPT; ++q) {
         int gx, gy, gz;
-        box_coords<Cfg>(h, tp, gx, gy, gz);
-        L[h] = inside(op, gx, gy, gz) ? x[gidx(op, gx, gy, gz)] : 0.0;
+        point_coords<Cfg>(q, tp, gx, gy, gz, cq[q]);
+        okq[q] = inside(op, gx, gy, gz);
+        gq[q] = okq[q] ? gidx(op, gx, gy, gz) : 0;
+        L[cq[q]] = okq[q] ? x[gq[q]] : 0.0;
+        bq[q] = okq[q] ? b[gq[q]] : 0.0;
     }
+    fill_halo<Cfg, DIM, double>(L, tp, op, [&](long long g) { return x[g]; });
     __syncthreads();
     const bool start = (P.k == 0) && (st->method == METHOD_BICGSTAB) && first != 2;
     TI* rin = vp<TI>(P.rin);
@@ -97,12 +109,10 @@ __global__ __launch_bounds__(NT) void k_residual(const DevProb* __restrict__ pro
     double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < Cfg::PPT; ++q) {
-        int gx, gy, gz, c;
-        point_coords<Cfg>(q, tp, gx, gy, gz, c);
-        if (!inside(op, gx, gy, gz)) continue;
-        const long long g = gidx(op, gx, gy, gz);
-        const double bv = P.b[g];
-        const double rv = bv - stencil_row<Cfg, DIM, double>(op, L, c, g);
+        if (!okq[q]) continue;
+        const long long g = gq[q];
+        const double bv = bq[q];
+        const double rv = bv - stencil_row<Cfg, DIM, double>(op, L, cq[q], g);
         P.r[g] = rv;
         acc[0] += rv * rv;
         acc[1] += bv * bv;
@@ -121,14 +131,14 @@ __global__ __launch_bounds__(NT) void k_residual(const DevProb* __restrict__ pro
 
 // Epilogue of the true residual (one workgroup per problem).
 __global__ __launch_bounds__(NT) void k_epi_residual(const DevProb* __restrict__ probs, int first) {
-    __shared__ double sh[NWAVE];
+    __shared__ double sh[NWAVE * 3];
     const DevProb& P = probs[blockIdx.x];
     SolveState* st = P.st;
     if (first != 2 && st->solve_state != SV_RUNNING) return;
     const bool start = (P.k == 0) && (st->method == METHOD_BICGSTAB) && first != 2;
-    const double rr = sum_partials(P.partial, P.ntiles, P.pstride, 0, sh);
-    const double bb = sum_partials(P.partial, P.ntiles, P.pstride, 1, sh);
-    const double ri = sum_partials(P.partial, P.ntiles, P.pstride, 2, sh);
+    double sums[3];
+    sum_partials_multi<3>(P.partial, P.ntiles, P.pstride, sums, sh);
+    const double rr = sums[0], bb = sums[1], ri = sums[2];
     if (threadIdx.x != 0) return;
     if (first == 2) {
         st->nu_final = sqrt(rr);
@@ -162,7 +172,13 @@ __global__ __launch_bounds__(NT) void k_epi_residual(const DevProb* __restrict__
     }
     if (st->solve_state == SV_RUNNING) {
         st->icyc += 1;
-        if (start) start_cycle(st, nu, ri);
+        if (start) {
+            start_cycle(st, nu, ri);
+            if (P.mirror) {
+                P.mirror->rr0 = nu * nu;
+                P.mirror->rr = nu * nu;
+            }
+        }
     }
     mirror_out(P, st);
 }
@@ -213,17 +229,13 @@ __global__ __launch_bounds__(NT) void k_proj_dot(const DevProb* __restrict__ pro
 
 // c summed in tile order, then H d = c by the LU factors of H.
 __global__ __launch_bounds__(NT) void k_epi_proj_dot(const DevProb* __restrict__ probs) {
-    __shared__ double sh[NWAVE];
+    __shared__ double scratch[NT];
     __shared__ double y[MAXK + 1];
     const DevProb& P = probs[blockIdx.x];
     SolveState* st = P.st;
     if (st->solve_state != SV_RUNNING || P.k == 0) return;
     const int k = P.k;
-    for (int i = 0; i < k; ++i) {
-        const double ci = sum_partials(P.partial, P.ntiles, P.pstride, i, sh);
-        if (threadIdx.x == 0) y[i] = ci;
-    }
-    __syncthreads();
+    sum_partial_columns(P.partial, P.ntiles, P.pstride, k, y, scratch);
     // LU solve: row interchanges, then L (unit lower) and U (upper), row-major.
     if (threadIdx.x == 0) {
         for (int i = 0; i < k; ++i) st->cvec[i] = y[i];
@@ -269,20 +281,28 @@ __global__ __launch_bounds__(NT) void k_proj_apply(const DevProb* __restrict__ p
     const int lt = t - P.tile_begin;
     const TilePos tp = tile_pos<Cfg>(lt, P.tx, P.ty);
     const DevOp& op = P.op;
-    const TV* V = reinterpret_cast<const TV*>(P.V);
+    const TV* __restrict__ V = reinterpret_cast<const TV*>(P.V);
+    const long long ldv = P.ldv;
     const int k = P.k;
     for (int i = threadIdx.x; i < k; i += NT) dsh[i] = st->d[i];
     __syncthreads();
-    for (int h = threadIdx.x; h < Cfg::BOX; h += NT) {
-        int gx, gy, gz;
-        box_coords<Cfg>(h, tp, gx, gy, gz);
+    auto wval = [&](long long g) {
         double w = 0.0;
-        if (inside(op, gx, gy, gz)) {
-            const long long g = gidx(op, gx, gy, gz);
-            for (int j = 0; j < k; ++j) w += (double)V[(long long)j * P.ldv + g] * dsh[j];
-        }
-        L[h] = w;
+        for (int j = 0; j < k; ++j) w += (double)V[(long long)j * ldv + g] * dsh[j];
+        return w;
+    };
+    long long gq[Cfg::PPT];
+    int cq[Cfg::PPT];
+    bool okq[Cfg::PPT];
+#pragma unroll
+    for (int q = 0; q < Cfg::PPT; ++q) {
+        int gx, gy, gz;
+        point_coords<Cfg>(q, tp, gx, gy, gz, cq[q]);
+        okq[q] = inside(op, gx, gy, gz);
+        gq[q] = okq[q] ? gidx(op, gx, gy, gz) : 0;
+        L[cq[q]] = okq[q] ? wval(gq[q]) : 0.0;
     }
+    fill_halo<Cfg, DIM, double>(L, tp, op, wval);
     __syncthreads();
     const bool start = st->method == METHOD_BICGSTAB;
     TI* rin = vp<TI>(P.rin);
@@ -291,10 +311,9 @@ __global__ __launch_bounds__(NT) void k_proj_apply(const DevProb* __restrict__ p
     double acc[2] = {0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < Cfg::PPT; ++q) {
-        int gx, gy, gz, c;
-        point_coords<Cfg>(q, tp, gx, gy, gz, c);
-        if (!inside(op, gx, gy, gz)) continue;
-        const long long g = gidx(op, gx, gy, gz);
+        if (!okq[q]) continue;
+        const long long g = gq[q];
+        const int c = cq[q];
         P.x[g] += L[c];
         const double rv = P.r[g] - stencil_row<Cfg, DIM, double>(op, L, c, g);
         P.r[g] = rv;
@@ -312,13 +331,14 @@ __global__ __launch_bounds__(NT) void k_proj_apply(const DevProb* __restrict__ p
 }
 
 __global__ __launch_bounds__(NT) void k_epi_proj_apply(const DevProb* __restrict__ probs) {
-    __shared__ double sh[NWAVE];
+    __shared__ double sh[NWAVE * 2];
     const DevProb& P = probs[blockIdx.x];
     SolveState* st = P.st;
     if (st->solve_state != SV_RUNNING || P.k == 0) return;
     const bool start = st->method == METHOD_BICGSTAB;
-    const double rr = sum_partials(P.partial, P.ntiles, P.pstride, 0, sh);
-    const double ri = sum_partials(P.partial, P.ntiles, P.pstride, 1, sh);
+    double sums[2];
+    sum_partials_multi<2>(P.partial, P.ntiles, P.pstride, sums, sh);
+    const double rr = sums[0], ri = sums[1];
     if (threadIdx.x != 0) return;
     st->mvp_boundary += 1;
     const double nu = sqrt(rr);
@@ -327,75 +347,100 @@ __global__ __launch_bounds__(NT) void k_epi_proj_apply(const DevProb* __restrict
         st->solve_state = SV_NONFINITE;
     else if (nu <= st->tau)
         st->solve_state = SV_CONVERGED;
-    else if (start)
+    else if (start) {
         start_cycle(st, nu, ri);
+        if (P.mirror) {
+            P.mirror->rr0 = nu * nu;
+            P.mirror->rr = nu * nu;
+        }
+    }
     mirror_out(P, st);
 }
 
 // ----------------------------------------------------- BiCGStab phase A
 template <class Cfg, int DIM, class TI>
-__global__ __launch_bounds__(NT) void k_bicg_a(const DevProb* __restrict__ probs, int nprob) {
+__global__ __launch_bounds__(NT) void k_bicg_a(const DevProb* __restrict__ probs, int nprob, int iter_host) {
     __shared__ TI L[Cfg::BOX];
     __shared__ double sh[NWAVE * 2];
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     const DevProb& P = probs[find_prob(probs, nprob, t)];
-    SolveState* st = P.st;
-    if (st->solve_state != SV_RUNNING || st->inner_state != IN_RUNNING) return;
     const int lt = t - P.tile_begin;
     const TilePos tp = tile_pos<Cfg>(lt, P.tx, P.ty);
     const DevOp& op = P.op;
-    const int iter = st->iter;
-    const bool first = iter == 0;
-    const int cur = iter & 1, prv = cur ^ 1;
-    TI* pnew = vp<TI>(P.p[cur]);
-    const TI* pold = vp<TI>(P.p[prv]);
-    TI* vnew = vp<TI>(P.v[cur]);
-    const TI* vold = vp<TI>(P.v[prv]);
+    // The host enqueues iteration iter_host of the cycle; while the problem is
+    // running the device's own count equals it, so the buffers and the first-
+    // iteration branch are known without the solver state, and the loads of
+    // this thread's tile points are issued before the state load returns.
+    const bool first = iter_host == 0;
+    const int cur = iter_host & 1, prv = cur ^ 1;
+    TI* __restrict__ pnew = vp<TI>(P.p[cur]);
+    const TI* __restrict__ pold = vp<TI>(P.p[prv]);
+    TI* __restrict__ vnew = vp<TI>(P.v[cur]);
+    const TI* __restrict__ vold = vp<TI>(P.v[prv]);
     TI* rin = vp<TI>(P.rin);
-    const TI* rhat = vp<TI>(P.rhat);
-    const TI* sv_ = vp<TI>(P.s);
-    const TI* tv_ = vp<TI>(P.t);
-    TI* e = vp<TI>(P.e);
-    const TI alpha = (TI)st->alpha, omega = (TI)st->omega;
-    const TI beta = first ? TI(0) : (TI)((st->rho / st->rho_old) * (st->alpha / st->omega));
-    for (int h = threadIdx.x; h < Cfg::BOX; h += NT) {
+    const TI* __restrict__ rhat = vp<TI>(P.rhat);
+    const TI* __restrict__ sv_ = vp<TI>(P.s);
+    const TI* __restrict__ tv_ = vp<TI>(P.t);
+    TI* __restrict__ e = vp<TI>(P.e);
+    long long gq[Cfg::PPT];
+    int cq[Cfg::PPT];
+    bool okq[Cfg::PPT];
+    TI rq[Cfg::PPT], sq[Cfg::PPT], poq[Cfg::PPT], tq[Cfg::PPT], voq[Cfg::PPT];
+#pragma unroll
+    for (int q = 0; q < Cfg::PPT; ++q) {
         int gx, gy, gz;
-        box_coords<Cfg>(h, tp, gx, gy, gz);
-        TI pv = TI(0);
-        if (inside(op, gx, gy, gz)) {
-            const long long g = gidx(op, gx, gy, gz);
+        point_coords<Cfg>(q, tp, gx, gy, gz, cq[q]);
+        okq[q] = inside(op, gx, gy, gz);
+        const long long g = okq[q] ? gidx(op, gx, gy, gz) : 0;
+        gq[q] = g;
+        rq[q] = sq[q] = poq[q] = tq[q] = voq[q] = TI(0);
+        if (okq[q]) {
             if (first) {
-                pv = rin[g];
+                rq[q] = rin[g];
             } else {
-                const TI rv = sv_[g] - omega * tv_[g];
-                pv = rv + beta * (pold[g] - omega * vold[g]);
+                sq[q] = sv_[g];
+                tq[q] = tv_[g];
+                poq[q] = pold[g];
+                voq[q] = vold[g];
             }
         }
-        L[h] = pv;
     }
+    SolveState* st = P.st;
+    if (st->solve_state != SV_RUNNING || st->inner_state != IN_RUNNING) return;
+    const TI alpha = (TI)st->alpha, omega = (TI)st->omega;
+    const TI beta = first ? TI(0) : (TI)((st->rho / st->rho_old) * (st->alpha / st->omega));
+    // new p on this thread's points (into LDS); r is kept for the update below
+#pragma unroll
+    for (int q = 0; q < Cfg::PPT; ++q) {
+        TI pv = rq[q];
+        if (!first) {
+            rq[q] = sq[q] - omega * tq[q];
+            pv = rq[q] + beta * (poq[q] - omega * voq[q]);
+        }
+        L[cq[q]] = okq[q] ? pv : TI(0);
+    }
+    fill_halo<Cfg, DIM, TI>(L, tp, op, [&](long long g) -> TI {
+        if (first) return rin[g];
+        const TI rv = sv_[g] - omega * tv_[g];
+        return rv + beta * (pold[g] - omega * vold[g]);
+    });
     __syncthreads();
     double acc[2] = {0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < Cfg::PPT; ++q) {
-        int gx, gy, gz, c;
-        point_coords<Cfg>(q, tp, gx, gy, gz, c);
-        if (!inside(op, gx, gy, gz)) continue;
-        const long long g = gidx(op, gx, gy, gz);
-        const TI vv = stencil_row<Cfg, DIM, TI>(op, L, c, g);
-        pnew[g] = L[c];
+        if (!okq[q]) continue;
+        const long long g = gq[q];
+        const TI vv = stencil_row<Cfg, DIM, TI>(op, L, cq[q], g);
+        pnew[g] = L[cq[q]];
         vnew[g] = vv;
-        TI rv;
         if (first) {
-            rv = rin[g];
             e[g] = TI(0);
         } else {
-            const TI sv = sv_[g];
-            rv = sv - omega * tv_[g];
-            rin[g] = rv;
-            e[g] = e[g] + alpha * pold[g] + omega * sv;
+            rin[g] = rq[q];
+            e[g] = e[g] + alpha * poq[q] + omega * sq[q];
         }
         acc[0] += (double)rhat[g] * (double)vv;
-        acc[1] += (double)rv * (double)rv;
+        acc[1] += (double)rq[q] * (double)rq[q];
     }
     double tot;
     block_sum<2>(acc, sh, tot);
@@ -404,12 +449,13 @@ __global__ __launch_bounds__(NT) void k_bicg_a(const DevProb* __restrict__ probs
 
 // alpha = rho / (r^.v); breakdown if r^.v vanishes.
 __global__ __launch_bounds__(NT) void k_epi_a(const DevProb* __restrict__ probs) {
-    __shared__ double sh[NWAVE];
+    __shared__ double sh[NWAVE * 2];
     const DevProb& P = probs[blockIdx.x];
     SolveState* st = P.st;
     if (st->solve_state != SV_RUNNING || st->inner_state != IN_RUNNING) return;
-    const double sig = sum_partials(P.partial, P.ntiles, P.pstride, 0, sh);
-    const double rr = sum_partials(P.partial, P.ntiles, P.pstride, 1, sh);
+    double sums[2];
+    sum_partials_multi<2>(P.partial, P.ntiles, P.pstride, sums, sh);
+    const double sig = sums[0], rr = sums[1];
     if (threadIdx.x != 0) return;
     st->mvp_inner += 1;
     st->sigma = sig;
@@ -425,46 +471,52 @@ __global__ __launch_bounds__(NT) void k_epi_a(const DevProb* __restrict__ probs)
 
 // ----------------------------------------------------- BiCGStab phase B
 template <class Cfg, int DIM, class TI>
-__global__ __launch_bounds__(NT) void k_bicg_b(const DevProb* __restrict__ probs, int nprob) {
+__global__ __launch_bounds__(NT) void k_bicg_b(const DevProb* __restrict__ probs, int nprob, int iter_host) {
     __shared__ TI L[Cfg::BOX];
     __shared__ double sh[NWAVE * 5];
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     const DevProb& P = probs[find_prob(probs, nprob, t)];
-    SolveState* st = P.st;
-    if (st->solve_state != SV_RUNNING || st->inner_state != IN_RUNNING) return;
     const int lt = t - P.tile_begin;
     const TilePos tp = tile_pos<Cfg>(lt, P.tx, P.ty);
     const DevOp& op = P.op;
-    const int cur = st->iter & 1;
-    const TI* v = vp<TI>(P.v[cur]);
-    const TI* rin = vp<TI>(P.rin);
-    const TI* rhat = vp<TI>(P.rhat);
-    TI* s = vp<TI>(P.s);
-    TI* tt_ = vp<TI>(P.t);
-    const TI alpha = (TI)st->alpha;
-    for (int h = threadIdx.x; h < Cfg::BOX; h += NT) {
+    const int cur = iter_host & 1;
+    const TI* __restrict__ v = vp<TI>(P.v[cur]);
+    const TI* __restrict__ rin = vp<TI>(P.rin);
+    const TI* __restrict__ rhat = vp<TI>(P.rhat);
+    TI* __restrict__ s = vp<TI>(P.s);
+    TI* __restrict__ tt_ = vp<TI>(P.t);
+    long long gq[Cfg::PPT];
+    int cq[Cfg::PPT];
+    bool okq[Cfg::PPT];
+    TI rhq[Cfg::PPT], rq[Cfg::PPT], vq[Cfg::PPT];
+#pragma unroll
+    for (int q = 0; q < Cfg::PPT; ++q) {
         int gx, gy, gz;
-        box_coords<Cfg>(h, tp, gx, gy, gz);
-        TI sv = TI(0);
-        if (inside(op, gx, gy, gz)) {
-            const long long g = gidx(op, gx, gy, gz);
-            sv = rin[g] - alpha * v[g];
-        }
-        L[h] = sv;
+        point_coords<Cfg>(q, tp, gx, gy, gz, cq[q]);
+        okq[q] = inside(op, gx, gy, gz);
+        const long long g = okq[q] ? gidx(op, gx, gy, gz) : 0;
+        gq[q] = g;
+        rq[q] = okq[q] ? rin[g] : TI(0);
+        vq[q] = okq[q] ? v[g] : TI(0);
+        rhq[q] = okq[q] ? rhat[g] : TI(0);
     }
+    SolveState* st = P.st;
+    if (st->solve_state != SV_RUNNING || st->inner_state != IN_RUNNING) return;
+    const TI alpha = (TI)st->alpha;
+#pragma unroll
+    for (int q = 0; q < Cfg::PPT; ++q) L[cq[q]] = okq[q] ? rq[q] - alpha * vq[q] : TI(0);
+    fill_halo<Cfg, DIM, TI>(L, tp, op, [&](long long g) -> TI { return rin[g] - alpha * v[g]; });
     __syncthreads();
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < Cfg::PPT; ++q) {
-        int gx, gy, gz, c;
-        point_coords<Cfg>(q, tp, gx, gy, gz, c);
-        if (!inside(op, gx, gy, gz)) continue;
-        const long long g = gidx(op, gx, gy, gz);
-        const TI sv = L[c];
-        const TI tv = stencil_row<Cfg, DIM, TI>(op, L, c, g);
+        if (!okq[q]) continue;
+        const long long g = gq[q];
+        const TI sv = L[cq[q]];
+        const TI tv = stencil_row<Cfg, DIM, TI>(op, L, cq[q], g);
         s[g] = sv;
         tt_[g] = tv;
-        const double rh = (double)rhat[g];
+        const double rh = (double)rhq[q];
         const double sd = (double)sv, td = (double)tv;
         acc[0] += sd * sd;
         acc[1] += td * sd;
@@ -479,12 +531,12 @@ __global__ __launch_bounds__(NT) void k_bicg_b(const DevProb* __restrict__ probs
 
 // omega, the next rho and the exit tests of the iteration.
 __global__ __launch_bounds__(NT) void k_epi_b(const DevProb* __restrict__ probs) {
-    __shared__ double sh[NWAVE];
+    __shared__ double sh[NWAVE * 5];
     const DevProb& P = probs[blockIdx.x];
     SolveState* st = P.st;
     if (st->solve_state != SV_RUNNING || st->inner_state != IN_RUNNING) return;
     double sums[5];
-    for (int i = 0; i < 5; ++i) sums[i] = sum_partials(P.partial, P.ntiles, P.pstride, i, sh);
+    sum_partials_multi<5>(P.partial, P.ntiles, P.pstride, sums, sh);
     if (threadIdx.x != 0) return;
     const double ss = sums[0], ts = sums[1], tt = sums[2], rs = sums[3], rt = sums[4];
     st->mvp_inner += 1;
@@ -526,7 +578,9 @@ __global__ __launch_bounds__(NT) void k_epi_b(const DevProb* __restrict__ probs)
             st->rho_old = st->rho;
             st->rho = rho_new;
         }
+        if (P.mirror) P.mirror->rr = rr;
     }
+    if (P.mirror) P.mirror->iter = st->iter;
     if (st->inner_state != IN_RUNNING) mirror_out(P, st);
 }
 
@@ -588,12 +642,12 @@ static void solve_launch_cfg(int which, const DevProb* probs, int nprob, int tot
             hipLaunchKernelGGL(k_epi_proj_apply, dim3(nprob), block, 0, s, probs);
             break;
         case K_BICG_A:
-            hipLaunchKernelGGL((k_bicg_a<Cfg, DIM, TI>), grid, block, 0, s, probs, nprob);
+            hipLaunchKernelGGL((k_bicg_a<Cfg, DIM, TI>), grid, block, 0, s, probs, nprob, flag);
             if (ev1) (void)hipEventRecord(ev1, s);
             hipLaunchKernelGGL(k_epi_a, dim3(nprob), block, 0, s, probs);
             break;
         case K_BICG_B:
-            hipLaunchKernelGGL((k_bicg_b<Cfg, DIM, TI>), grid, block, 0, s, probs, nprob);
+            hipLaunchKernelGGL((k_bicg_b<Cfg, DIM, TI>), grid, block, 0, s, probs, nprob, flag);
             if (ev1) (void)hipEventRecord(ev1, s);
             hipLaunchKernelGGL(k_epi_b, dim3(nprob), block, 0, s, probs);
             break;

@@ -25,6 +25,8 @@ void launch_fill(double* a, double v, long long n, hipStream_t s);
 void launch_copy(const double* a, double* b, long long n, hipStream_t s);
 
 // fused solve kernels over a problem group
+// flag: the residual kernel's mode (1 first call, 0 cycle end, 2 final check)
+// or, for the BiCGStab phases, the iteration index within the cycle.
 // e0/e1 (may be null): events recorded around the phase kernel (before its
 // epilogue launch) for measurement.
 void launch_solve_kernel(int which, int dim, int inner_f32, int vtype, int tile_id, const DevProb* probs,

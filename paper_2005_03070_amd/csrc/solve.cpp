@@ -90,7 +90,7 @@ static int launch_timed(const Group& g, int which, int cyc, int it) {
     tgdk_ctx ctx = g.ctx;
     const bool timed = (ctx->time_which == 1 && which == K_BICG_A) || (ctx->time_which == 2 && which == K_BICG_B);
     if (!timed) {
-        launch(g, which);
+        launch(g, which, it);
         return TGDK_OK;
     }
     if (ctx->tev_used * 2 + 2 > ctx->tev.size()) {
@@ -107,7 +107,7 @@ static int launch_timed(const Group& g, int which, int cyc, int it) {
     }
     ctx->tev_cyc[k] = cyc;
     ctx->tev_iter[k] = it;
-    launch_solve_kernel(which, g.dim, g.inner_f32, g.vtype, g.tile_id, g.d_probs, g.nprob, g.total_tiles, 0,
+    launch_solve_kernel(which, g.dim, g.inner_f32, g.vtype, g.tile_id, g.d_probs, g.nprob, g.total_tiles, it,
                         ctx->stream, ctx->tev[2 * k], ctx->tev[2 * k + 1]);
     return TGDK_OK;
 }
@@ -144,7 +144,34 @@ static Mirror read_mirror(const Group& g, int j) {
     r.inner_state = m->inner_state;
     r.icyc = m->icyc;
     r.iter = m->iter;
+    r.rr = m->rr;
+    r.rr0 = m->rr0;
+    r.target2 = m->target2;
     return r;
+}
+
+// Iterations the slowest running problem still needs, extrapolating the
+// average residual reduction per iteration of its current cycle (or of the
+// previous cycle early on); also returns that problem's completed iterations.
+static int predict_remaining(const Group& g, double prev_rate, int* observed) {
+    int best = -1;
+    *observed = 0;
+    for (int j = 0; j < g.nprob; ++j) {
+        const Mirror m = read_mirror(g, j);
+        if (m.solve_state != SV_RUNNING || m.inner_state != IN_RUNNING) continue;
+        double rate = prev_rate;
+        if (m.iter >= 2 && m.rr > 0.0 && m.rr0 > 0.0 && m.rr < m.rr0)
+            rate = std::pow(m.rr / m.rr0, 1.0 / m.iter);
+        int rem = 8;
+        if (rate > 0.0 && rate < 0.999 && m.rr > 0.0 && m.target2 > 0.0)
+            rem = m.rr <= m.target2 ? 1 : (int)std::ceil(std::log(m.target2 / m.rr) / std::log(rate));
+        rem = std::max(1, std::min(rem, 64));
+        if (rem > best) {
+            best = rem;
+            *observed = m.iter;
+        }
+    }
+    return best;
 }
 
 static int wait_event(hipEvent_t e) {
@@ -339,7 +366,9 @@ static int bicgstab_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const t
     if (rc) return rc;
     bool any_defl = false;
     for (const auto& p : ps) any_defl |= (p.defl != nullptr);
-    const int B = 8;  // iterations per enqueued batch
+    const int B_MAX = 16;  // largest batch of iterations enqueued at once
+    int first_batch = 4;
+    double prev_rate = 0.0;
     const int max_cycles = prm->ncyc + (prm->max_extra_cycles >= 0 ? prm->max_extra_cycles : prm->ncyc) + 2;
     const int maxit = prm->maxit_cycle > 0 ? prm->maxit_cycle : 100000;
     rc = ensure_events(ctx, 3);
@@ -352,21 +381,50 @@ static int bicgstab_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const t
             launch(g, K_PROJ_DOT);
             launch(g, K_PROJ_APPLY);
         }
-        // inner iterations, one batch ahead of the status check
-        int batches = 0;
-        const int max_batches = maxit / B + 2;
-        for (;;) {
-            for (int i = 0; i < B; ++i) {
-                if ((rc = launch_timed(g, K_BICG_A, cyc, batches * B + i))) return rc;
-                if ((rc = launch_timed(g, K_BICG_B, cyc, batches * B + i))) return rc;
+        // Inner iterations.  At most two batches are outstanding; after the
+        // older one completes the host reads the status mirror, predicts how
+        // many iterations the cycle still needs and enqueues only that many
+        // (launches past the end of a cycle return at once but still cost a
+        // dispatch each).
+        int enq = 0, head = 0, tail = 0;  // iterations enqueued; batch FIFO [head, tail)
+        auto enqueue = [&](int cnt) -> int {
+            for (int i = 0; i < cnt; ++i) {
+                int r2;
+                if ((r2 = launch_timed(g, K_BICG_A, cyc, enq + i))) return r2;
+                if ((r2 = launch_timed(g, K_BICG_B, cyc, enq + i))) return r2;
             }
-            TGDK_HIP(hipEventRecord(ctx->events[batches & 1], s));
-            ++batches;
-            if (batches >= 2) {
-                if ((rc = wait_event(ctx->events[batches & 1]))) return rc;  // the batch before the last
-                if (all_inner_done(g)) break;
+            enq += cnt;
+            TGDK_HIP(hipEventRecord(ctx->events[tail % 2], s));
+            ++tail;
+            return TGDK_OK;
+        };
+        if ((rc = enqueue(std::max(2, std::min(first_batch, B_MAX))))) return rc;
+        while (enq <= maxit + 1) {
+            if ((rc = wait_event(ctx->events[head % 2]))) return rc;
+            ++head;
+            if (all_inner_done(g)) break;
+            int seen = 0;
+            const int rem = predict_remaining(g, prev_rate, &seen);
+            const int want = rem - (enq - seen);
+            if (want > 0 && tail - head < 2) {
+                if ((rc = enqueue(std::min(want, B_MAX)))) return rc;
+            } else if (tail == head) {
+                if ((rc = enqueue(1))) return rc;
             }
-            if (batches > max_batches) break;
+        }
+
+        // next cycle's first batch: half of this cycle's length
+        {
+            int len = 0;
+            double rate = 0.0;
+            for (int j = 0; j < g.nprob; ++j) {
+                const Mirror m = read_mirror(g, j);
+                len = std::max(len, m.iter);
+                if (m.iter > 0 && m.rr0 > 0.0 && m.rr > 0.0 && m.rr < m.rr0)
+                    rate = std::max(rate, std::pow(m.rr / m.rr0, 1.0 / m.iter));
+            }
+            first_batch = std::max(2, len / 2);
+            if (rate > 0.0) prev_rate = rate;
         }
         launch(g, K_FINALIZE);
         launch(g, K_RESIDUAL, 0);

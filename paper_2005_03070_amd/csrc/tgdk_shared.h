@@ -61,6 +61,9 @@ struct SolveState {
 // Host-visible status mirror (in host-mapped memory).
 struct Mirror {
     int solve_state, inner_state, icyc, iter;
+    double rr;       // estimate of ||r_inner||^2 after the last iteration
+    double rr0;      // ||r_inner||^2 at the start of the cycle
+    double target2;  // squared target of the cycle
 };
 
 // One problem of a grouped launch.  All pointers are device pointers.
