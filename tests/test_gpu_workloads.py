@@ -1,0 +1,133 @@
+"""GPU checks at the full sizes of the workloads (3-D 255^3, 32 batched
+right-hand sides and 16 uneven instances, the 1023^2 adjoint).  The oracle
+cannot solve these sizes in seconds, so each check uses properties that hold
+at any size: the true residual recomputed by the oracle's operator on the
+CPU, agreement with the single-system solves, and directional derivatives."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import operators as O, adjoint as ADJ
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+
+
+def tg():
+    import paper_2005_03070_amd as m
+    return m
+
+
+def _t(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def _relres(oop, b, x, transpose=False):
+    r = b - (O.apply_transpose(oop, x) if transpose else O.apply(oop, x))
+    return np.linalg.norm(r) / np.linalg.norm(b)
+
+
+def test_3d_255_fp32_inner_with_fp32_stored_vectors():
+    """255^3 (n = 16.6 M), 7-point, coarse 127^3 GMRES-DR, 40 vectors stored in
+    float32, FP32 inner cycles with FP64 refinement: true residual <= 1e-8."""
+    c = W.CONFIGS["C3"]
+    op = tg().Operator.const_cd(c["n"], c["beta"])
+    b = W.rhs(op.n, c["seed"])
+    solver = tg().TwoGridSolver(op, m=c["m"], k=c["k"], nev=c["nev"], rtolev=1e-4, maxcyc=12,
+                                store=torch.float32)
+    x, reps = solver.solve(_t(b), rtol=1e-8, ncyc=20, precision="fp32_ir", max_extra=40)
+    r = reps[0]
+    assert solver.defl.k >= c["k"] and solver.defl.store == 1
+    oop = O.const_cd(c["n"], c["beta"])
+    rr = _relres(oop, b, x.cpu().numpy())
+    assert r.status == 0 and rr <= 1e-8, (r.status_name, rr)
+    assert abs(rr - r.relres_true) <= 1e-3 * rr
+
+
+def test_batched_32_rhs_511():
+    """32 right-hand sides on 511^2 sharing a 30-vector space, FP32 inner
+    cycles: each meets the tolerance, and two columns equal their single
+    solves bit for bit."""
+    c = W.CONFIGS["C4"]
+    op = tg().Operator.const_cd(c["n"], c["beta"])
+    B = W.rhs_block(op.n, c["seeds"]).T.copy()
+    solver = tg().TwoGridSolver(op, m=c["m"], k=c["k"], nev=c["nev"], rtolev=1e-6, maxcyc=60)
+    solver.setup(_t(B[0]))
+    Bt = _t(B)
+    X, reps = solver.solve(Bt, rtol=1e-8, ncyc=20, precision="fp32_ir")
+    oop = O.const_cd(c["n"], c["beta"])
+    Xh = X.cpu().numpy()
+    for j in range(32):
+        assert reps[j].status == 0
+        assert _relres(oop, B[j], Xh[j]) <= 1e-8
+    for j in (0, 17):
+        xj, rj = solver.solve(Bt[j].contiguous(), rtol=1e-8, ncyc=20, precision="fp32_ir")
+        assert torch.equal(xj, X[j])
+
+
+def test_sixteen_uneven_instances():
+    """16 instances N = 127..511, beta = 10..200, each with its own coarse
+    GMRES-DR space, solved in grouped launches; each meets the tolerance."""
+    insts = W.uneven_instances()
+    ops, spaces, bs, x0s, oops = [], [], [], [], []
+    for d in insts:
+        N, beta = d["N"], d["beta"]
+        op = tg().Operator.const_cd((N, N), (beta, 0.0))
+        b = _t(W.rhs(op.n, d["seed"]))
+        s = tg().TwoGridSolver(op, m=40, k=10, rtolev=1e-5, maxcyc=40)
+        x0s.append(s.setup(b))
+        ops.append(op)
+        spaces.append(s.defl)
+        bs.append(b)
+        oops.append(O.const_cd((N, N), (beta, 0.0)))
+    assert sum(o.n for o in ops) == 1850696
+    xs, reps = tg().solve_instances(ops, spaces, bs, x0s=x0s, rtol=1e-8, ncyc=20, precision="fp32_ir")
+    for j in range(16):
+        assert reps[j].status == 0
+        assert _relres(oops[j], bs[j].cpu().numpy(), xs[j].cpu().numpy()) <= 1e-8
+
+
+def test_adjoint_1023_directional_derivatives():
+    """-div(k grad u) + 60 u_x on 1023^2: the adjoint gradients agree with
+    central differences of the loss along random directions in b and in k,
+    each perturbed solve reaching 1e-12."""
+    c = W.CONFIGS["C5"]
+    dims = c["n"]
+    n = dims[0] * dims[1]
+    k = W.kfield(dims, c["kseed"])
+    b = W.rhs(n, c["bseed"])
+    ustar = W.rhs(n, c["bstar_seed"]) * 1e-4
+    beta = c["beta"]
+    cfg = {"m": c["m"], "k": c["k"], "rtolev": 1e-6, "maxcyc": 60, "solve": {"rtol": 1e-12, "ncyc": 20,
+                                                                            "max_extra": 60}}
+    bt = _t(b).requires_grad_(True)
+    kt = _t(k).requires_grad_(True)
+    u = tg().DeflatedSolve.apply(bt, kt, dims, beta, cfg)
+    L = 0.5 * ((u - _t(ustar)) ** 2).sum()
+    L.backward()
+    gb, gk = bt.grad.cpu().numpy(), kt.grad.cpu().numpy()
+    # the gradient kernel against the oracle's formula on the GPU's u and lambda
+    op = tg().Operator.div_k(dims, _t(k), beta)
+    lam, _ = tg().solve(op, _t(u.detach().cpu().numpy() - ustar), transpose=True, rtol=1e-12, max_extra=200)
+    g_or = ADJ.grad_k(lam.cpu().numpy(), u.detach().cpu().numpy(), dims)
+    assert np.abs(gk - g_or).max() <= 1e-6 * np.abs(g_or).max()
+
+    def loss(bb, kk):
+        opx = tg().Operator.div_k(dims, _t(kk), beta)
+        x, r = tg().solve(opx, _t(bb), rtol=1e-12, max_extra=200)
+        assert r[0].status == 0
+        d = x.cpu().numpy() - ustar
+        return 0.5 * float(d @ d)
+
+    rng = np.random.default_rng(c["dir_seed"])
+    db = rng.standard_normal(n)
+    eps = 1e-3 * np.linalg.norm(b) / np.linalg.norm(db)
+    fd = (loss(b + eps * db, k) - loss(b - eps * db, k)) / (2 * eps)
+    assert abs(fd - gb @ db) <= 1e-5 * abs(fd)
+    dk = rng.standard_normal(k.shape) * k
+    epsk = 1e-4
+    fdk = (loss(b, k + epsk * dk) - loss(b, k - epsk * dk)) / (2 * epsk)
+    assert abs(fdk - (gk * dk).sum()) <= 1e-4 * abs(fdk)
