@@ -135,6 +135,7 @@ extern "C" int tgdk_coarse_setup(tgdk_op op, const double* b, double* x, const t
     const DevOp dop = make_devop(op, tr);
     const int maxcyc = prm->maxcyc > 0 ? prm->maxcyc : 300;
     const double anorm = op_norm1(op, tr);
+    const bool verbose = getenv("TGDK_VERBOSE") != nullptr;
 
     double *V = nullptr, *Vt = nullptr, *w = nullptr, *Hd = nullptr, *dP = nullptr;
     const size_t hsz = (size_t)(m + 1) * m;
@@ -240,9 +241,33 @@ extern "C" int tgdk_coarse_setup(tgdk_op op, const double* b, double* x, const t
         }
         chosen = select_smallest(R.theta, k);
         nconv = 0;
-        for (int i = 0; i < (int)chosen.size() && i < nev; ++i)
-            if (eig_residual(m, Hbar, R, chosen[i]) / anorm <= prm->rtolev) ++nconv;
+        double worst = 0.0;
+        for (int i = 0; i < (int)chosen.size() && i < nev; ++i) {
+            const double er = eig_residual(m, Hbar, R, chosen[i]) / anorm;
+            worst = std::max(worst, er);
+            if (er <= prm->rtolev) ++nconv;
+        }
         const bool done = lin <= prm->rtol * bnorm && nconv >= nev;
+        if (verbose) {
+            double orth = 0.0;
+            if (cyc % 5 == 1 || done) {  // loss of orthogonality of the basis
+                std::vector<double> G((size_t)(m + 1) * (m + 1));
+                double* dG = nullptr;
+                if (m + 1 <= 64 && hipMalloc((void**)&dG, sizeof(double) * G.size()) == hipSuccess &&
+                    ctx->partial.ensure((size_t)gram_blocks(n) * G.size() * sizeof(double)) == TGDK_OK) {
+                    launch_gram(V, 0, n, m + 1, V, 0, n, m + 1, n, dG, (double*)ctx->partial.p, ctx->counters, s);
+                    (void)hipMemcpy(G.data(), dG, sizeof(double) * G.size(), hipMemcpyDeviceToHost);
+                    for (int i = 0; i <= m; ++i)
+                        for (int j = 0; j <= m; ++j)
+                            orth = std::max(orth, std::fabs(G[(size_t)i * (m + 1) + j] - (i == j ? 1.0 : 0.0)));
+                    (void)hipFree(dG);
+                    (void)ctx->partial.ensure((size_t)gs_blocks(n) * (MAXK + 1) * sizeof(double));
+                    part = (double*)ctx->partial.p;
+                }
+            }
+            fprintf(stderr, "[tgdk] gmres-dr cycle %d lin %.3e nconv %d worst %.3e kk %d orth %.1e\n", cyc,
+                    lin / bnorm, nconv, worst, (int)chosen.size(), orth);
+        }
         // real basis of the chosen vectors, then P_{k+1} = qr([G 0; q])
         std::vector<std::vector<double>> cols;
         for (size_t ii = 0; ii < chosen.size();) {

@@ -33,7 +33,7 @@ __global__ __launch_bounds__(NT) void k_apply(DevOp op, const T* __restrict__ x,
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < Cfg::PPT; ++q)
-        if (okq[q]) y[gq[q]] = stencil_row<Cfg, DIM, T>(op, L, cq[q], gq[q]);
+        if (okq[q]) st_stream<DIM>(&y[gq[q]], stencil_row<Cfg, DIM, T>(op, L, cq[q], gq[q]));
 }
 
 template <class Cfg, int DIM, class T>

@@ -431,13 +431,13 @@ __global__ __launch_bounds__(NT) void k_bicg_a(const DevProb* __restrict__ probs
         if (!okq[q]) continue;
         const long long g = gq[q];
         const TI vv = stencil_row<Cfg, DIM, TI>(op, L, cq[q], g);
-        pnew[g] = L[cq[q]];
-        vnew[g] = vv;
+        st_stream<DIM>(&pnew[g], L[cq[q]]);
+        st_stream<DIM>(&vnew[g], vv);
         if (first) {
-            e[g] = TI(0);
+            st_stream<DIM>(&e[g], TI(0));
         } else {
-            rin[g] = rq[q];
-            e[g] = e[g] + alpha * poq[q] + omega * sq[q];
+            st_stream<DIM>(&rin[g], rq[q]);
+            st_stream<DIM>(&e[g], e[g] + alpha * poq[q] + omega * sq[q]);
         }
         acc[0] += (double)rhat[g] * (double)vv;
         acc[1] += (double)rq[q] * (double)rq[q];
@@ -514,8 +514,8 @@ __global__ __launch_bounds__(NT) void k_bicg_b(const DevProb* __restrict__ probs
         const long long g = gq[q];
         const TI sv = L[cq[q]];
         const TI tv = stencil_row<Cfg, DIM, TI>(op, L, cq[q], g);
-        s[g] = sv;
-        tt_[g] = tv;
+        st_stream<DIM>(&s[g], sv);
+        st_stream<DIM>(&tt_[g], tv);
         const double rh = (double)rhq[q];
         const double sd = (double)sv, td = (double)tv;
         acc[0] += sd * sd;

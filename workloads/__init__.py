@@ -51,16 +51,18 @@ def uneven_instances():
 
 
 # Workload table.  "C1" is the small case the oracle finishes in seconds;
-# "C2" is the headline single-GPU configuration.
+# "C2" is the headline single-GPU configuration.  k vectors are kept and moved
+# to the fine grid; GMRES-DR stops once nev = 0.8 k of them have converged (the
+# paper's Example 1 converges 80 of the 100 vectors it keeps).
 CONFIGS = {
     "C1": dict(dim=2, n=(63, 63), beta=(40.0, 0.0), sigma=0.0, seed=1,
-               m=30, k=10, nev=10, rtolev=1e-8, ncyc=20, rtol=1e-8),
+               m=30, k=10, nev=8, rtolev=1e-8, ncyc=20, rtol=1e-8),
     "C2": dict(dim=2, n=(1023, 1023), beta=(100.0, 0.0), sigma=0.0, seed=2,
-               m=80, k=30, nev=30, rtolev=1e-8, ncyc=20, rtol=1e-8, m3=50),
+               m=80, k=30, nev=24, rtolev=1e-8, ncyc=20, rtol=1e-8, m3=50),
     "C3": dict(dim=3, n=(255, 255, 255), beta=(50.0, 20.0, 10.0), sigma=0.0, seed=3,
-               m=90, k=40, nev=40, rtolev=1e-8, ncyc=20, rtol=1e-8),
+               m=90, k=40, nev=32, rtolev=1e-8, ncyc=20, rtol=1e-8),
     "C4": dict(dim=2, n=(511, 511), beta=(100.0, 0.0), sigma=0.0, seeds=list(range(100, 132)),
-               m=80, k=30, nev=30, rtolev=1e-8, ncyc=20, rtol=1e-8),
+               m=80, k=30, nev=24, rtolev=1e-8, ncyc=20, rtol=1e-8),
     "C5": dict(dim=2, n=(1023, 1023), beta=(60.0, 0.0), sigma=0.0, kseed=5, bstar_seed=6,
-               bseed=7, dir_seed=8, m=80, k=30, nev=30, rtolev=1e-8, ncyc=20, rtol=1e-8),
+               bseed=7, dir_seed=8, m=80, k=30, nev=24, rtolev=1e-8, ncyc=20, rtol=1e-8),
 }
