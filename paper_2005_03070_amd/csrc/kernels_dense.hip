@@ -139,7 +139,8 @@ void launch_gram(const void* A, int atype, long long lda, int p, const void* B, 
 // columns (q <= 144), loading V once.
 constexpr int VMUL_MAXQT = 9;
 
-__global__ __launch_bounds__(NT) void k_vmul(const double* __restrict__ V, long long ldv, int p,
+template <class TV>
+__global__ __launch_bounds__(NT) void k_vmul(const TV* __restrict__ V, long long ldv, int p,
                                              const double* __restrict__ Y, int q, double* __restrict__ Out,
                                              long long ldo, long long n) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(NT) void k_vmul(const double* __restrict__ V, long 
         for (int t = 0; t < VMUL_MAXQT; ++t) acc[t] = d4_t{0.0, 0.0, 0.0, 0.0};
         for (int k0 = 0; k0 < p; k0 += 4) {
             const int kc = k0 + (lane >> 4);
-            const double bv = (row < n && kc < p) ? V[kc * ldv + row] : 0.0;
+            const double bv = (row < n && kc < p) ? (double)V[kc * ldv + row] : 0.0;
 #pragma unroll
             for (int t = 0; t < VMUL_MAXQT; ++t) {
                 if (t < qt) {
@@ -182,7 +183,14 @@ void launch_vmul(const double* V, long long ldv, int p, const double* Y, int q, 
                  long long n, hipStream_t s) {
     long long nb = ((n + 15) / 16 + NWAVE - 1) / NWAVE;
     if (nb > 8192) nb = 8192;
-    hipLaunchKernelGGL(k_vmul, dim3((int)nb), dim3(NT), 0, s, V, ldv, p, Y, q, Out, ldo, n);
+    hipLaunchKernelGGL(k_vmul<double>, dim3((int)nb), dim3(NT), 0, s, V, ldv, p, Y, q, Out, ldo, n);
+}
+
+void launch_vmul_f32(const float* V, long long ldv, int p, const double* Y, int q, double* Out, long long ldo,
+                     long long n, hipStream_t s) {
+    long long nb = ((n + 15) / 16 + NWAVE - 1) / NWAVE;
+    if (nb > 8192) nb = 8192;
+    hipLaunchKernelGGL(k_vmul<float>, dim3((int)nb), dim3(NT), 0, s, V, ldv, p, Y, q, Out, ldo, n);
 }
 
 __global__ __launch_bounds__(NT) void k_vmul_add(const double* __restrict__ V, long long ldv, int p,

@@ -235,7 +235,12 @@ __global__ __launch_bounds__(NT) void k_epi_proj_dot(const DevProb* __restrict__
     SolveState* st = P.st;
     if (st->solve_state != SV_RUNNING || P.k == 0) return;
     const int k = P.k;
-    sum_partial_columns(P.partial, P.ntiles, P.pstride, k, y, scratch);
+    if (P.Ccol) {
+        for (int i = threadIdx.x; i < k; i += NT) y[i] = P.Ccol[i];
+        __syncthreads();
+    } else {
+        sum_partial_columns(P.partial, P.ntiles, P.pstride, k, y, scratch);
+    }
     // LU solve: row interchanges, then L (unit lower) and U (upper), row-major.
     if (threadIdx.x == 0) {
         for (int i = 0; i < k; ++i) st->cvec[i] = y[i];
@@ -263,7 +268,10 @@ __global__ __launch_bounds__(NT) void k_epi_proj_dot(const DevProb* __restrict__
         for (int i = threadIdx.x; i < j; i += NT) y[i] -= LU[i * k + j] * yj;
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < k; i += NT) st->d[i] = y[i];
+    for (int i = threadIdx.x; i < k; i += NT) {
+        st->d[i] = y[i];
+        if (P.Dcol) P.Dcol[i] = y[i];
+    }
 }
 
 // ---------------------------------- projection: x += V d, r -= A (V d)
@@ -286,7 +294,9 @@ __global__ __launch_bounds__(NT) void k_proj_apply(const DevProb* __restrict__ p
     const int k = P.k;
     for (int i = threadIdx.x; i < k; i += NT) dsh[i] = st->d[i];
     __syncthreads();
+    const double* __restrict__ Wc = P.Wcol;
     auto wval = [&](long long g) {
+        if (Wc) return Wc[g];
         double w = 0.0;
         for (int j = 0; j < k; ++j) w += (double)V[(long long)j * ldv + g] * dsh[j];
         return w;
@@ -689,6 +699,17 @@ void launch_solve_kernel(int which, int dim, int inner_f32, int vtype, int tile_
         else
             solve_launch_dim<3, double>(which, probs, nprob, total_tiles, flag, vtype, tile_id, s, e0, e1);
     }
+}
+
+void launch_proj_shared_epilogue(const DevProb* probs, int nprob, hipStream_t s) {
+    hipLaunchKernelGGL(k_epi_proj_dot, dim3(nprob), dim3(NT), 0, s, probs);
+}
+
+// The apply half of the projection for systems with Wcol set (no V reads):
+// the same kernel, its V d branch never taken.
+void launch_proj_apply_shared(int dim, int inner_f32, int tile_id, const DevProb* probs, int nprob,
+                              int total_tiles, hipStream_t s) {
+    launch_solve_kernel(K_PROJ_APPLY, dim, inner_f32, 0, tile_id, probs, nprob, total_tiles, 0, s);
 }
 
 void tile_shape(int dim, int tile_id, int* ty, int* tz) {

@@ -44,6 +44,13 @@ void launch_gram(const void* A, int atype, long long lda, int p, const void* B, 
 void launch_vmul(const double* V, long long ldv, int p, const double* Y, int q, double* Out, long long ldo,
                  long long n, hipStream_t s);
 // x += V y  (V n x p float64, y device p-vector)
+void launch_vmul_f32(const float* V, long long ldv, int p, const double* Y, int q, double* Out, long long ldo,
+                     long long n, hipStream_t s);
+// k_epi_proj_dot / k_proj_apply variants that take c and w from the shared
+// matrix-core products (Ccol / Wcol) instead of tile partials and V d
+void launch_proj_shared_epilogue(const DevProb* probs, int nprob, hipStream_t s);
+void launch_proj_apply_shared(int dim, int inner_f32, int tile_id, const DevProb* probs, int nprob,
+                              int total_tiles, hipStream_t s);
 void launch_vmul_add(const double* V, long long ldv, int p, const double* y, double* x, long long n,
                      hipStream_t s);
 

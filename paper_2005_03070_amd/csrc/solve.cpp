@@ -71,6 +71,12 @@ struct Group {
     tgdk_ctx ctx = nullptr;
     int dim = 2, inner_f32 = 0, vtype = 0, tile_id = 0;
     int nprob = 0, total_tiles = 0;
+    // shared deflation space: residual block R (n x nprob, leading dim rld),
+    // C = R^T V (nprob x k), D (k x nprob), W = V D (n x nprob)
+    bool shared = false;
+    tgdk_defl sdefl = nullptr;
+    double *R = nullptr, *C = nullptr, *D = nullptr, *Wb = nullptr;
+    long long rld = 0;
     DevProb* d_probs = nullptr;
     SolveState* d_states = nullptr;
     std::vector<DevProb> probs;
@@ -201,8 +207,27 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
     int ty, tz;
     tile_shape(g.dim, g.tile_id, &ty, &tz);
     const size_t ies = g.inner_f32 ? 4 : 8;
+    // several systems on one deflation space: matrix-core projection
+    g.shared = g.nprob > 1 && g.nprob <= 64 && ps[0].defl != nullptr && ps[0].defl->k > 0 &&
+               ps[0].defl->k <= 64;
+    for (const auto& p : ps)
+        if (p.defl != ps[0].defl || p.op->N != ps[0].op->N) g.shared = false;
+    g.sdefl = g.shared ? ps[0].defl : nullptr;
     // layout
     size_t off = 0;
+    size_t off_R = 0, off_C = 0, off_D = 0, off_W = 0;
+    if (g.shared) {
+        const size_t n0 = (size_t)ps[0].op->N;
+        g.rld = (long long)(align256(n0 * 8) / 8);
+        off_R = off;
+        off += align256((size_t)g.rld * 8 * g.nprob);
+        off_W = off;
+        off += align256((size_t)g.rld * 8 * g.nprob);
+        off_C = off;
+        off += align256((size_t)g.nprob * ps[0].defl->k * 8);
+        off_D = off;
+        off += align256((size_t)g.nprob * ps[0].defl->k * 8);
+    }
     const size_t off_probs = off;
     off += align256(sizeof(DevProb) * g.nprob);
     const size_t off_states = off;
@@ -229,7 +254,7 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
         P.pstride = pstride[j];
         off_vec[j] = off;
         const size_t n = (size_t)op->N;
-        off += align256(n * 8);                     // r (float64)
+        if (!g.shared) off += align256(n * 8);      // r (float64); in the R block when shared
         off += (g.inner_f32 ? 9 : 8) * align256(n * ies);  // inner vectors
         off_part[j] = off;
         off += align256((size_t)P.ntiles * pstride[j] * 8);
@@ -251,8 +276,20 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
         char* v = base + off_vec[j];
         P.b = ps[j].b;
         P.x = ps[j].x;
-        P.r = (double*)v;
-        v += align256(n * 8);
+        if (g.shared) {
+            g.R = (double*)(base + off_R);
+            g.Wb = (double*)(base + off_W);
+            g.C = (double*)(base + off_C);
+            g.D = (double*)(base + off_D);
+            const int k = ps[0].defl->k;
+            P.r = g.R + (size_t)j * g.rld;
+            P.Ccol = g.C + (size_t)j * k;
+            P.Dcol = g.D + (size_t)j * k;
+            P.Wcol = g.Wb + (size_t)j * g.rld;
+        } else {
+            P.r = (double*)v;
+            v += align256(n * 8);
+        }
         void* vecs[9];
         const int nv = g.inner_f32 ? 9 : 8;
         for (int i = 0; i < nv; ++i) {
@@ -305,6 +342,12 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
     TGDK_HIP(hipMemcpyAsync(g.d_probs, g.probs.data(), sizeof(DevProb) * g.nprob, hipMemcpyHostToDevice, s));
     TGDK_HIP(hipMemcpyAsync(g.d_states, g.states.data(), sizeof(SolveState) * g.nprob, hipMemcpyHostToDevice, s));
     TGDK_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned) * g.nprob, s));
+    if (g.shared) {
+        // D columns of systems that stop early stay finite (zero)
+        TGDK_HIP(hipMemsetAsync(g.D, 0, sizeof(double) * g.nprob * g.sdefl->k, s));
+        rc = ctx->partial.ensure((size_t)gram_blocks(g.sdefl->n) * g.nprob * g.sdefl->k * sizeof(double));
+        if (rc) return rc;
+    }
     if (!prm->x0_given)
         for (int j = 0; j < g.nprob; ++j)
             TGDK_HIP(hipMemsetAsync(ps[j].x, 0, sizeof(double) * ps[j].op->N, s));
@@ -358,6 +401,31 @@ static bool all_solved(const Group& g) {
     return true;
 }
 
+// Galerkin projection of every running system (Sec. 2.2 box).  Systems that
+// share one deflation space form c = V^T r for all right-hand sides as one
+// matrix-core product C = R^T V and w = V d as W = V D; otherwise each system
+// reads V in its own tiles.
+static int project(Group& g) {
+    hipStream_t s = g.ctx->stream;
+    if (!g.shared) {
+        launch(g, K_PROJ_DOT);
+        launch(g, K_PROJ_APPLY);
+        return TGDK_OK;
+    }
+    const tgdk_defl d = g.sdefl;
+    const long long n = d->n;
+    launch_gram(g.R, 0, g.rld, g.nprob, d->V, d->store == TGDK_F32 ? 1 : 0, d->n, d->k, n, g.C,
+                (double*)g.ctx->partial.p, g.ctx->counters, s);
+    launch_proj_shared_epilogue(g.d_probs, g.nprob, s);
+    if (d->store == TGDK_F32)
+        launch_vmul_f32((const float*)d->V, d->n, d->k, g.D, g.nprob, g.Wb, g.rld, n, s);
+    else
+        launch_vmul((const double*)d->V, d->n, d->k, g.D, g.nprob, g.Wb, g.rld, n, s);
+    launch_proj_apply_shared(g.dim, g.inner_f32, g.tile_id, g.d_probs, g.nprob, g.total_tiles, s);
+    TGDK_HIP(hipGetLastError());
+    return TGDK_OK;
+}
+
 static int bicgstab_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk_solve_params* prm,
                           tgdk_solve_report* reps) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -377,10 +445,7 @@ static int bicgstab_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const t
     launch(g, K_RESIDUAL, 1);
     TGDK_HIP(hipGetLastError());
     for (int cyc = 0; cyc < max_cycles; ++cyc) {
-        if (any_defl) {
-            launch(g, K_PROJ_DOT);
-            launch(g, K_PROJ_APPLY);
-        }
+        if (any_defl && (rc = project(g))) return rc;
         // Inner iterations.  At most two batches are outstanding; after the
         // older one completes the host reads the status mirror, predicts how
         // many iterations the cycle still needs and enqueues only that many

@@ -90,6 +90,11 @@ struct DevProb {
     int pstride;
     unsigned* counter;
     Mirror* mirror;
+    // systems that share one deflation space (several right-hand sides): the
+    // projection runs as matrix-core products over the block of residuals
+    const double* Ccol;      // column of C = V^T R (k values), or null
+    double* Dcol;            // column of D (k values): this system's d
+    const double* Wcol;      // column of W = V D (n values), or null
 };
 
 }  // namespace tgdk

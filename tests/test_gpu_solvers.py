@@ -186,22 +186,34 @@ def test_gmres_first_cycle_equals_oracle_cycle():
     assert np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo) <= 1e-10
 
 
-def test_batched_rhs_bit_identical_to_single():
-    """Right-hand sides solved together: each column is bit-identical to its
-    single solve (same reductions in the same order)."""
+def test_batched_rhs_independent_of_grouping():
+    """Right-hand sides on one deflation space are projected together (one
+    matrix-core product C = R^T V, one W = V D).  Each column's arithmetic does
+    not depend on the other columns, so a column is bit-identical whichever
+    batch it is solved in; against the single solve (per-tile projection,
+    other summation order) it meets the tolerance in about as many steps."""
     dims, beta = (127, 127), (100.0, 0.0)
     op = tg().Operator.const_cd(dims, beta)
+    oop = O.const_cd(dims, beta)
     n = op.n
     B = np.stack([W.rhs(n, s) for s in (100, 101, 102, 103)])
     Wb = np.stack([W.rhs(n, 500 + i) for i in range(6)])
     space = tg().defl_from_basis(op, _t(Wb))
     for precision in ("fp64", "fp32_ir"):
         X, reps = tg().solve(op, _t(B), defl=space, rtol=1e-9, ncyc=10, precision=precision)
+        for pair in ((0, 2), (3, 1)):
+            Xp, rp = tg().solve(op, _t(B[list(pair)]), defl=space, rtol=1e-9, ncyc=10, precision=precision)
+            for i, j in enumerate(pair):
+                assert torch.equal(X[j], Xp[i]), (precision, j)
+                assert reps[j].mvp_inner == rp[i].mvp_inner
         for j in range(4):
             xj, rj = tg().solve(op, _t(B[j]), defl=space, rtol=1e-9, ncyc=10, precision=precision)
-            assert torch.equal(X[j], xj), (precision, j)
-            assert reps[j].mvp_inner == rj[0].mvp_inner
             assert reps[j].status == 0 and reps[j].relres_true <= 1e-9
+            assert _true_relres(oop, B[j], X[j].cpu().numpy()) <= 1e-9
+            assert rj[0].status == 0 and rj[0].relres_true <= 1e-9
+            # BiCGStab amplifies rounding differences, so the iteration counts
+            # of the two summation orders are close, not equal
+            assert abs(reps[j].mvp_inner - rj[0].mvp_inner) <= 0.15 * rj[0].mvp_inner, (precision, j)
 
 
 def test_instances_bit_identical_to_solo():
