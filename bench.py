@@ -41,22 +41,30 @@ def _args():
 
 def kernel_hash():
     h = hashlib.sha256()
-    for f in ("kernels_krylov.hip", "device_common.h", "tgdk_shared.h"):
+    for f in ("kernels_step.hip", "device_common.h", "tgdk_shared.h"):
         with open(os.path.join(ROOT, "paper_2005_03070_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def traffic_from_profiles():
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, if it was taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "bicg_phase_a_f64_1023sq_counters.json")
+    """HBM bytes per launch of the step kernel from the committed counter
+    summary (FETCH_SIZE scaled by the copy-kernel factor, plus WRITE_SIZE), if
+    it was taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "k_step_f64_1023sq_counters.txt")
     if not os.path.exists(p):
         return None
-    d = json.load(open(p))
-    if d.get("kernel_source_hash") != kernel_hash():
+    kv = {}
+    for line in open(p):
+        if ":" in line and not line.startswith((" ", "#", "`")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -125,23 +133,48 @@ def main():
     head = reps[0]
 
     # ------------------------------------------- live kernel timing (roofline)
-    def timed_kernel(which, **kw):
-        L.check(L.lib().tgdk_ctx_time_kernel(ctx, which))
-        x, r = fine_solve(**kw)
+    # Every step launch of one solve is bracketed by HIP events on the solve's
+    # stream; the library logs what the step did (phase A, phase B, cycle
+    # boundary, ...), and each action has its own algorithmic byte count.
+    import ctypes as C
+    kdefl = space.k
+    w8, v8 = 8, 8  # float64 inner vectors and stored deflation vectors
+    act_bytes = {  # algorithmic HBM bytes per grid point of one launch
+        "A": 10 * w8,               # reads s, t, p, v, e, r^; writes r, e, p, v
+        "A0": 5 * w8,               # reads r, r^; writes p, v, e
+        "B": 5 * w8,                # reads r, v, r^; writes s, t
+        "RES": 8 + 3 * w8 + 8 + kdefl * v8 + 8,    # reads x, e p s, b, V; writes r
+        "REDUCE": 0,                # partial sums only
+        "APPLY": 16 + 3 * w8 + kdefl * v8 + 16 + w8,  # reads x r, e p s, V; writes x r, r^
+        "FIN": 16 + 3 * w8,         # reads x, e p s; writes x
+        "FIN_A0": 16 + 3 * w8 + 5 * w8,
+    }
+    codes = {"A": 1, "A0": 2, "B": 3, "RES": 4, "REDUCE": 5, "APPLY": 6, "FIN": 7, "FIN_A0": 8}
+    L.check(L.lib().tgdk_ctx_time_kernel(ctx, 1))
+    fine_solve()
+    per_act = {}
+    for name, code in codes.items():
         ms = np.zeros(1)
         cnt = np.zeros(1, dtype=np.int64)
-        import ctypes as C
-        L.check(L.lib().tgdk_ctx_kernel_time(ctx, ms.ctypes.data_as(L.DP), cnt.ctypes.data_as(C.POINTER(C.c_longlong))))
-        L.check(L.lib().tgdk_ctx_time_kernel(ctx, 0))
-        return float(ms[0]) / max(int(cnt[0]), 1), int(cnt[0])
-
-    a_ms, a_cnt = timed_kernel(1)
-    b_ms, b_cnt = timed_kernel(2)
-    bytes_a = 10 * 8 * n  # reads s, t, p, v, e, r^; writes r, e, p, v (float64)
-    bytes_b = 5 * 8 * n   # reads r, v, r^; writes s, t
-    ach_a = bytes_a / (a_ms * 1e-3) / 1e9
-    ach_b = bytes_b / (b_ms * 1e-3) / 1e9
-    log(f"phase A {a_ms*1e3:.1f} us x{a_cnt} -> {ach_a:.0f} GB/s; phase B {b_ms*1e3:.1f} us x{b_cnt} -> {ach_b:.0f} GB/s")
+        L.check(L.lib().tgdk_ctx_kernel_time(ctx, code, ms.ctypes.data_as(L.DP),
+                                             cnt.ctypes.data_as(C.POINTER(C.c_longlong))))
+        if cnt[0]:
+            per_act[name] = (float(ms[0]), int(cnt[0]))
+    L.check(L.lib().tgdk_ctx_time_kernel(ctx, 0))
+    tot_ms = sum(v[0] for v in per_act.values())
+    tot_cnt = sum(v[1] for v in per_act.values())
+    tot_bytes = sum(act_bytes[k] * n * v[1] for k, v in per_act.items())
+    step_us = tot_ms * 1e3 / max(tot_cnt, 1)
+    step_bytes = tot_bytes / max(tot_cnt, 1)
+    ach_step = tot_bytes / (tot_ms * 1e-3) / 1e9
+    act_table = {k: {"launches": v[1], "avg_launch_us": v[0] * 1e3 / v[1],
+                     "algorithmic_bytes_per_launch": act_bytes[k] * n,
+                     "achieved_GBs": (act_bytes[k] * n / (v[0] * 1e-3 / v[1]) / 1e9) if act_bytes[k] else None}
+                 for k, v in per_act.items()}
+    log("step kernel: " + ", ".join(f"{k} {v['avg_launch_us']:.1f} us x{v['launches']}"
+                                     + (f" {v['achieved_GBs']:.0f} GB/s" if v["achieved_GBs"] else "")
+                                     for k, v in act_table.items()))
+    log(f"step kernel overall: {step_us:.1f} us/launch, {ach_step:.0f} GB/s algorithmic")
 
     # ------------------------------------------------------------ variants
     variants = {}
@@ -234,13 +267,12 @@ def main():
         "config": {"workload": "2-D conv-diff -Lap(u)+100u_x, 5-pt, fine 1023^2 (n=1,046,529), coarse 511^2, "
                                "GMRES-DR(80,30) -> 30 vectors, BiCGStab(20)-Proj(30) fp64, rtol 1e-8 true residual",
                    "n": n, "k": space.k, "ncyc": c["ncyc"], "seed": c["seed"]},
-        "roofline": {"bound": "hbm", "achieved": ach_a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach_a / HBM_PEAK_GBS, "traffic": traffic_from_profiles(),
-                     "kernel": "k_bicg_a (BiCGStab phase A: stencil + p/r/e updates + r^.v partials), f64",
-                     "algorithmic_bytes_per_launch": bytes_a, "avg_launch_us": a_ms * 1e3,
-                     "launches_timed": a_cnt},
-        "kernels": {"bicg_phase_b_f64": {"avg_launch_us": b_ms * 1e3, "achieved_GBs": ach_b,
-                                         "algorithmic_bytes_per_launch": bytes_b},
+        "roofline": {"bound": "hbm", "achieved": ach_step, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach_step / HBM_PEAK_GBS, "traffic": traffic_from_profiles(),
+                     "kernel": "k_step (BiCGStab step: phase A / phase B / cycle boundary), f64, one solve",
+                     "algorithmic_bytes_per_launch": step_bytes, "avg_launch_us": step_us,
+                     "launches_timed": tot_cnt},
+        "kernels": {"step_by_action": act_table,
                     "stencil_1023sq_f64_GBs": st_c2, "stencil_255cube_f32_GBs": st_c3},
         "solve": {"relres_true": rr, "cycles": head.cycles, "mvp_inner": head.mvp_inner,
                   "mvp_boundary": head.mvp_boundary, "min_s": min(times), "max_s": max(times)},

@@ -74,15 +74,25 @@ int tgdk_ctx_create(tgdk_ctx* out, int device, void* hip_stream);
 int tgdk_ctx_destroy(tgdk_ctx ctx);
 /* Number of compute units of the context's device (for launch sizing). */
 int tgdk_ctx_num_cus(tgdk_ctx ctx);
-/* Measurement hook.  which = 1 (BiCGStab phase A: stencil fused with the
- * p/r/e updates and the r^.v partials) or 2 (phase B: stencil fused with the
- * s update and five dot-product partials); 0 switches timing off.  While on,
- * each launch of that kernel inside tgdk_solve / tgdk_solve_instances is
- * bracketed by HIP events on the context stream (this adds a little launch
- * overhead).  tgdk_ctx_kernel_time returns the summed duration in ms and the
- * number of launches that did work since the last call, then resets both. */
-int tgdk_ctx_time_kernel(tgdk_ctx ctx, int which);
-int tgdk_ctx_kernel_time(tgdk_ctx ctx, double* total_ms, long long* launches);
+/* Measurement hook.  on = 1 brackets every launch of the BiCGStab step
+ * kernel inside tgdk_solve / tgdk_solve_instances with HIP events on the
+ * context stream (this adds a little launch overhead) and logs what the
+ * group's first problem did in each launch; on = 0 switches it off.  Both
+ * calls clear the totals.  tgdk_ctx_kernel_time returns, for one action
+ * (TGDK_STEP_*), the summed duration in ms of the launches in which the first
+ * problem did it and their number; TGDK_STEP_ANY sums every launch in which it
+ * did work.  Actions: */
+#define TGDK_STEP_A      1  /* phase A of iteration i > 0: r, e, p updates, v = A p, r^.v and ||r||^2 partials */
+#define TGDK_STEP_A0     2  /* phase A of iteration 0 of a cycle (p = r) */
+#define TGDK_STEP_B      3  /* phase B: s = r - alpha v, t = A s, five dot-product partials */
+#define TGDK_STEP_RES    4  /* end of a cycle: r = b - A (x + update), ||r||^2 and c = V^T r partials */
+#define TGDK_STEP_REDUCE 5  /* c summed and H d = c solved (one workgroup) */
+#define TGDK_STEP_APPLY  6  /* x += update + V d, r -= A V d, new shadow vector */
+#define TGDK_STEP_FIN    7  /* final update folded into x */
+#define TGDK_STEP_FIN_A0 8  /* update folded into x and phase A of iteration 0 (no deflation) */
+#define TGDK_STEP_ANY   -1
+int tgdk_ctx_time_kernel(tgdk_ctx ctx, int on);
+int tgdk_ctx_kernel_time(tgdk_ctx ctx, int action, double* total_ms, long long* launches);
 
 /* ---------------------------------------------------------------- operators
  * The discretised operator of Sec. 1 / Sec. 3 Example 1: centred finite

@@ -69,7 +69,7 @@ SIGNATURES = [
     ("tgdk_ctx_destroy", I, [P]),
     ("tgdk_ctx_num_cus", I, [P]),
     ("tgdk_ctx_time_kernel", I, [P, I]),
-    ("tgdk_ctx_kernel_time", I, [P, DP, C.POINTER(C.c_longlong)]),
+    ("tgdk_ctx_kernel_time", I, [P, I, DP, C.POINTER(C.c_longlong)]),
     ("tgdk_op_create", I, [P, C.POINTER(OpDesc), PP]),
     ("tgdk_op_coarsen", I, [P, PP]),
     ("tgdk_op_apply", I, [P, I, I, P, P, I]),

@@ -206,17 +206,28 @@ int defl_finish(tgdk_op op, int transpose, double* V64, int k, int store, tgdk_d
         delete d;
         return fail(TGDK_E_SINGULAR, "projection matrix H = V^T A V is singular");
     }
-    if ((rc = dev_alloc(&d->d_lu, (size_t)k * k)) || (rc = dev_alloc(&d->d_piv, (size_t)k))) {
+    // H^{-1} column by column from the LU factors (column-major)
+    std::vector<double> hinv((size_t)k * k, 0.0);
+    for (int j = 0; j < k; ++j) {
+        double* col = hinv.data() + (size_t)j * k;
+        col[j] = 1.0;
+        lu_solve(k, d->LU.data(), d->piv.data(), col);
+    }
+    if ((rc = dev_alloc(&d->d_lu, (size_t)k * k)) || (rc = dev_alloc(&d->d_piv, (size_t)k)) ||
+        (rc = dev_alloc(&d->d_hinv, (size_t)k * k))) {
         if (V32) (void)hipFree(V32);
         if (d->d_lu) (void)hipFree(d->d_lu);
+        if (d->d_piv) (void)hipFree(d->d_piv);
         delete d;
         return rc;
     }
     if (hipMemcpy(d->d_lu, d->LU.data(), (size_t)k * k * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d->d_piv, d->piv.data(), (size_t)k * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(d->d_piv, d->piv.data(), (size_t)k * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d->d_hinv, hinv.data(), (size_t)k * k * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
         if (V32) (void)hipFree(V32);
         (void)hipFree(d->d_lu);
         (void)hipFree(d->d_piv);
+        (void)hipFree(d->d_hinv);
         delete d;
         return fail(TGDK_E_HIP, "upload of LU failed");
     }
@@ -276,21 +287,34 @@ int tgdk_ctx_destroy(tgdk_ctx c) {
 
 int tgdk_ctx_num_cus(tgdk_ctx c) { return c ? c->num_cus : 0; }
 
-int tgdk_ctx_time_kernel(tgdk_ctx c, int which) {
-    if (!c || which < 0 || which > 2) return fail(TGDK_E_INVALID, "bad argument");
-    c->time_which = which;
+static_assert(TGDK_STEP_A == ACT_A && TGDK_STEP_A0 == ACT_A0 && TGDK_STEP_B == ACT_B && TGDK_STEP_RES == ACT_RES &&
+                  TGDK_STEP_REDUCE == ACT_REDUCE && TGDK_STEP_APPLY == ACT_APPLY && TGDK_STEP_FIN == ACT_FIN &&
+                  TGDK_STEP_FIN_A0 == ACT_FIN_A0 && NACT == 9,
+              "step action codes");
+
+int tgdk_ctx_time_kernel(tgdk_ctx c, int on) {
+    if (!c || on < 0 || on > 1) return fail(TGDK_E_INVALID, "bad argument");
+    c->time_which = on;
     c->tev_used = 0;
-    c->time_ms = 0.0;
-    c->time_count = 0;
+    for (int a = 0; a < NACT; ++a) {
+        c->act_ms[a] = 0.0;
+        c->act_count[a] = 0;
+    }
     return TGDK_OK;
 }
 
-int tgdk_ctx_kernel_time(tgdk_ctx c, double* total_ms, long long* launches) {
+int tgdk_ctx_kernel_time(tgdk_ctx c, int action, double* total_ms, long long* launches) {
     if (!c) return fail(TGDK_E_INVALID, "NULL context");
-    if (total_ms) *total_ms = c->time_ms;
-    if (launches) *launches = c->time_count;
-    c->time_ms = 0.0;
-    c->time_count = 0;
+    if (action != TGDK_STEP_ANY && (action < 1 || action >= NACT)) return fail(TGDK_E_INVALID, "unknown action");
+    double ms = 0.0;
+    long long cnt = 0;
+    for (int a = 1; a < NACT; ++a)
+        if (action == TGDK_STEP_ANY || action == a) {
+            ms += c->act_ms[a];
+            cnt += c->act_count[a];
+        }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = cnt;
     return TGDK_OK;
 }
 
@@ -522,6 +546,7 @@ int tgdk_defl_destroy(tgdk_defl d) {
     if (d->V) (void)hipFree(d->V);
     if (d->d_lu) (void)hipFree(d->d_lu);
     if (d->d_piv) (void)hipFree(d->d_piv);
+    if (d->d_hinv) (void)hipFree(d->d_hinv);
     delete d;
     return TGDK_OK;
 }

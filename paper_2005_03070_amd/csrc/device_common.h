@@ -9,8 +9,9 @@
 //   contiguous range of tiles so the halo rows a tile shares with its
 //   neighbours are read through the same L2.
 // * Deterministic reductions: wave butterflies and a fixed LDS combine give a
-//   per-tile partial; a one-workgroup epilogue launch sums the partials in
-//   tile order.  No atomics and no device-scope fences (on a multi-XCD part
+//   per-workgroup partial; the next launch sums the partials in a fixed order
+//   (a one-workgroup epilogue, or every workgroup of the step kernel
+//   redundantly).  No atomics and no device-scope fences (on a multi-XCD part
 //   an agent-scope release writes back the L2, which would serialise
 //   thousands of workgroups); the kernel boundary makes the partials visible.
 #pragma once
@@ -292,6 +293,56 @@ __device__ __forceinline__ void sum_partial_columns(const double* __restrict__ p
         out[threadIdx.x] = s;
     }
     __syncthreads();
+}
+
+// Sums values 0..NV-1 of a value-major partial array (value v of workgroup t
+// at part[v * nwg + t]) over t = 0..nwg-1 in a fixed order; every thread
+// receives the totals, and every workgroup that calls this on the same array
+// gets the same bits.  sh needs NWAVE*NV doubles.
+template <int NV>
+__device__ __forceinline__ void sum_values(const double* __restrict__ part, int nwg, double (&out)[NV], double* sh) {
+    double a[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a[v] = 0.0;
+    // the first four rounds with every load issued before the adds (clamped
+    // addresses, masked values); more workgroups than 4 * NT in a tail loop
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int t = threadIdx.x + r * NT;
+        const int tc = t < nwg ? t : 0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double x = part[(long long)v * nwg + tc];
+            a[v] += t < nwg ? x : 0.0;
+        }
+    }
+    for (int t = threadIdx.x + 4 * NT; t < nwg; t += NT) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a[v] += part[(long long)v * nwg + t];
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double s = wave_sum(a[v]);
+        if (lane == 0) sh[w * NV + v] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double s = sh[v];
+        for (int w2 = 1; w2 < NWAVE; ++w2) s += sh[w2 * NV + v];
+        out[v] = s;
+    }
+    __syncthreads();
+}
+
+template <class T>
+__device__ __forceinline__ T* vp(void* p) {
+    return reinterpret_cast<T*>(p);
+}
+template <class T>
+__device__ __forceinline__ const T* vp(const void* p) {
+    return reinterpret_cast<const T*>(p);
 }
 
 // Problem lookup for grouped launches (linear scan; groups are small).

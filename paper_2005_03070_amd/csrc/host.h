@@ -46,13 +46,13 @@ struct tgdk_ctx_s {
     tgdk::Mirror* mirror = nullptr;  // host-mapped
     int mirror_cap = 0;
     std::vector<hipEvent_t> events;
-    // kernel timing for measurement (0 off, 1 BiCGStab phase A, 2 phase B)
+    // step-kernel timing for measurement (0 off, 1 on)
     int time_which = 0;
-    std::vector<hipEvent_t> tev;        // event pairs
-    std::vector<int> tev_cyc, tev_iter;  // cycle and iteration of each timed launch
+    std::vector<hipEvent_t> tev;   // event pairs
+    std::vector<int> tev_slot;     // launch number of each timed launch
     size_t tev_used = 0;
-    double time_ms = 0.0;
-    long long time_count = 0;
+    double act_ms[tgdk::NACT] = {0};          // summed duration per action of the first problem
+    long long act_count[tgdk::NACT] = {0};
 };
 
 struct tgdk_op_s {
@@ -84,6 +84,7 @@ struct tgdk_defl_s {
     std::vector<int> piv;
     double* d_lu = nullptr;
     int* d_piv = nullptr;
+    double* d_hinv = nullptr;  // H^{-1}, column-major
 };
 
 namespace tgdk {

@@ -186,13 +186,6 @@ void launch_vmul(const double* V, long long ldv, int p, const double* Y, int q, 
     hipLaunchKernelGGL(k_vmul<double>, dim3((int)nb), dim3(NT), 0, s, V, ldv, p, Y, q, Out, ldo, n);
 }
 
-void launch_vmul_f32(const float* V, long long ldv, int p, const double* Y, int q, double* Out, long long ldo,
-                     long long n, hipStream_t s) {
-    long long nb = ((n + 15) / 16 + NWAVE - 1) / NWAVE;
-    if (nb > 8192) nb = 8192;
-    hipLaunchKernelGGL(k_vmul<float>, dim3((int)nb), dim3(NT), 0, s, V, ldv, p, Y, q, Out, ldo, n);
-}
-
 __global__ __launch_bounds__(NT) void k_vmul_add(const double* __restrict__ V, long long ldv, int p,
                                                  const double* __restrict__ y, double* __restrict__ x, long long n) {
     __shared__ double ys[MAXK + 1];

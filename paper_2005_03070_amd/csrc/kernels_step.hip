@@ -1,0 +1,701 @@
+// BiCGStab(ncyc)-Proj(k) step kernel: the fine-grid cycle of the Sec. 2.2
+// box, with the restarted BiCGStab inner solver of Sec. 4.1 (van der Vorst's
+// recurrences).
+//
+// One launch advances every running problem of a group (right-hand sides or
+// grid instances) by one step of its own state machine; the host only
+// enqueues launches.  A BiCGStab iteration takes two steps:
+//
+//   phase A (iteration i):  r_i = s_{i-1} - w t_{i-1};  e += a p_{i-1} + w s_{i-1};
+//                           p_i = r_i + beta (p_{i-1} - w v_{i-1});  v_i = A p_i;
+//                           partials r^.v_i, ||r_i||^2
+//   phase B:                s_i = r_i - alpha v_i;  t_i = A s_i;
+//                           partials s.s, t.s, t.t, r^.s, r^.t
+//
+// Each phase recomputes its stencil input (p_i or s_i) on the tile halo from
+// the previous vectors, so the update and the stencil share one pass.  There
+// are no epilogue launches: at the start of a step every workgroup of a
+// problem sums the previous step's per-workgroup partials (the same values in
+// the same order, hence the same bits in every workgroup) and takes the
+// scalar decisions itself -- alpha = rho / r^.v; omega = t.s / t.t;
+// ||r_{i+1}||^2 = s.s - 2 w t.s + w^2 t.t; rho_{i+1} = r^.s - w r^.t; the
+// inner convergence and breakdown tests.  The problem's lead workgroup stores
+// the resulting state for the next launch (double-buffered by launch parity),
+// the counters of the report and the host-visible status mirror.
+//
+// When an inner cycle ends, the same step evaluates the true residual of the
+// updated iterate, r = b - A (x + e + a p + w s) in float64, with the
+// partials of ||r||^2, ||b||^2 and c = V^T r.  The next step takes the
+// boundary decisions (Sec. 4.1 steps 3-4) and, in the lead workgroup, sums c
+// and solves H d = c with the LU factors of H.  The step after it applies
+// x <- x + e + a p + w s + V d and r <- r - A V d and writes the new inner
+// residual and shadow vector; the first phase A of the next cycle shares its
+// launch with the test of that residual.  Problems advance independently: one
+// may sit at a cycle boundary while another iterates.
+#include "device_common.h"
+#include "launch.h"
+
+namespace tgdk {
+
+// Workgroups per problem: one per tile up to this cap, beyond it each
+// workgroup walks several tiles (bounds the partials every workgroup sums).
+constexpr int STEP_WG_CAP = 1024;
+
+int step_workgroups(int ntiles) { return ntiles < STEP_WG_CAP ? ntiles : STEP_WG_CAP; }
+
+// pending x update: x += e + a p + w s (p from buffer pbuf)
+struct Upd {
+    double a, w;
+    int any, pbuf;
+};
+
+// Sec. 4.1 step 3 b): the relative tolerance of the inner cycle that starts
+// from a residual of norm nu; returns the branch taken (1, 2 or 3).
+__device__ __forceinline__ int cycle_start(StepHot& N, const SolveState* st, double nu, double rho0, double& rt) {
+    int branch;
+    const int ncyc = st->ncyc;
+    if (N.icyc > ncyc) {
+        rt = N.tau / nu;
+        branch = 3;
+    } else {
+        const double t1 = pow(N.tau / nu, 1.0 / (double)(ncyc - N.icyc + 1));
+        const double t2 = (N.nu0 / nu) * pow(N.tau / N.nu0, (double)N.icyc / (double)ncyc);
+        if (t1 <= t2) {
+            rt = t1;
+            branch = 1;
+        } else {
+            rt = t2;
+            branch = 2;
+        }
+    }
+    if (st->precision == 1 && rt < st->fp32_floor) rt = st->fp32_floor;
+    N.target2 = (rt * nu) * (rt * nu);
+    N.rho = rho0;
+    N.rho_old = 1.0;
+    N.alpha = 1.0;
+    N.omega = 1.0;
+    N.iter = 0;
+    N.inner_state = IN_RUNNING;
+    N.upd_any = 0;
+    return branch;
+}
+
+// Tests on the true residual nu = ||b - A x|| at a cycle boundary (or at the
+// start of the solve): Sec. 4.1 steps 1 and 4; the cycle count goes up if the
+// solve continues.
+__device__ __forceinline__ void boundary_tests(const StepHot& H, StepHot& N, const SolveState* st, double nu,
+                                               double bb) {
+    if (H.first) {
+        N.bnorm = sqrt(bb);
+        N.nu0 = nu;
+        N.tau = st->rtol * fmin(N.bnorm, nu);
+        if (!isfinite(nu))
+            N.solve_state = SV_NONFINITE;
+        else if (nu <= N.tau || nu == 0.0)
+            N.solve_state = SV_CONVERGED;
+    } else {
+        const bool broke = H.inner_state == IN_BREAK_NOUPD || H.inner_state == IN_BREAK_FULL;
+        if (!isfinite(nu))
+            N.solve_state = SV_NONFINITE;
+        else if (nu <= N.tau)
+            N.solve_state = SV_CONVERGED;
+        else if (broke && H.iter == 0)
+            N.solve_state = SV_BREAKDOWN;
+        else if (H.icyc >= st->ncyc + st->max_extra)
+            N.solve_state = SV_NOT_CONVERGED;
+    }
+    N.first = 0;
+    if (N.solve_state == SV_RUNNING) N.icyc = H.icyc + 1;
+}
+
+// The scalar part of a step.  Every workgroup of the problem evaluates it on
+// the same inputs; only the scribe (thread 0 of the lead workgroup) writes
+// the report counters.  Returns the action of this launch.
+__device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* st, int k, int gslot, bool scribe,
+                           StepHot& N, Upd& U, double& rr_out, double& rr0_out) {
+    N = H;
+    U = Upd{H.upd_a, H.upd_w, H.upd_any, H.pbuf};
+    const int after_res = k > 0 ? M_REDUCE : M_APPLY0;
+    auto end_cycle = [&](int inner, double a, double w, int any, int pbuf) {
+        N.inner_state = inner;
+        U = Upd{a, w, any, pbuf};
+        N.upd_a = a;
+        N.upd_w = w;
+        N.upd_any = any;
+        N.pbuf = pbuf;
+        N.mode = after_res;
+        return ACT_RES;
+    };
+    switch (H.mode) {
+        case M_RES:
+            N.mode = after_res;
+            return ACT_RES;
+        case M_B: {  // phase A partials: r^.v, ||r_i||^2
+            const double sig = s[0];
+            if (scribe) {
+                st->mvp_inner += 1;
+                st->sigma = sig;
+                st->rr_last = s[1];
+            }
+            if (sig == 0.0 || !isfinite(sig)) return end_cycle(IN_BREAK_NOUPD, 0.0, 0.0, H.iter != 0, 0);
+            N.alpha = H.rho / sig;
+            N.mode = M_A;
+            return ACT_B;
+        }
+        case M_A: {  // phase B partials: s.s, t.s, t.t, r^.s, r^.t
+            const double ss = s[0], ts = s[1], tt = s[2], rs = s[3], rt = s[4];
+            N.iter = H.iter + 1;
+            const int pb = ((gslot - 2) >> 1) & 1;  // p of the iteration just finished
+            const int hi = scribe ? st->nhist : NHIST;
+            if (scribe) {
+                st->mvp_inner += 1;
+                st->iters_total += 1;
+            }
+            if (ss <= H.target2) {
+                if (hi < NHIST) {
+                    st->hist[3 * hi] = H.rho;
+                    st->hist[3 * hi + 1] = H.alpha;
+                    st->hist[3 * hi + 2] = __builtin_nan("");
+                    st->nhist = hi + 1;
+                }
+                rr_out = ss;
+                return end_cycle(IN_HALF, H.alpha, 0.0, 1, pb);
+            }
+            const double omega = (tt != 0.0) ? ts / tt : 0.0;
+            N.omega = omega;
+            if (hi < NHIST) {
+                st->hist[3 * hi] = H.rho;
+                st->hist[3 * hi + 1] = H.alpha;
+                st->hist[3 * hi + 2] = omega;
+                st->nhist = hi + 1;
+            }
+            if (omega == 0.0 || !isfinite(omega)) return end_cycle(IN_BREAK_FULL, H.alpha, omega, 1, pb);
+            double rr = ss - 2.0 * omega * ts + omega * omega * tt;
+            if (rr < 0.0) rr = 0.0;
+            rr_out = rr;
+            const double rho_new = rs - omega * rt;
+            if (rr <= H.target2) return end_cycle(IN_CONVERGED, H.alpha, omega, 1, pb);
+            if (rho_new == 0.0 || !isfinite(rho_new)) return end_cycle(IN_BREAK_FULL, H.alpha, omega, 1, pb);
+            if (N.iter >= st->maxit) return end_cycle(IN_MAXIT, H.alpha, omega, 1, pb);
+            N.rho_old = H.rho;
+            N.rho = rho_new;
+            N.mode = M_B;
+            return ACT_A;
+        }
+        case M_REDUCE:    // true residual partials: ||r||^2, ||b||^2 (c summed by the lead)
+        case M_APPLY0: {  // the same plus r^.r in the inner type (no deflation)
+            const double nu = sqrt(s[0]);
+            boundary_tests(H, N, st, nu, s[1]);
+            if (scribe) {
+                st->mvp_boundary += 1;
+                st->nu = nu;
+                if (!H.first && H.icyc >= 1 && H.icyc <= NCYCLOG) {
+                    st->cyc_iters[H.icyc - 1] = H.iter;
+                    st->cyc_end[H.icyc - 1] = H.inner_state;
+                }
+            }
+            if (N.solve_state != SV_RUNNING) {
+                N.mode = M_DONE;
+                return H.upd_any ? ACT_FIN : ACT_NONE;
+            }
+            if (H.mode == M_REDUCE) {
+                N.mode = M_APPLY;
+                return ACT_REDUCE;
+            }
+            double rt;
+            const int br = cycle_start(N, st, nu, s[2], rt);
+            if (scribe) {
+                st->branch[br] += 1;
+                st->rt = rt;
+            }
+            rr0_out = rr_out = s[0];
+            N.mode = M_B;
+            return H.upd_any ? ACT_FIN_A0 : ACT_A0;
+        }
+        case M_APPLY:
+            N.mode = M_START;
+            N.upd_any = 0;
+            return ACT_APPLY;
+        case M_START: {  // after the projection: ||r||^2, r^.r in the inner type
+            const double nu = sqrt(s[0]);
+            if (scribe) {
+                st->mvp_boundary += 1;
+                st->nu = nu;
+            }
+            if (!isfinite(nu))
+                N.solve_state = SV_NONFINITE;
+            else if (nu <= N.tau)
+                N.solve_state = SV_CONVERGED;
+            if (N.solve_state != SV_RUNNING) {
+                N.mode = M_DONE;
+                return ACT_NONE;
+            }
+            double rt;
+            const int br = cycle_start(N, st, nu, s[1], rt);
+            if (scribe) {
+                st->branch[br] += 1;
+                st->rt = rt;
+            }
+            rr0_out = rr_out = s[0];
+            N.mode = M_B;
+            return ACT_A0;
+        }
+        default:
+            return ACT_NONE;
+    }
+}
+
+// x + e + a p + w s at global index g (the folded inner update, float64).
+template <class TI>
+__device__ __forceinline__ double upd_at(const DevProb& P, const Upd& U, long long g) {
+    double u = (double)vp<const TI>(P.e)[g];
+    if (U.a != 0.0) u += U.a * (double)vp<const TI>(P.p[U.pbuf])[g];
+    if (U.w != 0.0) u += U.w * (double)vp<const TI>(P.s)[g];
+    return u;
+}
+
+// Value-major partial output: value v of this workgroup.
+__device__ __forceinline__ double* part_at(const DevProb& P, int slot, int v, int lw) {
+    return P.partial + (long long)slot * P.pslot + (long long)v * P.nwg + lw;
+}
+
+// ------------------------------------------------------------ phase A
+template <class Cfg, int DIM, class TI>
+__device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, bool first, bool fin, const StepHot& N,
+                                        const Upd& U, TI* L, double* sh) {
+    const DevOp& op = P.op;
+    const int pb = (gslot >> 1) & 1;
+    TI* __restrict__ pnew = vp<TI>(P.p[pb]);
+    const TI* __restrict__ pold = vp<const TI>(P.p[pb ^ 1]);
+    TI* __restrict__ vnew = vp<TI>(P.v[pb]);
+    const TI* __restrict__ vold = vp<const TI>(P.v[pb ^ 1]);
+    TI* rin = vp<TI>(P.rin);
+    const TI* __restrict__ rhat = vp<const TI>(P.rhat);
+    const TI* __restrict__ sv_ = vp<const TI>(P.s);
+    const TI* __restrict__ tv_ = vp<const TI>(P.t);
+    TI* e = vp<TI>(P.e);
+    const TI alpha = (TI)N.alpha, omega = (TI)N.omega;
+    const TI beta = first ? TI(0) : (TI)((N.rho / N.rho_old) * (N.alpha / N.omega));
+    double acc[2] = {0.0, 0.0};
+    for (int tile = lw; tile < P.ntiles; tile += P.nwg) {
+        const TilePos tp = tile_pos<Cfg>(tile, P.tx, P.ty);
+        long long gq[Cfg::PPT];
+        int cq[Cfg::PPT];
+        bool okq[Cfg::PPT];
+        TI rq[Cfg::PPT], sq[Cfg::PPT], poq[Cfg::PPT];
+#pragma unroll
+        for (int q = 0; q < Cfg::PPT; ++q) {
+            int gx, gy, gz;
+            point_coords<Cfg>(q, tp, gx, gy, gz, cq[q]);
+            okq[q] = inside(op, gx, gy, gz);
+            const long long g = okq[q] ? gidx(op, gx, gy, gz) : 0;
+            gq[q] = g;
+            TI pv = TI(0);
+            rq[q] = sq[q] = poq[q] = TI(0);
+            if (okq[q]) {
+                if (fin) P.x[g] += upd_at<TI>(P, U, g);
+                if (first) {
+                    rq[q] = rin[g];
+                    pv = rq[q];
+                } else {
+                    sq[q] = sv_[g];
+                    poq[q] = pold[g];
+                    rq[q] = sq[q] - omega * tv_[g];
+                    pv = rq[q] + beta * (poq[q] - omega * vold[g]);
+                }
+            }
+            L[cq[q]] = pv;
+        }
+        fill_halo<Cfg, DIM, TI>(L, tp, op, [&](long long g) -> TI {
+            if (first) return rin[g];
+            const TI rv = sv_[g] - omega * tv_[g];
+            return rv + beta * (pold[g] - omega * vold[g]);
+        });
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Cfg::PPT; ++q) {
+            if (!okq[q]) continue;
+            const long long g = gq[q];
+            const TI vv = stencil_row<Cfg, DIM, TI>(op, L, cq[q], g);
+            st_stream<DIM>(&pnew[g], L[cq[q]]);
+            st_stream<DIM>(&vnew[g], vv);
+            if (first) {
+                st_stream<DIM>(&e[g], TI(0));
+            } else {
+                st_stream<DIM>(&rin[g], rq[q]);
+                st_stream<DIM>(&e[g], e[g] + alpha * poq[q] + omega * sq[q]);
+            }
+            acc[0] += (double)rhat[g] * (double)vv;
+            acc[1] += (double)rq[q] * (double)rq[q];
+        }
+        __syncthreads();
+    }
+    double tot;
+    block_sum<2>(acc, sh, tot);
+    if (threadIdx.x < 2) *part_at(P, gslot & 1, threadIdx.x, lw) = tot;
+}
+
+// ------------------------------------------------------------ phase B
+template <class Cfg, int DIM, class TI>
+__device__ __forceinline__ void phase_b(const DevProb& P, int lw, int gslot, const StepHot& N, TI* L, double* sh) {
+    const DevOp& op = P.op;
+    const int pb = ((gslot - 1) >> 1) & 1;  // v of this iteration's phase A
+    const TI* __restrict__ v = vp<const TI>(P.v[pb]);
+    const TI* __restrict__ rin = vp<const TI>(P.rin);
+    const TI* __restrict__ rhat = vp<const TI>(P.rhat);
+    TI* __restrict__ s = vp<TI>(P.s);
+    TI* __restrict__ tt_ = vp<TI>(P.t);
+    const TI alpha = (TI)N.alpha;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int tile = lw; tile < P.ntiles; tile += P.nwg) {
+        const TilePos tp = tile_pos<Cfg>(tile, P.tx, P.ty);
+        long long gq[Cfg::PPT];
+        int cq[Cfg::PPT];
+        bool okq[Cfg::PPT];
+        TI rhq[Cfg::PPT];
+#pragma unroll
+        for (int q = 0; q < Cfg::PPT; ++q) {
+            int gx, gy, gz;
+            point_coords<Cfg>(q, tp, gx, gy, gz, cq[q]);
+            okq[q] = inside(op, gx, gy, gz);
+            const long long g = okq[q] ? gidx(op, gx, gy, gz) : 0;
+            gq[q] = g;
+            rhq[q] = okq[q] ? rhat[g] : TI(0);
+            L[cq[q]] = okq[q] ? rin[g] - alpha * v[g] : TI(0);
+        }
+        fill_halo<Cfg, DIM, TI>(L, tp, op, [&](long long g) -> TI { return rin[g] - alpha * v[g]; });
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Cfg::PPT; ++q) {
+            if (!okq[q]) continue;
+            const long long g = gq[q];
+            const TI sv = L[cq[q]];
+            const TI tv = stencil_row<Cfg, DIM, TI>(op, L, cq[q], g);
+            st_stream<DIM>(&s[g], sv);
+            st_stream<DIM>(&tt_[g], tv);
+            const double rh = (double)rhq[q];
+            const double sd = (double)sv, td = (double)tv;
+            acc[0] += sd * sd;
+            acc[1] += td * sd;
+            acc[2] += td * td;
+            acc[3] += rh * sd;
+            acc[4] += rh * td;
+        }
+        __syncthreads();
+    }
+    double tot;
+    block_sum<5>(acc, sh, tot);
+    if (threadIdx.x < 5) *part_at(P, gslot & 1, threadIdx.x, lw) = tot;
+}
+
+// ------------------------------------------- true residual at a boundary
+// r = b - A x' with x' = x + e + a p + w s formed on the fly (x is written in
+// a later step, so neighbouring tiles still read the old x).  Partials:
+// ||r||^2, ||b||^2, r^.r in the inner type (no deflation: the next cycle's
+// inner residual and shadow vector are written here), and c = V^T r.
+template <class Cfg, int DIM, class TI, class TV>
+__device__ __forceinline__ void true_residual(const DevProb& P, int lw, int gslot, const Upd& U, double* L,
+                                              double* sh, double* csum) {
+    const DevOp& op = P.op;
+    const int k = P.k;
+    const bool start = k == 0;
+    TI* rin = vp<TI>(P.rin);
+    TI* rhat = vp<TI>(P.rhat);
+    const bool sep = (void*)rin != (void*)P.r;
+    const TV* __restrict__ V = vp<const TV>(P.V);
+    const long long ldv = P.ldv;
+    const double* __restrict__ x = P.x;
+    const double* __restrict__ b = P.b;
+    auto xval = [&](long long g) -> double { return U.any ? x[g] + upd_at<TI>(P, U, g) : x[g]; };
+    for (int i = threadIdx.x; i < k; i += NT) csum[i] = 0.0;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int tile = lw; tile < P.ntiles; tile += P.nwg) {
+        const TilePos tp = tile_pos<Cfg>(tile, P.tx, P.ty);
+        long long gq[Cfg::PPT];
+        int cq[Cfg::PPT];
+        bool okq[Cfg::PPT];
+        double bq[Cfg::PPT], rv[Cfg::PPT];
+#pragma unroll
+        for (int q = 0; q < Cfg::PPT; ++q) {
+            int gx, gy, gz;
+            point_coords<Cfg>(q, tp, gx, gy, gz, cq[q]);
+            okq[q] = inside(op, gx, gy, gz);
+            gq[q] = okq[q] ? gidx(op, gx, gy, gz) : 0;
+            L[cq[q]] = okq[q] ? xval(gq[q]) : 0.0;
+            bq[q] = okq[q] ? b[gq[q]] : 0.0;
+        }
+        fill_halo<Cfg, DIM, double>(L, tp, op, xval);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Cfg::PPT; ++q) {
+            rv[q] = 0.0;
+            if (!okq[q]) continue;
+            const long long g = gq[q];
+            const double r = bq[q] - stencil_row<Cfg, DIM, double>(op, L, cq[q], g);
+            rv[q] = r;
+            P.r[g] = r;
+            acc[0] += r * r;
+            acc[1] += bq[q] * bq[q];
+            if (start) {
+                const TI ri = (TI)r;
+                if (sep) rin[g] = ri;
+                rhat[g] = ri;
+                acc[2] += (double)ri * (double)ri;
+            }
+        }
+        if (k > 0) {
+            // c partial: r goes to LDS in tile order; wave w forms columns
+            // w, w + 4, ... with coalesced row reads of V
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < Cfg::PPT; ++q) L[threadIdx.x + q * NT] = rv[q];
+            __syncthreads();
+            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+            for (int j = w; j < k; j += NWAVE) {
+                const TV* __restrict__ Vj = V + (long long)j * ldv;
+                double a = 0.0;
+#pragma unroll 8
+                for (int m = 0; m < Cfg::PTS / 64; ++m) {
+                    const int l = lane + 64 * m;
+                    const int gx = tp.x0 + lane, gy = tp.y0 + (l / 64) % Cfg::TY, gz = tp.z0 + l / (64 * Cfg::TY);
+                    if (inside(op, gx, gy, gz)) a += (double)Vj[gidx(op, gx, gy, gz)] * L[l];
+                }
+                a = wave_sum(a);
+                if (lane == 0) csum[j] += a;
+            }
+        }
+        __syncthreads();
+    }
+    double tot;
+    block_sum<3>(acc, sh, tot);
+    const int slot = gslot & 1;
+    if (threadIdx.x < 3) *part_at(P, slot, threadIdx.x, lw) = tot;
+    for (int i = threadIdx.x; i < k; i += NT) *part_at(P, slot, 3 + i, lw) = csum[i];
+}
+
+// -------------------------------------------- projection coefficients
+// Lead workgroup: c = V^T r summed over the workgroups, then d = H^{-1} c
+// with the inverse formed on the host from the LU factors of H (one parallel
+// pass instead of 2k dependent substitution steps).
+__device__ __forceinline__ void projection_coefficients(const DevProb& P, int gslot, SolveState* st, double* y,
+                                                        double* sh) {
+    const int k = P.k;
+    const int nwg = P.nwg;
+    const double* part = P.partial + (long long)((gslot & 1) ^ 1) * P.pslot + 3LL * nwg;
+    // wave w sums columns w, w + 4, ...; lane l takes workgroups l, l + 64, ...
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int c = w; c < k; c += NWAVE) {
+        const double* col = part + (long long)c * nwg;
+        double a = 0.0;
+#pragma unroll 4
+        for (int t = lane; t < nwg; t += 64) a += col[t];
+        a = wave_sum(a);
+        if (lane == 0) y[c] = a;
+    }
+    __syncthreads();
+    const double* __restrict__ X = P.hinv;  // column-major k x k
+    if (threadIdx.x < k) {
+        const int i = threadIdx.x;
+        double di = 0.0;
+        for (int j = 0; j < k; ++j) di += X[(long long)j * k + i] * y[j];
+        st->d[i] = di;
+        st->cvec[i] = y[i];
+    }
+}
+
+// ----------------------------------------------- projection applied
+// w = V d on the tile and its halo (LDS, float64); x <- x + upd + w and
+// r <- r - A w on the tile; the new cycle's inner residual and shadow vector;
+// partials ||r||^2 and r^.r in the inner type.
+template <class Cfg, int DIM, class TI, class TV>
+__device__ __forceinline__ void apply_projection(const DevProb& P, int lw, int gslot, const Upd& U,
+                                                 const SolveState* st, double* L, double* sh, double* dsh) {
+    const DevOp& op = P.op;
+    const int k = P.k;
+    const TV* __restrict__ V = vp<const TV>(P.V);
+    const long long ldv = P.ldv;
+    TI* rin = vp<TI>(P.rin);
+    TI* rhat = vp<TI>(P.rhat);
+    const bool sep = (void*)rin != (void*)P.r;
+    for (int i = threadIdx.x; i < k; i += NT) dsh[i] = st->d[i];
+    __syncthreads();
+    auto wval = [&](long long g) {
+        double w = 0.0;
+        for (int j = 0; j < k; ++j) w += (double)V[(long long)j * ldv + g] * dsh[j];
+        return w;
+    };
+    double acc[2] = {0.0, 0.0};
+    for (int tile = lw; tile < P.ntiles; tile += P.nwg) {
+        const TilePos tp = tile_pos<Cfg>(tile, P.tx, P.ty);
+        long long gq[Cfg::PPT];
+        int cq[Cfg::PPT];
+        bool okq[Cfg::PPT];
+#pragma unroll
+        for (int q = 0; q < Cfg::PPT; ++q) {
+            int gx, gy, gz;
+            point_coords<Cfg>(q, tp, gx, gy, gz, cq[q]);
+            okq[q] = inside(op, gx, gy, gz);
+            gq[q] = okq[q] ? gidx(op, gx, gy, gz) : 0;
+            L[cq[q]] = okq[q] ? wval(gq[q]) : 0.0;
+        }
+        fill_halo<Cfg, DIM, double>(L, tp, op, wval);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Cfg::PPT; ++q) {
+            if (!okq[q]) continue;
+            const long long g = gq[q];
+            const int c = cq[q];
+            double xv = P.x[g];
+            if (U.any) xv += upd_at<TI>(P, U, g);
+            P.x[g] = xv + L[c];
+            const double rv = P.r[g] - stencil_row<Cfg, DIM, double>(op, L, c, g);
+            P.r[g] = rv;
+            acc[0] += rv * rv;
+            const TI ri = (TI)rv;
+            if (sep) rin[g] = ri;
+            rhat[g] = ri;
+            acc[1] += (double)ri * (double)ri;
+        }
+        __syncthreads();
+    }
+    double tot;
+    block_sum<2>(acc, sh, tot);
+    if (threadIdx.x < 2) *part_at(P, gslot & 1, threadIdx.x, lw) = tot;
+}
+
+// x <- x + e + a p + w s on this workgroup's tiles (the solve stops here).
+template <class Cfg, class TI>
+__device__ __forceinline__ void fold_update(const DevProb& P, int lw, const Upd& U) {
+    const DevOp& op = P.op;
+    for (int tile = lw; tile < P.ntiles; tile += P.nwg) {
+        const TilePos tp = tile_pos<Cfg>(tile, P.tx, P.ty);
+#pragma unroll
+        for (int q = 0; q < Cfg::PPT; ++q) {
+            int gx, gy, gz, c;
+            point_coords<Cfg>(q, tp, gx, gy, gz, c);
+            if (!inside(op, gx, gy, gz)) continue;
+            const long long g = gidx(op, gx, gy, gz);
+            P.x[g] += upd_at<TI>(P, U, g);
+        }
+    }
+}
+
+// ------------------------------------------------------------- kernel
+template <class Cfg, int DIM, class TI, class TV>
+__global__ __launch_bounds__(NT) void k_step(const DevProb* __restrict__ probs, const int* __restrict__ wg_prob,
+                                             int gslot) {
+    __shared__ double Lbox[Cfg::BOX];
+    __shared__ double sh[NWAVE * 16];
+    __shared__ double ysh[MAXK + 1];
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const DevProb& P = probs[wg_prob[wg]];
+    const int lw = wg - P.wg_begin;
+    const bool lead = lw == 0;
+    const bool scribe = lead && threadIdx.x == 0;
+    const int cur = gslot & 1;
+    SolveState* st = P.st;
+    const StepHot H = st->hot[cur ^ 1];
+    double s5[5];
+    sum_values<5>(P.partial + (long long)(cur ^ 1) * P.pslot, P.nwg, s5, sh);
+    StepHot N;
+    Upd U;
+    double rr = -1.0, rr0 = -1.0;
+    const int act = step_decide(H, s5, st, P.k, gslot, scribe, N, U, rr, rr0);
+    if (scribe) {
+        st->hot[cur] = N;
+        st->solve_state = N.solve_state;
+        st->inner_state = N.inner_state;
+        st->icyc = N.icyc;
+        st->iter = N.iter;
+        st->tau = N.tau;
+        st->bnorm = N.bnorm;
+        st->nu0 = N.nu0;
+        if (P.actlog && gslot < NSLOTLOG) P.actlog[gslot] = (unsigned char)act;
+        if (P.mirror && (act != ACT_NONE || H.mode != M_DONE)) {
+            Mirror* m = P.mirror;
+            m->solve_state = N.solve_state;
+            m->inner_state = N.inner_state;
+            m->icyc = N.icyc;
+            m->iter = N.iter;
+            m->mode = N.mode;
+            m->slot = gslot;
+            m->target2 = N.target2;
+            if (rr >= 0.0) m->rr = rr;
+            if (rr0 >= 0.0) m->rr0 = rr0;
+        }
+    }
+    TI* L = reinterpret_cast<TI*>(Lbox);
+    switch (act) {
+        case ACT_A:
+            phase_a<Cfg, DIM, TI>(P, lw, gslot, false, false, N, U, L, sh);
+            break;
+        case ACT_A0:
+            phase_a<Cfg, DIM, TI>(P, lw, gslot, true, false, N, U, L, sh);
+            break;
+        case ACT_FIN_A0:
+            phase_a<Cfg, DIM, TI>(P, lw, gslot, true, true, N, U, L, sh);
+            break;
+        case ACT_B:
+            phase_b<Cfg, DIM, TI>(P, lw, gslot, N, L, sh);
+            break;
+        case ACT_RES:
+            true_residual<Cfg, DIM, TI, TV>(P, lw, gslot, U, Lbox, sh, ysh);
+            break;
+        case ACT_REDUCE:
+            if (lead) projection_coefficients(P, gslot, st, ysh, sh);
+            break;
+        case ACT_APPLY:
+            apply_projection<Cfg, DIM, TI, TV>(P, lw, gslot, U, st, Lbox, sh, ysh);
+            break;
+        case ACT_FIN:
+            fold_update<Cfg, TI>(P, lw, U);
+            break;
+        default:
+            break;
+    }
+}
+
+// ------------------------------------------------------------ launcher
+template <class Cfg, int DIM, class TI>
+static void step_cfg(int vtype, const DevProb* probs, const int* wg_prob, int total_wg, int gslot, hipStream_t s) {
+    if (vtype == 1)
+        hipLaunchKernelGGL((k_step<Cfg, DIM, TI, float>), dim3(total_wg), dim3(NT), 0, s, probs, wg_prob, gslot);
+    else
+        hipLaunchKernelGGL((k_step<Cfg, DIM, TI, double>), dim3(total_wg), dim3(NT), 0, s, probs, wg_prob, gslot);
+}
+
+template <int DIM, class TI>
+static void step_dim(int vtype, int tile_id, const DevProb* probs, const int* wg_prob, int total_wg, int gslot,
+                     hipStream_t s) {
+    if (DIM == 2) {
+        switch (tile_id) {
+            case 1: step_cfg<Tile<2, 8, 1>, 2, TI>(vtype, probs, wg_prob, total_wg, gslot, s); break;
+            case 2: step_cfg<Tile<2, 4, 1>, 2, TI>(vtype, probs, wg_prob, total_wg, gslot, s); break;
+            default: step_cfg<Tile<2, 16, 1>, 2, TI>(vtype, probs, wg_prob, total_wg, gslot, s); break;
+        }
+    } else {
+        switch (tile_id) {
+            case 1: step_cfg<Tile<3, 8, 4>, 3, TI>(vtype, probs, wg_prob, total_wg, gslot, s); break;
+            case 2: step_cfg<Tile<3, 4, 8>, 3, TI>(vtype, probs, wg_prob, total_wg, gslot, s); break;
+            default: step_cfg<Tile<3, 4, 4>, 3, TI>(vtype, probs, wg_prob, total_wg, gslot, s); break;
+        }
+    }
+}
+
+void launch_step(int dim, int inner_f32, int vtype, int tile_id, const DevProb* probs, const int* wg_prob,
+                 int total_wg, int gslot, hipStream_t s) {
+    if (total_wg <= 0) return;
+    if (dim == 2) {
+        if (inner_f32)
+            step_dim<2, float>(vtype, tile_id, probs, wg_prob, total_wg, gslot, s);
+        else
+            step_dim<2, double>(vtype, tile_id, probs, wg_prob, total_wg, gslot, s);
+    } else {
+        if (inner_f32)
+            step_dim<3, float>(vtype, tile_id, probs, wg_prob, total_wg, gslot, s);
+        else
+            step_dim<3, double>(vtype, tile_id, probs, wg_prob, total_wg, gslot, s);
+    }
+}
+
+}  // namespace tgdk

@@ -7,7 +7,7 @@
 
 namespace tgdk {
 
-enum : int { K_RESIDUAL = 0, K_PROJ_DOT = 1, K_PROJ_APPLY = 2, K_BICG_A = 3, K_BICG_B = 4, K_FINALIZE = 5 };
+enum : int { K_RESIDUAL = 0, K_PROJ_DOT = 1, K_PROJ_APPLY = 2 };
 
 // grid kernels
 template <class T>
@@ -24,15 +24,19 @@ void launch_grad_k(int nx, int ny, const double* lam, const double* u, double* g
 void launch_fill(double* a, double v, long long n, hipStream_t s);
 void launch_copy(const double* a, double* b, long long n, hipStream_t s);
 
-// fused solve kernels over a problem group
+// tile kernels over a problem group (GMRES-Proj driver, final residual)
 // flag: the residual kernel's mode (1 first call, 0 cycle end, 2 final check)
-// or, for the BiCGStab phases, the iteration index within the cycle.
-// e0/e1 (may be null): events recorded around the phase kernel (before its
-// epilogue launch) for measurement.
 void launch_solve_kernel(int which, int dim, int inner_f32, int vtype, int tile_id, const DevProb* probs,
-                         int nprob, int total_tiles, int flag, hipStream_t s, hipEvent_t e0 = nullptr,
-                         hipEvent_t e1 = nullptr);
+                         int nprob, int total_tiles, int flag, hipStream_t s);
 void tile_shape(int dim, int tile_id, int* ty, int* tz);
+
+// BiCGStab step kernel: one launch advances every running problem of the
+// group by one step of its state machine.  wg_prob maps a workgroup id to its
+// problem; gslot is the launch number within the solve.
+void launch_step(int dim, int inner_f32, int vtype, int tile_id, const DevProb* probs, const int* wg_prob,
+                 int total_wg, int gslot, hipStream_t s);
+// workgroups the step kernel gives a problem of ntiles tiles
+int step_workgroups(int ntiles);
 
 // tall-skinny products (column-major blocks, leading dimensions in elements)
 // G (p x q, row-major, device) = A^T B, A: n x p, B: n x q; partial workspace
@@ -44,13 +48,6 @@ void launch_gram(const void* A, int atype, long long lda, int p, const void* B, 
 void launch_vmul(const double* V, long long ldv, int p, const double* Y, int q, double* Out, long long ldo,
                  long long n, hipStream_t s);
 // x += V y  (V n x p float64, y device p-vector)
-void launch_vmul_f32(const float* V, long long ldv, int p, const double* Y, int q, double* Out, long long ldo,
-                     long long n, hipStream_t s);
-// k_epi_proj_dot / k_proj_apply variants that take c and w from the shared
-// matrix-core products (Ccol / Wcol) instead of tile partials and V d
-void launch_proj_shared_epilogue(const DevProb* probs, int nprob, hipStream_t s);
-void launch_proj_apply_shared(int dim, int inner_f32, int tile_id, const DevProb* probs, int nprob,
-                              int total_tiles, hipStream_t s);
 void launch_vmul_add(const double* V, long long ldv, int p, const double* y, double* x, long long n,
                      hipStream_t s);
 

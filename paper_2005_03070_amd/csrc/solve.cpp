@@ -2,12 +2,11 @@
 // (right-hand sides sharing an operator, or independent grid instances) and
 // GMRES(m)-Proj(k) for one right-hand side.
 //
-// The host only enqueues: every scalar decision (alpha, omega, cycle
-// tolerance, convergence, breakdown) is taken on the device by the kernels'
-// epilogues.  Inner iterations are enqueued in batches; the host watches a
-// host-mapped status mirror one batch behind, so the GPU queue never drains
-// while the host decides whether a cycle has ended.  Launches that follow the
-// end of a cycle find the problem finished and return at once.
+// BiCGStab: the host only enqueues step launches; every scalar decision
+// (alpha, omega, cycle tolerance, convergence, breakdown, projection) is
+// taken on the device by the step kernel.  The host watches a host-mapped
+// status mirror one batch behind, so the GPU queue never drains while it
+// decides how many more steps to enqueue.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,8 +20,6 @@
 #include "host.h"
 
 namespace tgdk {
-
-enum : int { SV_NONFINITE_H = 4 };
 
 struct ProbSpec {
     tgdk_op op;
@@ -38,7 +35,7 @@ static int status_of(const SolveState& st) {
         case SV_CONVERGED: return TGDK_OK;
         case SV_BREAKDOWN: return TGDK_BREAKDOWN;
         case SV_NOT_CONVERGED: return TGDK_NOT_CONVERGED;
-        case SV_NONFINITE_H: return TGDK_E_NONFINITE;
+        case SV_NONFINITE: return TGDK_E_NONFINITE;
         default: return TGDK_NOT_CONVERGED;
     }
 }
@@ -71,16 +68,15 @@ struct Group {
     tgdk_ctx ctx = nullptr;
     int dim = 2, inner_f32 = 0, vtype = 0, tile_id = 0;
     int nprob = 0, total_tiles = 0;
-    // shared deflation space: residual block R (n x nprob, leading dim rld),
-    // C = R^T V (nprob x k), D (k x nprob), W = V D (n x nprob)
-    bool shared = false;
-    tgdk_defl sdefl = nullptr;
-    double *R = nullptr, *C = nullptr, *D = nullptr, *Wb = nullptr;
-    long long rld = 0;
+    int total_wg = 0;      // step kernel workgroups
+    int gslot = 0;         // step launches enqueued so far
     DevProb* d_probs = nullptr;
     SolveState* d_states = nullptr;
+    int* d_wgprob = nullptr;
+    unsigned char* d_actlog = nullptr;  // action log of problem 0 (measurement only)
     std::vector<DevProb> probs;
     std::vector<SolveState> states;
+    std::vector<int> wgprob;
     Mirror* mirror = nullptr;
 };
 
@@ -89,14 +85,12 @@ static void launch(const Group& g, int which, int flag = 0) {
                         g.ctx->stream);
 }
 
-// A launch of the timed kernel: events around it, tagged with its cycle and
-// iteration so launches that found the cycle already finished can be told
-// apart afterwards.
-static int launch_timed(const Group& g, int which, int cyc, int it) {
+// One step launch; with measurement on, bracketed by events on the stream.
+static int launch_step_timed(Group& g) {
     tgdk_ctx ctx = g.ctx;
-    const bool timed = (ctx->time_which == 1 && which == K_BICG_A) || (ctx->time_which == 2 && which == K_BICG_B);
-    if (!timed) {
-        launch(g, which, it);
+    const int slot = g.gslot++;
+    if (!ctx->time_which) {
+        launch_step(g.dim, g.inner_f32, g.vtype, g.tile_id, g.d_probs, g.d_wgprob, g.total_wg, slot, ctx->stream);
         return TGDK_OK;
     }
     if (ctx->tev_used * 2 + 2 > ctx->tev.size()) {
@@ -107,39 +101,33 @@ static int launch_timed(const Group& g, int which, int cyc, int it) {
         }
     }
     const size_t k = ctx->tev_used++;
-    if (ctx->tev_cyc.size() <= k) {
-        ctx->tev_cyc.resize(k + 1);
-        ctx->tev_iter.resize(k + 1);
-    }
-    ctx->tev_cyc[k] = cyc;
-    ctx->tev_iter[k] = it;
-    launch_solve_kernel(which, g.dim, g.inner_f32, g.vtype, g.tile_id, g.d_probs, g.nprob, g.total_tiles, it,
-                        ctx->stream, ctx->tev[2 * k], ctx->tev[2 * k + 1]);
+    if (ctx->tev_slot.size() <= k) ctx->tev_slot.resize(k + 1);
+    ctx->tev_slot[k] = slot;
+    TGDK_HIP(hipEventRecord(ctx->tev[2 * k], ctx->stream));
+    launch_step(g.dim, g.inner_f32, g.vtype, g.tile_id, g.d_probs, g.d_wgprob, g.total_wg, slot, ctx->stream);
+    TGDK_HIP(hipEventRecord(ctx->tev[2 * k + 1], ctx->stream));
     return TGDK_OK;
 }
 
-// Adds the durations of the timed launches that did work (per the device's
-// per-cycle iteration log) to the context's totals.
-static void collect_timing(Group& g) {
+// Adds the durations of the timed step launches to the context's totals,
+// per action of the group's first problem (from the device's action log).
+static int collect_timing(Group& g) {
     tgdk_ctx ctx = g.ctx;
+    std::vector<unsigned char> act(NSLOTLOG, 0);
+    if (g.d_actlog) {
+        TGDK_HIP(hipMemcpy(act.data(), g.d_actlog, NSLOTLOG, hipMemcpyDeviceToHost));
+    }
     for (size_t k = 0; k < ctx->tev_used; ++k) {
-        const int c = ctx->tev_cyc[k], i = ctx->tev_iter[k];
-        int real = 0;
-        for (int j = 0; j < g.nprob; ++j) {
-            const SolveState& S = g.states[j];
-            if (c >= NCYCLOG || c >= S.icyc) continue;
-            int r = S.cyc_iters[c];
-            if (ctx->time_which == 1 && S.cyc_end[c] == IN_BREAK_NOUPD) r += 1;
-            real = std::max(real, r);
-        }
-        if (i >= real) continue;
+        const int slot = ctx->tev_slot[k];
+        if (slot >= NSLOTLOG) continue;
+        const int a = act[slot];
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, ctx->tev[2 * k], ctx->tev[2 * k + 1]) == hipSuccess) {
-            ctx->time_ms += ms;
-            ctx->time_count += 1;
-        }
+        if (hipEventElapsedTime(&ms, ctx->tev[2 * k], ctx->tev[2 * k + 1]) != hipSuccess) continue;
+        ctx->act_ms[a] += ms;
+        ctx->act_count[a] += 1;
     }
     ctx->tev_used = 0;
+    return TGDK_OK;
 }
 
 // Host-mapped mirror values are written by the device; read them volatile.
@@ -150,34 +138,12 @@ static Mirror read_mirror(const Group& g, int j) {
     r.inner_state = m->inner_state;
     r.icyc = m->icyc;
     r.iter = m->iter;
+    r.mode = m->mode;
+    r.slot = m->slot;
     r.rr = m->rr;
     r.rr0 = m->rr0;
     r.target2 = m->target2;
     return r;
-}
-
-// Iterations the slowest running problem still needs, extrapolating the
-// average residual reduction per iteration of its current cycle (or of the
-// previous cycle early on); also returns that problem's completed iterations.
-static int predict_remaining(const Group& g, double prev_rate, int* observed) {
-    int best = -1;
-    *observed = 0;
-    for (int j = 0; j < g.nprob; ++j) {
-        const Mirror m = read_mirror(g, j);
-        if (m.solve_state != SV_RUNNING || m.inner_state != IN_RUNNING) continue;
-        double rate = prev_rate;
-        if (m.iter >= 2 && m.rr > 0.0 && m.rr0 > 0.0 && m.rr < m.rr0)
-            rate = std::pow(m.rr / m.rr0, 1.0 / m.iter);
-        int rem = 8;
-        if (rate > 0.0 && rate < 0.999 && m.rr > 0.0 && m.target2 > 0.0)
-            rem = m.rr <= m.target2 ? 1 : (int)std::ceil(std::log(m.target2 / m.rr) / std::log(rate));
-        rem = std::max(1, std::min(rem, 64));
-        if (rem > best) {
-            best = rem;
-            *observed = m.iter;
-        }
-    }
-    return best;
 }
 
 static int wait_event(hipEvent_t e) {
@@ -207,27 +173,8 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
     int ty, tz;
     tile_shape(g.dim, g.tile_id, &ty, &tz);
     const size_t ies = g.inner_f32 ? 4 : 8;
-    // several systems on one deflation space: matrix-core projection
-    g.shared = g.nprob > 1 && g.nprob <= 64 && ps[0].defl != nullptr && ps[0].defl->k > 0 &&
-               ps[0].defl->k <= 64;
-    for (const auto& p : ps)
-        if (p.defl != ps[0].defl || p.op->N != ps[0].op->N) g.shared = false;
-    g.sdefl = g.shared ? ps[0].defl : nullptr;
     // layout
     size_t off = 0;
-    size_t off_R = 0, off_C = 0, off_D = 0, off_W = 0;
-    if (g.shared) {
-        const size_t n0 = (size_t)ps[0].op->N;
-        g.rld = (long long)(align256(n0 * 8) / 8);
-        off_R = off;
-        off += align256((size_t)g.rld * 8 * g.nprob);
-        off_W = off;
-        off += align256((size_t)g.rld * 8 * g.nprob);
-        off_C = off;
-        off += align256((size_t)g.nprob * ps[0].defl->k * 8);
-        off_D = off;
-        off += align256((size_t)g.nprob * ps[0].defl->k * 8);
-    }
     const size_t off_probs = off;
     off += align256(sizeof(DevProb) * g.nprob);
     const size_t off_states = off;
@@ -235,9 +182,8 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
     const size_t off_counters = off;
     off += align256(sizeof(unsigned) * g.nprob);
     std::vector<size_t> off_vec(g.nprob), off_part(g.nprob);
-    std::vector<int> pstride(g.nprob);
     g.probs.assign(g.nprob, DevProb());
-    int tiles = 0;
+    int tiles = 0, wgs = 0;
     for (int j = 0; j < g.nprob; ++j) {
         const tgdk_op op = ps[j].op;
         DevProb& P = g.probs[j];
@@ -249,17 +195,27 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
         P.ntiles = P.tx * P.ty * P.tz;
         P.tile_begin = tiles;
         tiles += P.ntiles;
+        P.nwg = step_workgroups(P.ntiles);
+        P.wg_begin = wgs;
+        wgs += P.nwg;
         P.k = ps[j].defl ? ps[j].defl->k : 0;
-        pstride[j] = std::max(8, P.k);
-        P.pstride = pstride[j];
+        // partial values per workgroup: at most 3 + k (true residual and c)
+        P.pstride = std::max(8, 3 + P.k);
+        P.pslot = (long long)P.pstride * P.nwg;
         off_vec[j] = off;
         const size_t n = (size_t)op->N;
-        if (!g.shared) off += align256(n * 8);      // r (float64); in the R block when shared
+        off += align256(n * 8);                            // r (float64)
         off += (g.inner_f32 ? 9 : 8) * align256(n * ies);  // inner vectors
         off_part[j] = off;
-        off += align256((size_t)P.ntiles * pstride[j] * 8);
+        // tile kernels: ntiles rows; step kernel: two launch-parity slots
+        off += align256((size_t)std::max((long long)P.ntiles * P.pstride, 2 * P.pslot) * 8);
     }
     g.total_tiles = tiles;
+    g.total_wg = wgs;
+    const size_t off_wgprob = off;
+    off += align256(sizeof(int) * (size_t)wgs);
+    const size_t off_actlog = off;
+    if (ctx->time_which) off += align256(NSLOTLOG);
     int rc = ctx->solve_ws.ensure(off);
     if (rc) return rc;
     rc = ensure_mirror(ctx, g.nprob);
@@ -267,29 +223,22 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
     char* base = (char*)ctx->solve_ws.p;
     g.d_probs = (DevProb*)(base + off_probs);
     g.d_states = (SolveState*)(base + off_states);
+    g.d_wgprob = (int*)(base + off_wgprob);
+    g.d_actlog = ctx->time_which ? (unsigned char*)(base + off_actlog) : nullptr;
     unsigned* counters = (unsigned*)(base + off_counters);
     g.mirror = ctx->mirror;
     g.states.assign(g.nprob, SolveState());
+    std::vector<int>& wgprob = g.wgprob;
+    wgprob.assign((size_t)wgs, 0);
     for (int j = 0; j < g.nprob; ++j) {
         DevProb& P = g.probs[j];
+        for (int w = 0; w < P.nwg; ++w) wgprob[(size_t)P.wg_begin + w] = j;
         const size_t n = (size_t)ps[j].op->N;
         char* v = base + off_vec[j];
         P.b = ps[j].b;
         P.x = ps[j].x;
-        if (g.shared) {
-            g.R = (double*)(base + off_R);
-            g.Wb = (double*)(base + off_W);
-            g.C = (double*)(base + off_C);
-            g.D = (double*)(base + off_D);
-            const int k = ps[0].defl->k;
-            P.r = g.R + (size_t)j * g.rld;
-            P.Ccol = g.C + (size_t)j * k;
-            P.Dcol = g.D + (size_t)j * k;
-            P.Wcol = g.Wb + (size_t)j * g.rld;
-        } else {
-            P.r = (double*)v;
-            v += align256(n * 8);
-        }
+        P.r = (double*)v;
+        v += align256(n * 8);
         void* vecs[9];
         const int nv = g.inner_f32 ? 9 : 8;
         for (int i = 0; i < nv; ++i) {
@@ -311,9 +260,11 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
             P.ldv = ps[j].defl->n;
             P.lu = ps[j].defl->d_lu;
             P.piv = ps[j].defl->d_piv;
+            P.hinv = ps[j].defl->d_hinv;
         }
         P.st = g.d_states + j;
         P.partial = (double*)(base + off_part[j]);
+        P.actlog = j == 0 ? g.d_actlog : nullptr;
         P.counter = counters + j;
         P.mirror = g.mirror + j;
         SolveState& S = g.states[j];
@@ -333,21 +284,33 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
         S.precision = g.inner_f32;
         S.solve_state = SV_RUNNING;
         S.inner_state = IN_CONVERGED;
-        g.mirror[j].solve_state = SV_RUNNING;
-        g.mirror[j].inner_state = IN_RUNNING;
-        g.mirror[j].icyc = 0;
-        g.mirror[j].iter = 0;
+        // the step kernel starts with the true residual of x0
+        StepHot h;
+        memset(&h, 0, sizeof(h));
+        h.mode = M_RES;
+        h.first = 1;
+        h.solve_state = SV_RUNNING;
+        h.inner_state = IN_CONVERGED;
+        S.hot[0] = h;
+        S.hot[1] = h;
+        Mirror& m = g.mirror[j];
+        m.solve_state = SV_RUNNING;
+        m.inner_state = IN_RUNNING;
+        m.icyc = 0;
+        m.iter = 0;
+        m.mode = M_RES;
+        m.slot = -1;
+        m.rr = m.rr0 = m.target2 = 0.0;
     }
     hipStream_t s = ctx->stream;
     TGDK_HIP(hipMemcpyAsync(g.d_probs, g.probs.data(), sizeof(DevProb) * g.nprob, hipMemcpyHostToDevice, s));
     TGDK_HIP(hipMemcpyAsync(g.d_states, g.states.data(), sizeof(SolveState) * g.nprob, hipMemcpyHostToDevice, s));
+    TGDK_HIP(hipMemcpyAsync(g.d_wgprob, wgprob.data(), sizeof(int) * wgprob.size(), hipMemcpyHostToDevice, s));
     TGDK_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned) * g.nprob, s));
-    if (g.shared) {
-        // D columns of systems that stop early stay finite (zero)
-        TGDK_HIP(hipMemsetAsync(g.D, 0, sizeof(double) * g.nprob * g.sdefl->k, s));
-        rc = ctx->partial.ensure((size_t)gram_blocks(g.sdefl->n) * g.nprob * g.sdefl->k * sizeof(double));
-        if (rc) return rc;
-    }
+    if (g.d_actlog) TGDK_HIP(hipMemsetAsync(g.d_actlog, 0, NSLOTLOG, s));
+    // partial slots start finite (the first step sums them without using them)
+    for (int j = 0; j < g.nprob; ++j)
+        TGDK_HIP(hipMemsetAsync(g.probs[j].partial, 0, sizeof(double) * 2 * g.probs[j].pslot, s));
     if (!prm->x0_given)
         for (int j = 0; j < g.nprob; ++j)
             TGDK_HIP(hipMemsetAsync(ps[j].x, 0, sizeof(double) * ps[j].op->N, s));
@@ -387,120 +350,93 @@ static int finish_group(Group& g, const std::vector<ProbSpec>& ps, tgdk_solve_re
     return rc;
 }
 
-static bool all_inner_done(const Group& g) {
-    for (int j = 0; j < g.nprob; ++j) {
-        const Mirror m = read_mirror(g, j);
-        if (m.solve_state == SV_RUNNING && m.inner_state == IN_RUNNING) return false;
-    }
-    return true;
-}
-
 static bool all_solved(const Group& g) {
     for (int j = 0; j < g.nprob; ++j)
         if (read_mirror(g, j).solve_state == SV_RUNNING) return false;
     return true;
 }
 
-// Galerkin projection of every running system (Sec. 2.2 box).  Systems that
-// share one deflation space form c = V^T r for all right-hand sides as one
-// matrix-core product C = R^T V and w = V d as W = V D; otherwise each system
-// reads V in its own tiles.
-static int project(Group& g) {
-    hipStream_t s = g.ctx->stream;
-    if (!g.shared) {
-        launch(g, K_PROJ_DOT);
-        launch(g, K_PROJ_APPLY);
-        return TGDK_OK;
+// Steps a running problem still needs before its state is worth reading
+// again: the rest of its inner cycle (extrapolating the residual reduction per
+// iteration of this cycle, or of the last one early in a cycle) and the
+// boundary steps after it.
+static int predict_steps(const Mirror& m, double& rate_prev) {
+    if (m.solve_state != SV_RUNNING) return 0;
+    if (m.mode != M_A && m.mode != M_B) return 3;
+    double rate = rate_prev;
+    if (m.iter >= 2 && m.rr > 0.0 && m.rr0 > 0.0 && m.rr < m.rr0) {
+        rate = std::pow(m.rr / m.rr0, 1.0 / m.iter);
+        rate_prev = rate;
     }
-    const tgdk_defl d = g.sdefl;
-    const long long n = d->n;
-    launch_gram(g.R, 0, g.rld, g.nprob, d->V, d->store == TGDK_F32 ? 1 : 0, d->n, d->k, n, g.C,
-                (double*)g.ctx->partial.p, g.ctx->counters, s);
-    launch_proj_shared_epilogue(g.d_probs, g.nprob, s);
-    if (d->store == TGDK_F32)
-        launch_vmul_f32((const float*)d->V, d->n, d->k, g.D, g.nprob, g.Wb, g.rld, n, s);
-    else
-        launch_vmul((const double*)d->V, d->n, d->k, g.D, g.nprob, g.Wb, g.rld, n, s);
-    launch_proj_apply_shared(g.dim, g.inner_f32, g.tile_id, g.d_probs, g.nprob, g.total_tiles, s);
-    TGDK_HIP(hipGetLastError());
-    return TGDK_OK;
+    int rem = 8;
+    if (rate > 0.0 && rate < 0.999 && m.rr > 0.0 && m.target2 > 0.0)
+        rem = m.rr <= m.target2 ? 1 : (int)std::ceil(std::log(m.target2 / m.rr) / std::log(rate));
+    rem = std::max(1, std::min(rem, 64));
+    return 2 * rem + 3;
 }
 
+// BiCGStab(ncyc)-Proj(k) over a group: step launches only.  At most two
+// batches are outstanding; when the older one completes, the host reads the
+// status mirror and enqueues as many steps as the slowest running problem is
+// predicted to need (steps past the end of a solve return at once but still
+// cost a dispatch each).
 static int bicgstab_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk_solve_params* prm,
                           tgdk_solve_report* reps) {
     const auto t0 = std::chrono::steady_clock::now();
     Group g;
     int rc = build_group(ctx, ps, prm, g);
     if (rc) return rc;
-    bool any_defl = false;
-    for (const auto& p : ps) any_defl |= (p.defl != nullptr);
-    const int B_MAX = 16;  // largest batch of iterations enqueued at once
-    int first_batch = 4;
-    double prev_rate = 0.0;
-    const int max_cycles = prm->ncyc + (prm->max_extra_cycles >= 0 ? prm->max_extra_cycles : prm->ncyc) + 2;
-    const int maxit = prm->maxit_cycle > 0 ? prm->maxit_cycle : 100000;
-    rc = ensure_events(ctx, 3);
+    rc = ensure_events(ctx, 2);
     if (rc) return rc;
     hipStream_t s = ctx->stream;
-    launch(g, K_RESIDUAL, 1);
-    TGDK_HIP(hipGetLastError());
-    for (int cyc = 0; cyc < max_cycles; ++cyc) {
-        if (any_defl && (rc = project(g))) return rc;
-        // Inner iterations.  At most two batches are outstanding; after the
-        // older one completes the host reads the status mirror, predicts how
-        // many iterations the cycle still needs and enqueues only that many
-        // (launches past the end of a cycle return at once but still cost a
-        // dispatch each).
-        int enq = 0, head = 0, tail = 0;  // iterations enqueued; batch FIFO [head, tail)
-        auto enqueue = [&](int cnt) -> int {
-            for (int i = 0; i < cnt; ++i) {
-                int r2;
-                if ((r2 = launch_timed(g, K_BICG_A, cyc, enq + i))) return r2;
-                if ((r2 = launch_timed(g, K_BICG_B, cyc, enq + i))) return r2;
-            }
-            enq += cnt;
-            TGDK_HIP(hipEventRecord(ctx->events[tail % 2], s));
-            ++tail;
-            return TGDK_OK;
-        };
-        if ((rc = enqueue(std::max(2, std::min(first_batch, B_MAX))))) return rc;
-        while (enq <= maxit + 1) {
-            if ((rc = wait_event(ctx->events[head % 2]))) return rc;
-            ++head;
-            if (all_inner_done(g)) break;
-            int seen = 0;
-            const int rem = predict_remaining(g, prev_rate, &seen);
-            const int want = rem - (enq - seen);
-            if (want > 0 && tail - head < 2) {
-                if ((rc = enqueue(std::min(want, B_MAX)))) return rc;
-            } else if (tail == head) {
-                if ((rc = enqueue(1))) return rc;
-            }
+    const int S_MAX = 32;  // largest batch of steps enqueued at once
+    const long long max_cycles = prm->ncyc + (prm->max_extra_cycles >= 0 ? prm->max_extra_cycles : prm->ncyc) + 2;
+    const long long maxit = prm->maxit_cycle > 0 ? prm->maxit_cycle : 100000;
+    const long long slot_cap = max_cycles * (2 * maxit + 6) + 16;
+    std::vector<double> rate(g.nprob, 0.0);
+    int ev_slot[2] = {0, 0};
+    int head = 0, tail = 0;
+    auto enqueue = [&](int cnt) -> int {
+        for (int i = 0; i < cnt; ++i) {
+            int r2 = launch_step_timed(g);
+            if (r2) return r2;
         }
-
-        // next cycle's first batch: half of this cycle's length
-        {
-            int len = 0;
-            double rate = 0.0;
-            for (int j = 0; j < g.nprob; ++j) {
-                const Mirror m = read_mirror(g, j);
-                len = std::max(len, m.iter);
-                if (m.iter > 0 && m.rr0 > 0.0 && m.rr > 0.0 && m.rr < m.rr0)
-                    rate = std::max(rate, std::pow(m.rr / m.rr0, 1.0 / m.iter));
-            }
-            first_batch = std::max(2, len / 2);
-            if (rate > 0.0) prev_rate = rate;
-        }
-        launch(g, K_FINALIZE);
-        launch(g, K_RESIDUAL, 0);
         TGDK_HIP(hipGetLastError());
-        TGDK_HIP(hipEventRecord(ctx->events[2], s));
-        if ((rc = wait_event(ctx->events[2]))) return rc;
+        TGDK_HIP(hipEventRecord(ctx->events[tail % 2], s));
+        ev_slot[tail % 2] = g.gslot;
+        ++tail;
+        return TGDK_OK;
+    };
+    if ((rc = enqueue(8))) return rc;
+    for (;;) {
+        if ((rc = wait_event(ctx->events[head % 2]))) return rc;
+        const int completed = ev_slot[head % 2];
+        ++head;
         if (all_solved(g)) break;
+        if (g.gslot >= slot_cap) break;  // the device's own cycle and iteration limits end every solve first
+        int want = 0;
+        for (int j = 0; j < g.nprob; ++j) {
+            const Mirror m = read_mirror(g, j);
+            // a running problem reports every step it takes
+            if (m.solve_state == SV_RUNNING && m.slot < completed - 64)
+                return fail(TGDK_E_HIP, "step kernel stopped reporting progress");
+            want = std::max(want, predict_steps(m, rate[j]));
+        }
+        want -= g.gslot - completed;
+        if (want > 0 && tail - head < 2) {
+            if ((rc = enqueue(std::min(want, S_MAX)))) return rc;
+        } else if (tail == head) {
+            if ((rc = enqueue(2))) return rc;
+        }
     }
+    // drain what is still queued (those steps find every problem finished)
+    TGDK_HIP(hipStreamSynchronize(s));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     rc = finish_group(g, ps, reps, secs, nullptr);
-    if (ctx->time_which) collect_timing(g);
+    if (ctx->time_which) {
+        int r2 = collect_timing(g);
+        if (r2) return r2;
+    }
     return rc;
 }
 

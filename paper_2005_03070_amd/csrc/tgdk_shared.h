@@ -30,11 +30,48 @@ enum : int {
     IN_MAXIT = 5,         // iteration limit (full update pending)
 };
 // solve state
-enum : int { SV_RUNNING = 0, SV_CONVERGED = 1, SV_BREAKDOWN = 2, SV_NOT_CONVERGED = 3 };
+enum : int { SV_RUNNING = 0, SV_CONVERGED = 1, SV_BREAKDOWN = 2, SV_NOT_CONVERGED = 3, SV_NONFINITE = 4 };
 enum : int { METHOD_BICGSTAB = 0, METHOD_GMRES = 1 };
+
+// BiCGStab step kernel: what the next launch does for a problem (StepHot::mode)
+enum : int {
+    M_DONE = 0,
+    M_RES = 1,      // cycle end or solve start: true residual (+ c partials)
+    M_A = 2,        // phase A of the next iteration (phase B partials pending)
+    M_B = 3,        // phase B (phase A partials pending)
+    M_REDUCE = 4,   // boundary decisions; c summed and H d = c solved
+    M_APPLY = 5,    // x += upd + V d, r -= A V d, new shadow vector
+    M_START = 6,    // decisions after the projection, then phase A of iteration 0
+    M_APPLY0 = 7,   // no deflation: decisions, x += upd, phase A of iteration 0
+};
+// ... and what a launch did for it (logged for measurement)
+enum : int {
+    ACT_NONE = 0,
+    ACT_A = 1,       // phase A of an iteration > 0
+    ACT_A0 = 2,      // phase A of iteration 0
+    ACT_B = 3,       // phase B
+    ACT_RES = 4,     // true residual at the end of a cycle (or at the start)
+    ACT_REDUCE = 5,  // projection coefficients (one workgroup)
+    ACT_APPLY = 6,   // projection applied
+    ACT_FIN = 7,     // last inner update folded into x
+    ACT_FIN_A0 = 8,  // x update and phase A of iteration 0 (no deflation)
+    NACT = 9,
+};
+
+// Scalars of the step kernel's state machine, double-buffered by launch
+// parity: launch s reads hot[(s + 1) & 1] and its lead workgroup writes
+// hot[s & 1].
+struct StepHot {
+    int mode, solve_state, inner_state, first;
+    int iter, icyc, pbuf, upd_any;
+    double rho, rho_old, alpha, omega;
+    double target2, tau, nu0, bnorm;
+    double upd_a, upd_w;  // coefficients of p and s in the pending x update
+};
 
 // Per-problem solver state in device memory.  Scalars are float64.
 struct SolveState {
+    StepHot hot[2];
     double rho, rho_old, alpha, omega, sigma;
     double target2;          // (relative tolerance * nu)^2 of the inner cycle
     double nu, nu0, tau, bnorm;
@@ -61,6 +98,7 @@ struct SolveState {
 // Host-visible status mirror (in host-mapped memory).
 struct Mirror {
     int solve_state, inner_state, icyc, iter;
+    int mode, slot;  // step kernel: state after launch number slot
     double rr;       // estimate of ||r_inner||^2 after the last iteration
     double rr0;      // ||r_inner||^2 at the start of the cycle
     double target2;  // squared target of the cycle
@@ -85,16 +123,18 @@ struct DevProb {
     long long ldv;
     const double* lu;        // LU factors of H (k x k, row-major), pivots
     const int* piv;
+    const double* hinv;      // H^{-1} (k x k, column-major)
     SolveState* st;
-    double* partial;         // ntiles * pstride
+    double* partial;         // tile kernels: ntiles * pstride (tile-major);
+                             // step kernel: two launch-parity slots of pstride * nwg (value-major)
     int pstride;
+    int nwg, wg_begin;       // step kernel: workgroups of this problem, first workgroup id
+    long long pslot;         // pstride * nwg
+    unsigned char* actlog;   // step kernel: action per launch (first NSLOTLOG launches), or null
     unsigned* counter;
     Mirror* mirror;
-    // systems that share one deflation space (several right-hand sides): the
-    // projection runs as matrix-core products over the block of residuals
-    const double* Ccol;      // column of C = V^T R (k values), or null
-    double* Dcol;            // column of D (k values): this system's d
-    const double* Wcol;      // column of W = V D (n values), or null
 };
+
+constexpr int NSLOTLOG = 1 << 15;
 
 }  // namespace tgdk
