@@ -28,6 +28,10 @@ METRIC = "fine-solve time to rel.resid 1e-8 (s) + stencil HBM GB/s; FP32/batched
 HBM_PEAK_GBS = 8000.0
 
 
+def log(*m):
+    print("[bench]", *m, file=sys.stderr, flush=True)
+
+
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -36,6 +40,10 @@ def _args():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="setup, warm-up and timed solves only (for hardware-counter runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 512 MiB device buffer three times (counter scale of a plain copy)")
     return ap.parse_args()
 
 
@@ -76,6 +84,15 @@ def main():
     import numpy as np
     import torch
 
+    if a.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {src.numel() * 8 / 2**20:.0f} MiB three times")
+        return
+
     import paper_2005_03070_amd as tg
     from paper_2005_03070_amd import _lib as L
     from paper_2005_03070_amd.api import context
@@ -90,7 +107,6 @@ def main():
     b = torch.tensor(b_np, device=dev)
     op = tg.Operator.const_cd((nx, ny), c["beta"])
     ctx, _ = context(dev)
-    log = lambda *m: print("[bench]", *m, file=sys.stderr, flush=True)  # noqa: E731
 
     # ---------------------------------------------------------------- setup
     t0 = time.perf_counter()
@@ -131,11 +147,17 @@ def main():
     sec = total / a.steps
     log(f"fp64 BiCGStab(20)-Proj(30): {sec*1e3:.1f} ms/solve, mvps {reps[0].mvp_inner}, relres {rr:.2e}")
     head = reps[0]
+    if a.solve_only:
+        return
 
     # ------------------------------------------- live kernel timing (roofline)
-    # Every step launch of one solve is bracketed by HIP events on the solve's
-    # stream; the library logs what the step did (phase A, phase B, cycle
-    # boundary, ...), and each action has its own algorithmic byte count.
+    # One more solve with the library's measurement on: every step launch
+    # stamps its first workgroup start and last workgroup end on the device
+    # wall clock and logs what it did (phase A, phase B, cycle boundary, ...);
+    # each action has its own algorithmic byte count.  (A HIP event pair around
+    # every launch would add about 4 us to a 20 us launch.)  HIP events on the
+    # solve's stream bracket the whole solve, giving the share of its GPU time
+    # spent inside step kernels.
     import ctypes as C
     kdefl = space.k
     w8, v8 = 8, 8  # float64 inner vectors and stored deflation vectors
@@ -151,7 +173,13 @@ def main():
     }
     codes = {"A": 1, "A0": 2, "B": 3, "RES": 4, "REDUCE": 5, "APPLY": 6, "FIN": 7, "FIN_A0": 8}
     L.check(L.lib().tgdk_ctx_time_kernel(ctx, 1))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
     fine_solve()
+    ev1.record()
+    torch.cuda.synchronize()
+    solve_event_ms = ev0.elapsed_time(ev1)
     per_act = {}
     for name, code in codes.items():
         ms = np.zeros(1)
@@ -174,7 +202,8 @@ def main():
     log("step kernel: " + ", ".join(f"{k} {v['avg_launch_us']:.1f} us x{v['launches']}"
                                      + (f" {v['achieved_GBs']:.0f} GB/s" if v["achieved_GBs"] else "")
                                      for k, v in act_table.items()))
-    log(f"step kernel overall: {step_us:.1f} us/launch, {ach_step:.0f} GB/s algorithmic")
+    log(f"step kernel overall: {step_us:.1f} us/launch, {ach_step:.0f} GB/s algorithmic; "
+        f"{tot_ms:.1f} ms of step kernels in a {solve_event_ms:.1f} ms solve (HIP events)")
 
     # ------------------------------------------------------------ variants
     variants = {}
@@ -271,7 +300,8 @@ def main():
                      "frac": ach_step / HBM_PEAK_GBS, "traffic": traffic_from_profiles(),
                      "kernel": "k_step (BiCGStab step: phase A / phase B / cycle boundary), f64, one solve",
                      "algorithmic_bytes_per_launch": step_bytes, "avg_launch_us": step_us,
-                     "launches_timed": tot_cnt},
+                     "launches_timed": tot_cnt, "timing": "device wall clock per launch",
+                     "step_kernel_ms": tot_ms, "solve_ms_hip_events": solve_event_ms},
         "kernels": {"step_by_action": act_table,
                     "stencil_1023sq_f64_GBs": st_c2, "stencil_255cube_f32_GBs": st_c3},
         "solve": {"relres_true": rr, "cycles": head.cycles, "mvp_inner": head.mvp_inner,

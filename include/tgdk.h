@@ -74,11 +74,12 @@ int tgdk_ctx_create(tgdk_ctx* out, int device, void* hip_stream);
 int tgdk_ctx_destroy(tgdk_ctx ctx);
 /* Number of compute units of the context's device (for launch sizing). */
 int tgdk_ctx_num_cus(tgdk_ctx ctx);
-/* Measurement hook.  on = 1 brackets every launch of the BiCGStab step
- * kernel inside tgdk_solve / tgdk_solve_instances with HIP events on the
- * context stream (this adds a little launch overhead) and logs what the
- * group's first problem did in each launch; on = 0 switches it off.  Both
- * calls clear the totals.  tgdk_ctx_kernel_time returns, for one action
+/* Measurement hook.  on = 1 makes every launch of the BiCGStab step kernel
+ * inside tgdk_solve / tgdk_solve_instances (first 4096 launches of a call)
+ * record its duration -- last end minus first start of the workgroups of the
+ * group's first problem, on the device's constant-rate wall clock -- and what
+ * that problem did in it; on = 0 switches it off.  Both calls clear the
+ * totals.  tgdk_ctx_kernel_time returns, for one action
  * (TGDK_STEP_*), the summed duration in ms of the launches in which the first
  * problem did it and their number; TGDK_STEP_ANY sums every launch in which it
  * did work.  Actions: */

@@ -280,7 +280,6 @@ int tgdk_ctx_destroy(tgdk_ctx c) {
     if (c->dscal) (void)hipFree(c->dscal);
     if (c->mirror) (void)hipHostFree(c->mirror);
     for (auto e : c->events) (void)hipEventDestroy(e);
-    for (auto e : c->tev) (void)hipEventDestroy(e);
     delete c;
     return TGDK_OK;
 }
@@ -295,7 +294,6 @@ static_assert(TGDK_STEP_A == ACT_A && TGDK_STEP_A0 == ACT_A0 && TGDK_STEP_B == A
 int tgdk_ctx_time_kernel(tgdk_ctx c, int on) {
     if (!c || on < 0 || on > 1) return fail(TGDK_E_INVALID, "bad argument");
     c->time_which = on;
-    c->tev_used = 0;
     for (int a = 0; a < NACT; ++a) {
         c->act_ms[a] = 0.0;
         c->act_count[a] = 0;

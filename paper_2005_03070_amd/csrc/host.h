@@ -48,9 +48,6 @@ struct tgdk_ctx_s {
     std::vector<hipEvent_t> events;
     // step-kernel timing for measurement (0 off, 1 on)
     int time_which = 0;
-    std::vector<hipEvent_t> tev;   // event pairs
-    std::vector<int> tev_slot;     // launch number of each timed launch
-    size_t tev_used = 0;
     double act_ms[tgdk::NACT] = {0};          // summed duration per action of the first problem
     long long act_count[tgdk::NACT] = {0};
 };

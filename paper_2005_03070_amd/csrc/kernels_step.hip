@@ -584,6 +584,7 @@ __device__ __forceinline__ void fold_update(const DevProb& P, int lw, const Upd&
 template <class Cfg, int DIM, class TI, class TV>
 __global__ __launch_bounds__(NT) void k_step(const DevProb* __restrict__ probs, const int* __restrict__ wg_prob,
                                              int gslot) {
+    const unsigned long long t_begin = (unsigned long long)wall_clock64();
     __shared__ double Lbox[Cfg::BOX];
     __shared__ double sh[NWAVE * 16];
     __shared__ double ysh[MAXK + 1];
@@ -652,6 +653,16 @@ __global__ __launch_bounds__(NT) void k_step(const DevProb* __restrict__ probs, 
             break;
         default:
             break;
+    }
+    // measurement: this workgroup's start and end on the constant-rate wall
+    // clock (plain stores; the host takes the first start and the last end)
+    if (P.tstamp && gslot < NTSLOG) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long* t = P.tstamp + 2 * ((long long)gslot * P.nwg + lw);
+            t[0] = t_begin;
+            t[1] = (unsigned long long)wall_clock64();
+        }
     }
 }
 

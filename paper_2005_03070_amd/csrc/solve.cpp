@@ -74,6 +74,7 @@ struct Group {
     SolveState* d_states = nullptr;
     int* d_wgprob = nullptr;
     unsigned char* d_actlog = nullptr;  // action log of problem 0 (measurement only)
+    unsigned long long* d_ts = nullptr;  // per-launch first start / last end (measurement only)
     std::vector<DevProb> probs;
     std::vector<SolveState> states;
     std::vector<int> wgprob;
@@ -85,48 +86,40 @@ static void launch(const Group& g, int which, int flag = 0) {
                         g.ctx->stream);
 }
 
-// One step launch; with measurement on, bracketed by events on the stream.
+// One step launch (with measurement on, the kernel stamps its start and end).
 static int launch_step_timed(Group& g) {
-    tgdk_ctx ctx = g.ctx;
     const int slot = g.gslot++;
-    if (!ctx->time_which) {
-        launch_step(g.dim, g.inner_f32, g.vtype, g.tile_id, g.d_probs, g.d_wgprob, g.total_wg, slot, ctx->stream);
-        return TGDK_OK;
-    }
-    if (ctx->tev_used * 2 + 2 > ctx->tev.size()) {
-        for (int i = 0; i < 256; ++i) {
-            hipEvent_t e;
-            TGDK_HIP(hipEventCreate(&e));
-            ctx->tev.push_back(e);
-        }
-    }
-    const size_t k = ctx->tev_used++;
-    if (ctx->tev_slot.size() <= k) ctx->tev_slot.resize(k + 1);
-    ctx->tev_slot[k] = slot;
-    TGDK_HIP(hipEventRecord(ctx->tev[2 * k], ctx->stream));
-    launch_step(g.dim, g.inner_f32, g.vtype, g.tile_id, g.d_probs, g.d_wgprob, g.total_wg, slot, ctx->stream);
-    TGDK_HIP(hipEventRecord(ctx->tev[2 * k + 1], ctx->stream));
+    launch_step(g.dim, g.inner_f32, g.vtype, g.tile_id, g.d_probs, g.d_wgprob, g.total_wg, slot, g.ctx->stream);
     return TGDK_OK;
 }
 
-// Adds the durations of the timed step launches to the context's totals,
-// per action of the group's first problem (from the device's action log).
+// Adds the duration of every measured step launch (last workgroup end minus
+// first workgroup start, device wall clock; the group's first problem's
+// workgroups) to the context's totals, per action of that problem (from the
+// device's action log).
 static int collect_timing(Group& g) {
     tgdk_ctx ctx = g.ctx;
-    std::vector<unsigned char> act(NSLOTLOG, 0);
-    if (g.d_actlog) {
-        TGDK_HIP(hipMemcpy(act.data(), g.d_actlog, NSLOTLOG, hipMemcpyDeviceToHost));
-    }
-    for (size_t k = 0; k < ctx->tev_used; ++k) {
-        const int slot = ctx->tev_slot[k];
-        if (slot >= NSLOTLOG) continue;
-        const int a = act[slot];
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, ctx->tev[2 * k], ctx->tev[2 * k + 1]) != hipSuccess) continue;
-        ctx->act_ms[a] += ms;
+    if (!g.d_ts || !g.d_actlog) return TGDK_OK;
+    const int nl = std::min(g.gslot, NTSLOG);
+    const size_t nwg = (size_t)g.probs[0].nwg;
+    std::vector<unsigned char> act((size_t)nl, 0);
+    std::vector<unsigned long long> ts(2 * (size_t)nl * nwg, 0);
+    TGDK_HIP(hipMemcpy(act.data(), g.d_actlog, (size_t)nl, hipMemcpyDeviceToHost));
+    TGDK_HIP(hipMemcpy(ts.data(), g.d_ts, sizeof(unsigned long long) * ts.size(), hipMemcpyDeviceToHost));
+    int khz = 0;
+    TGDK_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device));
+    if (khz <= 0) return fail(TGDK_E_HIP, "device wall clock rate unknown");
+    for (int l = 0; l < nl; ++l) {
+        unsigned long long t0 = ~0ull, t1 = 0;
+        for (size_t w = 0; w < nwg; ++w) {
+            t0 = std::min(t0, ts[2 * ((size_t)l * nwg + w)]);
+            t1 = std::max(t1, ts[2 * ((size_t)l * nwg + w) + 1]);
+        }
+        if (t1 <= t0) continue;
+        const int a = act[(size_t)l];
+        ctx->act_ms[a] += (double)(t1 - t0) / (double)khz;
         ctx->act_count[a] += 1;
     }
-    ctx->tev_used = 0;
     return TGDK_OK;
 }
 
@@ -216,6 +209,8 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
     off += align256(sizeof(int) * (size_t)wgs);
     const size_t off_actlog = off;
     if (ctx->time_which) off += align256(NSLOTLOG);
+    const size_t off_ts = off;
+    if (ctx->time_which) off += align256(sizeof(unsigned long long) * 2 * NTSLOG * (size_t)g.probs[0].nwg);
     int rc = ctx->solve_ws.ensure(off);
     if (rc) return rc;
     rc = ensure_mirror(ctx, g.nprob);
@@ -225,6 +220,7 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
     g.d_states = (SolveState*)(base + off_states);
     g.d_wgprob = (int*)(base + off_wgprob);
     g.d_actlog = ctx->time_which ? (unsigned char*)(base + off_actlog) : nullptr;
+    g.d_ts = ctx->time_which ? (unsigned long long*)(base + off_ts) : nullptr;
     unsigned* counters = (unsigned*)(base + off_counters);
     g.mirror = ctx->mirror;
     g.states.assign(g.nprob, SolveState());
@@ -265,6 +261,7 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
         P.st = g.d_states + j;
         P.partial = (double*)(base + off_part[j]);
         P.actlog = j == 0 ? g.d_actlog : nullptr;
+        P.tstamp = j == 0 ? g.d_ts : nullptr;
         P.counter = counters + j;
         P.mirror = g.mirror + j;
         SolveState& S = g.states[j];
@@ -308,6 +305,8 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
     TGDK_HIP(hipMemcpyAsync(g.d_wgprob, wgprob.data(), sizeof(int) * wgprob.size(), hipMemcpyHostToDevice, s));
     TGDK_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned) * g.nprob, s));
     if (g.d_actlog) TGDK_HIP(hipMemsetAsync(g.d_actlog, 0, NSLOTLOG, s));
+    if (g.d_ts)
+        TGDK_HIP(hipMemsetAsync(g.d_ts, 0, sizeof(unsigned long long) * 2 * NTSLOG * (size_t)g.probs[0].nwg, s));
     // partial slots start finite (the first step sums them without using them)
     for (int j = 0; j < g.nprob; ++j)
         TGDK_HIP(hipMemsetAsync(g.probs[j].partial, 0, sizeof(double) * 2 * g.probs[j].pslot, s));
@@ -356,23 +355,25 @@ static bool all_solved(const Group& g) {
     return true;
 }
 
-// Steps a running problem still needs before its state is worth reading
-// again: the rest of its inner cycle (extrapolating the residual reduction per
-// iteration of this cycle, or of the last one early in a cycle) and the
-// boundary steps after it.
-static int predict_steps(const Mirror& m, double& rate_prev) {
+// Steps a running problem will take before it can have finished: the rest of
+// its inner cycle (extrapolating the residual reduction per iteration of this
+// cycle, or of the last one early in a cycle), the boundary steps, and a next
+// cycle as long as this one (enqueued ahead, so the queue does not drain at a
+// boundary; launches past the end of the solve return at once).
+struct Predict {
+    double rate = 0.0;  // residual reduction per iteration
+    int len = 8;        // iterations of the current (or last) cycle
+};
+static int predict_steps(const Mirror& m, Predict& pr) {
     if (m.solve_state != SV_RUNNING) return 0;
-    if (m.mode != M_A && m.mode != M_B) return 3;
-    double rate = rate_prev;
-    if (m.iter >= 2 && m.rr > 0.0 && m.rr0 > 0.0 && m.rr < m.rr0) {
-        rate = std::pow(m.rr / m.rr0, 1.0 / m.iter);
-        rate_prev = rate;
-    }
+    if (m.mode != M_A && m.mode != M_B) return 3 + 2 * pr.len + 3;
+    if (m.iter >= 2 && m.rr > 0.0 && m.rr0 > 0.0 && m.rr < m.rr0) pr.rate = std::pow(m.rr / m.rr0, 1.0 / m.iter);
     int rem = 8;
-    if (rate > 0.0 && rate < 0.999 && m.rr > 0.0 && m.target2 > 0.0)
-        rem = m.rr <= m.target2 ? 1 : (int)std::ceil(std::log(m.target2 / m.rr) / std::log(rate));
+    if (pr.rate > 0.0 && pr.rate < 0.999 && m.rr > 0.0 && m.target2 > 0.0)
+        rem = m.rr <= m.target2 ? 1 : (int)std::ceil(std::log(m.target2 / m.rr) / std::log(pr.rate));
     rem = std::max(1, std::min(rem, 64));
-    return 2 * rem + 3;
+    pr.len = std::max(2, m.iter + rem);
+    return 2 * rem + 3 + 2 * pr.len + 3;
 }
 
 // BiCGStab(ncyc)-Proj(k) over a group: step launches only.  At most two
@@ -389,11 +390,11 @@ static int bicgstab_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const t
     rc = ensure_events(ctx, 2);
     if (rc) return rc;
     hipStream_t s = ctx->stream;
-    const int S_MAX = 32;  // largest batch of steps enqueued at once
+    const int S_MAX = 24;  // largest batch of steps enqueued at once
     const long long max_cycles = prm->ncyc + (prm->max_extra_cycles >= 0 ? prm->max_extra_cycles : prm->ncyc) + 2;
     const long long maxit = prm->maxit_cycle > 0 ? prm->maxit_cycle : 100000;
     const long long slot_cap = max_cycles * (2 * maxit + 6) + 16;
-    std::vector<double> rate(g.nprob, 0.0);
+    std::vector<Predict> pred(g.nprob);
     int ev_slot[2] = {0, 0};
     int head = 0, tail = 0;
     auto enqueue = [&](int cnt) -> int {
@@ -420,14 +421,16 @@ static int bicgstab_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const t
             // a running problem reports every step it takes
             if (m.solve_state == SV_RUNNING && m.slot < completed - 64)
                 return fail(TGDK_E_HIP, "step kernel stopped reporting progress");
-            want = std::max(want, predict_steps(m, rate[j]));
+            want = std::max(want, predict_steps(m, pred[j]));
         }
         want -= g.gslot - completed;
-        if (want > 0 && tail - head < 2) {
-            if ((rc = enqueue(std::min(want, S_MAX)))) return rc;
-        } else if (tail == head) {
-            if ((rc = enqueue(2))) return rc;
+        // keep two batches queued while steps are predicted
+        while (want > 0 && tail - head < 2) {
+            const int cnt = std::min(want, S_MAX);
+            if ((rc = enqueue(cnt))) return rc;
+            want -= cnt;
         }
+        if (tail == head && (rc = enqueue(2))) return rc;
     }
     // drain what is still queued (those steps find every problem finished)
     TGDK_HIP(hipStreamSynchronize(s));

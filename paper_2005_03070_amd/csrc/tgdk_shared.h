@@ -131,10 +131,12 @@ struct DevProb {
     int nwg, wg_begin;       // step kernel: workgroups of this problem, first workgroup id
     long long pslot;         // pstride * nwg
     unsigned char* actlog;   // step kernel: action per launch (first NSLOTLOG launches), or null
+    unsigned long long* tstamp;  // step kernel: start/end stamp per launch and workgroup (first NTSLOG launches), or null
     unsigned* counter;
     Mirror* mirror;
 };
 
 constexpr int NSLOTLOG = 1 << 15;
+constexpr int NTSLOG = 1 << 12;
 
 }  // namespace tgdk
