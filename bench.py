@@ -49,7 +49,7 @@ def _args():
 
 def kernel_hash():
     h = hashlib.sha256()
-    for f in ("kernels_step.hip", "device_common.h", "tgdk_shared.h"):
+    for f in ("step_kernel.h", "kernels_step2d.hip", "march3d.h", "device_common.h", "tgdk_shared.h"):
         with open(os.path.join(ROOT, "paper_2005_03070_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

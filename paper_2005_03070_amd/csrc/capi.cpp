@@ -55,6 +55,7 @@ DevOp make_devop(const tgdk_op_s* op, int transpose) {
     for (int i = 0; i < 7; ++i) d.cc[i] = transpose ? op->ccT[i] : op->cc[i];
     d.coef64 = transpose ? op->coefT64 : op->coef64;
     d.coef32 = transpose ? op->coefT32 : op->coef32;
+    d.zero = op->ctx->zero;
     return d;
 }
 
@@ -264,7 +265,8 @@ int tgdk_ctx_create(tgdk_ctx* out, int device, void* hip_stream) {
     c->num_cus = prop.multiProcessorCount;
     if (hipMalloc((void**)&c->counters, 64 * sizeof(unsigned)) != hipSuccess ||
         hipMemset(c->counters, 0, 64 * sizeof(unsigned)) != hipSuccess ||
-        hipMalloc((void**)&c->dscal, 4096 * sizeof(double)) != hipSuccess) {
+        hipMalloc((void**)&c->dscal, 4096 * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&c->zero, 4096) != hipSuccess || hipMemset(c->zero, 0, 4096) != hipSuccess) {
         delete c;
         return fail(TGDK_E_NOMEM, "context allocation failed");
     }
@@ -278,6 +280,7 @@ int tgdk_ctx_destroy(tgdk_ctx c) {
     (void)hipStreamSynchronize(c->stream);
     if (c->counters) (void)hipFree(c->counters);
     if (c->dscal) (void)hipFree(c->dscal);
+    if (c->zero) (void)hipFree(c->zero);
     if (c->mirror) (void)hipHostFree(c->mirror);
     for (auto e : c->events) (void)hipEventDestroy(e);
     delete c;
@@ -572,7 +575,7 @@ int tgdk_tune(tgdk_op op, int dtype, int nrhs, int* tile_y) {
             while (fgets(line, sizeof(line), f)) {
                 int id;
                 const size_t kl = strlen(key);
-                if (strncmp(line, key, kl) == 0 && sscanf(line + kl, " tile=%d", &id) == 1 && id >= 0 && id <= 2) {
+                if (strncmp(line, key, kl) == 0 && sscanf(line + kl, " tile=%d", &id) == 1 && id >= 0 && id < NTILE_IDS) {
                     op->tile_id[dtype] = id;
                     fclose(f);
                     if (tile_y) {
@@ -601,7 +604,7 @@ int tgdk_tune(tgdk_op op, int dtype, int nrhs, int* tile_y) {
     (void)hipEventCreate(&e1);
     float best = 1e30f;
     int best_id = 0;
-    for (int id = 0; id <= 2; ++id) {
+    for (int id = 0; id < NTILE_IDS; ++id) {
         op->tile_id[dtype] = id;
         for (int w = 0; w < 3; ++w) op_apply_internal(op, 0, dtype, x, y, nrhs);
         (void)hipEventRecord(e0, op->ctx->stream);

@@ -38,6 +38,29 @@ struct Tile {
     static_assert(PTS % NT == 0, "tile must be a multiple of the workgroup");
 };
 
+// The tile shapes a launch can use, by id (picked per operator by the tuner):
+//   2-D: 0 = 64x16, 1 = 64x8, 2 = 64x4, 3 = 64x32
+//   3-D: 0 = 64x4x4, 1 = 64x8x4, 2 = 64x4x8, 3 = 64x2x8
+// with_tile<DIM>(id, f) calls f(Tile<...>{}) for that shape (host side).
+template <int DIM, class F>
+inline void with_tile(int tile_id, F&& f) {
+    if constexpr (DIM == 2) {
+        switch (tile_id) {
+            case 1: f(Tile<2, 8, 1>{}); break;
+            case 2: f(Tile<2, 4, 1>{}); break;
+            case 3: f(Tile<2, 32, 1>{}); break;
+            default: f(Tile<2, 16, 1>{}); break;
+        }
+    } else {
+        switch (tile_id) {
+            case 1: f(Tile<3, 8, 4>{}); break;
+            case 2: f(Tile<3, 4, 8>{}); break;
+            case 3: f(Tile<3, 2, 8>{}); break;
+            default: f(Tile<3, 4, 4>{}); break;
+        }
+    }
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int G) {
     const int q = G / NXCD, rem = G % NXCD;
     const int xcd = b % NXCD, local = b / NXCD;
@@ -74,6 +97,48 @@ template <class Cfg, int DIM, class T>
 __device__ __forceinline__ T stencil_row(const DevOp& op, const T* __restrict__ L, int c, long long g) {
     T cC, cW, cE, cS, cN, cD = 0, cU = 0;
     if (op.var) {
+        const T* cf = coef_ptr<T>(op);
+        const long long n = op.n;
+        cC = cf[g];
+        cW = cf[n + g];
+        cE = cf[2 * n + g];
+        cS = cf[3 * n + g];
+        cN = cf[4 * n + g];
+        if (DIM == 3) {
+            cD = cf[5 * n + g];
+            cU = cf[6 * n + g];
+        }
+    } else {
+        cC = (T)op.cc[0];
+        cW = (T)op.cc[1];
+        cE = (T)op.cc[2];
+        cS = (T)op.cc[3];
+        cN = (T)op.cc[4];
+        if (DIM == 3) {
+            cD = (T)op.cc[5];
+            cU = (T)op.cc[6];
+        }
+    }
+    T y = cC * L[c];
+    y += cW * L[c - 1];
+    y += cE * L[c + 1];
+    y += cS * L[c - Cfg::BX];
+    y += cN * L[c + Cfg::BX];
+    if (DIM == 3) {
+        y += cD * L[c - Cfg::BX * Cfg::BY];
+        y += cU * L[c + Cfg::BX * Cfg::BY];
+    }
+    return y;
+}
+
+// stencil_row with the coefficient kind narrowed at compile time: VAR = false
+// takes the constants only, so the constant-coefficient kernels carry no
+// branch and no wait for coefficient loads in their inner loops (VAR = true
+// decides per operator at run time); same terms, same order.
+template <class Cfg, int DIM, bool VAR, class T>
+__device__ __forceinline__ T stencil_row_t(const DevOp& op, const T* __restrict__ L, int c, long long g) {
+    T cC, cW, cE, cS, cN, cD = 0, cU = 0;
+    if (VAR && op.var) {
         const T* cf = coef_ptr<T>(op);
         const long long n = op.n;
         cC = cf[g];

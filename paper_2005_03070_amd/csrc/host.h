@@ -41,6 +41,7 @@ struct tgdk_ctx_s {
     tgdk::DevBuf partial;      // doubles
     unsigned* counters = nullptr;  // 64 zero-initialised counters
     double* dscal = nullptr;   // small device scalar area (4096 doubles)
+    void* zero = nullptr;      // 4 KiB of zeros, never written
     // solve workspace (grow-only, reused across calls)
     tgdk::DevBuf solve_ws;
     tgdk::Mirror* mirror = nullptr;  // host-mapped

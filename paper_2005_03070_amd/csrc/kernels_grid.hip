@@ -2,6 +2,9 @@
 // the adjoint coefficient gradient.
 #include "device_common.h"
 #include "launch.h"
+#include "march3d.h"
+
+#include <type_traits>
 
 namespace tgdk {
 
@@ -45,20 +48,59 @@ static void apply_cfg(const DevOp& op, const T* x, T* y, int nrhs, hipStream_t s
     hipLaunchKernelGGL((k_apply<Cfg, DIM, T>), grid, dim3(NT), 0, s, op, x, y, tx, ty);
 }
 
+// 3-D y = A x by z marching (march3d.h): one workgroup per column chunk
+// (blockIdx.x, XCD-remapped) and right-hand side (blockIdx.y).
+template <class T>
+struct ApplyPhase {
+    const T* __restrict__ x;
+    T* __restrict__ y;
+    const T* zero;
+    struct Own {
+        T v;
+    };
+    using Ring = Own;
+    __device__ __forceinline__ void load(Own& o, long long g) const { o.v = *(g >= 0 ? x + g : zero); }
+    __device__ __forceinline__ T value(const Own& o) const { return o.v; }
+    __device__ __forceinline__ void emit(long long g, const Own&, T yv) { y[g] = yv; }
+};
+
+template <class M, bool VAR, class T>
+__global__ __launch_bounds__(NT) void k_apply_march(DevOp op, const T* __restrict__ x, T* __restrict__ y, int cx,
+                                                    int cy, int mz) {
+    __shared__ T L[M::PLANE];
+    const Chunk k = chunk_of<M>(xcd_remap(blockIdx.x, gridDim.x), cx, cy, mz, op.nz);
+    const long long off = (long long)blockIdx.y * op.n;
+    ApplyPhase<T> ph{x + off, y + off, reinterpret_cast<const T*>(op.zero)};
+    march_chunk<M, VAR, T>(op, k, L, ph);
+}
+
+// chunks per launch the 3-D marching stencil aims for
+constexpr int APPLY_MARCH_CHUNKS = 1024;
+
 template <class T>
 void launch_apply(const DevOp& op, const T* x, T* y, int nrhs, int tile_id, hipStream_t s) {
     if (op.dim == 2) {
-        switch (tile_id) {
-            case 1: apply_cfg<Tile<2, 8, 1>, 2, T>(op, x, y, nrhs, s); break;
-            case 2: apply_cfg<Tile<2, 4, 1>, 2, T>(op, x, y, nrhs, s); break;
-            default: apply_cfg<Tile<2, 16, 1>, 2, T>(op, x, y, nrhs, s); break;
-        }
-    } else {
-        switch (tile_id) {
-            case 1: apply_cfg<Tile<3, 8, 4>, 3, T>(op, x, y, nrhs, s); break;
-            case 2: apply_cfg<Tile<3, 4, 8>, 3, T>(op, x, y, nrhs, s); break;
-            default: apply_cfg<Tile<3, 4, 4>, 3, T>(op, x, y, nrhs, s); break;
-        }
+        with_tile<2>(tile_id, [&](auto cfg) { apply_cfg<decltype(cfg), 2, T>(op, x, y, nrhs, s); });
+        return;
+    }
+    int target = APPLY_MARCH_CHUNKS, variant = 0;
+    if (const char* e = getenv("TGDK_MARCH_TARGET")) target = atoi(e);
+    if (const char* e = getenv("TGDK_MARCH_VARIANT")) variant = atoi(e);
+    auto go = [&](auto mcfg) {
+        using M = decltype(mcfg);
+        const int cx = (op.nx + 63) / 64, cy = (op.ny + M::MY - 1) / M::MY;
+        const int mz = march_depth(op.nz, cx, cy, target);
+        const int cz = (op.nz + mz - 1) / mz;
+        dim3 grid(cx * cy * cz, nrhs);
+        if (op.var)
+            hipLaunchKernelGGL((k_apply_march<M, true, T>), grid, dim3(NT), 0, s, op, x, y, cx, cy, mz);
+        else
+            hipLaunchKernelGGL((k_apply_march<M, false, T>), grid, dim3(NT), 0, s, op, x, y, cx, cy, mz);
+    };
+    switch (variant) {
+        case 2: go(March<32>{}); break;
+        case 4: go(March<8>{}); break;
+        default: go(March<16>{}); break;
     }
 }
 template void launch_apply<double>(const DevOp&, const double*, double*, int, int, hipStream_t);

@@ -367,19 +367,9 @@ static void solve_launch_cfg(int which, const DevProb* probs, int nprob, int tot
 template <int DIM, class TI>
 static void solve_launch_dim(int which, const DevProb* probs, int nprob, int total_tiles, int flag, int vtype,
                              int tile_id, hipStream_t s) {
-    if (DIM == 2) {
-        switch (tile_id) {
-            case 1: solve_launch_cfg<Tile<2, 8, 1>, 2, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
-            case 2: solve_launch_cfg<Tile<2, 4, 1>, 2, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
-            default: solve_launch_cfg<Tile<2, 16, 1>, 2, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
-        }
-    } else {
-        switch (tile_id) {
-            case 1: solve_launch_cfg<Tile<3, 8, 4>, 3, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
-            case 2: solve_launch_cfg<Tile<3, 4, 8>, 3, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
-            default: solve_launch_cfg<Tile<3, 4, 4>, 3, TI>(which, probs, nprob, total_tiles, flag, vtype, s); break;
-        }
-    }
+    with_tile<DIM>(tile_id, [&](auto cfg) {
+        solve_launch_cfg<decltype(cfg), DIM, TI>(which, probs, nprob, total_tiles, flag, vtype, s);
+    });
 }
 
 void launch_solve_kernel(int which, int dim, int inner_f32, int vtype, int tile_id, const DevProb* probs,
@@ -399,13 +389,16 @@ void launch_solve_kernel(int which, int dim, int inner_f32, int vtype, int tile_
 }
 
 void tile_shape(int dim, int tile_id, int* ty, int* tz) {
-    if (dim == 2) {
-        *tz = 1;
-        *ty = tile_id == 1 ? 8 : (tile_id == 2 ? 4 : 16);
-    } else {
-        *ty = tile_id == 1 ? 8 : 4;
-        *tz = tile_id == 2 ? 8 : 4;
-    }
+    if (dim == 2)
+        with_tile<2>(tile_id, [&](auto cfg) {
+            *ty = decltype(cfg)::TY;
+            *tz = 1;
+        });
+    else
+        with_tile<3>(tile_id, [&](auto cfg) {
+            *ty = decltype(cfg)::TY;
+            *tz = decltype(cfg)::TZ;
+        });
 }
 
 }  // namespace tgdk

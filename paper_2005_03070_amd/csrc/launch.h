@@ -32,11 +32,13 @@ void tile_shape(int dim, int tile_id, int* ty, int* tz);
 
 // BiCGStab step kernel: one launch advances every running problem of the
 // group by one step of its state machine.  wg_prob maps a workgroup id to its
-// problem; gslot is the launch number within the solve.
-void launch_step(int dim, int inner_f32, int vtype, int tile_id, const DevProb* probs, const int* wg_prob,
+// problem; gslot is the launch number within the solve; var: the operator has
+// per-row coefficient arrays.
+void launch_step(int dim, int inner_f32, int var, int tile_id, const DevProb* probs, const int* wg_prob,
                  int total_wg, int gslot, hipStream_t s);
-// workgroups the step kernel gives a problem of ntiles tiles
-int step_workgroups(int ntiles);
+template <int DIM>
+void launch_step_dim(int inner_f32, int var, int tile_id, const DevProb* probs, const int* wg_prob, int total_wg,
+                     int gslot, hipStream_t s);
 
 // tall-skinny products (column-major blocks, leading dimensions in elements)
 // G (p x q, row-major, device) = A^T B, A: n x p, B: n x q; partial workspace

@@ -30,6 +30,13 @@ struct ProbSpec {
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Workgroups of the step kernel per problem: on 2-D grids one per tile up to
+// this cap (beyond it each walks several tiles; the cap bounds the partial
+// sums every workgroup reads), on 3-D grids about STEP_CHUNKS z-marching
+// chunks.
+constexpr int STEP_WG_CAP = 1024;
+constexpr int STEP_CHUNKS = 1024;
+
 static int status_of(const SolveState& st) {
     switch (st.solve_state) {
         case SV_CONVERGED: return TGDK_OK;
@@ -67,6 +74,7 @@ static int ensure_events(tgdk_ctx ctx, int n) {
 struct Group {
     tgdk_ctx ctx = nullptr;
     int dim = 2, inner_f32 = 0, vtype = 0, tile_id = 0;
+    int var = 0;  // some operator of the group has per-row coefficient arrays
     int nprob = 0, total_tiles = 0;
     int total_wg = 0;      // step kernel workgroups
     int gslot = 0;         // step launches enqueued so far
@@ -89,7 +97,7 @@ static void launch(const Group& g, int which, int flag = 0) {
 // One step launch (with measurement on, the kernel stamps its start and end).
 static int launch_step_timed(Group& g) {
     const int slot = g.gslot++;
-    launch_step(g.dim, g.inner_f32, g.vtype, g.tile_id, g.d_probs, g.d_wgprob, g.total_wg, slot, g.ctx->stream);
+    launch_step(g.dim, g.inner_f32, g.var, g.tile_id, g.d_probs, g.d_wgprob, g.total_wg, slot, g.ctx->stream);
     return TGDK_OK;
 }
 
@@ -188,7 +196,22 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
         P.ntiles = P.tx * P.ty * P.tz;
         P.tile_begin = tiles;
         tiles += P.ntiles;
-        P.nwg = step_workgroups(P.ntiles);
+        if (g.dim == 3) {
+            // z-marching chunks of the step kernel's phases (64 x MY columns,
+            // about 1024 chunks in all); the boundary actions walk box tiles
+            const int my = 8;
+            P.mcx = (op->n[0] + 63) / 64;
+            P.mcy = (op->n[1] + my - 1) / my;
+            const long long cols = (long long)P.mcx * P.mcy;
+            long long mz = (cols * op->n[2] + STEP_CHUNKS - 1) / STEP_CHUNKS;
+            mz = std::max(4LL, std::min(mz, (long long)op->n[2]));
+            P.mz = (int)mz;
+            P.nchunks = (int)(cols * ((op->n[2] + P.mz - 1) / P.mz));
+            P.nwg = P.nchunks;
+        } else {
+            P.nwg = std::min(P.ntiles, STEP_WG_CAP);
+        }
+        g.var |= P.op.var;
         P.wg_begin = wgs;
         wgs += P.nwg;
         P.k = ps[j].defl ? ps[j].defl->k : 0;
@@ -257,6 +280,7 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
             P.lu = ps[j].defl->d_lu;
             P.piv = ps[j].defl->d_piv;
             P.hinv = ps[j].defl->d_hinv;
+            P.vtype = ps[j].defl->store == TGDK_F32 ? 1 : 0;
         }
         P.st = g.d_states + j;
         P.partial = (double*)(base + off_part[j]);

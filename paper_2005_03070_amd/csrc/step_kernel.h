@@ -32,16 +32,19 @@
 // residual and shadow vector; the first phase A of the next cycle shares its
 // launch with the test of that residual.  Problems advance independently: one
 // may sit at a cycle boundary while another iterates.
+//
+// 2-D grids: one workgroup per 64 x TY tile (walking several tiles when a
+// problem has more than 1024).  3-D grids: phases A and B march along z over
+// a column chunk per workgroup (march3d.h); the rare boundary actions use box
+// tiles.  Included by kernels_step2d.hip and kernels_step3d.hip, which
+// instantiate the two dimensions in separate translation units.
+#pragma once
+
 #include "device_common.h"
 #include "launch.h"
+#include "march3d.h"
 
 namespace tgdk {
-
-// Workgroups per problem: one per tile up to this cap, beyond it each
-// workgroup walks several tiles (bounds the partials every workgroup sums).
-constexpr int STEP_WG_CAP = 1024;
-
-int step_workgroups(int ntiles) { return ntiles < STEP_WG_CAP ? ntiles : STEP_WG_CAP; }
 
 // pending x update: x += e + a p + w s (p from buffer pbuf)
 struct Upd {
@@ -245,6 +248,11 @@ __device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* s
     }
 }
 
+// Element i of the stored deflation basis (float64 or float32, widened).
+__device__ __forceinline__ double vload(const DevProb& P, long long i) {
+    return P.vtype ? (double)reinterpret_cast<const float*>(P.V)[i] : reinterpret_cast<const double*>(P.V)[i];
+}
+
 // x + e + a p + w s at global index g (the folded inner update, float64).
 template <class TI>
 __device__ __forceinline__ double upd_at(const DevProb& P, const Upd& U, long long g) {
@@ -260,7 +268,7 @@ __device__ __forceinline__ double* part_at(const DevProb& P, int slot, int v, in
 }
 
 // ------------------------------------------------------------ phase A
-template <class Cfg, int DIM, class TI>
+template <class Cfg, int DIM, bool VAR, class TI>
 __device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, bool first, bool fin, const StepHot& N,
                                         const Upd& U, TI* L, double* sh) {
     const DevOp& op = P.op;
@@ -316,7 +324,7 @@ __device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, boo
         for (int q = 0; q < Cfg::PPT; ++q) {
             if (!okq[q]) continue;
             const long long g = gq[q];
-            const TI vv = stencil_row<Cfg, DIM, TI>(op, L, cq[q], g);
+            const TI vv = stencil_row_t<Cfg, DIM, VAR, TI>(op, L, cq[q], g);
             st_stream<DIM>(&pnew[g], L[cq[q]]);
             st_stream<DIM>(&vnew[g], vv);
             if (first) {
@@ -336,7 +344,7 @@ __device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, boo
 }
 
 // ------------------------------------------------------------ phase B
-template <class Cfg, int DIM, class TI>
+template <class Cfg, int DIM, bool VAR, class TI>
 __device__ __forceinline__ void phase_b(const DevProb& P, int lw, int gslot, const StepHot& N, TI* L, double* sh) {
     const DevOp& op = P.op;
     const int pb = ((gslot - 1) >> 1) & 1;  // v of this iteration's phase A
@@ -370,7 +378,7 @@ __device__ __forceinline__ void phase_b(const DevProb& P, int lw, int gslot, con
             if (!okq[q]) continue;
             const long long g = gq[q];
             const TI sv = L[cq[q]];
-            const TI tv = stencil_row<Cfg, DIM, TI>(op, L, cq[q], g);
+            const TI tv = stencil_row_t<Cfg, DIM, VAR, TI>(op, L, cq[q], g);
             st_stream<DIM>(&s[g], sv);
             st_stream<DIM>(&tt_[g], tv);
             const double rh = (double)rhq[q];
@@ -388,12 +396,33 @@ __device__ __forceinline__ void phase_b(const DevProb& P, int lw, int gslot, con
     if (threadIdx.x < 5) *part_at(P, gslot & 1, threadIdx.x, lw) = tot;
 }
 
+// c partial of one tile: wave w adds V_j^T r over the tile to csum[j] for
+// j = w, w + 4, ... (r of the tile in LDS in tile order).
+template <class Cfg, class TV>
+__device__ __forceinline__ void c_partials(const DevProb& P, const TilePos& tp, const TV* __restrict__ V,
+                                           const double* __restrict__ L, double* csum) {
+    const DevOp& op = P.op;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int j = w; j < P.k; j += NWAVE) {
+        const TV* __restrict__ Vj = V + (long long)j * P.ldv;
+        double a = 0.0;
+#pragma unroll 8
+        for (int m = 0; m < Cfg::PTS / 64; ++m) {
+            const int l = lane + 64 * m;
+            const int gx = tp.x0 + lane, gy = tp.y0 + (l / 64) % Cfg::TY, gz = tp.z0 + l / (64 * Cfg::TY);
+            if (inside(op, gx, gy, gz)) a += (double)Vj[gidx(op, gx, gy, gz)] * L[l];
+        }
+        a = wave_sum(a);
+        if (lane == 0) csum[j] += a;
+    }
+}
+
 // ------------------------------------------- true residual at a boundary
 // r = b - A x' with x' = x + e + a p + w s formed on the fly (x is written in
 // a later step, so neighbouring tiles still read the old x).  Partials:
 // ||r||^2, ||b||^2, r^.r in the inner type (no deflation: the next cycle's
 // inner residual and shadow vector are written here), and c = V^T r.
-template <class Cfg, int DIM, class TI, class TV>
+template <class Cfg, int DIM, bool VAR, class TI>
 __device__ __forceinline__ void true_residual(const DevProb& P, int lw, int gslot, const Upd& U, double* L,
                                               double* sh, double* csum) {
     const DevOp& op = P.op;
@@ -402,7 +431,6 @@ __device__ __forceinline__ void true_residual(const DevProb& P, int lw, int gslo
     TI* rin = vp<TI>(P.rin);
     TI* rhat = vp<TI>(P.rhat);
     const bool sep = (void*)rin != (void*)P.r;
-    const TV* __restrict__ V = vp<const TV>(P.V);
     const long long ldv = P.ldv;
     const double* __restrict__ x = P.x;
     const double* __restrict__ b = P.b;
@@ -431,7 +459,7 @@ __device__ __forceinline__ void true_residual(const DevProb& P, int lw, int gslo
             rv[q] = 0.0;
             if (!okq[q]) continue;
             const long long g = gq[q];
-            const double r = bq[q] - stencil_row<Cfg, DIM, double>(op, L, cq[q], g);
+            const double r = bq[q] - stencil_row_t<Cfg, DIM, VAR, double>(op, L, cq[q], g);
             rv[q] = r;
             P.r[g] = r;
             acc[0] += r * r;
@@ -450,19 +478,10 @@ __device__ __forceinline__ void true_residual(const DevProb& P, int lw, int gslo
 #pragma unroll
             for (int q = 0; q < Cfg::PPT; ++q) L[threadIdx.x + q * NT] = rv[q];
             __syncthreads();
-            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-            for (int j = w; j < k; j += NWAVE) {
-                const TV* __restrict__ Vj = V + (long long)j * ldv;
-                double a = 0.0;
-#pragma unroll 8
-                for (int m = 0; m < Cfg::PTS / 64; ++m) {
-                    const int l = lane + 64 * m;
-                    const int gx = tp.x0 + lane, gy = tp.y0 + (l / 64) % Cfg::TY, gz = tp.z0 + l / (64 * Cfg::TY);
-                    if (inside(op, gx, gy, gz)) a += (double)Vj[gidx(op, gx, gy, gz)] * L[l];
-                }
-                a = wave_sum(a);
-                if (lane == 0) csum[j] += a;
-            }
+            if (P.vtype)
+                c_partials<Cfg>(P, tp, reinterpret_cast<const float*>(P.V), L, csum);
+            else
+                c_partials<Cfg>(P, tp, reinterpret_cast<const double*>(P.V), L, csum);
         }
         __syncthreads();
     }
@@ -507,12 +526,11 @@ __device__ __forceinline__ void projection_coefficients(const DevProb& P, int gs
 // w = V d on the tile and its halo (LDS, float64); x <- x + upd + w and
 // r <- r - A w on the tile; the new cycle's inner residual and shadow vector;
 // partials ||r||^2 and r^.r in the inner type.
-template <class Cfg, int DIM, class TI, class TV>
+template <class Cfg, int DIM, bool VAR, class TI>
 __device__ __forceinline__ void apply_projection(const DevProb& P, int lw, int gslot, const Upd& U,
                                                  const SolveState* st, double* L, double* sh, double* dsh) {
     const DevOp& op = P.op;
     const int k = P.k;
-    const TV* __restrict__ V = vp<const TV>(P.V);
     const long long ldv = P.ldv;
     TI* rin = vp<TI>(P.rin);
     TI* rhat = vp<TI>(P.rhat);
@@ -521,7 +539,7 @@ __device__ __forceinline__ void apply_projection(const DevProb& P, int lw, int g
     __syncthreads();
     auto wval = [&](long long g) {
         double w = 0.0;
-        for (int j = 0; j < k; ++j) w += (double)V[(long long)j * ldv + g] * dsh[j];
+        for (int j = 0; j < k; ++j) w += vload(P, (long long)j * ldv + g) * dsh[j];
         return w;
     };
     double acc[2] = {0.0, 0.0};
@@ -548,7 +566,7 @@ __device__ __forceinline__ void apply_projection(const DevProb& P, int lw, int g
             double xv = P.x[g];
             if (U.any) xv += upd_at<TI>(P, U, g);
             P.x[g] = xv + L[c];
-            const double rv = P.r[g] - stencil_row<Cfg, DIM, double>(op, L, c, g);
+            const double rv = P.r[g] - stencil_row_t<Cfg, DIM, VAR, double>(op, L, c, g);
             P.r[g] = rv;
             acc[0] += rv * rv;
             const TI ri = (TI)rv;
@@ -580,12 +598,177 @@ __device__ __forceinline__ void fold_update(const DevProb& P, int lw, const Upd&
     }
 }
 
+// ------------------------------------------------ 3-D phases by z marching
+// The same arithmetic as phase_a / phase_b (same expressions, same order),
+// written as march_chunk phases: raw loads per point and plane, the stencil
+// input, and the outputs at the plane being computed.
+template <class TI>
+struct MarchA {  // phase A of iteration i > 0
+    const TI *s, *t, *po, *vo, *rh, *zero;
+    TI *pnew, *vnew, *rin, *e;
+    TI alpha, omega, beta;
+    double acc[2] = {0.0, 0.0};
+    struct Own {
+        TI s, t, po, vo, e, rh;
+    };
+    struct Ring {
+        TI s, t, po, vo;
+    };
+    __device__ __forceinline__ const TI* at(const TI* a, long long g) const { return g >= 0 ? a + g : zero; }
+    __device__ __forceinline__ void load(Own& o, long long g) const {
+        o.s = *at(s, g);
+        o.t = *at(t, g);
+        o.po = *at(po, g);
+        o.vo = *at(vo, g);
+        o.e = *at(e, g);
+        o.rh = *at(rh, g);
+    }
+    __device__ __forceinline__ void load(Ring& o, long long g) const {
+        o.s = *at(s, g);
+        o.t = *at(t, g);
+        o.po = *at(po, g);
+        o.vo = *at(vo, g);
+    }
+    template <class R>
+    __device__ __forceinline__ TI value(const R& o) const {
+        const TI r = o.s - omega * o.t;
+        return r + beta * (o.po - omega * o.vo);
+    }
+    __device__ __forceinline__ void emit(long long g, const Own& c, TI y) {
+        const TI r = c.s - omega * c.t;
+        pnew[g] = r + beta * (c.po - omega * c.vo);
+        vnew[g] = y;
+        rin[g] = r;
+        e[g] = c.e + alpha * c.po + omega * c.s;
+        acc[0] += (double)c.rh * (double)y;
+        acc[1] += (double)r * (double)r;
+    }
+};
+
+template <class TI>
+struct MarchA0 {  // phase A of iteration 0, optionally folding the last update into x
+    const TI *rin, *rh, *zero;
+    TI *pnew, *vnew, *e;
+    const DevProb* P;
+    Upd U;
+    bool fin;
+    double acc[2] = {0.0, 0.0};
+    struct Own {
+        TI r, rh;
+    };
+    struct Ring {
+        TI r;
+    };
+    __device__ __forceinline__ const TI* at(const TI* a, long long g) const { return g >= 0 ? a + g : zero; }
+    __device__ __forceinline__ void load(Own& o, long long g) const {
+        o.r = *at(rin, g);
+        o.rh = *at(rh, g);
+    }
+    __device__ __forceinline__ void load(Ring& o, long long g) const { o.r = *at(rin, g); }
+    template <class R>
+    __device__ __forceinline__ TI value(const R& o) const {
+        return o.r;
+    }
+    __device__ __forceinline__ void emit(long long g, const Own& c, TI y) {
+        if (fin) P->x[g] += upd_at<TI>(*P, U, g);
+        pnew[g] = c.r;
+        vnew[g] = y;
+        e[g] = TI(0);
+        acc[0] += (double)c.rh * (double)y;
+        acc[1] += (double)c.r * (double)c.r;
+    }
+};
+
+template <class TI>
+struct MarchB {  // phase B
+    const TI *rin, *v, *rh, *zero;
+    TI *s, *t;
+    TI alpha;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    struct Own {
+        TI r, v, rh;
+    };
+    struct Ring {
+        TI r, v;
+    };
+    __device__ __forceinline__ const TI* at(const TI* a, long long g) const { return g >= 0 ? a + g : zero; }
+    __device__ __forceinline__ void load(Own& o, long long g) const {
+        o.r = *at(rin, g);
+        o.v = *at(v, g);
+        o.rh = *at(rh, g);
+    }
+    __device__ __forceinline__ void load(Ring& o, long long g) const {
+        o.r = *at(rin, g);
+        o.v = *at(v, g);
+    }
+    template <class R>
+    __device__ __forceinline__ TI value(const R& o) const {
+        return o.r - alpha * o.v;
+    }
+    __device__ __forceinline__ void emit(long long g, const Own& c, TI y) {
+        const TI sv = c.r - alpha * c.v;
+        s[g] = sv;
+        t[g] = y;
+        const double rh = (double)c.rh, sd = (double)sv, td = (double)y;
+        acc[0] += sd * sd;
+        acc[1] += td * sd;
+        acc[2] += td * td;
+        acc[3] += rh * sd;
+        acc[4] += rh * td;
+    }
+};
+
+// z-marching tile of the 3-D step kernel: 64 x 8 (two points per thread and
+// plane, so that four planes of phase A's six raw values stay in registers)
+template <class TI>
+using StepMarch = March<8>;
+
+template <bool VAR, class TI, class Ph, int NV>
+__device__ __forceinline__ void march_phase(const DevProb& P, int lw, int gslot, Ph& ph, TI* L, double* sh) {
+    using M = StepMarch<TI>;
+    if (lw < P.nchunks) {
+        const Chunk k = chunk_of<M>(lw, P.mcx, P.mcy, P.mz, P.op.nz);
+        march_chunk<M, VAR, TI>(P.op, k, L, ph);
+    }
+    double tot;
+    block_sum<NV>(ph.acc, sh, tot);
+    if (threadIdx.x < NV) *part_at(P, gslot & 1, threadIdx.x, lw) = tot;
+}
+
+template <bool VAR, class TI>
+__device__ __forceinline__ void march_a(const DevProb& P, int lw, int gslot, bool first, bool fin, const StepHot& N,
+                                        const Upd& U, TI* L, double* sh) {
+    const int pb = (gslot >> 1) & 1;
+    const TI* zero = reinterpret_cast<const TI*>(P.op.zero);
+    if (first) {
+        MarchA0<TI> ph{vp<const TI>(P.rin), vp<const TI>(P.rhat), zero, vp<TI>(P.p[pb]), vp<TI>(P.v[pb]),
+                       vp<TI>(P.e), &P, U, fin};
+        march_phase<VAR, TI, MarchA0<TI>, 2>(P, lw, gslot, ph, L, sh);
+    } else {
+        const TI alpha = (TI)N.alpha, omega = (TI)N.omega;
+        const TI beta = (TI)((N.rho / N.rho_old) * (N.alpha / N.omega));
+        MarchA<TI> ph{vp<const TI>(P.s), vp<const TI>(P.t), vp<const TI>(P.p[pb ^ 1]), vp<const TI>(P.v[pb ^ 1]),
+                      vp<const TI>(P.rhat), zero, vp<TI>(P.p[pb]), vp<TI>(P.v[pb]), vp<TI>(P.rin), vp<TI>(P.e),
+                      alpha, omega, beta};
+        march_phase<VAR, TI, MarchA<TI>, 2>(P, lw, gslot, ph, L, sh);
+    }
+}
+
+template <bool VAR, class TI>
+__device__ __forceinline__ void march_b(const DevProb& P, int lw, int gslot, const StepHot& N, TI* L, double* sh) {
+    const int pb = ((gslot - 1) >> 1) & 1;
+    MarchB<TI> ph{vp<const TI>(P.rin), vp<const TI>(P.v[pb]), vp<const TI>(P.rhat),
+                  reinterpret_cast<const TI*>(P.op.zero), vp<TI>(P.s), vp<TI>(P.t), (TI)N.alpha};
+    march_phase<VAR, TI, MarchB<TI>, 5>(P, lw, gslot, ph, L, sh);
+}
+
 // ------------------------------------------------------------- kernel
-template <class Cfg, int DIM, class TI, class TV>
+template <class Cfg, int DIM, bool VAR, class TI>
 __global__ __launch_bounds__(NT) void k_step(const DevProb* __restrict__ probs, const int* __restrict__ wg_prob,
                                              int gslot) {
     const unsigned long long t_begin = (unsigned long long)wall_clock64();
-    __shared__ double Lbox[Cfg::BOX];
+    constexpr int NBOX = (DIM == 3 && StepMarch<TI>::PLANE > Cfg::BOX) ? StepMarch<TI>::PLANE : Cfg::BOX;
+    __shared__ double Lbox[NBOX];
     __shared__ double sh[NWAVE * 16];
     __shared__ double ysh[MAXK + 1];
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
@@ -628,25 +811,27 @@ __global__ __launch_bounds__(NT) void k_step(const DevProb* __restrict__ probs, 
     TI* L = reinterpret_cast<TI*>(Lbox);
     switch (act) {
         case ACT_A:
-            phase_a<Cfg, DIM, TI>(P, lw, gslot, false, false, N, U, L, sh);
-            break;
         case ACT_A0:
-            phase_a<Cfg, DIM, TI>(P, lw, gslot, true, false, N, U, L, sh);
-            break;
         case ACT_FIN_A0:
-            phase_a<Cfg, DIM, TI>(P, lw, gslot, true, true, N, U, L, sh);
+            if constexpr (DIM == 3)
+                march_a<VAR, TI>(P, lw, gslot, act != ACT_A, act == ACT_FIN_A0, N, U, L, sh);
+            else
+                phase_a<Cfg, DIM, VAR, TI>(P, lw, gslot, act != ACT_A, act == ACT_FIN_A0, N, U, L, sh);
             break;
         case ACT_B:
-            phase_b<Cfg, DIM, TI>(P, lw, gslot, N, L, sh);
+            if constexpr (DIM == 3)
+                march_b<VAR, TI>(P, lw, gslot, N, L, sh);
+            else
+                phase_b<Cfg, DIM, VAR, TI>(P, lw, gslot, N, L, sh);
             break;
         case ACT_RES:
-            true_residual<Cfg, DIM, TI, TV>(P, lw, gslot, U, Lbox, sh, ysh);
+            true_residual<Cfg, DIM, VAR, TI>(P, lw, gslot, U, Lbox, sh, ysh);
             break;
         case ACT_REDUCE:
             if (lead) projection_coefficients(P, gslot, st, ysh, sh);
             break;
         case ACT_APPLY:
-            apply_projection<Cfg, DIM, TI, TV>(P, lw, gslot, U, st, Lbox, sh, ysh);
+            apply_projection<Cfg, DIM, VAR, TI>(P, lw, gslot, U, st, Lbox, sh, ysh);
             break;
         case ACT_FIN:
             fold_update<Cfg, TI>(P, lw, U);
@@ -667,46 +852,24 @@ __global__ __launch_bounds__(NT) void k_step(const DevProb* __restrict__ probs, 
 }
 
 // ------------------------------------------------------------ launcher
-template <class Cfg, int DIM, class TI>
-static void step_cfg(int vtype, const DevProb* probs, const int* wg_prob, int total_wg, int gslot, hipStream_t s) {
-    if (vtype == 1)
-        hipLaunchKernelGGL((k_step<Cfg, DIM, TI, float>), dim3(total_wg), dim3(NT), 0, s, probs, wg_prob, gslot);
-    else
-        hipLaunchKernelGGL((k_step<Cfg, DIM, TI, double>), dim3(total_wg), dim3(NT), 0, s, probs, wg_prob, gslot);
-}
-
-template <int DIM, class TI>
-static void step_dim(int vtype, int tile_id, const DevProb* probs, const int* wg_prob, int total_wg, int gslot,
-                     hipStream_t s) {
-    if (DIM == 2) {
-        switch (tile_id) {
-            case 1: step_cfg<Tile<2, 8, 1>, 2, TI>(vtype, probs, wg_prob, total_wg, gslot, s); break;
-            case 2: step_cfg<Tile<2, 4, 1>, 2, TI>(vtype, probs, wg_prob, total_wg, gslot, s); break;
-            default: step_cfg<Tile<2, 16, 1>, 2, TI>(vtype, probs, wg_prob, total_wg, gslot, s); break;
+template <int DIM>
+void launch_step_dim(int inner_f32, int var, int tile_id, const DevProb* probs, const int* wg_prob, int total_wg,
+                     int gslot, hipStream_t s) {
+    with_tile<DIM>(tile_id, [&](auto cfg) {
+        using Cfg = decltype(cfg);
+        const dim3 grid(total_wg), block(NT);
+        if (inner_f32) {
+            if (var)
+                hipLaunchKernelGGL((k_step<Cfg, DIM, true, float>), grid, block, 0, s, probs, wg_prob, gslot);
+            else
+                hipLaunchKernelGGL((k_step<Cfg, DIM, false, float>), grid, block, 0, s, probs, wg_prob, gslot);
+        } else {
+            if (var)
+                hipLaunchKernelGGL((k_step<Cfg, DIM, true, double>), grid, block, 0, s, probs, wg_prob, gslot);
+            else
+                hipLaunchKernelGGL((k_step<Cfg, DIM, false, double>), grid, block, 0, s, probs, wg_prob, gslot);
         }
-    } else {
-        switch (tile_id) {
-            case 1: step_cfg<Tile<3, 8, 4>, 3, TI>(vtype, probs, wg_prob, total_wg, gslot, s); break;
-            case 2: step_cfg<Tile<3, 4, 8>, 3, TI>(vtype, probs, wg_prob, total_wg, gslot, s); break;
-            default: step_cfg<Tile<3, 4, 4>, 3, TI>(vtype, probs, wg_prob, total_wg, gslot, s); break;
-        }
-    }
-}
-
-void launch_step(int dim, int inner_f32, int vtype, int tile_id, const DevProb* probs, const int* wg_prob,
-                 int total_wg, int gslot, hipStream_t s) {
-    if (total_wg <= 0) return;
-    if (dim == 2) {
-        if (inner_f32)
-            step_dim<2, float>(vtype, tile_id, probs, wg_prob, total_wg, gslot, s);
-        else
-            step_dim<2, double>(vtype, tile_id, probs, wg_prob, total_wg, gslot, s);
-    } else {
-        if (inner_f32)
-            step_dim<3, float>(vtype, tile_id, probs, wg_prob, total_wg, gslot, s);
-        else
-            step_dim<3, double>(vtype, tile_id, probs, wg_prob, total_wg, gslot, s);
-    }
+    });
 }
 
 }  // namespace tgdk

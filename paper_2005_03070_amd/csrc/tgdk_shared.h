@@ -8,6 +8,7 @@ namespace tgdk {
 constexpr int MAXK = 128;   // largest deflation space / GMRES cycle length
 constexpr int NHIST = 8;    // recorded first BiCGStab scalars
 constexpr int NCYCLOG = 512;  // cycles whose inner iteration counts are logged
+constexpr int NTILE_IDS = 4;  // tile shapes of the grid kernels (ids 0..3)
 
 // An operator as the kernels see it (passed by value or inside DevProb).
 struct DevOp {
@@ -18,6 +19,7 @@ struct DevOp {
     double cc[7];            // constant coefficients C, W, E, S, N, D, U
     const double* coef64;    // var: (2*dim+1) arrays of n, same order
     const float* coef32;
+    const void* zero;        // 4 KiB of zeros (loads of out-of-domain points read here)
 };
 
 // inner cycle state
@@ -121,6 +123,8 @@ struct DevProb {
     void* e;
     const void* V;           // deflation basis, column-major, leading dim ldv
     long long ldv;
+    int vtype;               // V stored as 0 float64, 1 float32
+    int mcx, mcy, mz, nchunks;  // 3-D step kernel: z-marching chunks (mcx x mcy columns, mz planes deep)
     const double* lu;        // LU factors of H (k x k, row-major), pivots
     const int* piv;
     const double* hinv;      // H^{-1} (k x k, column-major)
