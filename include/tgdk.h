@@ -88,9 +88,10 @@ int tgdk_ctx_num_cus(tgdk_ctx ctx);
 #define TGDK_STEP_B      3  /* phase B: s = r - alpha v, t = A s, five dot-product partials */
 #define TGDK_STEP_RES    4  /* end of a cycle: r = b - A (x + update), ||r||^2 and c = V^T r partials */
 #define TGDK_STEP_REDUCE 5  /* c summed and H d = c solved (one workgroup) */
-#define TGDK_STEP_APPLY  6  /* x += update + V d, r -= A V d, new shadow vector */
+#define TGDK_STEP_APPLY  6  /* x += update + V d, r -= A V d, new shadow vector (3-D: r -= A w only) */
 #define TGDK_STEP_FIN    7  /* final update folded into x */
 #define TGDK_STEP_FIN_A0 8  /* update folded into x and phase A of iteration 0 (no deflation) */
+#define TGDK_STEP_APPLYW 9  /* 3-D: w = V d and x += update + w (APPLY then does r -= A w) */
 #define TGDK_STEP_ANY   -1
 int tgdk_ctx_time_kernel(tgdk_ctx ctx, int on);
 int tgdk_ctx_kernel_time(tgdk_ctx ctx, int action, double* total_ms, long long* launches);

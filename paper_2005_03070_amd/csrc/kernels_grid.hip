@@ -59,9 +59,11 @@ struct ApplyPhase {
         T v;
     };
     using Ring = Own;
+    static constexpr bool PLANE_HOOK = false;
     __device__ __forceinline__ void load(Own& o, long long g) const { o.v = *(g >= 0 ? x + g : zero); }
     __device__ __forceinline__ T value(const Own& o) const { return o.v; }
-    __device__ __forceinline__ void emit(long long g, const Own&, T yv) { y[g] = yv; }
+    __device__ __forceinline__ void emit(int, long long g, const Own&, T yv) { y[g] = yv; }
+    __device__ __forceinline__ void plane_done(const Chunk&, int) {}
 };
 
 template <class M, bool VAR, class T>

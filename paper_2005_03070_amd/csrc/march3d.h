@@ -123,8 +123,10 @@ namespace tgdk {
 //   void load(Own&, long long g)   g < 0: a point outside the domain (reads zeros)
 //   void load(Ring&, long long g)
 //   T value(const Own&), T value(const Ring&)     the stencil input u
-//   void emit(long long g, const Own& c, T y)     outputs at own point g of plane z,
-//                                                 y = (A u) there
+//   void emit(int q, long long g, const Own& c, T y)   outputs at own point q
+//                                                 (global index g) of plane z, y = (A u) there
+//   void plane_done(const Chunk&, int z)          after every thread's emits of plane z
+//                                                 (between two workgroup barriers)
 // Four register sets hold the own points of planes z-1, z, z+1 and z+2 (the
 // last in flight while plane z is computed); the loop is unrolled four times
 // so the sets change roles by position, never by register moves (a move
@@ -187,8 +189,12 @@ __device__ __forceinline__ void march_chunk(const DevOp& op, const Chunk& k, T* 
         for (int q = 0; q < M::PPT; ++q)
             if (okq[q]) {
                 const long long g = z * plane + bq[q];
-                ph.emit(g, oc[q], stencil_march<M, VAR, T>(op, L, cq[q], g, ph.value(om[q]), ph.value(op_[q])));
+                ph.emit(q, g, oc[q], stencil_march<M, VAR, T>(op, L, cq[q], g, ph.value(om[q]), ph.value(op_[q])));
             }
+        if constexpr (Ph::PLANE_HOOK) {
+            __syncthreads();
+            ph.plane_done(k, z);
+        }
         __syncthreads();
     };
     Own o0[M::PPT], o1[M::PPT], o2[M::PPT], o3[M::PPT];

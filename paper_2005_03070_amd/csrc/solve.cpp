@@ -222,6 +222,7 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
         const size_t n = (size_t)op->N;
         off += align256(n * 8);                            // r (float64)
         off += (g.inner_f32 ? 9 : 8) * align256(n * ies);  // inner vectors
+        if (g.dim == 3 && P.k > 0) off += align256(n * 8);  // w = V d (3-D boundary)
         off_part[j] = off;
         // tile kernels: ntiles rows; step kernel: two launch-parity slots
         off += align256((size_t)std::max((long long)P.ntiles * P.pstride, 2 * P.pslot) * 8);
@@ -274,6 +275,7 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
         P.s = vecs[i++];
         P.t = vecs[i++];
         P.e = vecs[i++];
+        if (g.dim == 3 && P.k > 0) P.w = (double*)v;
         if (ps[j].defl) {
             P.V = ps[j].defl->V;
             P.ldv = ps[j].defl->n;

@@ -114,8 +114,8 @@ __device__ __forceinline__ void boundary_tests(const StepHot& H, StepHot& N, con
 // The scalar part of a step.  Every workgroup of the problem evaluates it on
 // the same inputs; only the scribe (thread 0 of the lead workgroup) writes
 // the report counters.  Returns the action of this launch.
-__device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* st, int k, int gslot, bool scribe,
-                           StepHot& N, Upd& U, double& rr_out, double& rr0_out) {
+__device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* st, int k, int dim, int gslot,
+                           bool scribe, StepHot& N, Upd& U, double& rr_out, double& rr0_out) {
     N = H;
     U = Upd{H.upd_a, H.upd_w, H.upd_any, H.pbuf};
     const int after_res = k > 0 ? M_REDUCE : M_APPLY0;
@@ -202,7 +202,7 @@ __device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* s
                 return H.upd_any ? ACT_FIN : ACT_NONE;
             }
             if (H.mode == M_REDUCE) {
-                N.mode = M_APPLY;
+                N.mode = dim == 3 ? M_APPLYW : M_APPLY;
                 return ACT_REDUCE;
             }
             double rt;
@@ -215,6 +215,10 @@ __device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* s
             N.mode = M_B;
             return H.upd_any ? ACT_FIN_A0 : ACT_A0;
         }
+        case M_APPLYW:
+            N.mode = M_APPLY;
+            N.upd_any = 0;
+            return ACT_APPLYW;
         case M_APPLY:
             N.mode = M_START;
             N.upd_any = 0;
@@ -634,7 +638,9 @@ struct MarchA {  // phase A of iteration i > 0
         const TI r = o.s - omega * o.t;
         return r + beta * (o.po - omega * o.vo);
     }
-    __device__ __forceinline__ void emit(long long g, const Own& c, TI y) {
+    static constexpr bool PLANE_HOOK = false;
+    __device__ __forceinline__ void plane_done(const Chunk&, int) {}
+    __device__ __forceinline__ void emit(int, long long g, const Own& c, TI y) {
         const TI r = c.s - omega * c.t;
         pnew[g] = r + beta * (c.po - omega * c.vo);
         vnew[g] = y;
@@ -669,7 +675,9 @@ struct MarchA0 {  // phase A of iteration 0, optionally folding the last update 
     __device__ __forceinline__ TI value(const R& o) const {
         return o.r;
     }
-    __device__ __forceinline__ void emit(long long g, const Own& c, TI y) {
+    static constexpr bool PLANE_HOOK = false;
+    __device__ __forceinline__ void plane_done(const Chunk&, int) {}
+    __device__ __forceinline__ void emit(int, long long g, const Own& c, TI y) {
         if (fin) P->x[g] += upd_at<TI>(*P, U, g);
         pnew[g] = c.r;
         vnew[g] = y;
@@ -705,7 +713,9 @@ struct MarchB {  // phase B
     __device__ __forceinline__ TI value(const R& o) const {
         return o.r - alpha * o.v;
     }
-    __device__ __forceinline__ void emit(long long g, const Own& c, TI y) {
+    static constexpr bool PLANE_HOOK = false;
+    __device__ __forceinline__ void plane_done(const Chunk&, int) {}
+    __device__ __forceinline__ void emit(int, long long g, const Own& c, TI y) {
         const TI sv = c.r - alpha * c.v;
         s[g] = sv;
         t[g] = y;
@@ -762,6 +772,225 @@ __device__ __forceinline__ void march_b(const DevProb& P, int lw, int gslot, con
     march_phase<VAR, TI, MarchB<TI>, 5>(P, lw, gslot, ph, L, sh);
 }
 
+// --------------------------------------- 3-D cycle boundary by z marching
+// True residual r = b - A x' with x' = x + e + a p + w s formed on the fly,
+// with its partials; then, in a second pass over the workgroup's own chunk
+// (r read back after a workgroup barrier), c = V^T r (chunk_columns).
+template <class TI>
+struct MarchRes {
+    const double *x, *b;
+    const TI *e, *p, *s;
+    const double* zero64;
+    const TI* zeroT;
+    Upd U;
+    double* r;
+    TI *rin, *rhat;
+    bool start, sep;
+    double acc[3] = {0.0, 0.0, 0.0};
+    static constexpr bool PLANE_HOOK = false;
+    struct Own {
+        double x, b;
+        TI e, p, s;
+    };
+    struct Ring {
+        double x;
+        TI e, p, s;
+    };
+    template <class R>
+    __device__ __forceinline__ void load_upd(R& o, long long g) const {
+        o.x = *(g >= 0 ? x + g : zero64);
+        o.e = *(U.any && g >= 0 ? e + g : zeroT);
+        o.p = *(U.any && U.a != 0.0 && g >= 0 ? p + g : zeroT);
+        o.s = *(U.any && U.w != 0.0 && g >= 0 ? s + g : zeroT);
+    }
+    __device__ __forceinline__ void load(Own& o, long long g) const {
+        load_upd(o, g);
+        o.b = *(g >= 0 ? b + g : zero64);
+    }
+    __device__ __forceinline__ void load(Ring& o, long long g) const { load_upd(o, g); }
+    template <class R>
+    __device__ __forceinline__ double value(const R& o) const {
+        if (!U.any) return o.x;
+        double u = (double)o.e;
+        if (U.a != 0.0) u += U.a * (double)o.p;
+        if (U.w != 0.0) u += U.w * (double)o.s;
+        return o.x + u;
+    }
+    __device__ __forceinline__ void emit(int, long long g, const Own& c, double y) {
+        const double rr = c.b - y;
+        r[g] = rr;
+        acc[0] += rr * rr;
+        acc[1] += c.b * c.b;
+        if (start) {
+            const TI ri = (TI)rr;
+            if (sep) rin[g] = ri;
+            rhat[g] = ri;
+            acc[2] += (double)ri * (double)ri;
+        }
+    }
+    __device__ __forceinline__ void plane_done(const Chunk&, int) {}
+};
+
+// c partial of one chunk: the workgroup streams the chunk's points (thread
+// t takes points t, t + 256, ... in x-y-z order, coalesced) against four
+// columns of V at a time, reading r once per group of columns; per-thread
+// sums are combined by block_sum, so the order is fixed.
+template <class M, class TV>
+__device__ __forceinline__ void chunk_columns(const DevProb& P, const Chunk& c, const TV* __restrict__ V,
+                                              double* csum, double* sh) {
+    const DevOp& op = P.op;
+    const long long plane = (long long)op.nx * op.ny;
+    const double* __restrict__ r = P.r;
+    const int k = P.k;
+    const int npts = 64 * M::MY * (c.z1 - c.z0);
+    for (int j0 = 0; j0 < k; j0 += 4) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        const TV* __restrict__ Vj[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) Vj[jj] = V + (long long)(j0 + jj < k ? j0 + jj : j0) * P.ldv;
+#pragma unroll 4
+        for (int l = threadIdx.x; l < npts; l += NT) {
+            const int gx = c.x0 + (l & 63), gy = c.y0 + ((l >> 6) % M::MY), z = c.z0 + l / (64 * M::MY);
+            if (gx < op.nx && gy < op.ny) {
+                const long long g = z * plane + (long long)gy * op.nx + gx;
+                const double rv = r[g];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) a[jj] += (double)Vj[jj][g] * rv;
+            }
+        }
+        double tot;
+        block_sum<4>(a, sh, tot);
+        if (threadIdx.x < 4 && j0 + threadIdx.x < k) csum[j0 + threadIdx.x] = tot;
+    }
+}
+
+template <bool VAR, class TI>
+__device__ __forceinline__ void march_res(const DevProb& P, int lw, int gslot, const Upd& U, double* Lbox,
+                                          double* sh, double* csum) {
+    using M = StepMarch<TI>;
+    const int k = P.k;
+    for (int i = threadIdx.x; i < k; i += NT) csum[i] = 0.0;
+    TI* rin = vp<TI>(P.rin);
+    MarchRes<TI> ph{P.x, P.b, vp<const TI>(P.e), vp<const TI>(P.p[U.pbuf]), vp<const TI>(P.s),
+                    reinterpret_cast<const double*>(P.op.zero), reinterpret_cast<const TI*>(P.op.zero), U, P.r,
+                    rin, vp<TI>(P.rhat), k == 0, (void*)rin != (void*)P.r};
+    if (lw < P.nchunks) {
+        const Chunk c = chunk_of<M>(lw, P.mcx, P.mcy, P.mz, P.op.nz);
+        // the 64 x 8 chunk as two 64 x 4 half columns: one point per thread
+        // and plane keeps the residual's raw loads within the register
+        // budget of the whole kernel
+        using MH = March<M::MY / 2>;
+        Chunk h = c;
+        march_chunk<MH, VAR, double>(P.op, h, Lbox, ph);
+        h.y0 += MH::MY;
+        if (h.y0 < P.op.ny) march_chunk<MH, VAR, double>(P.op, h, Lbox, ph);
+        __syncthreads();  // r of the chunk, written above, is read back below
+        if (k > 0) {
+            if (P.vtype)
+                chunk_columns<M>(P, c, reinterpret_cast<const float*>(P.V), csum, sh);
+            else
+                chunk_columns<M>(P, c, reinterpret_cast<const double*>(P.V), csum, sh);
+        }
+    }
+    __syncthreads();
+    double tot;
+    block_sum<3>(ph.acc, sh, tot);
+    const int slot = gslot & 1;
+    if (threadIdx.x < 3) *part_at(P, slot, threadIdx.x, lw) = tot;
+    for (int i = threadIdx.x; i < k; i += NT) *part_at(P, slot, 3 + i, lw) = csum[i];
+}
+
+// w = V d and x <- (x + e + a p + w s) + w on this workgroup's chunk (pointwise).
+template <class TI, class TV>
+__device__ __forceinline__ void apply_w_points(const DevProb& P, int lw, const Upd& U, const TV* __restrict__ V,
+                                               const double* __restrict__ dsh) {
+    using M = StepMarch<TI>;
+    if (lw >= P.nchunks) return;
+    const DevOp& op = P.op;
+    const Chunk c = chunk_of<M>(lw, P.mcx, P.mcy, P.mz, op.nz);
+    const long long plane = (long long)op.nx * op.ny;
+    const int k = P.k;
+    for (int z = c.z0; z < c.z1; ++z) {
+#pragma unroll
+        for (int q = 0; q < M::PPT; ++q) {
+            int lx, ly, ci;
+            own_point<M>(q, lx, ly, ci);
+            const int gx = c.x0 + lx, gy = c.y0 + ly;
+            if (gx >= op.nx || gy >= op.ny) continue;
+            const long long g = z * plane + (long long)gy * op.nx + gx;
+            double w = 0.0;
+#pragma unroll 8
+            for (int j = 0; j < k; ++j) w += (double)V[(long long)j * P.ldv + g] * dsh[j];
+            P.w[g] = w;
+            double xv = P.x[g];
+            if (U.any) xv += upd_at<TI>(P, U, g);
+            P.x[g] = xv + w;
+        }
+    }
+}
+
+template <class TI>
+__device__ __forceinline__ void apply_w(const DevProb& P, int lw, const Upd& U, const SolveState* st, double* dsh) {
+    for (int i = threadIdx.x; i < P.k; i += NT) dsh[i] = st->d[i];
+    __syncthreads();
+    if (P.vtype)
+        apply_w_points<TI>(P, lw, U, reinterpret_cast<const float*>(P.V), dsh);
+    else
+        apply_w_points<TI>(P, lw, U, reinterpret_cast<const double*>(P.V), dsh);
+}
+
+// r <- r - A w; the new cycle's inner residual and shadow vector; partials
+// ||r||^2 and r^.r in the inner type.
+template <class TI>
+struct MarchApply {
+    const double *w, *rr_, *zero;
+    double* r;
+    TI *rin, *rhat;
+    bool sep;
+    double acc[2] = {0.0, 0.0};
+    static constexpr bool PLANE_HOOK = false;
+    struct Own {
+        double w, r;
+    };
+    struct Ring {
+        double w;
+    };
+    __device__ __forceinline__ void load(Own& o, long long g) const {
+        o.w = *(g >= 0 ? w + g : zero);
+        o.r = *(g >= 0 ? rr_ + g : zero);
+    }
+    __device__ __forceinline__ void load(Ring& o, long long g) const { o.w = *(g >= 0 ? w + g : zero); }
+    template <class R>
+    __device__ __forceinline__ double value(const R& o) const {
+        return o.w;
+    }
+    __device__ __forceinline__ void emit(int, long long g, const Own& c, double y) {
+        const double rv = c.r - y;
+        r[g] = rv;
+        acc[0] += rv * rv;
+        const TI ri = (TI)rv;
+        if (sep) rin[g] = ri;
+        rhat[g] = ri;
+        acc[1] += (double)ri * (double)ri;
+    }
+    __device__ __forceinline__ void plane_done(const Chunk&, int) {}
+};
+
+template <bool VAR, class TI>
+__device__ __forceinline__ void march_apply(const DevProb& P, int lw, int gslot, double* Lbox, double* sh) {
+    using M = StepMarch<TI>;
+    TI* rin = vp<TI>(P.rin);
+    MarchApply<TI> ph{P.w, P.r, reinterpret_cast<const double*>(P.op.zero), P.r, rin, vp<TI>(P.rhat),
+                      (void*)rin != (void*)P.r};
+    if (lw < P.nchunks) {
+        const Chunk c = chunk_of<M>(lw, P.mcx, P.mcy, P.mz, P.op.nz);
+        march_chunk<M, VAR, double>(P.op, c, Lbox, ph);
+    }
+    double tot;
+    block_sum<2>(ph.acc, sh, tot);
+    if (threadIdx.x < 2) *part_at(P, gslot & 1, threadIdx.x, lw) = tot;
+}
+
 // ------------------------------------------------------------- kernel
 template <class Cfg, int DIM, bool VAR, class TI>
 __global__ __launch_bounds__(NT) void k_step(const DevProb* __restrict__ probs, const int* __restrict__ wg_prob,
@@ -784,7 +1013,7 @@ __global__ __launch_bounds__(NT) void k_step(const DevProb* __restrict__ probs, 
     StepHot N;
     Upd U;
     double rr = -1.0, rr0 = -1.0;
-    const int act = step_decide(H, s5, st, P.k, gslot, scribe, N, U, rr, rr0);
+    const int act = step_decide(H, s5, st, P.k, DIM, gslot, scribe, N, U, rr, rr0);
     if (scribe) {
         st->hot[cur] = N;
         st->solve_state = N.solve_state;
@@ -825,13 +1054,22 @@ __global__ __launch_bounds__(NT) void k_step(const DevProb* __restrict__ probs, 
                 phase_b<Cfg, DIM, VAR, TI>(P, lw, gslot, N, L, sh);
             break;
         case ACT_RES:
-            true_residual<Cfg, DIM, VAR, TI>(P, lw, gslot, U, Lbox, sh, ysh);
+            if constexpr (DIM == 3)
+                march_res<VAR, TI>(P, lw, gslot, U, Lbox, sh, ysh);
+            else
+                true_residual<Cfg, DIM, VAR, TI>(P, lw, gslot, U, Lbox, sh, ysh);
+            break;
+        case ACT_APPLYW:
+            apply_w<TI>(P, lw, U, st, ysh);
             break;
         case ACT_REDUCE:
             if (lead) projection_coefficients(P, gslot, st, ysh, sh);
             break;
         case ACT_APPLY:
-            apply_projection<Cfg, DIM, VAR, TI>(P, lw, gslot, U, st, Lbox, sh, ysh);
+            if constexpr (DIM == 3)
+                march_apply<VAR, TI>(P, lw, gslot, Lbox, sh);
+            else
+                apply_projection<Cfg, DIM, VAR, TI>(P, lw, gslot, U, st, Lbox, sh, ysh);
             break;
         case ACT_FIN:
             fold_update<Cfg, TI>(P, lw, U);

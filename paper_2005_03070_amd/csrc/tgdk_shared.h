@@ -45,6 +45,7 @@ enum : int {
     M_APPLY = 5,    // x += upd + V d, r -= A V d, new shadow vector
     M_START = 6,    // decisions after the projection, then phase A of iteration 0
     M_APPLY0 = 7,   // no deflation: decisions, x += upd, phase A of iteration 0
+    M_APPLYW = 8,   // 3-D: w = V d, x += upd + w (then M_APPLY: r -= A w)
 };
 // ... and what a launch did for it (logged for measurement)
 enum : int {
@@ -57,7 +58,8 @@ enum : int {
     ACT_APPLY = 6,   // projection applied
     ACT_FIN = 7,     // last inner update folded into x
     ACT_FIN_A0 = 8,  // x update and phase A of iteration 0 (no deflation)
-    NACT = 9,
+    ACT_APPLYW = 9,  // 3-D: w = V d and x += upd + w (the stencil part follows as ACT_APPLY)
+    NACT = 10,
 };
 
 // Scalars of the step kernel's state machine, double-buffered by launch
@@ -125,6 +127,7 @@ struct DevProb {
     long long ldv;
     int vtype;               // V stored as 0 float64, 1 float32
     int mcx, mcy, mz, nchunks;  // 3-D step kernel: z-marching chunks (mcx x mcy columns, mz planes deep)
+    double* w;               // 3-D with deflation: w = V d (n values)
     const double* lu;        // LU factors of H (k x k, row-major), pivots
     const int* piv;
     const double* hinv;      // H^{-1} (k x k, column-major)
