@@ -187,11 +187,9 @@ def test_gmres_first_cycle_equals_oracle_cycle():
 
 
 def test_batched_rhs_independent_of_grouping():
-    """Right-hand sides on one deflation space are projected together (one
-    matrix-core product C = R^T V, one W = V D).  Each column's arithmetic does
-    not depend on the other columns, so a column is bit-identical whichever
-    batch it is solved in; against the single solve (per-tile projection,
-    other summation order) it meets the tolerance in about as many steps."""
+    """Right-hand sides on one deflation space solved in one group: every
+    system runs its own state machine with its own reductions, so a column is
+    bit-identical whichever group it is solved in, including a group of one."""
     dims, beta = (127, 127), (100.0, 0.0)
     op = tg().Operator.const_cd(dims, beta)
     oop = O.const_cd(dims, beta)
@@ -208,12 +206,10 @@ def test_batched_rhs_independent_of_grouping():
                 assert reps[j].mvp_inner == rp[i].mvp_inner
         for j in range(4):
             xj, rj = tg().solve(op, _t(B[j]), defl=space, rtol=1e-9, ncyc=10, precision=precision)
+            assert torch.equal(X[j], xj), (precision, j)
+            assert reps[j].mvp_inner == rj[0].mvp_inner
             assert reps[j].status == 0 and reps[j].relres_true <= 1e-9
             assert _true_relres(oop, B[j], X[j].cpu().numpy()) <= 1e-9
-            assert rj[0].status == 0 and rj[0].relres_true <= 1e-9
-            # BiCGStab amplifies rounding differences, so the iteration counts
-            # of the two summation orders are close, not equal
-            assert abs(reps[j].mvp_inner - rj[0].mvp_inner) <= 0.15 * rj[0].mvp_inner, (precision, j)
 
 
 def test_instances_bit_identical_to_solo():

@@ -50,7 +50,7 @@ def test_3d_255_fp32_inner_with_fp32_stored_vectors():
 def test_batched_32_rhs_511():
     """32 right-hand sides on 511^2 sharing a 30-vector space, FP32 inner
     cycles: each meets the tolerance, and two columns equal their solves in a
-    batch of two bit for bit."""
+    batch of two and alone bit for bit."""
     c = W.CONFIGS["C4"]
     op = tg().Operator.const_cd(c["n"], c["beta"])
     B = W.rhs_block(op.n, c["seeds"]).T.copy()
@@ -65,6 +65,8 @@ def test_batched_32_rhs_511():
         assert _relres(oop, B[j], Xh[j]) <= 1e-8
     X2, _ = solver.solve(Bt[[0, 17]].contiguous(), rtol=1e-8, ncyc=20, precision="fp32_ir")
     assert torch.equal(X2[0], X[0]) and torch.equal(X2[1], X[17])
+    x17, _ = solver.solve(Bt[17].contiguous(), rtol=1e-8, ncyc=20, precision="fp32_ir")
+    assert torch.equal(x17, X[17])
 
 
 def test_sixteen_uneven_instances():
