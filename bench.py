@@ -170,8 +170,9 @@ def main():
         "APPLY": 16 + 3 * w8 + kdefl * v8 + 16 + w8,  # reads x r, e p s, V; writes x r, r^
         "FIN": 16 + 3 * w8,         # reads x, e p s; writes x
         "FIN_A0": 16 + 3 * w8 + 5 * w8,
+        "APPLYW": 8 + 3 * w8 + kdefl * v8 + 16,   # 3-D only: reads x, e p s, V; writes x, w
     }
-    codes = {"A": 1, "A0": 2, "B": 3, "RES": 4, "REDUCE": 5, "APPLY": 6, "FIN": 7, "FIN_A0": 8}
+    codes = {"A": 1, "A0": 2, "B": 3, "RES": 4, "REDUCE": 5, "APPLY": 6, "FIN": 7, "FIN_A0": 8, "APPLYW": 9}
     L.check(L.lib().tgdk_ctx_time_kernel(ctx, 1))
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -230,6 +231,79 @@ def main():
         variants["bicgstab20_no_deflation_fp64"] = {
             "seconds": time.perf_counter() - t, "relres_true": true_relres(x_nd), "status": r_nd[0].status_name,
             "cycles": r_nd[0].cycles, "mvp_inner": r_nd[0].mvp_inner}
+
+    # --------------------------- the other workloads: 3-D, batched right-hand sides
+    workloads = {}
+    if not a.no_variants:
+        def act_times(ctx_):
+            out = {}
+            for name, code in codes.items():
+                ms = np.zeros(1)
+                cnt = np.zeros(1, dtype=np.int64)
+                L.check(L.lib().tgdk_ctx_kernel_time(ctx_, code, ms.ctypes.data_as(L.DP),
+                                                     cnt.ctypes.data_as(C.POINTER(C.c_longlong))))
+                if cnt[0]:
+                    out[name] = (float(ms[0]) * 1e3 / int(cnt[0]), int(cnt[0]))
+            return out
+
+        def timed(fn, reps=2):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                res = fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / reps, res
+
+        # 3-D: 255^3, 40+ vectors stored in float32, FP32 inner + FP64 refinement vs FP64
+        c3 = W.CONFIGS["C3"]
+        op3 = tg.Operator.const_cd(c3["n"], c3["beta"])
+        b3 = torch.tensor(W.rhs(op3.n, c3["seed"]), device=dev)
+        t = time.perf_counter()
+        s3 = tg.TwoGridSolver(op3, m=c3["m"], k=c3["k"], nev=c3["nev"], rtolev=1e-4, maxcyc=12, store=torch.float32)
+        x03 = s3.setup(b3)
+        torch.cuda.synchronize()
+        w3 = {"setup_seconds": time.perf_counter() - t, "k": s3.defl.k}
+        for prec in ("fp64", "fp32_ir"):
+            kw = dict(x0=x03, precision=prec, rtol=c3["rtol"], ncyc=c3["ncyc"], max_extra=40)
+            sec3, (x3, r3) = timed(lambda: s3.solve(b3, **kw))
+            L.check(L.lib().tgdk_ctx_time_kernel(ctx, 1))
+            s3.solve(b3, **kw)
+            acts = act_times(ctx)
+            L.check(L.lib().tgdk_ctx_time_kernel(ctx, 0))
+            wv = 4 if prec == "fp32_ir" else 8
+            per = {k: {"avg_launch_us": us, "launches": cnt,
+                       "achieved_GBs": ({"A": 10, "B": 5, "A0": 5}[k] * wv * op3.n / (us * 1e-6) / 1e9)
+                       if k in ("A", "B", "A0") else None}
+                   for k, (us, cnt) in acts.items()}
+            w3[prec] = {"seconds": sec3, "mvp_inner": r3[0].mvp_inner, "cycles": r3[0].cycles,
+                        "relres_true": r3[0].relres_true, "status": r3[0].status_name, "step_by_action": per}
+            log(f"255^3 {prec}: {sec3*1e3:.1f} ms, mvps {r3[0].mvp_inner}, relres {r3[0].relres_true:.2e}; "
+                + ", ".join(f"{k} {v['avg_launch_us']:.0f} us" + (f" {v['achieved_GBs']:.0f} GB/s" if v["achieved_GBs"] else "")
+                            for k, v in per.items()))
+        workloads["3d_255cube_k40_f32V"] = w3
+        del s3, x03, b3, op3
+        torch.cuda.empty_cache()
+
+        # batched: 32 right-hand sides on 511^2 sharing 30 vectors
+        c4 = W.CONFIGS["C4"]
+        op4 = tg.Operator.const_cd(c4["n"], c4["beta"])
+        B4 = torch.tensor(W.rhs_block(op4.n, c4["seeds"]).T.copy(), device=dev)
+        s4 = tg.TwoGridSolver(op4, m=c4["m"], k=c4["k"], nev=c4["nev"], rtolev=1e-6, maxcyc=60)
+        s4.setup(B4[0].contiguous())
+        w4 = {}
+        for prec in ("fp64", "fp32_ir"):
+            secb, (X4, r4) = timed(lambda: s4.solve(B4, precision=prec), reps=1)
+            ok = all(q.status == 0 for q in r4) and max(q.relres_true for q in r4) <= c4["rtol"]
+            w4[f"batched32_{prec}_seconds"] = secb
+            w4[f"batched32_{prec}_all_converged"] = ok
+            log(f"511^2 x 32 RHS batched {prec}: {secb*1e3:.1f} ms (all converged: {ok})")
+        seqs, _ = timed(lambda: [s4.solve(B4[j].contiguous(), precision="fp64") for j in range(32)], reps=1)
+        w4["sequential32_fp64_seconds"] = seqs
+        log(f"511^2 x 32 RHS one after another fp64: {seqs*1e3:.1f} ms")
+        workloads["batched_32rhs_511sq_k30"] = w4
+        del s4, B4, op4
+        torch.cuda.empty_cache()
 
     # ------------------------------------------ standalone stencil bandwidth
     def stencil_gbs(opx, dtype, rotate_bytes=2 << 30):
@@ -308,6 +382,7 @@ def main():
                   "mvp_boundary": head.mvp_boundary, "min_s": min(times), "max_s": max(times)},
         "setup": {"seconds": setup_s, "gmresdr_cycles": srep.cycles, "nconv": srep.nconv, "mvps": srep.mvps},
         "variants": variants,
+        "workloads": workloads,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

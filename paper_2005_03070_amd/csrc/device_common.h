@@ -261,6 +261,60 @@ __device__ __forceinline__ void fill_halo(T* L, const TilePos& tp, const DevOp& 
     }
 }
 
+// The halo of a tile as fixed per-thread slots (the same enumeration as
+// fill_halo): HK slots per thread; slot h of this thread has LDS index ch[h]
+// (-1: unused slot) and global index gh[h] (-1: outside the domain).  Lets a
+// kernel issue every halo load before any arithmetic or LDS store.
+template <class Cfg, int DIM>
+struct Halo {
+    static constexpr int HR = (DIM == 3) ? (2 * Cfg::TZ + 2 * Cfg::BY) : 2;
+    static constexpr int NHR = HR * 64;
+    static constexpr int NHC = Cfg::BY * Cfg::BZ * 2;
+    static constexpr int KR = (NHR + NT - 1) / NT, KC = (NHC + NT - 1) / NT;
+    static constexpr int HK = KR + KC;
+};
+
+template <class Cfg, int DIM>
+__device__ __forceinline__ void halo_slots(const TilePos& tp, const DevOp& op, int (&ch)[Halo<Cfg, DIM>::HK],
+                                           long long (&gh)[Halo<Cfg, DIM>::HK]) {
+    using H = Halo<Cfg, DIM>;
+    constexpr int BX = Cfg::BX, BY = Cfg::BY, BZ = Cfg::BZ, TY = Cfg::TY, TZ = Cfg::TZ, HZ = Cfg::HZ;
+#pragma unroll
+    for (int k = 0; k < H::KR; ++k) {
+        const int e = threadIdx.x + k * NT;
+        ch[k] = -1;
+        gh[k] = -1;
+        if (e < H::NHR) {
+            const int hr = e >> 6, lane = e & 63;
+            int hy, hz;
+            if (hr < 2 * TZ) {
+                hz = (hr >> 1) + HZ;
+                hy = (hr & 1) ? TY + 1 : 0;
+            } else {
+                const int i2 = hr - 2 * TZ;
+                hz = (i2 >= BY) ? BZ - 1 : 0;
+                hy = i2 % BY;
+            }
+            const int gx = tp.x0 + lane, gy = tp.y0 + hy - 1, gz = tp.z0 + hz - HZ;
+            ch[k] = (hz * BY + hy) * BX + lane + 1;
+            if (gx < op.nx && gy >= 0 && gy < op.ny && gz >= 0 && gz < op.nz) gh[k] = gidx(op, gx, gy, gz);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < H::KC; ++k) {
+        const int e = threadIdx.x + k * NT;
+        ch[H::KR + k] = -1;
+        gh[H::KR + k] = -1;
+        if (e < H::NHC) {
+            const int br = e >> 1, side = e & 1;
+            const int hz = br / BY, hy = br % BY, hx = side ? BX - 1 : 0;
+            const int gx = tp.x0 + hx - 1, gy = tp.y0 + hy - 1, gz = tp.z0 + hz - HZ;
+            ch[H::KR + k] = (hz * BY + hy) * BX + hx;
+            if (inside(op, gx, gy, gz)) gh[H::KR + k] = gidx(op, gx, gy, gz);
+        }
+    }
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

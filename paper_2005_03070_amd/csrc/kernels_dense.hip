@@ -1,19 +1,34 @@
 // Tall-skinny kernels: Gram products A^T B, V Y products, and the classical
 // Gram-Schmidt steps of the Arnoldi process.  All reductions over the long
-// dimension are deterministic (per-block partials summed in block order by the
-// last block).
+// dimension are deterministic: per-block partials, then one workgroup per
+// value sums them in a fixed order (k_sum_partials).
 #include "device_common.h"
 #include "launch.h"
 
 namespace tgdk {
 
-constexpr int GS_ROWS_PER_BLOCK = 1024;
+constexpr int GS_ROWS_PER_BLOCK = NT;  // rows per block before the cap (grid-strided beyond)
+constexpr int GS_MAX_BLOCKS = 1024;  // measured best on 1M rows x 25 columns (4 rows per thread)
 
 int gs_blocks(long long n) {
     long long b = (n + GS_ROWS_PER_BLOCK - 1) / GS_ROWS_PER_BLOCK;
-    if (b > 1024) b = 1024;
+    if (b > GS_MAX_BLOCKS) b = GS_MAX_BLOCKS;
     if (b < 1) b = 1;
     return (int)b;
+}
+
+// Sums value i of per-block partials (partial[b * pstride + i], b < nblocks)
+// in a fixed order: one workgroup per value, threads take blocks t, t + NT,
+// ..., then the block combine.  out[i] = sum (or sqrt(sum) if root).
+__global__ __launch_bounds__(NT) void k_sum_partials(const double* __restrict__ partial, int nblocks,
+                                                     long long pstride, double* __restrict__ out, int root) {
+    __shared__ double sh[NWAVE];
+    const int i = blockIdx.x;
+    double a = 0.0;
+#pragma unroll 8
+    for (int b = threadIdx.x; b < nblocks; b += NT) a += partial[(long long)b * pstride + i];
+    const double s = block_sum_one(a, sh);
+    if (threadIdx.x == 0) out[i] = root ? sqrt(s) : s;
 }
 
 template <class T>
@@ -30,7 +45,7 @@ __device__ __forceinline__ double ld(const void* p, long long i) {
 // Each workgroup stages 64-row chunks of A and B in LDS (coalesced column
 // loads, float32 inputs widened exactly), and its four waves accumulate the
 // 16 x 16 output tiles over the chunk; per-workgroup partial tiles are summed
-// in workgroup order by k_gram_finish.
+// in a fixed order by k_sum_partials (one workgroup per entry).
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
 constexpr int GRAM_MAX = 64;   // p, q <= 64
@@ -101,16 +116,7 @@ __global__ __launch_bounds__(NT) void k_gram(const void* A_, long long lda, int 
     (void)G;
 }
 
-// Sums the per-block Gram partials in block order.
-__global__ __launch_bounds__(NT) void k_gram_finish(const double* __restrict__ partial, int nblocks, int npair,
-                                                    double* __restrict__ G) {
-    for (int pr = blockIdx.x * NT + threadIdx.x; pr < npair; pr += gridDim.x * NT) {
-        double s = 0.0;
-        for (int b = 0; b < nblocks; ++b) s += partial[(long long)b * npair + pr];
-        G[pr] = s;
-    }
-}
-
+// Sums the per-block Gram partials: one workgroup per entry (k_sum_partials).
 void launch_gram(const void* A, int atype, long long lda, int p, const void* B, int btype, long long ldb, int q,
                  long long n, double* G, double* partial, unsigned* counter, hipStream_t s) {
     const int nb = gram_blocks(n);
@@ -127,7 +133,7 @@ void launch_gram(const void* A, int atype, long long lda, int p, const void* B, 
         hipLaunchKernelGGL((k_gram<double, float>), dim3(nb), dim3(NT), 0, s, A, lda, p, B, ldb, q, n, G, partial,
                            counter);
     const int npair = p * q;
-    hipLaunchKernelGGL(k_gram_finish, dim3((npair + NT - 1) / NT), dim3(NT), 0, s, partial, nb, npair, G);
+    hipLaunchKernelGGL(k_sum_partials, dim3(npair), dim3(NT), 0, s, partial, nb, (long long)npair, G, 0);
 }
 
 // ---------------------------------------------------------------- V * Y
@@ -206,8 +212,10 @@ void launch_vmul_add(const double* V, long long ldv, int p, const double* y, dou
 }
 
 // ------------------------------------------------- Gram-Schmidt (Arnoldi)
-// MODE 0: hout = V^T w.  MODE 1: w -= V h, then hout = V^T w.
-// MODE 2: w -= V h, then hout[0] = ||w||.
+// gs_blocks blocks of NT threads, rows grid-strided (4 rows per thread at 1M rows).
+// MODE 0: hout = V^T w.  MODE 1: w -= V h, then hout = V^T w, fused per row:
+// the row's V values are read for the update and again, from cache, for the
+// dot products.  MODE 2: w -= V h, then hout[0] = ||w||.
 template <int MODE>
 __global__ __launch_bounds__(NT) void k_gs(const double* __restrict__ V, long long ldv, int p, double* w,
                                            const double* __restrict__ h, long long n, double* hout,
@@ -216,26 +224,31 @@ __global__ __launch_bounds__(NT) void k_gs(const double* __restrict__ V, long lo
     __shared__ double hs[MAXK + 1];
     const long long stride = (long long)gridDim.x * NT;
     const long long g0 = blockIdx.x * (long long)NT + threadIdx.x;
-    if (MODE >= 1 && p > 0) {
+    if (MODE >= 1)
         for (int i = threadIdx.x; i < p; i += NT) hs[i] = h[i];
-        __syncthreads();
-        for (long long g = g0; g < n; g += stride) {
-            double a = w[g];
-            for (int i = 0; i < p; ++i) a -= V[i * ldv + g] * hs[i];
-            w[g] = a;
-        }
-    }
+    __syncthreads();
+    const int pstride = MAXK + 1;
     if (MODE <= 1) {
-        const int pstride = MAXK + 1;
         for (int c0 = 0; c0 < p; c0 += 16) {
+            const int nc = p - c0 < 16 ? p - c0 : 16;
             double acc[16];
 #pragma unroll
             for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
             for (long long g = g0; g < n; g += stride) {
-                const double wv = w[g];
+                double wv = w[g];
+                if (MODE == 1 && c0 == 0) {
+                    // update of this row before its first dot products
+#pragma unroll 8
+                    for (int i = 0; i < p; ++i) wv -= V[i * ldv + g] * hs[i];
+                    w[g] = wv;
+                }
+                // unconditional loads (columns past p re-read column c0, a
+                // cache hit, and are masked), so all 16 are in flight at once
 #pragma unroll
-                for (int jj = 0; jj < 16; ++jj)
-                    if (c0 + jj < p) acc[jj] += V[(c0 + jj) * ldv + g] * wv;
+                for (int jj = 0; jj < 16; ++jj) {
+                    const double v = V[(long long)(jj < nc ? c0 + jj : c0) * ldv + g];
+                    acc[jj] += jj < nc ? v * wv : 0.0;
+                }
             }
             double tot;
             block_sum<16>(acc, sh, tot);
@@ -244,33 +257,19 @@ __global__ __launch_bounds__(NT) void k_gs(const double* __restrict__ V, long lo
         }
     } else {
         double acc[1] = {0.0};
-        for (long long g = g0; g < n; g += stride) acc[0] += w[g] * w[g];
+        for (long long g = g0; g < n; g += stride) {
+            double a = w[g];
+#pragma unroll 8
+            for (int i = 0; i < p; ++i) a -= V[i * ldv + g] * hs[i];
+            if (p > 0) w[g] = a;
+            acc[0] += a * a;
+        }
         double tot;
         block_sum<1>(acc, sh, tot);
-        if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+        if (threadIdx.x == 0) partial[(long long)blockIdx.x * pstride] = tot;
     }
     (void)counter;
     (void)hout;
-}
-
-// Sums the per-block partials in block order: hout[i] for i < p, or
-// hout[0] = sqrt(sum) for the norm (MODE 2).
-template <int MODE>
-__global__ __launch_bounds__(NT) void k_gs_finish(const double* __restrict__ partial, int nblocks, int p,
-                                                  double* __restrict__ hout) {
-    __shared__ double sh[NWAVE];
-    if (MODE <= 1) {
-        // one thread per value, blocks added in order (loads coalesced across values)
-        for (int i = threadIdx.x; i < p; i += NT) {
-            double s = 0.0;
-#pragma unroll 8
-            for (int b = 0; b < nblocks; ++b) s += partial[(long long)b * (MAXK + 1) + i];
-            hout[i] = s;
-        }
-    } else {
-        const double s = sum_partials(partial, nblocks, 1, 0, sh);
-        if (threadIdx.x == 0) hout[0] = sqrt(s);
-    }
 }
 
 void launch_gs_dot(const double* V, long long ldv, int p, const double* w, long long n, double* hout,
@@ -278,25 +277,25 @@ void launch_gs_dot(const double* V, long long ldv, int p, const double* w, long 
     const int nb = gs_blocks(n);
     hipLaunchKernelGGL((k_gs<0>), dim3(nb), dim3(NT), 0, s, V, ldv, p, const_cast<double*>(w),
                        (const double*)nullptr, n, hout, partial, counter);
-    hipLaunchKernelGGL((k_gs_finish<0>), dim3(1), dim3(NT), 0, s, partial, nb, p, hout);
+    if (p > 0) hipLaunchKernelGGL(k_sum_partials, dim3(p), dim3(NT), 0, s, partial, nb, (long long)(MAXK + 1), hout, 0);
 }
 void launch_gs_update_dot(const double* V, long long ldv, int p, double* w, const double* h, long long n,
                           double* hout, double* partial, unsigned* counter, hipStream_t s) {
     const int nb = gs_blocks(n);
     hipLaunchKernelGGL((k_gs<1>), dim3(nb), dim3(NT), 0, s, V, ldv, p, w, h, n, hout, partial, counter);
-    hipLaunchKernelGGL((k_gs_finish<1>), dim3(1), dim3(NT), 0, s, partial, nb, p, hout);
+    if (p > 0) hipLaunchKernelGGL(k_sum_partials, dim3(p), dim3(NT), 0, s, partial, nb, (long long)(MAXK + 1), hout, 0);
 }
 void launch_gs_update_norm(const double* V, long long ldv, int p, double* w, const double* h, long long n,
                            double* nrm, double* partial, unsigned* counter, hipStream_t s) {
     const int nb = gs_blocks(n);
     hipLaunchKernelGGL((k_gs<2>), dim3(nb), dim3(NT), 0, s, V, ldv, p, w, h, n, nrm, partial, counter);
-    hipLaunchKernelGGL((k_gs_finish<2>), dim3(1), dim3(NT), 0, s, partial, nb, p, nrm);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(NT), 0, s, partial, nb, (long long)(MAXK + 1), nrm, 1);
 }
 void launch_norm2(const double* w, long long n, double* out, double* partial, unsigned* counter, hipStream_t s) {
     const int nb = gs_blocks(n);
     hipLaunchKernelGGL((k_gs<2>), dim3(nb), dim3(NT), 0, s, (const double*)nullptr, 0LL, 0,
                        const_cast<double*>(w), (const double*)nullptr, n, out, partial, counter);
-    hipLaunchKernelGGL((k_gs_finish<2>), dim3(1), dim3(NT), 0, s, partial, nb, 0, out);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(NT), 0, s, partial, nb, (long long)(MAXK + 1), out, 1);
 }
 
 __global__ void k_scale(const double* w, double* v, const double* __restrict__ nrm,

@@ -272,9 +272,14 @@ __device__ __forceinline__ double* part_at(const DevProb& P, int slot, int v, in
 }
 
 // ------------------------------------------------------------ phase A
-template <class Cfg, int DIM, bool VAR, class TI>
-__device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, bool first, bool fin, const StepHot& N,
+// 2-D tiles.  Every load of a tile (own points and halo slots, plus e and r^
+// for the outputs) is issued first, from clamped addresses (points outside
+// the domain read the zero page), so all of them are in flight together;
+// then the stencil input goes to LDS and the outputs are formed.
+template <class Cfg, int DIM, bool VAR, bool FIRST, class TI>
+__device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, bool fin, const StepHot& N,
                                         const Upd& U, TI* L, double* sh) {
+    using HL = Halo<Cfg, DIM>;
     const DevOp& op = P.op;
     const int pb = (gslot >> 1) & 1;
     TI* __restrict__ pnew = vp<TI>(P.p[pb]);
@@ -286,56 +291,91 @@ __device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, boo
     const TI* __restrict__ sv_ = vp<const TI>(P.s);
     const TI* __restrict__ tv_ = vp<const TI>(P.t);
     TI* e = vp<TI>(P.e);
+    const TI* zero = reinterpret_cast<const TI*>(op.zero);
+    auto at = [&](const TI* arr, long long g) { return g >= 0 ? arr + g : zero; };
     const TI alpha = (TI)N.alpha, omega = (TI)N.omega;
-    const TI beta = first ? TI(0) : (TI)((N.rho / N.rho_old) * (N.alpha / N.omega));
+    const TI beta = FIRST ? TI(0) : (TI)((N.rho / N.rho_old) * (N.alpha / N.omega));
     double acc[2] = {0.0, 0.0};
     for (int tile = lw; tile < P.ntiles; tile += P.nwg) {
         const TilePos tp = tile_pos<Cfg>(tile, P.tx, P.ty);
         long long gq[Cfg::PPT];
         int cq[Cfg::PPT];
-        bool okq[Cfg::PPT];
-        TI rq[Cfg::PPT], sq[Cfg::PPT], poq[Cfg::PPT];
 #pragma unroll
         for (int q = 0; q < Cfg::PPT; ++q) {
             int gx, gy, gz;
             point_coords<Cfg>(q, tp, gx, gy, gz, cq[q]);
-            okq[q] = inside(op, gx, gy, gz);
-            const long long g = okq[q] ? gidx(op, gx, gy, gz) : 0;
-            gq[q] = g;
-            TI pv = TI(0);
-            rq[q] = sq[q] = poq[q] = TI(0);
-            if (okq[q]) {
-                if (fin) P.x[g] += upd_at<TI>(P, U, g);
-                if (first) {
-                    rq[q] = rin[g];
-                    pv = rq[q];
-                } else {
-                    sq[q] = sv_[g];
-                    poq[q] = pold[g];
-                    rq[q] = sq[q] - omega * tv_[g];
-                    pv = rq[q] + beta * (poq[q] - omega * vold[g]);
-                }
+            gq[q] = inside(op, gx, gy, gz) ? gidx(op, gx, gy, gz) : -1;
+        }
+        int ch[HL::HK];
+        long long gh[HL::HK];
+        halo_slots<Cfg, DIM>(tp, op, ch, gh);
+        // loads of the stencil input's sources: own points and halo slots
+        TI a0[Cfg::PPT], a1[Cfg::PPT], a2[Cfg::PPT], a3[Cfg::PPT];
+        TI h0[HL::HK], h1[HL::HK], h2[HL::HK], h3[HL::HK];
+#pragma unroll
+        for (int q = 0; q < Cfg::PPT; ++q) {
+            if (FIRST) {
+                a0[q] = *at(rin, gq[q]);
+            } else {
+                a0[q] = *at(sv_, gq[q]);
+                a1[q] = *at(tv_, gq[q]);
+                a2[q] = *at(pold, gq[q]);
+                a3[q] = *at(vold, gq[q]);
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < HL::HK; ++h) {
+            if (FIRST) {
+                h0[h] = *at(rin, gh[h]);
+            } else {
+                h0[h] = *at(sv_, gh[h]);
+                h1[h] = *at(tv_, gh[h]);
+                h2[h] = *at(pold, gh[h]);
+                h3[h] = *at(vold, gh[h]);
+            }
+        }
+        if (fin) {
+#pragma unroll
+            for (int q = 0; q < Cfg::PPT; ++q)
+                if (gq[q] >= 0) P.x[gq[q]] += upd_at<TI>(P, U, gq[q]);
+        }
+        // stencil input p_i on the tile and its halo
+        TI rq[Cfg::PPT];
+#pragma unroll
+        for (int q = 0; q < Cfg::PPT; ++q) {
+            TI pv;
+            if (FIRST) {
+                rq[q] = a0[q];
+                pv = rq[q];
+            } else {
+                rq[q] = a0[q] - omega * a1[q];
+                pv = rq[q] + beta * (a2[q] - omega * a3[q]);
             }
             L[cq[q]] = pv;
         }
-        fill_halo<Cfg, DIM, TI>(L, tp, op, [&](long long g) -> TI {
-            if (first) return rin[g];
-            const TI rv = sv_[g] - omega * tv_[g];
-            return rv + beta * (pold[g] - omega * vold[g]);
-        });
+#pragma unroll
+        for (int h = 0; h < HL::HK; ++h) {
+            if (ch[h] < 0) continue;
+            if (FIRST) {
+                L[ch[h]] = h0[h];
+            } else {
+                const TI rv = h0[h] - omega * h1[h];
+                L[ch[h]] = rv + beta * (h2[h] - omega * h3[h]);
+            }
+        }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < Cfg::PPT; ++q) {
-            if (!okq[q]) continue;
+            if (gq[q] < 0) continue;
             const long long g = gq[q];
             const TI vv = stencil_row_t<Cfg, DIM, VAR, TI>(op, L, cq[q], g);
             st_stream<DIM>(&pnew[g], L[cq[q]]);
             st_stream<DIM>(&vnew[g], vv);
-            if (first) {
+            if (FIRST) {
                 st_stream<DIM>(&e[g], TI(0));
             } else {
                 st_stream<DIM>(&rin[g], rq[q]);
-                st_stream<DIM>(&e[g], e[g] + alpha * poq[q] + omega * sq[q]);
+                st_stream<DIM>(&e[g], e[g] + alpha * a2[q] + omega * a0[q]);
             }
             acc[0] += (double)rhat[g] * (double)vv;
             acc[1] += (double)rq[q] * (double)rq[q];
@@ -348,8 +388,10 @@ __device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, boo
 }
 
 // ------------------------------------------------------------ phase B
+// 2-D tiles, loads first as in phase_a.
 template <class Cfg, int DIM, bool VAR, class TI>
 __device__ __forceinline__ void phase_b(const DevProb& P, int lw, int gslot, const StepHot& N, TI* L, double* sh) {
+    using HL = Halo<Cfg, DIM>;
     const DevOp& op = P.op;
     const int pb = ((gslot - 1) >> 1) & 1;  // v of this iteration's phase A
     const TI* __restrict__ v = vp<const TI>(P.v[pb]);
@@ -357,35 +399,49 @@ __device__ __forceinline__ void phase_b(const DevProb& P, int lw, int gslot, con
     const TI* __restrict__ rhat = vp<const TI>(P.rhat);
     TI* __restrict__ s = vp<TI>(P.s);
     TI* __restrict__ tt_ = vp<TI>(P.t);
+    const TI* zero = reinterpret_cast<const TI*>(op.zero);
+    auto at = [&](const TI* arr, long long g) { return g >= 0 ? arr + g : zero; };
     const TI alpha = (TI)N.alpha;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int tile = lw; tile < P.ntiles; tile += P.nwg) {
         const TilePos tp = tile_pos<Cfg>(tile, P.tx, P.ty);
         long long gq[Cfg::PPT];
         int cq[Cfg::PPT];
-        bool okq[Cfg::PPT];
-        TI rhq[Cfg::PPT];
 #pragma unroll
         for (int q = 0; q < Cfg::PPT; ++q) {
             int gx, gy, gz;
             point_coords<Cfg>(q, tp, gx, gy, gz, cq[q]);
-            okq[q] = inside(op, gx, gy, gz);
-            const long long g = okq[q] ? gidx(op, gx, gy, gz) : 0;
-            gq[q] = g;
-            rhq[q] = okq[q] ? rhat[g] : TI(0);
-            L[cq[q]] = okq[q] ? rin[g] - alpha * v[g] : TI(0);
+            gq[q] = inside(op, gx, gy, gz) ? gidx(op, gx, gy, gz) : -1;
         }
-        fill_halo<Cfg, DIM, TI>(L, tp, op, [&](long long g) -> TI { return rin[g] - alpha * v[g]; });
+        int ch[HL::HK];
+        long long gh[HL::HK];
+        halo_slots<Cfg, DIM>(tp, op, ch, gh);
+        TI rq[Cfg::PPT], vq[Cfg::PPT], hr[HL::HK], hv[HL::HK];
+#pragma unroll
+        for (int q = 0; q < Cfg::PPT; ++q) {
+            rq[q] = *at(rin, gq[q]);
+            vq[q] = *at(v, gq[q]);
+        }
+#pragma unroll
+        for (int h = 0; h < HL::HK; ++h) {
+            hr[h] = *at(rin, gh[h]);
+            hv[h] = *at(v, gh[h]);
+        }
+#pragma unroll
+        for (int q = 0; q < Cfg::PPT; ++q) L[cq[q]] = rq[q] - alpha * vq[q];
+#pragma unroll
+        for (int h = 0; h < HL::HK; ++h)
+            if (ch[h] >= 0) L[ch[h]] = hr[h] - alpha * hv[h];
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < Cfg::PPT; ++q) {
-            if (!okq[q]) continue;
+            if (gq[q] < 0) continue;
             const long long g = gq[q];
             const TI sv = L[cq[q]];
             const TI tv = stencil_row_t<Cfg, DIM, VAR, TI>(op, L, cq[q], g);
             st_stream<DIM>(&s[g], sv);
             st_stream<DIM>(&tt_[g], tv);
-            const double rh = (double)rhq[q];
+            const double rh = (double)rhat[g];
             const double sd = (double)sv, td = (double)tv;
             acc[0] += sd * sd;
             acc[1] += td * sd;
@@ -1044,8 +1100,10 @@ __global__ __launch_bounds__(NT) void k_step(const DevProb* __restrict__ probs, 
         case ACT_FIN_A0:
             if constexpr (DIM == 3)
                 march_a<VAR, TI>(P, lw, gslot, act != ACT_A, act == ACT_FIN_A0, N, U, L, sh);
+            else if (act == ACT_A)
+                phase_a<Cfg, DIM, VAR, false, TI>(P, lw, gslot, false, N, U, L, sh);
             else
-                phase_a<Cfg, DIM, VAR, TI>(P, lw, gslot, act != ACT_A, act == ACT_FIN_A0, N, U, L, sh);
+                phase_a<Cfg, DIM, VAR, true, TI>(P, lw, gslot, act == ACT_FIN_A0, N, U, L, sh);
             break;
         case ACT_B:
             if constexpr (DIM == 3)
