@@ -42,6 +42,8 @@ def _args():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--solve-only", action="store_true",
                     help="setup, warm-up and timed solves only (for hardware-counter runs)")
+    ap.add_argument("--workload", choices=("2d", "3d"), default="2d",
+                    help="with --solve-only: 2d = 1023^2 FP64 (the headline), 3d = 255^3 FP32 inner + FP64 refinement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB device buffer three times (counter scale of a plain copy)")
     return ap.parse_args()
@@ -83,6 +85,27 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if a.solve_only and a.workload == "3d":
+        import paper_2005_03070_amd as tg
+        import workloads as W
+        c3 = W.CONFIGS["C3"]
+        op3 = tg.Operator.const_cd(c3["n"], c3["beta"])
+        b3 = torch.tensor(W.rhs(op3.n, c3["seed"]), device="cuda:0")
+        s3 = tg.TwoGridSolver(op3, m=c3["m"], k=c3["k"], nev=c3["nev"], rtolev=1e-4, maxcyc=12,
+                              store=torch.float32)
+        x03 = s3.setup(b3)
+        kw = dict(x0=x03, precision="fp32_ir", rtol=c3["rtol"], ncyc=c3["ncyc"], max_extra=40)
+        for _ in range(a.warmup):
+            s3.solve(b3, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            x3, r3 = s3.solve(b3, **kw)
+        torch.cuda.synchronize()
+        log(f"255^3 fp32_ir: {(time.perf_counter() - t0) / a.steps * 1e3:.1f} ms/solve, mvps {r3[0].mvp_inner}, "
+            f"relres {r3[0].relres_true:.2e}")
+        return
 
     if a.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float64, device="cuda:0")
