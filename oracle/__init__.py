@@ -24,6 +24,8 @@ Modules and the part of the paper each follows:
 * ``bicgstab``   -- BiCGStab(ncyc)-Proj(k) with the per-cycle tolerance
   (Sec. 4.1 algorithm box, step 3 a-d).
 * ``gmres``      -- GMRES(m)-Proj(k) (Sec. 2.2 algorithm box).
+* ``idr``        -- IDR(s)(ncyc)-Proj(k): the Sec. 4.1 box with IDR(s) (the
+  biorthogonal variant of van Gijzen and Sonneveld) as the inner solver.
 * ``gmresdr``    -- GMRES-DR(m,k) on the coarse grid (Sec. 2.1; phase 1 of
   the Sec. 3 algorithm).
 * ``deflation``  -- the fine-grid deflation space built from moved vectors

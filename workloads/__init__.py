@@ -26,6 +26,12 @@ def rhs_block(n, seeds):
     return np.stack([rhs(n, s) for s in seeds], axis=1)
 
 
+def shadow_draw(n, s, seed):
+    """The s random columns of IDR(s)'s shadow space, (s, n) float64 N(0,1)
+    (row j = column j of the n x s matrix, before orthonormalisation)."""
+    return rng(seed).standard_normal((s, n))
+
+
 def kfield(dims, seed, scale=0.5):
     """Per-cell coefficient ``k = exp(scale * z)``, ``z ~ N(0,1)``, shape
     ``(n_y + 1, n_x + 1)`` for an ``n_x x n_y`` interior grid."""
