@@ -247,6 +247,24 @@ def main():
 
         run("fp32_inner_fp64_refinement", max(3, a.steps // 2), precision="fp32_ir")
         run("gmres50_proj30_fp64", 2, method="gmres", m3=c["m3"])
+
+        # IDR(4)(20)-Proj(30): IDR(s) in place of BiCGStab in the same cycles
+        def run_idr(name, steps, **kw):
+            f = lambda: tg.solve_idr(op, b, s=4, x0=x0, defl=space, ncyc=c["ncyc"], rtol=c["rtol"], **kw)
+            f()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(steps):
+                xv, rv = f()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / steps
+            variants[name] = {"seconds": dt, "relres_true": true_relres(xv), "status": rv.status_name,
+                              "cycles": rv.cycles, "mvp_inner": rv.mvp_inner, "mvp_boundary": rv.mvp_boundary,
+                              "us_per_inner_mvp": dt * 1e6 / max(rv.mvp_inner, 1)}
+            log(f"{name}: {dt*1e3:.1f} ms, mvps {rv.mvp_inner}, relres {variants[name]['relres_true']:.2e}")
+
+        run_idr("idr4_proj30_fp64", 2)
+        run_idr("idr4_proj30_fp32_ir", 2, precision="fp32_ir")
         # no deflation, from zero: the restarted BiCGStab baseline
         t = time.perf_counter()
         x_nd, r_nd = tg.solve(op, b, rtol=c["rtol"], ncyc=c["ncyc"], max_extra=40)

@@ -54,11 +54,13 @@ extern "C" {
 /* solver methods and precisions */
 #define TGDK_BICGSTAB_PROJ 0
 #define TGDK_GMRES_PROJ    1
+#define TGDK_IDRS_PROJ     2   /* tgdk_solve_idr only */
 #define TGDK_FP64          0
 #define TGDK_FP32_IR       1
 
 #define TGDK_MAX_DEFL 128   /* largest GMRES cycle length m (deflation spaces: k <= 64) */
 #define TGDK_NHIST    8     /* recorded BiCGStab scalars of the first iterations */
+#define TGDK_IDR_SMAX 32    /* largest IDR shadow-space dimension s */
 
 /* Text of the last non-OK return on the calling thread ("" if none). */
 const char* tgdk_last_error(void);
@@ -223,14 +225,14 @@ int tgdk_defl_destroy(tgdk_defl defl);
  * reports: host array of nrhs reports.  Returns the worst status over the
  * right-hand sides. */
 typedef struct {
-    int method;            /* TGDK_BICGSTAB_PROJ or TGDK_GMRES_PROJ */
-    int ncyc;              /* BiCGStab: requested cycles (>= 1) */
+    int method;            /* TGDK_BICGSTAB_PROJ, TGDK_GMRES_PROJ or TGDK_IDRS_PROJ */
+    int ncyc;              /* BiCGStab, IDR: requested cycles (>= 1) */
     int m3;                /* GMRES: cycle length m (1..TGDK_MAX_DEFL) */
     int precision;         /* TGDK_FP64 or TGDK_FP32_IR */
     int x0_given;
     int transpose;
     int maxit_cycle;
-    int max_extra_cycles;  /* BiCGStab: cycles allowed past ncyc; GMRES: max cycles */
+    int max_extra_cycles;  /* BiCGStab, IDR: cycles allowed past ncyc; GMRES: max cycles */
     double rtol;
     double fp32_floor;
 } tgdk_solve_params;
@@ -253,6 +255,33 @@ int tgdk_solve(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int nrh
  * dimension) solved together: every kernel launch covers the tiles of all
  * instances, so small and uneven grids fill the device in one launch per
  * step.  Same parameters and reports (one per instance) as tgdk_solve. */
+/* IDR(s)(ncyc)-Proj(k) on one right-hand side: the same cycles, projection
+ * and cycle tolerance as BiCGStab(ncyc)-Proj(k) (Sec. 4.1 box, step 3 a-d),
+ * with IDR(s) as the inner solver of step c (the paper runs s = 4 by
+ * default, Sec. 4.1; s = 5 and 20 in the Helmholtz examples of Sec. 5).
+ * The inner solver is the biorthogonal IDR(s) of van Gijzen and Sonneveld
+ * (ACM TOMS 38(1), 2011): each cycle starts afresh (G = U = 0, M = I,
+ * omega = 1) from the residual after the projection; rounds of s steps and
+ * one dimension reduction, with omega the minimal-residual value enlarged
+ * when the angle between r and A r is small (cos < kappa; kappa = 0.7 in
+ * that paper, 0 gives the plain minimal-residual omega).
+ *  - shadow: device float64, n x s column-major (s columns of n): the raw
+ *    columns of the shadow space.  The library orthonormalises a copy
+ *    (CholQR2); shadow is not modified.  TGDK_E_SINGULAR if rank deficient.
+ *  - 1 <= s <= TGDK_IDR_SMAX, s <= n; 0 <= kappa < 1.
+ *  - params.method must be TGDK_IDRS_PROJ; ncyc, max_extra_cycles,
+ *    precision (TGDK_FP32_IR: G, U, P, r and e in float32), rtol,
+ *    fp32_floor, x0_given, transpose as for BiCGStab; maxit_cycle bounds
+ *    the operator applications of one inner cycle.
+ *  - report: iters_inner = mvp_inner = inner operator applications;
+ *    first_rho[i] = ||r|| after the i-th update of the inner residual in the
+ *    first cycle, first_alpha[i] = that update's coefficient (beta, or omega
+ *    at a dimension reduction), first_omega[i] = 1 at a dimension reduction,
+ *    else 0.
+ * Blocking; returns the report's status. */
+int tgdk_solve_idr(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int s, const double* shadow,
+                   double kappa, const tgdk_solve_params* params, tgdk_solve_report* report);
+
 int tgdk_solve_instances(int ninst, const tgdk_op* ops, const tgdk_defl* defls,
                          const double* const* b, double* const* x,
                          const tgdk_solve_params* params, tgdk_solve_report* reports);

@@ -52,6 +52,8 @@ class IdrResult:
     mvps: int
     status: str                                   # "converged", "breakdown", "maxit"
     resnorms: list = field(default_factory=list)  # ||r|| after every update of r
+    coefs: list = field(default_factory=list)     # the coefficient of that update (beta, or omega)
+    kinds: list = field(default_factory=list)     # 0 after a step, 1 after a dimension reduction
     round_resnorms: list = field(default_factory=list)  # ||r|| after every dimension reduction
     checks: list = field(default_factory=list)    # per round: (max |upper(P^T G)|, max |P^T r| before the reduction)
 
@@ -106,6 +108,8 @@ def idrs_inner(matvec, r0, target, P, maxit, kappa=0.7, dtype=np.float64, check=
             e = (e + dtype(beta) * uk).astype(dtype)
             nr = norm(r)
             res.resnorms.append(nr)
+            res.coefs.append(beta)
+            res.kinds.append(0)
             if nr <= target:
                 res.status = "converged"
                 res.e, res.mvps = e, mvps
@@ -136,6 +140,8 @@ def idrs_inner(matvec, r0, target, P, maxit, kappa=0.7, dtype=np.float64, check=
         r = (r - dtype(om) * t).astype(dtype)
         nr = norm(r)
         res.resnorms.append(nr)
+        res.coefs.append(om)
+        res.kinds.append(1)
         res.round_resnorms.append(nr)
         if nr <= target:
             res.status = "converged"
@@ -150,7 +156,9 @@ def idrs_proj(op, b, P, x0=None, V=None, H=None, rtol=1e-8, ncyc=20, max_extra=N
     """IDR(s)(ncyc)-Proj(k) on ``A x = b`` with shadow matrix ``P`` (n x s).
 
     ``V`` (n x k, orthonormal) and ``H = V^T A V`` may be None (k = 0).
-    Returns ``(x, SolveReport)``; ``first_scalars`` stays empty."""
+    Returns ``(x, SolveReport)``; ``first_scalars`` holds, for the first
+    updates of r in the first cycle, (||r||, coefficient, 1 at a dimension
+    reduction else 0)."""
     mv = (lambda z: operators.apply_transpose(op, z)) if transpose else (lambda z: operators.apply(op, z))
     if max_extra is None:
         max_extra = ncyc
@@ -181,6 +189,8 @@ def idrs_proj(op, b, P, x0=None, V=None, H=None, rtol=1e-8, ncyc=20, max_extra=N
             rt = max(rt, fp32_floor)
         inner = idrs_inner(mv, r, rt * nu, Pin, maxit_cycle, kappa=kappa, dtype=inner_dtype)  # step c)
         rep.mvp_inner += inner.mvps
+        if icyc == 1:
+            rep.first_scalars = list(zip(inner.resnorms, inner.coefs, inner.kinds))[:8]
         rep.branches.append(branch)
         rep.inner_iters.append(inner.mvps)
         x = x + inner.e.astype(np.float64)

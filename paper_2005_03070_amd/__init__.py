@@ -6,9 +6,9 @@ include/tgdk.h) with a thin Python binding.
 """
 from . import _lib
 from .api import (DeflationSpace, Operator, Report, SetupReport, coarse_setup, context, defl_from_basis,
-                  defl_prolongate, grad_k, prolongate, restrict, solve, solve_instances)
+                  defl_prolongate, grad_k, prolongate, restrict, solve, solve_idr, solve_instances)
 from .autograd import DeflatedSolve, TwoGridSolver
 
 __all__ = ["Operator", "DeflationSpace", "Report", "SetupReport", "coarse_setup", "context", "defl_from_basis",
-           "defl_prolongate", "grad_k", "prolongate", "restrict", "solve", "solve_instances", "DeflatedSolve",
+           "defl_prolongate", "grad_k", "prolongate", "restrict", "solve", "solve_idr", "solve_instances", "DeflatedSolve",
            "TwoGridSolver"]

@@ -15,10 +15,11 @@ OK, E_INVALID, E_NOMEM, E_HIP, E_SINGULAR, E_NONFINITE = 0, -1, -2, -3, -4, -5
 NOT_CONVERGED, BREAKDOWN = 1, 2
 F64, F32 = 0, 1
 CONST_CD, VAR_STENCIL, DIV_K = 0, 1, 2
-BICGSTAB_PROJ, GMRES_PROJ = 0, 1
+BICGSTAB_PROJ, GMRES_PROJ, IDRS_PROJ = 0, 1, 2
 FP64, FP32_IR = 0, 1
 MAX_DEFL = 128
 NHIST = 8
+IDR_SMAX = 32
 
 STATUS_NAMES = {OK: "ok", NOT_CONVERGED: "not_converged", BREAKDOWN: "breakdown",
                 E_INVALID: "invalid", E_NOMEM: "nomem", E_HIP: "hip", E_SINGULAR: "singular",
@@ -84,6 +85,7 @@ SIGNATURES = [
     ("tgdk_defl_copy", I, [P, P, DP]),
     ("tgdk_defl_destroy", I, [P]),
     ("tgdk_solve", I, [P, P, P, P, I, C.POINTER(SolveParams), C.POINTER(SolveReport)]),
+    ("tgdk_solve_idr", I, [P, P, P, P, I, P, D, C.POINTER(SolveParams), C.POINTER(SolveReport)]),
     ("tgdk_solve_instances", I, [I, PP, PP, PP, PP, C.POINTER(SolveParams), C.POINTER(SolveReport)]),
     ("tgdk_adjoint_grad_k", I, [P, P, P, P]),
     ("tgdk_tune", I, [P, I, I, C.POINTER(I)]),

@@ -229,7 +229,7 @@ class Report:
 
 def _params(method, ncyc, m3, precision, x0_given, transpose, maxit_cycle, max_extra, rtol, fp32_floor):
     p = L.SolveParams()
-    p.method = L.GMRES_PROJ if method == "gmres" else L.BICGSTAB_PROJ
+    p.method = {"gmres": L.GMRES_PROJ, "idr": L.IDRS_PROJ}.get(method, L.BICGSTAB_PROJ)
     p.ncyc = ncyc
     p.m3 = m3
     p.precision = L.FP32_IR if precision == "fp32_ir" else L.FP64
@@ -269,6 +269,33 @@ def solve(op, b, x0=None, defl=None, method="bicgstab", ncyc=20, m3=50, precisio
     check(lib().tgdk_solve(op.h, defl.h if defl is not None else None, C.c_void_p(b.data_ptr()),
                            C.c_void_p(out.data_ptr()), nrhs, C.byref(p), reps))
     return out, _reports(reps)
+
+
+def solve_idr(op, b, s=4, shadow=None, x0=None, defl=None, ncyc=20, precision="fp64", rtol=1e-8, kappa=0.7,
+              transpose=False, maxit_cycle=100000, max_extra=None, fp32_floor=1e-4, seed=0, out=None):
+    """IDR(s)(ncyc)-Proj(k) on A x = b (one right-hand side, b of shape (n,)
+    float64).  shadow: (s, n) float64 device tensor, the raw columns of the
+    shadow space (orthonormalised by the library); None draws s standard
+    normal columns on the device from ``seed``.  Returns (x, Report)."""
+    _ptr(b, numel=op.n, what="b")
+    if shadow is None:
+        gen = torch.Generator(device=b.device)
+        gen.manual_seed(seed)
+        shadow = torch.randn((s, op.n), dtype=torch.float64, device=b.device, generator=gen)
+    if tuple(shadow.shape) != (s, op.n):
+        raise ValueError(f"shadow must have shape ({s}, {op.n})")
+    _ptr(shadow, numel=op.n * s, what="shadow")
+    if out is None:
+        out = torch.empty_like(b)
+    _ptr(out, numel=op.n, what="x")
+    if x0 is not None:
+        out.copy_(x0)
+    p = _params("idr", ncyc, 0, precision, x0 is not None, transpose, maxit_cycle, max_extra, rtol, fp32_floor)
+    rep = L.SolveReport()
+    check(lib().tgdk_solve_idr(op.h, defl.h if defl is not None else None, C.c_void_p(b.data_ptr()),
+                               C.c_void_p(out.data_ptr()), s, C.c_void_p(shadow.data_ptr()), kappa, C.byref(p),
+                               C.byref(rep)))
+    return out, _reports([rep])[0]
 
 
 def solve_instances(ops, defls, bs, x0s=None, ncyc=20, precision="fp64", rtol=1e-8, maxit_cycle=100000,

@@ -14,8 +14,9 @@ namespace tgdk {
 // from global memory once per tile plus the halo.
 template <class Cfg, int DIM, class T>
 __global__ __launch_bounds__(NT) void k_apply(DevOp op, const T* __restrict__ x, T* __restrict__ y,
-                                              int tx, int ty) {
+                                              int tx, int ty, const int* __restrict__ gate) {
     __shared__ T L[Cfg::BOX];
+    if (gate && *gate) return;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const TilePos tp = tile_pos<Cfg>(tile, tx, ty);
     const long long off = (long long)blockIdx.y * op.n;
@@ -40,12 +41,12 @@ __global__ __launch_bounds__(NT) void k_apply(DevOp op, const T* __restrict__ x,
 }
 
 template <class Cfg, int DIM, class T>
-static void apply_cfg(const DevOp& op, const T* x, T* y, int nrhs, hipStream_t s) {
+static void apply_cfg(const DevOp& op, const T* x, T* y, int nrhs, const int* gate, hipStream_t s) {
     const int tx = (op.nx + Cfg::TX - 1) / Cfg::TX;
     const int ty = (op.ny + Cfg::TY - 1) / Cfg::TY;
     const int tz = (op.nz + Cfg::TZ - 1) / Cfg::TZ;
     dim3 grid(tx * ty * tz, nrhs);
-    hipLaunchKernelGGL((k_apply<Cfg, DIM, T>), grid, dim3(NT), 0, s, op, x, y, tx, ty);
+    hipLaunchKernelGGL((k_apply<Cfg, DIM, T>), grid, dim3(NT), 0, s, op, x, y, tx, ty, gate);
 }
 
 // 3-D y = A x by z marching (march3d.h): one workgroup per column chunk
@@ -68,8 +69,9 @@ struct ApplyPhase {
 
 template <class M, bool VAR, class T>
 __global__ __launch_bounds__(NT) void k_apply_march(DevOp op, const T* __restrict__ x, T* __restrict__ y, int cx,
-                                                    int cy, int mz) {
+                                                    int cy, int mz, const int* __restrict__ gate) {
     __shared__ T L[M::PLANE];
+    if (gate && *gate) return;
     const Chunk k = chunk_of<M>(xcd_remap(blockIdx.x, gridDim.x), cx, cy, mz, op.nz);
     const long long off = (long long)blockIdx.y * op.n;
     ApplyPhase<T> ph{x + off, y + off, reinterpret_cast<const T*>(op.zero)};
@@ -80,33 +82,23 @@ __global__ __launch_bounds__(NT) void k_apply_march(DevOp op, const T* __restric
 constexpr int APPLY_MARCH_CHUNKS = 1024;
 
 template <class T>
-void launch_apply(const DevOp& op, const T* x, T* y, int nrhs, int tile_id, hipStream_t s) {
+void launch_apply(const DevOp& op, const T* x, T* y, int nrhs, int tile_id, hipStream_t s, const int* gate) {
     if (op.dim == 2) {
-        with_tile<2>(tile_id, [&](auto cfg) { apply_cfg<decltype(cfg), 2, T>(op, x, y, nrhs, s); });
+        with_tile<2>(tile_id, [&](auto cfg) { apply_cfg<decltype(cfg), 2, T>(op, x, y, nrhs, gate, s); });
         return;
     }
-    int target = APPLY_MARCH_CHUNKS, variant = 0;
-    if (const char* e = getenv("TGDK_MARCH_TARGET")) target = atoi(e);
-    if (const char* e = getenv("TGDK_MARCH_VARIANT")) variant = atoi(e);
-    auto go = [&](auto mcfg) {
-        using M = decltype(mcfg);
-        const int cx = (op.nx + 63) / 64, cy = (op.ny + M::MY - 1) / M::MY;
-        const int mz = march_depth(op.nz, cx, cy, target);
-        const int cz = (op.nz + mz - 1) / mz;
-        dim3 grid(cx * cy * cz, nrhs);
-        if (op.var)
-            hipLaunchKernelGGL((k_apply_march<M, true, T>), grid, dim3(NT), 0, s, op, x, y, cx, cy, mz);
-        else
-            hipLaunchKernelGGL((k_apply_march<M, false, T>), grid, dim3(NT), 0, s, op, x, y, cx, cy, mz);
-    };
-    switch (variant) {
-        case 2: go(March<32>{}); break;
-        case 4: go(March<8>{}); break;
-        default: go(March<16>{}); break;
-    }
+    using M = March<16>;
+    const int cx = (op.nx + 63) / 64, cy = (op.ny + M::MY - 1) / M::MY;
+    const int mz = march_depth(op.nz, cx, cy, APPLY_MARCH_CHUNKS);
+    const int cz = (op.nz + mz - 1) / mz;
+    dim3 grid(cx * cy * cz, nrhs);
+    if (op.var)
+        hipLaunchKernelGGL((k_apply_march<M, true, T>), grid, dim3(NT), 0, s, op, x, y, cx, cy, mz, gate);
+    else
+        hipLaunchKernelGGL((k_apply_march<M, false, T>), grid, dim3(NT), 0, s, op, x, y, cx, cy, mz, gate);
 }
-template void launch_apply<double>(const DevOp&, const double*, double*, int, int, hipStream_t);
-template void launch_apply<float>(const DevOp&, const float*, float*, int, int, hipStream_t);
+template void launch_apply<double>(const DevOp&, const double*, double*, int, int, hipStream_t, const int*);
+template void launch_apply<float>(const DevOp&, const float*, float*, int, int, hipStream_t, const int*);
 
 // ------------------------------------------------- operator construction
 // 2-D -div(k grad u) + beta.grad(u) + sigma u from per-cell k (cells

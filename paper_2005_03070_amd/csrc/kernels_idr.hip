@@ -1,0 +1,442 @@
+// IDR(s) inner cycles of IDR(s)(ncyc)-Proj(k): Sec. 4.1 box, step c), with
+// the biorthogonal IDR(s) of van Gijzen and Sonneveld (ACM TOMS 38(1),
+// 2011) as the inner solver in place of BiCGStab.
+//
+// A cycle is a sequence of rounds; a round is s steps and a dimension
+// reduction, s + 1 operator applications.  Step k builds a direction
+//   u_k = U_(k:) c + omega (r - G_(k:) c),   g_k = A u_k,
+// makes g_k orthogonal to p_0 .. p_(k-1) (g_k -= G_(:k) alpha, u_k -= U_(:k) alpha,
+// which keeps M = P^T G lower triangular), then
+//   r -= beta g_k,  e += beta u_k,  beta = f_k / M_kk,  f = P^T r.
+// The reduction takes t = A r, omega from t and r, e += omega r, r -= omega t.
+//
+// Launch structure: the host enqueues the kernels of whole rounds ahead (the
+// step index k is a launch argument).  Each reduction over n is a vector
+// kernel writing per-workgroup partial sums (value-major, part[v * nb + b])
+// and a one-workgroup epilogue that sums them in a fixed order and takes every
+// scalar decision on the device: the small triangular solves with M, beta,
+// omega, convergence, breakdown and the iteration limit.  When the cycle
+// ends the epilogue sets the state's gate word; every later kernel of the
+// cycle (these and the gated stencil launches) then returns at once, so rounds
+// enqueued past the end cost only their dispatch.
+//
+// The alpha of the orthogonalisation come from one product m = P^T g_k and a
+// forward substitution with the leading k x k block of M (the same numbers as
+// orthogonalising against p_0 .. p_(k-1) one after another); M_(k:,k) is then
+// computed afresh from the orthogonalised g_k.
+#include <algorithm>
+
+#include "device_common.h"
+#include "launch.h"
+
+namespace tgdk {
+
+constexpr int IDR_BLOCKS = 1024;  // cap on the workgroups of the vector kernels
+constexpr int IDR_CH = 8;         // products with P accumulated per pass
+
+int idr_blocks(long long n) {
+    long long b = (n + 2 * NT - 1) / (2 * NT);
+    return (int)std::max(1LL, std::min(b, (long long)IDR_BLOCKS));
+}
+
+// Per-workgroup sums of P_j . y (j in [0, s)) and, with SELF, y . y as value
+// s, written to part.  y(i, first) returns entry i of y; first is true on
+// the first pass only (where y may be formed and stored).  Columns beyond
+// IDR_CH take further passes that read y back.
+template <class TI, bool SELF, class Y>
+__device__ __forceinline__ void dots_with_P(const IdrArgs& a, Y&& y) {
+    __shared__ double sh[NWAVE * (IDR_CH + 1)];
+    const TI* __restrict__ P = vp<TI>(a.P);
+    const long long n = a.n;
+    const long long stride = (long long)gridDim.x * NT;
+    const long long i0 = (long long)blockIdx.x * NT + threadIdx.x;
+    for (int c0 = 0; c0 < a.s; c0 += IDR_CH) {
+        const bool first = c0 == 0;
+        double acc[IDR_CH + 1];
+#pragma unroll
+        for (int j = 0; j <= IDR_CH; ++j) acc[j] = 0.0;
+        const int nc = min(IDR_CH, a.s - c0);
+        for (long long i = i0; i < n; i += stride) {
+            const double yv = y(i, first);
+#pragma unroll
+            for (int j = 0; j < IDR_CH; ++j)
+                if (j < nc) acc[j] += (double)P[(long long)(c0 + j) * n + i] * yv;
+            if (SELF && first) acc[IDR_CH] += yv * yv;
+        }
+        double tot;
+        block_sum<IDR_CH + 1>(acc, sh, tot);
+        if (threadIdx.x < nc) a.part[(long long)(c0 + threadIdx.x) * a.nb + blockIdx.x] = tot;
+        if (SELF && first && threadIdx.x == IDR_CH) a.part[(long long)a.s * a.nb + blockIdx.x] = tot;
+    }
+}
+
+// Cycle start: f = P^T r, r . r (values 0..s-1, s).
+template <class TI>
+__global__ __launch_bounds__(NT) void k_idr_start(IdrArgs a) {
+    if (a.ss->solve_state != SV_RUNNING) return;
+    const TI* __restrict__ r = vp<TI>(a.r);
+    dots_with_P<TI, true>(a, [&](long long i, bool) { return (double)r[i]; });
+}
+
+// Direction of step k: u_k = U_(k:) c + omega (r - G_(k:) c); in the first
+// round of a cycle G = U = 0 and omega = 1, so u_k = r.
+template <class TI>
+__global__ __launch_bounds__(NT) void k_idr_dir(IdrArgs a, int k) {
+    __shared__ double cs[IDR_SMAX];
+    const IdrState* st = a.st;
+    if (st->gate) return;
+    const TI* __restrict__ r = vp<TI>(a.r);
+    const TI* __restrict__ G = vp<TI>(a.G);
+    TI* U = vp<TI>(a.U);
+    const long long n = a.n;
+    TI* uk = U + (long long)k * n;
+    const long long stride = (long long)gridDim.x * NT;
+    const long long i0 = (long long)blockIdx.x * NT + threadIdx.x;
+    if (st->round0) {
+        for (long long i = i0; i < n; i += stride) uk[i] = r[i];
+        return;
+    }
+    const int m = a.s - k;
+    if (threadIdx.x < m) cs[threadIdx.x] = st->c[threadIdx.x];
+    __syncthreads();
+    const double om = st->om;
+    for (long long i = i0; i < n; i += stride) {
+        double gc = 0.0, uc = 0.0;
+        for (int j = 0; j < m; ++j) {
+            gc += (double)G[(long long)(k + j) * n + i] * cs[j];
+            uc += (double)U[(long long)(k + j) * n + i] * cs[j];
+        }
+        const TI v = (TI)((double)r[i] - gc);
+        uk[i] = (TI)(uc + om * (double)v);
+    }
+}
+
+// m = P^T g_k before the orthogonalisation (k > 0).
+template <class TI>
+__global__ __launch_bounds__(NT) void k_idr_gdot(IdrArgs a, int k) {
+    if (a.st->gate) return;
+    const TI* __restrict__ g = vp<TI>(a.G) + (long long)k * a.n;
+    dots_with_P<TI, false>(a, [&](long long i, bool) { return (double)g[i]; });
+}
+
+// g_k -= G_(:k) alpha, u_k -= U_(:k) alpha, then P^T g_k (values 0..s-1).
+template <class TI>
+__global__ __launch_bounds__(NT) void k_idr_orth(IdrArgs a, int k) {
+    __shared__ double al[IDR_SMAX];
+    const IdrState* st = a.st;
+    if (st->gate) return;
+    if (threadIdx.x < k) al[threadIdx.x] = st->alpha[threadIdx.x];
+    __syncthreads();
+    TI* G = vp<TI>(a.G);
+    TI* U = vp<TI>(a.U);
+    const long long n = a.n;
+    TI* g = G + (long long)k * n;
+    TI* u = U + (long long)k * n;
+    dots_with_P<TI, false>(a, [&](long long i, bool first) {
+        if (!first || k == 0) return (double)g[i];
+        double gs = (double)g[i], us = (double)u[i];
+        for (int j = 0; j < k; ++j) {
+            gs -= al[j] * (double)G[(long long)j * n + i];
+            us -= al[j] * (double)U[(long long)j * n + i];
+        }
+        const TI gt = (TI)gs;
+        g[i] = gt;
+        u[i] = (TI)us;
+        return (double)gt;
+    });
+}
+
+// r -= beta g_k, e += beta u_k (e = beta u_k on the cycle's first update);
+// r . r (value 0).
+template <class TI>
+__global__ __launch_bounds__(NT) void k_idr_upd(IdrArgs a, int k) {
+    __shared__ double sh[NWAVE];
+    const IdrState* st = a.st;
+    if (st->gate) return;
+    TI* r = vp<TI>(a.r);
+    TI* e = vp<TI>(a.e);
+    const long long n = a.n;
+    const TI* __restrict__ g = vp<TI>(a.G) + (long long)k * n;
+    const TI* __restrict__ u = vp<TI>(a.U) + (long long)k * n;
+    const double beta = st->beta;
+    const bool efirst = st->efirst;
+    const long long stride = (long long)gridDim.x * NT;
+    double acc = 0.0;
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
+        const TI rv = (TI)((double)r[i] - beta * (double)g[i]);
+        r[i] = rv;
+        e[i] = efirst ? (TI)(beta * (double)u[i]) : (TI)((double)e[i] + beta * (double)u[i]);
+        acc += (double)rv * (double)rv;
+    }
+    const double tot = block_sum_one(acc, sh);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
+}
+
+// Dimension reduction, first half: t . t, t . r, r . r (values 0, 1, 2).
+template <class TI>
+__global__ __launch_bounds__(NT) void k_idr_tdot(IdrArgs a) {
+    __shared__ double sh[NWAVE * 3];
+    if (a.st->gate) return;
+    const TI* __restrict__ r = vp<TI>(a.r);
+    const TI* __restrict__ t = vp<TI>(a.t);
+    const long long stride = (long long)gridDim.x * NT;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < a.n; i += stride) {
+        const double tv = (double)t[i], rv = (double)r[i];
+        acc[0] += tv * tv;
+        acc[1] += tv * rv;
+        acc[2] += rv * rv;
+    }
+    double tot;
+    block_sum<3>(acc, sh, tot);
+    if (threadIdx.x < 3) a.part[(long long)threadIdx.x * a.nb + blockIdx.x] = tot;
+}
+
+// Dimension reduction, second half: e += omega r, r -= omega t; then
+// f = P^T r, r . r (values 0..s-1, s) for the next round.
+template <class TI>
+__global__ __launch_bounds__(NT) void k_idr_red(IdrArgs a) {
+    const IdrState* st = a.st;
+    if (st->gate) return;
+    TI* r = vp<TI>(a.r);
+    TI* e = vp<TI>(a.e);
+    const TI* __restrict__ t = vp<TI>(a.t);
+    const double om = st->om;
+    const bool efirst = st->efirst;
+    dots_with_P<TI, true>(a, [&](long long i, bool first) {
+        if (!first) return (double)r[i];
+        const double rv = (double)r[i];
+        e[i] = efirst ? (TI)(om * rv) : (TI)((double)e[i] + om * rv);
+        const TI rn = (TI)(rv - om * (double)t[i]);
+        r[i] = rn;
+        return (double)rn;
+    });
+}
+
+// x += e at the end of a cycle (float64; nothing if e was never written).
+template <class TI>
+__global__ __launch_bounds__(NT) void k_idr_fold(IdrArgs a) {
+    if (a.ss->solve_state != SV_RUNNING || a.st->efirst) return;
+    const TI* __restrict__ e = vp<TI>(a.e);
+    const long long stride = (long long)gridDim.x * NT;
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < a.n; i += stride) a.x[i] += (double)e[i];
+}
+
+// ------------------------------------------------------------ epilogues
+enum : int { E_START = 0, E_ALPHA = 1, E_M = 2, E_UPD = 3, E_OM = 4, E_RED = 5 };
+
+// c = solution of the lower-triangular system M_(k:, k:) c = f_(k:).
+__device__ void idr_coeffs(IdrState* st, int k) {
+    const int s = st->s;
+    for (int i = k; i < s; ++i) {
+        double v = st->f[i];
+        for (int j = k; j < i; ++j) v -= st->M[i * s + j] * st->c[j - k];
+        st->c[i - k] = v / st->M[i * s + i];
+    }
+}
+
+__device__ void idr_end(const IdrArgs& a, int status) {
+    IdrState* st = a.st;
+    SolveState* ss = a.ss;
+    st->status = status;
+    st->gate = 1;
+    ss->iter = st->mvps;
+    ss->inner_state = status;
+    ss->mvp_inner += st->mvps;
+    ss->iters_total += st->mvps;
+    if (a.mirror) {
+        a.mirror->inner_state = status;
+        a.mirror->iter = st->mvps;
+        a.mirror->rr = st->rr;
+        __threadfence_system();
+    }
+}
+
+// ||r|| and the coefficient of an update of r in the first cycle (the
+// report's first scalars: norm, coefficient, 1 at a dimension reduction).
+__device__ void idr_hist(const IdrArgs& a, double rr, double coef, int red) {
+    SolveState* ss = a.ss;
+    if (ss->icyc == 1 && ss->nhist < NHIST) {
+        const int h = ss->nhist++;
+        ss->hist[3 * h] = sqrt(rr);
+        ss->hist[3 * h + 1] = coef;
+        ss->hist[3 * h + 2] = (double)red;
+    }
+}
+
+__device__ void idr_progress(const IdrArgs& a) {
+    if (a.mirror) {
+        a.mirror->rr = a.st->rr;
+        a.mirror->iter = a.st->mvps;
+        __threadfence_system();
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_idr_epi(IdrArgs a, int which, int k, int nv) {
+    __shared__ double v[IDR_SMAX + 4];
+    IdrState* st = a.st;
+    if (which == E_START ? a.ss->solve_state != SV_RUNNING : st->gate != 0) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int q = w; q < nv; q += NWAVE) {
+        double acc = 0.0;
+        for (int b = lane; b < a.nb; b += 64) acc += a.part[(long long)q * a.nb + b];
+        acc = wave_sum(acc);
+        if (lane == 0) v[q] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int s = st->s;
+    SolveState* ss = a.ss;
+    switch (which) {
+        case E_START: {
+            for (int i = 0; i < s * s; ++i) st->M[i] = 0.0;
+            for (int i = 0; i < s; ++i) {
+                st->M[i * s + i] = 1.0;
+                st->f[i] = v[i];
+                st->c[i] = v[i];
+            }
+            st->rr = v[s];
+            st->om = 1.0;
+            st->round0 = 1;
+            st->efirst = 1;
+            st->mvps = 0;
+            st->target2 = ss->target2;
+            st->maxit = ss->maxit;
+            st->status = IN_RUNNING;
+            st->gate = 0;
+            if (a.mirror) {
+                a.mirror->rr0 = st->rr;
+                a.mirror->target2 = st->target2;
+                a.mirror->inner_state = IN_RUNNING;
+            }
+            idr_progress(a);
+            if (st->rr <= st->target2) idr_end(a, IN_CONVERGED);
+            break;
+        }
+        case E_ALPHA: {
+            // forward substitution with the leading k x k block of M
+            for (int i = 0; i < k; ++i) {
+                double x = v[i];
+                for (int j = 0; j < i; ++j) x -= st->M[i * s + j] * st->alpha[j];
+                st->alpha[i] = x / st->M[i * s + i];
+            }
+            break;
+        }
+        case E_M: {
+            st->mvps += 1;
+            for (int i = k; i < s; ++i) st->M[i * s + k] = v[i];
+            const double mkk = st->M[k * s + k];
+            if (mkk == 0.0 || !isfinite(mkk)) {
+                idr_end(a, IN_BREAK_NOUPD);
+                break;
+            }
+            st->beta = st->f[k] / mkk;
+            break;
+        }
+        case E_UPD: {
+            const double rr = v[0];
+            st->rr = rr;
+            st->efirst = 0;
+            idr_hist(a, rr, st->beta, 0);
+            if (rr <= st->target2) {
+                idr_end(a, IN_CONVERGED);
+                break;
+            }
+            if (!isfinite(rr)) {
+                idr_end(a, IN_BREAK_NOUPD);
+                break;
+            }
+            for (int i = k + 1; i < s; ++i) st->f[i] -= st->beta * st->M[i * s + k];
+            if (st->mvps >= st->maxit) {
+                idr_end(a, IN_MAXIT);
+                break;
+            }
+            if (k + 1 < s) idr_coeffs(st, k + 1);
+            idr_progress(a);
+            break;
+        }
+        case E_OM: {
+            st->mvps += 1;
+            const double tt = v[0], ts = v[1], rr = v[2];
+            if (tt == 0.0 || ts == 0.0 || !isfinite(ts / tt)) {
+                idr_end(a, IN_BREAK_NOUPD);
+                break;
+            }
+            double om = ts / tt;
+            const double rho = fabs(ts) / (sqrt(tt) * sqrt(rr));
+            if (rho < st->kappa) om = om * st->kappa / rho;
+            st->om = om;
+            break;
+        }
+        case E_RED: {
+            const double rr = v[s];
+            st->rr = rr;
+            st->efirst = 0;
+            idr_hist(a, rr, st->om, 1);
+            if (rr <= st->target2) {
+                idr_end(a, IN_CONVERGED);
+                break;
+            }
+            if (!isfinite(rr)) {
+                idr_end(a, IN_BREAK_NOUPD);
+                break;
+            }
+            for (int i = 0; i < s; ++i) st->f[i] = v[i];
+            st->round0 = 0;
+            if (st->mvps >= st->maxit) {
+                idr_end(a, IN_MAXIT);
+                break;
+            }
+            idr_coeffs(st, 0);
+            idr_progress(a);
+            break;
+        }
+    }
+}
+
+// ------------------------------------------------------------- launchers
+template <class TI>
+static void idr_launch_t(int what, const IdrArgs& a, int k, hipStream_t s) {
+    const dim3 grid(a.nb), block(NT);
+    switch (what) {
+        case IDR_START:
+            hipLaunchKernelGGL(k_idr_start<TI>, grid, block, 0, s, a);
+            hipLaunchKernelGGL(k_idr_epi, dim3(1), block, 0, s, a, (int)E_START, 0, a.s + 1);
+            break;
+        case IDR_DIR:
+            hipLaunchKernelGGL(k_idr_dir<TI>, grid, block, 0, s, a, k);
+            break;
+        case IDR_ALPHA:
+            hipLaunchKernelGGL(k_idr_gdot<TI>, grid, block, 0, s, a, k);
+            hipLaunchKernelGGL(k_idr_epi, dim3(1), block, 0, s, a, (int)E_ALPHA, k, a.s);
+            break;
+        case IDR_ORTH:
+            hipLaunchKernelGGL(k_idr_orth<TI>, grid, block, 0, s, a, k);
+            hipLaunchKernelGGL(k_idr_epi, dim3(1), block, 0, s, a, (int)E_M, k, a.s);
+            break;
+        case IDR_UPD:
+            hipLaunchKernelGGL(k_idr_upd<TI>, grid, block, 0, s, a, k);
+            hipLaunchKernelGGL(k_idr_epi, dim3(1), block, 0, s, a, (int)E_UPD, k, 1);
+            break;
+        case IDR_OMEGA:
+            hipLaunchKernelGGL(k_idr_tdot<TI>, grid, block, 0, s, a);
+            hipLaunchKernelGGL(k_idr_epi, dim3(1), block, 0, s, a, (int)E_OM, 0, 3);
+            break;
+        case IDR_RED:
+            hipLaunchKernelGGL(k_idr_red<TI>, grid, block, 0, s, a);
+            hipLaunchKernelGGL(k_idr_epi, dim3(1), block, 0, s, a, (int)E_RED, 0, a.s + 1);
+            break;
+        case IDR_FOLD:
+            hipLaunchKernelGGL(k_idr_fold<TI>, grid, block, 0, s, a);
+            break;
+    }
+}
+
+void launch_idr(int what, int inner_f32, const IdrArgs& a, int k, hipStream_t s) {
+    if (inner_f32)
+        idr_launch_t<float>(what, a, k, s);
+    else
+        idr_launch_t<double>(what, a, k, s);
+}
+
+}  // namespace tgdk

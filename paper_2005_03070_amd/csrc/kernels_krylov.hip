@@ -1,9 +1,10 @@
-// Tile kernels of the GMRES(m)-Proj(k) driver and of the final true-residual
-// check: r = b - A x, the Galerkin projection c = V^T r, H d = c, and
-// x += V d, r -= A V d (Sec. 2.2 box).  One launch covers every tile of every
-// problem of a group; per-tile partial sums are reduced in tile order by a
-// one-workgroup-per-problem epilogue launch.  The BiCGStab cycles themselves
-// run in the step kernel (kernels_step.hip).
+// Tile kernels of the cycle boundary of the host-driven solvers (GMRES-Proj,
+// IDR(s)-Proj) and of the final true-residual check: r = b - A x, the
+// Galerkin projection c = V^T r, H d = c, and x += V d, r -= A V d (Sec. 2.2
+// box).  One launch covers every tile of every problem of a group; per-tile
+// partial sums are reduced in tile order by a one-workgroup-per-problem
+// epilogue launch.  The BiCGStab cycles run in the step kernel
+// (step_kernel.h).
 #include "device_common.h"
 #include "launch.h"
 
@@ -54,7 +55,8 @@ __device__ void start_cycle(SolveState* st, double nu, double rho0) {
 // ---------------------------------------------------------- true residual
 // r = b - A x (float64).  first != 0 on the first call of a solve (also sums
 // ||b||^2).  Without deflation vectors (k = 0) a BiCGStab cycle starts here:
-// the inner residual and shadow vector are written in the inner type.
+// the inner residual (and BiCGStab's shadow vector) are written in the inner
+// type.
 template <class Cfg, int DIM, class TI>
 __global__ __launch_bounds__(NT) void k_residual(const DevProb* __restrict__ probs, int nprob, int first) {
     __shared__ double L[Cfg::BOX];
@@ -82,7 +84,8 @@ __global__ __launch_bounds__(NT) void k_residual(const DevProb* __restrict__ pro
     }
     fill_halo<Cfg, DIM, double>(L, tp, op, [&](long long g) { return x[g]; });
     __syncthreads();
-    const bool start = (P.k == 0) && (st->method == METHOD_BICGSTAB) && first != 2;
+    const bool start = (P.k == 0) && (st->method != METHOD_GMRES) && first != 2;
+    const bool shadow = st->method == METHOD_BICGSTAB;
     TI* rin = vp<TI>(P.rin);
     TI* rhat = vp<TI>(P.rhat);
     const bool sep = (void*)rin != (void*)P.r;
@@ -99,7 +102,7 @@ __global__ __launch_bounds__(NT) void k_residual(const DevProb* __restrict__ pro
         if (start) {
             const TI ri = (TI)rv;
             if (sep) rin[g] = ri;
-            rhat[g] = ri;
+            if (shadow) rhat[g] = ri;
             acc[2] += (double)ri * (double)ri;
         }
     }
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(NT) void k_epi_residual(const DevProb* __restrict__
     const DevProb& P = probs[blockIdx.x];
     SolveState* st = P.st;
     if (first != 2 && st->solve_state != SV_RUNNING) return;
-    const bool start = (P.k == 0) && (st->method == METHOD_BICGSTAB) && first != 2;
+    const bool start = (P.k == 0) && (st->method != METHOD_GMRES) && first != 2;
     double sums[3];
     sum_partials_multi<3>(P.partial, P.ntiles, P.pstride, sums, sh);
     const double rr = sums[0], bb = sums[1], ri = sums[2];
@@ -145,7 +148,8 @@ __global__ __launch_bounds__(NT) void k_epi_residual(const DevProb* __restrict__
             st->solve_state = SV_NONFINITE;
         else if (nu <= st->tau)
             st->solve_state = SV_CONVERGED;
-        else if (st->method == METHOD_BICGSTAB && broke && st->iter == 0)
+        else if (broke && ((st->method == METHOD_BICGSTAB && st->iter == 0) ||
+                           (st->method == METHOD_IDR && st->iter <= 1)))
             st->solve_state = SV_BREAKDOWN;
         else if (st->icyc >= st->ncyc + st->max_extra)
             st->solve_state = SV_NOT_CONVERGED;
@@ -248,7 +252,8 @@ __global__ __launch_bounds__(NT) void k_epi_proj_dot(const DevProb* __restrict__
 
 // ---------------------------------- projection: x += V d, r -= A (V d)
 // w = V d is formed on the tile halo in LDS; then x += w and r -= A w on the
-// tile.  Starts the BiCGStab cycle (inner residual, shadow vector, rticyc).
+// tile.  Starts the next inner cycle (inner residual, BiCGStab's shadow
+// vector, the cycle tolerance).
 template <class Cfg, int DIM, class TV, class TI>
 __global__ __launch_bounds__(NT) void k_proj_apply(const DevProb* __restrict__ probs, int nprob) {
     __shared__ double L[Cfg::BOX];
@@ -284,7 +289,8 @@ __global__ __launch_bounds__(NT) void k_proj_apply(const DevProb* __restrict__ p
     }
     fill_halo<Cfg, DIM, double>(L, tp, op, wval);
     __syncthreads();
-    const bool start = st->method == METHOD_BICGSTAB;
+    const bool start = st->method != METHOD_GMRES;
+    const bool shadow = st->method == METHOD_BICGSTAB;
     TI* rin = vp<TI>(P.rin);
     TI* rhat = vp<TI>(P.rhat);
     const bool sep = (void*)rin != (void*)P.r;
@@ -301,7 +307,7 @@ __global__ __launch_bounds__(NT) void k_proj_apply(const DevProb* __restrict__ p
         if (start) {
             const TI ri = (TI)rv;
             if (sep) rin[g] = ri;
-            rhat[g] = ri;
+            if (shadow) rhat[g] = ri;
             acc[1] += (double)ri * (double)ri;
         }
     }
@@ -315,7 +321,7 @@ __global__ __launch_bounds__(NT) void k_epi_proj_apply(const DevProb* __restrict
     const DevProb& P = probs[blockIdx.x];
     SolveState* st = P.st;
     if (st->solve_state != SV_RUNNING || P.k == 0) return;
-    const bool start = st->method == METHOD_BICGSTAB;
+    const bool start = st->method != METHOD_GMRES;
     double sums[2];
     sum_partials_multi<2>(P.partial, P.ntiles, P.pstride, sums, sh);
     const double rr = sums[0], ri = sums[1];

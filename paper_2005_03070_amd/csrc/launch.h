@@ -10,8 +10,10 @@ namespace tgdk {
 enum : int { K_RESIDUAL = 0, K_PROJ_DOT = 1, K_PROJ_APPLY = 2 };
 
 // grid kernels
+// gate: null, or a device word; a nonzero word makes the launch a no-op
 template <class T>
-void launch_apply(const DevOp& op, const T* x, T* y, int nrhs, int tile_id, hipStream_t s);
+void launch_apply(const DevOp& op, const T* x, T* y, int nrhs, int tile_id, hipStream_t s,
+                  const int* gate = nullptr);
 void launch_build_divk(int nx, int ny, const double* kc, double bx, double by, double sigma, double* coef,
                        hipStream_t s);
 void launch_transpose_coef(int dim, int nx, int ny, int nz, const double* c, double* ct, hipStream_t s);
@@ -39,6 +41,21 @@ void launch_step(int dim, int inner_f32, int var, int tile_id, const DevProb* pr
 template <int DIM>
 void launch_step_dim(int inner_f32, int var, int tile_id, const DevProb* probs, const int* wg_prob, int total_wg,
                      int gslot, hipStream_t s);
+
+// IDR(s) inner cycles (kernels_idr.hip): what = one of the IDR_* actions,
+// k = the step of the round for IDR_DIR, IDR_ALPHA, IDR_ORTH, IDR_UPD.
+enum : int {
+    IDR_START = 0,  // f = P^T r, ||r||; the cycle's scalars reset
+    IDR_DIR = 1,    // u_k from r, G, U and c
+    IDR_ALPHA = 2,  // P^T g_k, alpha (k > 0)
+    IDR_ORTH = 3,   // g_k, u_k orthogonalised; M_(k:,k), beta
+    IDR_UPD = 4,    // r -= beta g_k, e += beta u_k; convergence; next c
+    IDR_OMEGA = 5,  // omega from t = A r
+    IDR_RED = 6,    // e += omega r, r -= omega t; f = P^T r; convergence; next c
+    IDR_FOLD = 7,   // x += e
+};
+int idr_blocks(long long n);
+void launch_idr(int what, int inner_f32, const IdrArgs& a, int k, hipStream_t s);
 
 // tall-skinny products (column-major blocks, leading dimensions in elements)
 // G (p x q, row-major, device) = A^T B, A: n x p, B: n x q; partial workspace

@@ -294,8 +294,10 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
         memset(&S, 0, sizeof(S));
         S.rtol = prm->rtol;
         S.fp32_floor = prm->fp32_floor > 0 ? prm->fp32_floor : 1e-4;
-        S.method = prm->method == TGDK_GMRES_PROJ ? METHOD_GMRES : METHOD_BICGSTAB;
-        if (S.method == METHOD_BICGSTAB) {
+        S.method = prm->method == TGDK_GMRES_PROJ ? METHOD_GMRES
+                   : prm->method == TGDK_IDRS_PROJ ? METHOD_IDR
+                                                   : METHOD_BICGSTAB;
+        if (S.method != METHOD_GMRES) {
             S.ncyc = prm->ncyc;
             S.max_extra = prm->max_extra_cycles >= 0 ? prm->max_extra_cycles : prm->ncyc;
         } else {
@@ -565,9 +567,145 @@ static int gmres_single(tgdk_ctx ctx, const ProbSpec& p, const tgdk_solve_params
     return finish_group(g, ps, rep, secs, &extra);
 }
 
+// IDR(s)(ncyc)-Proj(k): one right-hand side.  The cycle boundary is the
+// GMRES driver's (true residual, projection; the cycle tolerance is set on
+// the device); the IDR rounds are enqueued ahead in batches sized from the
+// residual reduction seen so far, at most two batches outstanding, and end on
+// the device (kernels_idr.hip).  The host waits only at cycle ends.
+static int idr_single(tgdk_ctx ctx, const ProbSpec& p, int s, const double* shadow, double kappa,
+                      const tgdk_solve_params* prm, tgdk_solve_report* rep) {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<ProbSpec> ps{p};
+    Group g;
+    int rc = build_group(ctx, ps, prm, g);
+    if (rc) return rc;
+    if ((rc = ensure_events(ctx, 2))) return rc;
+    hipStream_t hs = ctx->stream;
+    const long long n = p.op->N;
+    const int f32 = g.inner_f32;
+    const size_t ies = f32 ? 4 : 8;
+    const size_t sn = (size_t)s * n;
+    // G, U, P in the inner type; P64 (the orthonormalised draw); the state
+    const size_t off_u = align256(sn * ies), off_p = off_u + align256(sn * ies);
+    const size_t off_p64 = off_p + (f32 ? align256(sn * ies) : 0);
+    const size_t off_st = off_p64 + align256(sn * 8);
+    const size_t bytes = off_st + align256(sizeof(IdrState));
+    char* wk = nullptr;
+    if (hipMalloc((void**)&wk, bytes) != hipSuccess) return fail(TGDK_E_NOMEM, "IDR workspace allocation failed");
+    double* P64 = (double*)(wk + off_p64);
+    IdrState* d_st = (IdrState*)(wk + off_st);
+    auto done = [&](int code) {
+        (void)hipStreamSynchronize(hs);
+        (void)hipFree(wk);
+        return code;
+    };
+#define IDR_HIP(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess) return done(fail(TGDK_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_))); \
+    } while (0)
+    IDR_HIP(hipMemcpyAsync(P64, shadow, sn * 8, hipMemcpyDeviceToDevice, hs));
+    if ((rc = cholqr2(ctx, P64, n, s))) return done(rc == TGDK_E_SINGULAR ? fail(rc, "shadow space is rank deficient") : rc);
+    if (f32) launch_to_f32(P64, (float*)(wk + off_p), (long long)sn, hs);
+    IdrState h;
+    memset(&h, 0, sizeof(h));
+    h.gate = 1;
+    h.s = s;
+    h.kappa = kappa;
+    h.status = IN_CONVERGED;
+    IDR_HIP(hipMemcpyAsync(d_st, &h, sizeof(h), hipMemcpyHostToDevice, hs));
+    IdrArgs a;
+    memset(&a, 0, sizeof(a));
+    DevProb& P = g.probs[0];
+    a.r = P.rin;
+    a.e = P.e;
+    a.t = P.t;
+    a.G = wk;
+    a.U = wk + off_u;
+    a.P = f32 ? (const void*)(wk + off_p) : (const void*)P64;
+    a.x = p.x;
+    a.n = n;
+    a.nb = idr_blocks(n);
+    a.s = s;
+    a.st = d_st;
+    a.ss = g.d_states;
+    a.mirror = g.mirror;
+    // partial sums: s + 1 values (P^T r and r . r), 3 for omega
+    if ((rc = ctx->partial.ensure((size_t)a.nb * std::max(s + 1, 3) * sizeof(double)))) return done(rc);
+    a.part = (double*)ctx->partial.p;
+    const DevOp op = make_devop(p.op, prm->transpose);
+    const int tile = p.op->tile_id[f32];
+    const int* gate = &d_st->gate;
+    const size_t eln = (size_t)n * ies;
+    auto col = [&](void* base, int k) { return (void*)((char*)base + (size_t)k * eln); };
+    auto apply = [&](const void* x, void* y) {
+        if (f32)
+            launch_apply<float>(op, (const float*)x, (float*)y, 1, tile, hs, gate);
+        else
+            launch_apply<double>(op, (const double*)x, (double*)y, 1, tile, hs, gate);
+    };
+    auto round = [&]() {
+        for (int k = 0; k < s; ++k) {
+            launch_idr(IDR_DIR, f32, a, k, hs);
+            apply(col(a.U, k), col(a.G, k));
+            if (k > 0) launch_idr(IDR_ALPHA, f32, a, k, hs);
+            launch_idr(IDR_ORTH, f32, a, k, hs);
+            launch_idr(IDR_UPD, f32, a, k, hs);
+        }
+        apply(a.r, a.t);
+        launch_idr(IDR_OMEGA, f32, a, 0, hs);
+        launch_idr(IDR_RED, f32, a, 0, hs);
+    };
+    const int maxcyc = prm->ncyc + (prm->max_extra_cycles >= 0 ? prm->max_extra_cycles : prm->ncyc) + 2;
+    launch(g, K_RESIDUAL, 1);
+    IDR_HIP(hipGetLastError());
+    IDR_HIP(hipStreamSynchronize(hs));
+    double rate = 0.0;  // squared residual reduction per operator application
+    for (int cyc = 0; cyc < maxcyc; ++cyc) {
+        if (all_solved(g)) break;
+        if (p.defl) {
+            launch(g, K_PROJ_DOT);
+            launch(g, K_PROJ_APPLY);
+        }
+        launch_idr(IDR_START, f32, a, 0, hs);
+        IDR_HIP(hipGetLastError());
+        // rounds until the device ends the cycle
+        int ev_mvps = -1, head = 0, tail = 0, nr = 1;
+        for (;;) {
+            while (tail - head < 2) {
+                for (int i = 0; i < nr; ++i) round();
+                IDR_HIP(hipGetLastError());
+                IDR_HIP(hipEventRecord(ctx->events[tail % 2], hs));
+                ++tail;
+            }
+            if ((rc = wait_event(ctx->events[head % 2]))) return done(rc);
+            ++head;
+            const Mirror m = read_mirror(g, 0);
+            if (m.solve_state != SV_RUNNING || m.inner_state != IN_RUNNING) break;
+            if (m.iter == ev_mvps) return done(fail(TGDK_E_HIP, "IDR cycle stopped reporting progress"));
+            ev_mvps = m.iter;
+            if (m.iter >= 2 && m.rr > 0.0 && m.rr0 > 0.0 && m.rr < m.rr0) rate = std::pow(m.rr / m.rr0, 1.0 / m.iter);
+            int rem = s + 1;
+            if (rate > 0.0 && rate < 0.9999 && m.rr > 0.0 && m.target2 > 0.0 && m.rr > m.target2)
+                rem = (int)std::ceil(std::log(m.target2 / m.rr) / std::log(rate));
+            nr = std::max(1, std::min(8, (rem + s) / (s + 1)));
+        }
+        launch_idr(IDR_FOLD, f32, a, 0, hs);
+        launch(g, K_RESIDUAL, 0);
+        IDR_HIP(hipGetLastError());
+        IDR_HIP(hipStreamSynchronize(hs));
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    rc = finish_group(g, ps, rep, secs, nullptr);
+    return done(rc);
+#undef IDR_HIP
+}
+
 static int check_params(const tgdk_solve_params* prm) {
     if (!prm) return fail(TGDK_E_INVALID, "params is NULL");
     if (prm->method == TGDK_BICGSTAB_PROJ) {
+        if (prm->ncyc < 1) return fail(TGDK_E_INVALID, "ncyc must be >= 1");
+    } else if (prm->method == TGDK_IDRS_PROJ) {
         if (prm->ncyc < 1) return fail(TGDK_E_INVALID, "ncyc must be >= 1");
     } else if (prm->method == TGDK_GMRES_PROJ) {
         if (prm->m3 < 1 || prm->m3 > MAXK) return fail(TGDK_E_INVALID, "m3 out of range");
@@ -605,11 +743,26 @@ int tgdk_solve(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int nrh
     TGDK_HIP(hipSetDevice(fine->ctx->device));
     std::vector<ProbSpec> ps(nrhs);
     for (int j = 0; j < nrhs; ++j) ps[j] = ProbSpec{fine, defl, b + (size_t)j * fine->N, x + (size_t)j * fine->N};
+    if (prm->method == TGDK_IDRS_PROJ) return fail(TGDK_E_INVALID, "IDR(s)-Proj is solved by tgdk_solve_idr");
     if (prm->method == TGDK_GMRES_PROJ) {
         if (nrhs != 1) return fail(TGDK_E_INVALID, "GMRES-Proj takes one right-hand side");
         return gmres_single(fine->ctx, ps[0], prm, reports);
     }
     return bicgstab_group(fine->ctx, ps, prm, reports);
+}
+
+int tgdk_solve_idr(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int s, const double* shadow,
+                   double kappa, const tgdk_solve_params* prm, tgdk_solve_report* report) {
+    if (!fine || !b || !x || !shadow || !report) return fail(TGDK_E_INVALID, "bad argument");
+    int rc = check_params(prm);
+    if (rc) return rc;
+    if (prm->method != TGDK_IDRS_PROJ) return fail(TGDK_E_INVALID, "params.method must be TGDK_IDRS_PROJ");
+    if (s < 1 || s > IDR_SMAX) return fail(TGDK_E_INVALID, "s out of range (1..TGDK_IDR_SMAX)");
+    if ((long long)s > fine->N) return fail(TGDK_E_INVALID, "s exceeds the number of unknowns");
+    if (!(kappa >= 0.0 && kappa < 1.0)) return fail(TGDK_E_INVALID, "kappa must be in [0, 1)");
+    if ((rc = check_defl(fine, defl, prm))) return rc;
+    TGDK_HIP(hipSetDevice(fine->ctx->device));
+    return idr_single(fine->ctx, ProbSpec{fine, defl, b, x}, s, shadow, kappa, prm, report);
 }
 
 int tgdk_solve_instances(int ninst, const tgdk_op* ops, const tgdk_defl* defls, const double* const* b,
