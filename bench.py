@@ -44,6 +44,8 @@ def _args():
                     help="setup, warm-up and timed solves only (for hardware-counter runs)")
     ap.add_argument("--workload", choices=("2d", "3d"), default="2d",
                     help="with --solve-only: 2d = 1023^2 FP64 (the headline), 3d = 255^3 FP32 inner + FP64 refinement")
+    ap.add_argument("--method", choices=("bicgstab", "idr"), default="bicgstab",
+                    help="with --solve-only --workload 2d: the inner solver (idr = IDR(4), FP64)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB device buffer three times (counter scale of a plain copy)")
     return ap.parse_args()
@@ -146,6 +148,20 @@ def main():
         kw.setdefault("ncyc", c["ncyc"])
         kw.setdefault("rtol", c["rtol"])
         return tg.solve(op, b, x0=x0, defl=space, **kw)
+
+    if a.solve_only and a.method == "idr":
+        shadow = torch.tensor(W.shadow_draw(n, 4, 5), device=dev)
+        for _ in range(a.warmup):
+            tg.solve_idr(op, b, s=4, shadow=shadow, x0=x0, defl=space, ncyc=c["ncyc"], rtol=c["rtol"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            xi, ri = tg.solve_idr(op, b, s=4, shadow=shadow, x0=x0, defl=space, ncyc=c["ncyc"], rtol=c["rtol"])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.steps
+        log(f"fp64 IDR(4)(20)-Proj(30): {dt*1e3:.1f} ms/solve, mvps {ri.mvp_inner}, cycles {ri.cycles}, "
+            f"relres {ri.relres_true:.2e}, {dt*1e6/max(ri.mvp_inner, 1):.1f} us per inner mvp")
+        return
 
     def true_relres(x):
         r = b - op.apply(x)

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "idr_shared.h"
 #include "tgdk_shared.h"
 
 namespace tgdk {
