@@ -273,6 +273,10 @@ int tgdk_solve(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int nrh
  *    precision (TGDK_FP32_IR: G, U, P, r and e in float32), rtol,
  *    fp32_floor, x0_given, transpose as for BiCGStab; maxit_cycle bounds
  *    the operator applications of one inner cycle.
+ *  - TGDK_FP32_IR is for moderately conditioned grids: on the 1023^2
+ *    convection-diffusion grid the float32 IDR cycles stop reducing the
+ *    true residual near 1e-6 relative and then diverge (the same happens
+ *    in a plain float32 reference implementation); use TGDK_FP64 there.
  *  - report: iters_inner = mvp_inner = inner operator applications;
  *    first_rho[i] = ||r|| after the i-th update of the inner residual in the
  *    first cycle, first_alpha[i] = that update's coefficient (beta, or omega

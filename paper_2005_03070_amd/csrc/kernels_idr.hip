@@ -223,30 +223,39 @@ __global__ __launch_bounds__(NT) void k_idr_fold(IdrArgs a) {
 }
 
 // ------------------------------------------------------------ epilogues
+// One workgroup: the waves sum the partials of each value in a fixed order,
+// the cycle's small arrays (M, f, c, alpha) are staged in LDS, thread 0 takes
+// the decisions there (no dependent global-memory round trips), and the
+// workgroup writes the arrays back.
 enum : int { E_START = 0, E_ALPHA = 1, E_M = 2, E_UPD = 3, E_OM = 4, E_RED = 5 };
 
+struct EpiArrays {
+    double M[IDR_SMAX * IDR_SMAX];  // row-major s x s
+    double f[IDR_SMAX], c[IDR_SMAX], alpha[IDR_SMAX];
+};
+
 // c = solution of the lower-triangular system M_(k:, k:) c = f_(k:).
-__device__ void idr_coeffs(IdrState* st, int k) {
-    const int s = st->s;
+__device__ void idr_coeffs(EpiArrays& L, int s, int k) {
     for (int i = k; i < s; ++i) {
-        double v = st->f[i];
-        for (int j = k; j < i; ++j) v -= st->M[i * s + j] * st->c[j - k];
-        st->c[i - k] = v / st->M[i * s + i];
+        double v = L.f[i];
+        for (int j = k; j < i; ++j) v -= L.M[i * s + j] * L.c[j - k];
+        L.c[i - k] = v / L.M[i * s + i];
     }
 }
 
 __device__ void idr_end(const IdrArgs& a, int status) {
     IdrState* st = a.st;
     SolveState* ss = a.ss;
+    const int mvps = st->mvps;
     st->status = status;
     st->gate = 1;
-    ss->iter = st->mvps;
+    ss->iter = mvps;
     ss->inner_state = status;
-    ss->mvp_inner += st->mvps;
-    ss->iters_total += st->mvps;
+    ss->mvp_inner += mvps;
+    ss->iters_total += mvps;
     if (a.mirror) {
         a.mirror->inner_state = status;
-        a.mirror->iter = st->mvps;
+        a.mirror->iter = mvps;
         a.mirror->rr = st->rr;
         __threadfence_system();
     }
@@ -264,80 +273,72 @@ __device__ void idr_hist(const IdrArgs& a, double rr, double coef, int red) {
     }
 }
 
-__device__ void idr_progress(const IdrArgs& a) {
+__device__ void idr_progress(const IdrArgs& a, double rr, int mvps) {
     if (a.mirror) {
-        a.mirror->rr = a.st->rr;
-        a.mirror->iter = a.st->mvps;
+        a.mirror->rr = rr;
+        a.mirror->iter = mvps;
         __threadfence_system();
     }
 }
 
-__global__ __launch_bounds__(NT) void k_idr_epi(IdrArgs a, int which, int k, int nv) {
-    __shared__ double v[IDR_SMAX + 4];
+// The decisions of epilogue `which` (thread 0, on the staged arrays).
+__device__ void idr_decide(const IdrArgs& a, int which, int k, const double* v, EpiArrays& L) {
     IdrState* st = a.st;
-    if (which == E_START ? a.ss->solve_state != SV_RUNNING : st->gate != 0) return;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int q = w; q < nv; q += NWAVE) {
-        double acc = 0.0;
-        for (int b = lane; b < a.nb; b += 64) acc += a.part[(long long)q * a.nb + b];
-        acc = wave_sum(acc);
-        if (lane == 0) v[q] = acc;
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    const int s = st->s;
     SolveState* ss = a.ss;
+    const int s = a.s;
     switch (which) {
         case E_START: {
-            for (int i = 0; i < s * s; ++i) st->M[i] = 0.0;
+            for (int i = 0; i < s * s; ++i) L.M[i] = 0.0;
             for (int i = 0; i < s; ++i) {
-                st->M[i * s + i] = 1.0;
-                st->f[i] = v[i];
-                st->c[i] = v[i];
+                L.M[i * s + i] = 1.0;
+                L.f[i] = v[i];
+                L.c[i] = v[i];
             }
-            st->rr = v[s];
+            const double rr = v[s], target2 = ss->target2;
+            st->rr = rr;
             st->om = 1.0;
             st->round0 = 1;
             st->efirst = 1;
             st->mvps = 0;
-            st->target2 = ss->target2;
+            st->target2 = target2;
             st->maxit = ss->maxit;
             st->status = IN_RUNNING;
             st->gate = 0;
             if (a.mirror) {
-                a.mirror->rr0 = st->rr;
-                a.mirror->target2 = st->target2;
+                a.mirror->rr0 = rr;
+                a.mirror->target2 = target2;
                 a.mirror->inner_state = IN_RUNNING;
             }
-            idr_progress(a);
-            if (st->rr <= st->target2) idr_end(a, IN_CONVERGED);
+            idr_progress(a, rr, 0);
+            if (rr <= target2) idr_end(a, IN_CONVERGED);
             break;
         }
         case E_ALPHA: {
             // forward substitution with the leading k x k block of M
             for (int i = 0; i < k; ++i) {
                 double x = v[i];
-                for (int j = 0; j < i; ++j) x -= st->M[i * s + j] * st->alpha[j];
-                st->alpha[i] = x / st->M[i * s + i];
+                for (int j = 0; j < i; ++j) x -= L.M[i * s + j] * L.alpha[j];
+                L.alpha[i] = x / L.M[i * s + i];
             }
             break;
         }
         case E_M: {
             st->mvps += 1;
-            for (int i = k; i < s; ++i) st->M[i * s + k] = v[i];
-            const double mkk = st->M[k * s + k];
+            for (int i = k; i < s; ++i) L.M[i * s + k] = v[i];
+            const double mkk = L.M[k * s + k];
             if (mkk == 0.0 || !isfinite(mkk)) {
                 idr_end(a, IN_BREAK_NOUPD);
                 break;
             }
-            st->beta = st->f[k] / mkk;
+            st->beta = L.f[k] / mkk;
             break;
         }
         case E_UPD: {
-            const double rr = v[0];
+            const double rr = v[0], beta = st->beta;
+            const int mvps = st->mvps;
             st->rr = rr;
             st->efirst = 0;
-            idr_hist(a, rr, st->beta, 0);
+            idr_hist(a, rr, beta, 0);
             if (rr <= st->target2) {
                 idr_end(a, IN_CONVERGED);
                 break;
@@ -346,13 +347,13 @@ __global__ __launch_bounds__(NT) void k_idr_epi(IdrArgs a, int which, int k, int
                 idr_end(a, IN_BREAK_NOUPD);
                 break;
             }
-            for (int i = k + 1; i < s; ++i) st->f[i] -= st->beta * st->M[i * s + k];
-            if (st->mvps >= st->maxit) {
+            for (int i = k + 1; i < s; ++i) L.f[i] -= beta * L.M[i * s + k];
+            if (mvps >= st->maxit) {
                 idr_end(a, IN_MAXIT);
                 break;
             }
-            if (k + 1 < s) idr_coeffs(st, k + 1);
-            idr_progress(a);
+            if (k + 1 < s) idr_coeffs(L, s, k + 1);
+            idr_progress(a, rr, mvps);
             break;
         }
         case E_OM: {
@@ -364,12 +365,14 @@ __global__ __launch_bounds__(NT) void k_idr_epi(IdrArgs a, int which, int k, int
             }
             double om = ts / tt;
             const double rho = fabs(ts) / (sqrt(tt) * sqrt(rr));
-            if (rho < st->kappa) om = om * st->kappa / rho;
+            const double kappa = st->kappa;
+            if (rho < kappa) om = om * kappa / rho;
             st->om = om;
             break;
         }
         case E_RED: {
             const double rr = v[s];
+            const int mvps = st->mvps;
             st->rr = rr;
             st->efirst = 0;
             idr_hist(a, rr, st->om, 1);
@@ -381,16 +384,53 @@ __global__ __launch_bounds__(NT) void k_idr_epi(IdrArgs a, int which, int k, int
                 idr_end(a, IN_BREAK_NOUPD);
                 break;
             }
-            for (int i = 0; i < s; ++i) st->f[i] = v[i];
+            for (int i = 0; i < s; ++i) L.f[i] = v[i];
             st->round0 = 0;
-            if (st->mvps >= st->maxit) {
+            if (mvps >= st->maxit) {
                 idr_end(a, IN_MAXIT);
                 break;
             }
-            idr_coeffs(st, 0);
-            idr_progress(a);
+            idr_coeffs(L, s, 0);
+            idr_progress(a, rr, mvps);
             break;
         }
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_idr_epi(IdrArgs a, int which, int k, int nv) {
+    __shared__ double v[IDR_SMAX + 4];
+    __shared__ EpiArrays L;
+    IdrState* st = a.st;
+    if (which == E_START ? a.ss->solve_state != SV_RUNNING : st->gate != 0) return;
+    const int s = a.s;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int q = w; q < nv; q += NWAVE) {
+        double acc = 0.0;
+        for (int b = lane; b < a.nb; b += 64) acc += a.part[(long long)q * a.nb + b];
+        acc = wave_sum(acc);
+        if (lane == 0) v[q] = acc;
+    }
+    // stage what the decisions read
+    const bool readM = which == E_ALPHA || which == E_M || which == E_UPD || which == E_RED;
+    if (readM)
+        for (int i = threadIdx.x; i < s * s; i += NT) L.M[i] = st->M[i];
+    for (int i = threadIdx.x; i < s; i += NT) {
+        L.f[i] = st->f[i];
+        L.c[i] = st->c[i];
+        L.alpha[i] = st->alpha[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) idr_decide(a, which, k, v, L);
+    __syncthreads();
+    // write back what the decisions may have changed
+    if (which == E_START)
+        for (int i = threadIdx.x; i < s * s; i += NT) st->M[i] = L.M[i];
+    else if (which == E_M)
+        for (int i = k + threadIdx.x; i < s; i += NT) st->M[i * s + k] = L.M[i * s + k];
+    for (int i = threadIdx.x; i < s; i += NT) {
+        st->f[i] = L.f[i];
+        st->c[i] = L.c[i];
+        st->alpha[i] = L.alpha[i];
     }
 }
 

@@ -71,4 +71,11 @@ CONFIGS = {
                m=80, k=30, nev=24, rtolev=1e-8, ncyc=20, rtol=1e-8),
     "C5": dict(dim=2, n=(1023, 1023), beta=(60.0, 0.0), sigma=0.0, kseed=5, bstar_seed=6,
                bseed=7, dir_seed=8, m=80, k=30, nev=24, rtolev=1e-8, ncyc=20, rtol=1e-8),
+    # Indefinite Helmholtz -Lap(u) - kappa^2 u, kappa = 25 (about 40 negative
+    # eigenvalues), on the 511^2 grid of the paper's Example 4 with a random
+    # normal right-hand side; the wavenumber is scaled down from 100 so that
+    # the 60 vectors the deflation spaces hold here cover the eigenvalues
+    # nearest zero (Example 4 deflates 150 of about 800 negative ones).
+    "H1": dict(dim=2, n=(511, 511), beta=(0.0, 0.0), sigma=-625.0, seed=4,
+               m=128, k=60, nev=48, rtolev=1e-8, ncyc=20, rtol=1e-10, s=20),
 }
