@@ -49,7 +49,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import operators
-from .projection import galerkin
+from .projection import projector
 
 OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
 
@@ -144,11 +144,12 @@ class SolveReport:
 
 def bicgstab_proj(op, b, x0=None, V=None, H=None, rtol=1e-8, ncyc=20,
                   max_extra=None, maxit_cycle=100000, precision="fp64",
-                  fp32_floor=1e-4, transpose=False):
+                  fp32_floor=1e-4, transpose=False, projection="galerkin"):
     """BiCGStab(ncyc)-Proj(k) on ``A x = b`` (or ``A^T x = b``).
 
-    ``V`` (n x k, orthonormal) and ``H = V^T A V`` may be None (k = 0).
-    Returns ``(x, SolveReport)``."""
+    ``V`` (n x k, orthonormal) and ``H = V^T A V`` may be None (k = 0);
+    ``projection="minres"`` takes the MinRes variant of step a) (``H`` is then
+    not used).  Returns ``(x, SolveReport)``."""
     mv = (lambda z: operators.apply_transpose(op, z)) if transpose else (lambda z: operators.apply(op, z))
     if max_extra is None:
         max_extra = ncyc
@@ -164,11 +165,12 @@ def bicgstab_proj(op, b, x0=None, V=None, H=None, rtol=1e-8, ncyc=20,
         rep.relres_true = nu0 / bnorm if bnorm > 0 else 0.0
         return x, rep
     inner_dtype = np.float32 if precision == "fp32_ir" else np.float64
+    proj = projector(op, V, H, transpose, projection) if V is not None and V.shape[1] > 0 else None
     icyc = 0
     while True:
         icyc += 1
-        if V is not None and V.shape[1] > 0:           # step a)
-            x, r, _ = galerkin(op, V, H, x, r, transpose=transpose)
+        if proj is not None:                            # step a)
+            x, r, _ = proj(x, r)
             rep.mvp_boundary += 1
         nu = float(np.linalg.norm(r))
         if nu <= tau:                                   # step d) (after projection)

@@ -18,7 +18,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import operators
-from .projection import galerkin
+from .projection import projector
 
 OK, NOT_CONVERGED = 0, 1
 
@@ -75,8 +75,11 @@ class GmresReport:
 
 
 def gmres_proj(op, b, x0=None, V=None, H=None, rtol=1e-8, m=50, maxcyc=1000,
-               transpose=False):
-    """GMRES(m)-Proj(k) on ``A x = b``; ``V``/``H`` may be None (k = 0).
+               transpose=False, projection="galerkin", lengths=None):
+    """GMRES(m)-Proj(k) on ``A x = b``; ``V``/``H`` may be None (k = 0);
+    ``projection="minres"`` takes the MinRes variant of the projection.
+    ``lengths``: variable restarting (Sec. 4.3, Table 4.3): cycle j
+    (1-based) has ``lengths[j-1]`` steps while the list lasts, then ``m``.
 
     The overall tolerance is ``tau = rtol * min(||b||, ||r0||)``, as for
     BiCGStab(ncyc)-Proj(k)."""
@@ -92,14 +95,16 @@ def gmres_proj(op, b, x0=None, V=None, H=None, rtol=1e-8, m=50, maxcyc=1000,
     if nu0 <= tau:
         rep.relres_true = nu0 / bnorm if bnorm else 0.0
         return x, rep
+    proj = projector(op, V, H, transpose, projection) if V is not None and V.shape[1] > 0 else None
     for icyc in range(1, maxcyc + 1):
-        if V is not None and V.shape[1] > 0:          # (A) projection
-            x, r, _ = galerkin(op, V, H, x, r, transpose=transpose)
+        if proj is not None:                          # (A) projection
+            x, r, _ = proj(x, r)
             rep.mvp_boundary += 1
             if float(np.linalg.norm(r)) <= tau:
                 rep.cycles = icyc
                 break
-        e, lsq, steps = gmres_cycle(mv, r, m)          # (B) one GMRES(m) cycle
+        mc = lengths[icyc - 1] if lengths is not None and icyc <= len(lengths) else m
+        e, lsq, steps = gmres_cycle(mv, r, mc)         # (B) one GMRES(mc) cycle
         rep.mvp_inner += steps
         x = x + e
         r = b - mv(x)

@@ -37,7 +37,7 @@ import numpy as np
 from . import operators
 from .bicgstab import BREAKDOWN, NOT_CONVERGED, OK, SolveReport, cycle_tolerance
 from .deflation import orthonormalize
-from .projection import galerkin
+from .projection import projector
 
 
 def shadow_space(P0):
@@ -152,7 +152,7 @@ def idrs_inner(matvec, r0, target, P, maxit, kappa=0.7, dtype=np.float64, check=
 
 
 def idrs_proj(op, b, P, x0=None, V=None, H=None, rtol=1e-8, ncyc=20, max_extra=None, maxit_cycle=100000,
-              precision="fp64", fp32_floor=1e-4, kappa=0.7, transpose=False):
+              precision="fp64", fp32_floor=1e-4, kappa=0.7, transpose=False, projection="galerkin"):
     """IDR(s)(ncyc)-Proj(k) on ``A x = b`` with shadow matrix ``P`` (n x s).
 
     ``V`` (n x k, orthonormal) and ``H = V^T A V`` may be None (k = 0).
@@ -175,11 +175,12 @@ def idrs_proj(op, b, P, x0=None, V=None, H=None, rtol=1e-8, ncyc=20, max_extra=N
         return x, rep
     inner_dtype = np.float32 if precision == "fp32_ir" else np.float64
     Pin = np.asarray(P, dtype=inner_dtype)
+    proj = projector(op, V, H, transpose, projection) if V is not None and V.shape[1] > 0 else None
     icyc = 0
     while True:
         icyc += 1
-        if V is not None and V.shape[1] > 0:            # step a)
-            x, r, _ = galerkin(op, V, H, x, r, transpose=transpose)
+        if proj is not None:                            # step a)
+            x, r, _ = proj(x, r)
             rep.mvp_boundary += 1
         nu = float(np.linalg.norm(r))
         if nu <= tau:

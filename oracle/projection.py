@@ -8,7 +8,9 @@ approximate eigenvectors, form ``H = V^T A V`` and ``c = V^T r0``, solve
 
 ``H`` is formed once per operator and reused for every cycle and every
 right-hand side (Sec. 4.1, Example 2: a second right-hand side "does not need
-the coarse-grid work or forming of the projection matrix").
+the coarse-grid work or forming of the projection matrix").  The MinRes
+variant the paper notes after the box (not used in its experiments) is
+:func:`minres_projection`.
 """
 from __future__ import annotations
 
@@ -36,9 +38,35 @@ def galerkin(op, V, H, x, r, transpose=False):
     return x + xh, r - Axh, d
 
 
-def minres_projection(op, V, x, r):
-    """MinRes variant mentioned after the Sec. 2.2 box: ``H = (AV)^T AV``,
-    ``c = (AV)^T r0``.  Not used by the solvers (the paper uses Galerkin)."""
-    AV = operators.apply(op, V)
-    d = np.linalg.solve(AV.T @ AV, AV.T @ r)
-    return x + V @ d, r - AV @ d, d
+def minres_matrix(op, V, transpose=False):
+    """``W = A V`` (``A^T V`` if ``transpose``) and ``H = W^T W`` of the MinRes
+    projection."""
+    W = operators.apply_transpose(op, V) if transpose else operators.apply(op, V)
+    return W, W.T @ W
+
+
+def minres_projection(op, V, x, r, transpose=False, W=None, H=None):
+    """The MinRes variant noted after the Sec. 2.2 box: the box's steps with
+    ``H = (AV)^T AV`` and ``c = (AV)^T r0`` in place of ``V^T A V`` and
+    ``V^T r0``; the update is the box's (``x0 + V d``, ``r0 - A V d``).
+    ``W``, ``H`` from :func:`minres_matrix` (computed here if not given).
+    Returns ``(x_new, r_new, d)``."""
+    if W is None:
+        W, H = minres_matrix(op, V, transpose)
+    c = W.T @ r
+    d = np.linalg.solve(H, c)
+    xh = V @ d
+    Axh = operators.apply_transpose(op, xh) if transpose else operators.apply(op, xh)
+    return x + xh, r - Axh, d
+
+
+def projector(op, V, H, transpose=False, projection="galerkin"):
+    """The projection step of the solvers as a function ``(x, r) -> (x, r, d)``:
+    Galerkin with the given ``H = V^T A V``, or MinRes (its ``W`` and ``H``
+    formed here once)."""
+    if projection == "minres":
+        W, Hm = minres_matrix(op, V, transpose)
+        return lambda x, r: minres_projection(op, V, x, r, transpose, W, Hm)
+    if projection != "galerkin":
+        raise ValueError(projection)
+    return lambda x, r: galerkin(op, V, H, x, r, transpose=transpose)
