@@ -196,10 +196,23 @@ int tgdk_coarse_setup(tgdk_op coarse, const double* b_c, double* x_c,
 int tgdk_defl_prolongate(tgdk_defl coarse_space, tgdk_op fine, int store_dtype, tgdk_defl* fine_space);
 int tgdk_defl_from_basis(tgdk_op op, const double* W, int k, int transpose, int store_dtype,
                          tgdk_defl* out);
+/* MinRes projection (the variant the paper notes after the Sec. 2.2 box):
+ * the same V, with H = (AV)^T (AV) and c = (AV)^T r in place of V^T A V and
+ * V^T r; the update is unchanged (x += V d, r -= A V d), so the new residual
+ * is the least-squares residual of r over span(AV) and never grows.
+ * Builds a new space on the same operator and orientation that also stores
+ * W = A V (or A^T V) in the store type of V (H is formed from the stored W).
+ * Every solver accepts either kind of space.  TGDK_E_SINGULAR if AV is rank
+ * deficient. */
+#define TGDK_PROJ_GALERKIN 0
+#define TGDK_PROJ_MINRES   1
+int tgdk_defl_minres(tgdk_defl galerkin_space, tgdk_defl* minres_space);
 /* k and the store type of a space. */
 int tgdk_defl_info(tgdk_defl defl, int* k, int* store_dtype, long long* n);
-/* Copy V out as float64 (device, n x k) and H (host, k x k row-major); either
- * pointer may be NULL. */
+/* TGDK_PROJ_GALERKIN or TGDK_PROJ_MINRES. */
+int tgdk_defl_projection(tgdk_defl defl);
+/* Copy V out as float64 (device, n x k) and H (host, k x k row-major; the
+ * space's own H, (AV)^T AV for a MinRes space); either pointer may be NULL. */
 int tgdk_defl_copy(tgdk_defl defl, double* V_out, double* H_out);
 int tgdk_defl_destroy(tgdk_defl defl);
 
@@ -235,6 +248,11 @@ typedef struct {
     int max_extra_cycles;  /* BiCGStab, IDR: cycles allowed past ncyc; GMRES: max cycles */
     double rtol;
     double fp32_floor;
+    /* GMRES: variable restarting (Sec. 4.3, Table 4.3): cycle j (0-based)
+     * has cycle_lengths[j] steps for j < n_cycle_lengths, then m3 steps;
+     * every length in 1..m3.  NULL / 0: every cycle has m3 steps. */
+    const int* cycle_lengths;  /* host array */
+    int n_cycle_lengths;
 } tgdk_solve_params;
 
 typedef struct {

@@ -16,6 +16,7 @@ NOT_CONVERGED, BREAKDOWN = 1, 2
 F64, F32 = 0, 1
 CONST_CD, VAR_STENCIL, DIV_K = 0, 1, 2
 BICGSTAB_PROJ, GMRES_PROJ, IDRS_PROJ = 0, 1, 2
+PROJ_GALERKIN, PROJ_MINRES = 0, 1
 FP64, FP32_IR = 0, 1
 MAX_DEFL = 128
 NHIST = 8
@@ -46,7 +47,8 @@ class GmresDrReport(C.Structure):
 class SolveParams(C.Structure):
     _fields_ = [("method", C.c_int), ("ncyc", C.c_int), ("m3", C.c_int), ("precision", C.c_int),
                 ("x0_given", C.c_int), ("transpose", C.c_int), ("maxit_cycle", C.c_int),
-                ("max_extra_cycles", C.c_int), ("rtol", C.c_double), ("fp32_floor", C.c_double)]
+                ("max_extra_cycles", C.c_int), ("rtol", C.c_double), ("fp32_floor", C.c_double),
+                ("cycle_lengths", C.POINTER(C.c_int)), ("n_cycle_lengths", C.c_int)]
 
 
 class SolveReport(C.Structure):
@@ -81,6 +83,8 @@ SIGNATURES = [
     ("tgdk_coarse_setup", I, [P, P, P, C.POINTER(GmresDrParams), PP, C.POINTER(GmresDrReport)]),
     ("tgdk_defl_prolongate", I, [P, P, I, PP]),
     ("tgdk_defl_from_basis", I, [P, P, I, I, I, PP]),
+    ("tgdk_defl_minres", I, [P, PP]),
+    ("tgdk_defl_projection", I, [P]),
     ("tgdk_defl_info", I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(C.c_longlong)]),
     ("tgdk_defl_copy", I, [P, P, DP]),
     ("tgdk_defl_destroy", I, [P]),

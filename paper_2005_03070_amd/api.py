@@ -147,6 +147,14 @@ class DeflationSpace:
         k, st, n = C.c_int(), C.c_int(), C.c_longlong()
         check(lib().tgdk_defl_info(handle, C.byref(k), C.byref(st), C.byref(n)))
         self.k, self.store, self.n = k.value, st.value, n.value
+        self.projection = "minres" if lib().tgdk_defl_projection(handle) == L.PROJ_MINRES else "galerkin"
+
+    def minres(self):
+        """The MinRes-projection space over the same V: H = (AV)^T AV and
+        c = (AV)^T r (see include/tgdk.h, tgdk_defl_minres)."""
+        h = C.c_void_p()
+        check(lib().tgdk_defl_minres(self.h, C.byref(h)))
+        return DeflationSpace(h, self.op, self.transpose)
 
     def basis(self):
         """(V as a (k, n) float64 tensor, H as a k x k numpy array)."""
@@ -254,9 +262,10 @@ def _reports(reps):
 
 
 def solve(op, b, x0=None, defl=None, method="bicgstab", ncyc=20, m3=50, precision="fp64", rtol=1e-8,
-          transpose=False, maxit_cycle=100000, max_extra=None, fp32_floor=1e-4, out=None):
+          transpose=False, maxit_cycle=100000, max_extra=None, fp32_floor=1e-4, out=None, cycle_lengths=None):
     """Fine solve of A x = b (A^T x = b if transpose).  b: (n,) or (nrhs, n)
-    float64.  Returns (x, [Report per right-hand side])."""
+    float64.  cycle_lengths (GMRES): lengths of the first cycles, each in
+    1..m3 (variable restarting).  Returns (x, [Report per right-hand side])."""
     nrhs = 1 if b.dim() == 1 else b.shape[0]
     _ptr(b, numel=op.n * nrhs, what="b")
     if out is None:
@@ -265,6 +274,10 @@ def solve(op, b, x0=None, defl=None, method="bicgstab", ncyc=20, m3=50, precisio
     if x0 is not None:
         out.copy_(x0)
     p = _params(method, ncyc, m3, precision, x0 is not None, transpose, maxit_cycle, max_extra, rtol, fp32_floor)
+    if cycle_lengths is not None:
+        lens = (C.c_int * len(cycle_lengths))(*[int(v) for v in cycle_lengths])
+        p.cycle_lengths = C.cast(lens, C.POINTER(C.c_int))
+        p.n_cycle_lengths = len(cycle_lengths)
     reps = (L.SolveReport * nrhs)()
     check(lib().tgdk_solve(op.h, defl.h if defl is not None else None, C.c_void_p(b.data_ptr()),
                            C.c_void_p(out.data_ptr()), nrhs, C.byref(p), reps))

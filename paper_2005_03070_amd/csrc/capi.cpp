@@ -159,7 +159,7 @@ int cholqr2(tgdk_ctx ctx, double* W, long long n, int k) {
     return rc;
 }
 
-int defl_finish(tgdk_op op, int transpose, double* V64, int k, int store, tgdk_defl* out) {
+int defl_finish(tgdk_op op, int transpose, double* V64, int k, int store, tgdk_defl* out, int projection) {
     tgdk_ctx ctx = op->ctx;
     hipStream_t s = ctx->stream;
     const long long n = op->N;
@@ -176,18 +176,35 @@ int defl_finish(tgdk_op op, int transpose, double* V64, int k, int store, tgdk_d
         return rc;
     }
     rc = op_apply_internal(op, transpose, TGDK_F64, V64, AV, k);
+    const bool minres = projection == TGDK_PROJ_MINRES;
+    float* W32 = nullptr;  // MinRes, float32 storage: the stored A V
+    if (!rc && minres && store == TGDK_F32) {
+        rc = dev_alloc(&W32, (size_t)n * k);
+        if (!rc) {
+            launch_to_f32(AV, W32, (long long)n * k, s);
+            launch_to_f64(W32, AV, (long long)n * k, s);  // H is formed from the rounded W
+        }
+    }
     std::vector<double> H((size_t)k * k);
     double* dG = nullptr;
     if (!rc) rc = dev_alloc(&dG, (size_t)k * k);
     if (!rc) rc = ctx->partial.ensure((size_t)gram_blocks(n) * k * k * sizeof(double));
     if (!rc) {
-        launch_gram(V64, 0, n, k, AV, 0, n, k, n, dG, (double*)ctx->partial.p, ctx->counters, s);
+        // Galerkin H = V^T (A V); MinRes H = (A V)^T (A V)
+        launch_gram(minres ? AV : V64, 0, n, k, AV, 0, n, k, n, dG, (double*)ctx->partial.p, ctx->counters, s);
         if (hipMemcpyAsync(H.data(), dG, H.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             rc = fail(TGDK_E_HIP, "forming H failed");
     }
     if (dG) (void)hipFree(dG);
-    (void)hipFree(AV);
+    void* W = nullptr;  // the stored left basis (MinRes only)
+    if (minres && !rc) {
+        W = store == TGDK_F32 ? (void*)W32 : (void*)AV;
+        if (store == TGDK_F32) (void)hipFree(AV);
+    } else {
+        (void)hipFree(AV);
+        if (W32) (void)hipFree(W32);
+    }
     if (rc) {
         if (V32) (void)hipFree(V32);
         return rc;
@@ -199,13 +216,17 @@ int defl_finish(tgdk_op op, int transpose, double* V64, int k, int store, tgdk_d
     d->k = k;
     d->n = n;
     d->store = store;
+    d->projection = minres ? TGDK_PROJ_MINRES : TGDK_PROJ_GALERKIN;
+    d->W = W;
     d->H = H;
     d->LU = H;
     d->piv.assign(k, 0);
     if (lu_factor(k, d->LU.data(), d->piv.data()) != 0) {
         if (V32) (void)hipFree(V32);
+        if (W) (void)hipFree(W);
         delete d;
-        return fail(TGDK_E_SINGULAR, "projection matrix H = V^T A V is singular");
+        return fail(TGDK_E_SINGULAR, minres ? "projection matrix H = (AV)^T AV is singular"
+                                            : "projection matrix H = V^T A V is singular");
     }
     // H^{-1} column by column from the LU factors (column-major)
     std::vector<double> hinv((size_t)k * k, 0.0);
@@ -219,6 +240,7 @@ int defl_finish(tgdk_op op, int transpose, double* V64, int k, int store, tgdk_d
         if (V32) (void)hipFree(V32);
         if (d->d_lu) (void)hipFree(d->d_lu);
         if (d->d_piv) (void)hipFree(d->d_piv);
+        if (W) (void)hipFree(W);
         delete d;
         return rc;
     }
@@ -229,6 +251,7 @@ int defl_finish(tgdk_op op, int transpose, double* V64, int k, int store, tgdk_d
         (void)hipFree(d->d_lu);
         (void)hipFree(d->d_piv);
         (void)hipFree(d->d_hinv);
+        if (W) (void)hipFree(W);
         delete d;
         return fail(TGDK_E_HIP, "upload of LU failed");
     }
@@ -496,7 +519,7 @@ int tgdk_defl_prolongate(tgdk_defl cs, tgdk_op fine, int store_dtype, tgdk_defl*
         (void)hipFree(PW);
         return rc;
     }
-    rc = defl_finish(fine, cs->transpose, PW, k, store_dtype, out);
+    rc = defl_finish(fine, cs->transpose, PW, k, store_dtype, out, TGDK_PROJ_GALERKIN);
     if (rc) (void)hipFree(PW);
     return rc;
 }
@@ -513,10 +536,28 @@ int tgdk_defl_from_basis(tgdk_op op, const double* W, int k, int transpose, int 
         (void)hipFree(V);
         return rc;
     }
-    rc = defl_finish(op, transpose ? 1 : 0, V, k, store_dtype, out);
+    rc = defl_finish(op, transpose ? 1 : 0, V, k, store_dtype, out, TGDK_PROJ_GALERKIN);
     if (rc) (void)hipFree(V);
     return rc;
 }
+
+int tgdk_defl_minres(tgdk_defl g, tgdk_defl* out) {
+    if (!g || !out) return fail(TGDK_E_INVALID, "NULL argument");
+    TGDK_HIP(hipSetDevice(g->ctx->device));
+    double* V = nullptr;
+    int rc = dev_alloc(&V, (size_t)g->n * g->k);
+    if (rc) return rc;
+    if (g->store == TGDK_F64)
+        TGDK_HIP(hipMemcpyAsync(V, g->V, (size_t)g->n * g->k * sizeof(double), hipMemcpyDeviceToDevice,
+                                g->ctx->stream));
+    else
+        launch_to_f64((const float*)g->V, V, (long long)g->n * g->k, g->ctx->stream);
+    rc = defl_finish(g->op, g->transpose, V, g->k, g->store, out, TGDK_PROJ_MINRES);
+    if (rc) (void)hipFree(V);
+    return rc;
+}
+
+int tgdk_defl_projection(tgdk_defl d) { return d ? d->projection : TGDK_E_INVALID; }
 
 int tgdk_defl_info(tgdk_defl d, int* k, int* store, long long* n) {
     if (!d) return fail(TGDK_E_INVALID, "NULL space");
@@ -545,6 +586,7 @@ int tgdk_defl_destroy(tgdk_defl d) {
     if (!d) return TGDK_OK;
     (void)hipSetDevice(d->ctx->device);
     if (d->V) (void)hipFree(d->V);
+    if (d->W) (void)hipFree(d->W);
     if (d->d_lu) (void)hipFree(d->d_lu);
     if (d->d_piv) (void)hipFree(d->d_piv);
     if (d->d_hinv) (void)hipFree(d->d_hinv);

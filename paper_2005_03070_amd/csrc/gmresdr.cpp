@@ -359,7 +359,7 @@ extern "C" int tgdk_coarse_setup(tgdk_op op, const double* b, double* x, const t
     TGDK_HIP(hipStreamSynchronize(s));
     cleanup();
     tgdk_defl d = nullptr;
-    rc = defl_finish(op, tr, W, kk, TGDK_F64, &d);
+    rc = defl_finish(op, tr, W, kk, TGDK_F64, &d, TGDK_PROJ_GALERKIN);
     if (rc) {
         (void)hipFree(W);
         return rc;

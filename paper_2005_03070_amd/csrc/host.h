@@ -78,6 +78,8 @@ struct tgdk_defl_s {
     long long n = 0;
     int store = TGDK_F64;
     void* V = nullptr;         // n x k column-major (ldv = n)
+    int projection = TGDK_PROJ_GALERKIN;
+    void* W = nullptr;         // MinRes: A V (or A^T V), same layout and type as V; else null
     std::vector<double> H, LU;
     std::vector<int> piv;
     double* d_lu = nullptr;
@@ -89,8 +91,9 @@ namespace tgdk {
 
 DevOp make_devop(const tgdk_op_s* op, int transpose);
 double op_norm1(tgdk_op op, int transpose);
-// Builds H = V^T A V (V float64 device, n x k), its LU, and the defl handle.
-int defl_finish(tgdk_op op, int transpose, double* V64, int k, int store, tgdk_defl* out);
+// Builds H = V^T A V (Galerkin) or (AV)^T AV with W = A V kept (MinRes) from V
+// (float64 device, n x k, owned by the handle on success), its LU, and the handle.
+int defl_finish(tgdk_op op, int transpose, double* V64, int k, int store, tgdk_defl* out, int projection);
 // Orthonormalise W (n x k, device float64) in place by CholQR2.
 int cholqr2(tgdk_ctx ctx, double* W, long long n, int k);
 int op_apply_internal(tgdk_op op, int transpose, int dtype, const void* x, void* y, int nrhs);

@@ -181,7 +181,7 @@ __global__ __launch_bounds__(NT) void k_proj_dot(const DevProb* __restrict__ pro
     const int lt = t - P.tile_begin;
     const TilePos tp = tile_pos<Cfg>(lt, P.tx, P.ty);
     const DevOp& op = P.op;
-    const TV* V = reinterpret_cast<const TV*>(P.V);
+    const TV* V = reinterpret_cast<const TV*>(P.Vl);  // left basis of c
     const int k = P.k;
     double rv[Cfg::PPT];
     long long gq[Cfg::PPT];

@@ -278,6 +278,7 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
         if (g.dim == 3 && P.k > 0) P.w = (double*)v;
         if (ps[j].defl) {
             P.V = ps[j].defl->V;
+            P.Vl = ps[j].defl->W ? ps[j].defl->W : ps[j].defl->V;
             P.ldv = ps[j].defl->n;
             P.lu = ps[j].defl->d_lu;
             P.piv = ps[j].defl->d_piv;
@@ -519,8 +520,10 @@ static int gmres_single(tgdk_ctx ctx, const ProbSpec& p, const tgdk_solve_params
             if (all_solved(g)) break;
         }
         launch_scale(g.probs[0].r, V, d_nu, n, s);
-        int steps = m;
-        for (int j = 0; j < m; ++j) {
+        // this cycle's length (variable restarting), at most m
+        const int mc = cyc < prm->n_cycle_lengths && prm->cycle_lengths ? prm->cycle_lengths[cyc] : m;
+        int steps = mc;
+        for (int j = 0; j < mc; ++j) {
             launch_apply<double>(op, V + (size_t)j * n, w, 1, p.op->tile_id[0], s);
             launch_gs_dot(V, n, j + 1, w, n, H1 + (size_t)j * (m + 1), (double*)ctx->partial.p, ctx->counters, s);
             launch_gs_update_dot(V, n, j + 1, w, H1 + (size_t)j * (m + 1), n, H2 + (size_t)j * (m + 1),
@@ -537,7 +540,7 @@ static int gmres_single(tgdk_ctx ctx, const ProbSpec& p, const tgdk_solve_params
         TGDK_HIP(hipStreamSynchronize(s));
         // Hbar (row-major (m+1) x m); stop at an exact zero subdiagonal
         std::fill(Hbar.begin(), Hbar.end(), 0.0);
-        for (int j = 0; j < m; ++j) {
+        for (int j = 0; j < mc; ++j) {
             for (int i = 0; i <= j; ++i) Hbar[(size_t)i * m + j] = h1[(size_t)j * (m + 1) + i] + h2[(size_t)j * (m + 1) + i];
             Hbar[(size_t)(j + 1) * m + j] = nrm[j];
             if (nrm[j] == 0.0) {
@@ -709,6 +712,11 @@ static int check_params(const tgdk_solve_params* prm) {
         if (prm->ncyc < 1) return fail(TGDK_E_INVALID, "ncyc must be >= 1");
     } else if (prm->method == TGDK_GMRES_PROJ) {
         if (prm->m3 < 1 || prm->m3 > MAXK) return fail(TGDK_E_INVALID, "m3 out of range");
+        if (prm->n_cycle_lengths < 0 || (prm->n_cycle_lengths > 0 && !prm->cycle_lengths))
+            return fail(TGDK_E_INVALID, "cycle_lengths");
+        for (int j = 0; j < prm->n_cycle_lengths; ++j)
+            if (prm->cycle_lengths[j] < 1 || prm->cycle_lengths[j] > prm->m3)
+                return fail(TGDK_E_INVALID, "cycle lengths must be in 1..m3");
         if (prm->precision != TGDK_FP64) return fail(TGDK_E_INVALID, "GMRES-Proj runs in float64 only");
     } else {
         return fail(TGDK_E_INVALID, "unknown method");

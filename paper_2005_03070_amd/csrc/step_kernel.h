@@ -539,9 +539,9 @@ __device__ __forceinline__ void true_residual(const DevProb& P, int lw, int gslo
             for (int q = 0; q < Cfg::PPT; ++q) L[threadIdx.x + q * NT] = rv[q];
             __syncthreads();
             if (P.vtype)
-                c_partials<Cfg>(P, tp, reinterpret_cast<const float*>(P.V), L, csum);
+                c_partials<Cfg>(P, tp, reinterpret_cast<const float*>(P.Vl), L, csum);
             else
-                c_partials<Cfg>(P, tp, reinterpret_cast<const double*>(P.V), L, csum);
+                c_partials<Cfg>(P, tp, reinterpret_cast<const double*>(P.Vl), L, csum);
         }
         __syncthreads();
     }
@@ -943,9 +943,9 @@ __device__ __forceinline__ void march_res(const DevProb& P, int lw, int gslot, c
         __syncthreads();  // r of the chunk, written above, is read back below
         if (k > 0) {
             if (P.vtype)
-                chunk_columns<M>(P, c, reinterpret_cast<const float*>(P.V), csum, sh);
+                chunk_columns<M>(P, c, reinterpret_cast<const float*>(P.Vl), csum, sh);
             else
-                chunk_columns<M>(P, c, reinterpret_cast<const double*>(P.V), csum, sh);
+                chunk_columns<M>(P, c, reinterpret_cast<const double*>(P.Vl), csum, sh);
         }
     }
     __syncthreads();

@@ -124,6 +124,7 @@ struct DevProb {
     void* t;
     void* e;
     const void* V;           // deflation basis, column-major, leading dim ldv
+    const void* Vl;          // basis of c = Vl^T r: V (Galerkin) or A V (MinRes), same layout and type
     long long ldv;
     int vtype;               // V stored as 0 float64, 1 float32
     int mcx, mcy, mz, nchunks;  // 3-D step kernel: z-marching chunks (mcx x mcy columns, mz planes deep)

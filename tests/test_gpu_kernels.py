@@ -122,5 +122,6 @@ def test_every_tile_shape_gives_identical_stencil(tmp_path, monkeypatch):
         assert all(np.array_equal(outs[0], o) for o in outs[1:])
         monkeypatch.setenv("TGDK_TUNE_CACHE", str(tmp_path / "fresh.txt"))
         ty = op.tune()
-        assert ty in (4, 8, 16)
+        # candidate tile heights: 2-D 16, 8, 4, 32; 3-D 4, 8, 4, 2 (timing decides)
+        assert ty in ((16, 8, 4, 32) if len(dims) == 2 else (4, 8, 2))
         assert "tile=" in (tmp_path / "fresh.txt").read_text()

@@ -1,0 +1,155 @@
+"""GPU parity of the MinRes projection (H = (AV)^T AV, c = (AV)^T r; the
+variant noted after the Sec. 2.2 box) in every solver, and of variable GMRES
+cycle lengths (Sec. 4.3, Table 4.3), against the oracle through the C-ABI:
+the space's H, the first inner scalars after a MinRes projection (2-D step
+kernel, 3-D marching boundary with float32-stored V and W), GMRES and IDR
+with MinRes spaces, and GMRES restarted with given cycle lengths."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spl
+import torch
+
+import workloads as W
+from oracle import operators as O, projection as PR, deflation as OD, bicgstab as OB, gmres as OG, idr as OI
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+
+
+def tg():
+    import paper_2005_03070_amd as m
+    return m
+
+
+def _t(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def _direct(oop, b):
+    return spl.spsolve(O.to_csr(oop).tocsc(), b)
+
+
+def _relres(oop, b, x):
+    return np.linalg.norm(b - O.apply(oop, x)) / np.linalg.norm(b)
+
+
+def _space(oop, cdims, k, seed):
+    Wc = W.rng(seed).standard_normal((int(np.prod(cdims)), k))
+    return OD.deflation_space(oop, Wc, cdims)
+
+
+def _c1():
+    c = W.CONFIGS["C1"]
+    oop = O.const_cd(c["n"], c["beta"])
+    return c, oop, W.rhs(oop.n, c["seed"])
+
+
+def test_minres_space_matrix():
+    """The MinRes space keeps V and holds H = (AV)^T AV (oracle's to 1e-12)."""
+    c, oop, b = _c1()
+    V, H = _space(oop, (31, 31), 10, 41)
+    op = tg().Operator.const_cd(c["n"], c["beta"])
+    g = tg().defl_from_basis(op, _t(V.T))
+    m = g.minres()
+    assert g.projection == "galerkin" and m.projection == "minres" and m.k == g.k
+    Vg, Hg = g.basis()
+    Vm, Hm = m.basis()
+    assert torch.equal(Vg, Vm)
+    _, Hm_o = PR.minres_matrix(oop, Vg.cpu().numpy().T)
+    np.testing.assert_allclose(Hm, Hm_o, rtol=1e-12, atol=1e-12 * np.abs(Hm_o).max())
+    np.testing.assert_allclose(Hg, H, rtol=1e-10, atol=1e-10 * np.abs(H).max())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_bicgstab_minres_2d(precision):
+    """BiCGStab(20)-Proj(10) with a MinRes space: in FP64 the first inner
+    scalars (the first cycle starts after a MinRes projection) agree with the
+    oracle's to 1e-10; the solution equals the direct solve and the oracle's."""
+    c, oop, b = _c1()
+    V, H = _space(oop, (31, 31), 10, 42)
+    op = tg().Operator.const_cd(c["n"], c["beta"])
+    space = tg().defl_from_basis(op, _t(V.T)).minres()
+    x, reps = tg().solve(op, _t(b), defl=space, rtol=1e-10, ncyc=20, precision=precision)
+    r = reps[0]
+    xo, orep = OB.bicgstab_proj(oop, b, V=V, H=H, rtol=1e-10, ncyc=20, precision=precision, projection="minres")
+    xg = x.cpu().numpy()
+    assert r.status == 0 and _relres(oop, b, xg) <= 1e-10
+    xs = _direct(oop, b)
+    assert np.linalg.norm(xg - xs) / np.linalg.norm(xs) <= 1e-7
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-7
+    if precision == "fp64":
+        np.testing.assert_allclose(np.array(r.first_scalars)[:5], np.array(orep.first_scalars)[:5], rtol=1e-10)
+
+
+@pytest.mark.parametrize("precision,store", [("fp64", torch.float64), ("fp32_ir", torch.float32)])
+def test_bicgstab_minres_3d(precision, store):
+    """Ragged 47 x 31 x 21 grid: the marching cycle boundary forms
+    c = (AV)^T r from the stored W (float32 with float32 V); the solution
+    equals the direct solve; in FP64 the first scalars agree with the
+    oracle's."""
+    dims, cdims, beta = (47, 31, 21), (23, 15, 10), (30.0, 10.0, 5.0)
+    oop = O.const_cd(dims, beta)
+    b = W.rhs(oop.n, 43)
+    V, H = _space(oop, cdims, 8, 44)
+    op = tg().Operator.const_cd(dims, beta)
+    space = tg().defl_from_basis(op, _t(V.T), store=store).minres()
+    x, reps = tg().solve(op, _t(b), defl=space, rtol=1e-10, ncyc=20, precision=precision)
+    r = reps[0]
+    xg = x.cpu().numpy()
+    assert r.status == 0 and _relres(oop, b, xg) <= 1e-10
+    xs = _direct(oop, b)
+    assert np.linalg.norm(xg - xs) / np.linalg.norm(xs) <= 1e-7
+    if precision == "fp64":
+        xo, orep = OB.bicgstab_proj(oop, b, V=V, H=H, rtol=1e-10, ncyc=20, projection="minres")
+        np.testing.assert_allclose(np.array(r.first_scalars)[:5], np.array(orep.first_scalars)[:5], rtol=1e-10)
+
+
+def test_gmres_and_idr_with_minres_space():
+    """GMRES(30)-Proj(10) and IDR(4)-Proj(10) with a MinRes space: GMRES's
+    cycles and iterate follow the oracle's (same cycle count, iterate to
+    1e-8); IDR's first scalars to 1e-10; both reach the direct solution."""
+    c, oop, b = _c1()
+    V, H = _space(oop, (31, 31), 10, 45)
+    op = tg().Operator.const_cd(c["n"], c["beta"])
+    space = tg().defl_from_basis(op, _t(V.T)).minres()
+    xs = _direct(oop, b)
+    x, reps = tg().solve(op, _t(b), defl=space, method="gmres", m3=30, rtol=1e-10)
+    xo, orep = OG.gmres_proj(oop, b, V=V, H=H, rtol=1e-10, m=30, projection="minres")
+    xg = x.cpu().numpy()
+    assert reps[0].status == 0 and abs(reps[0].cycles - orep.cycles) <= 1
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-8
+    assert np.linalg.norm(xg - xs) / np.linalg.norm(xs) <= 1e-7
+    draw = W.shadow_draw(oop.n, 4, 46)
+    x, r = tg().solve_idr(op, _t(b), s=4, shadow=_t(draw), defl=space, rtol=1e-10)
+    xo, orep = OI.idrs_proj(oop, b, OI.shadow_space(draw.T), V=V, H=H, rtol=1e-10, projection="minres")
+    assert r.status == 0
+    np.testing.assert_allclose(np.array(r.first_scalars)[:, :2], np.array(orep.first_scalars)[:, :2], rtol=1e-10)
+    assert np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs) <= 1e-7
+
+
+def test_gmres_variable_cycle_lengths():
+    """GMRES restarted with seeded random cycle lengths in 1..40 (the second
+    variable-restart scheme of Sec. 4.3) on the small workload, deflated:
+    the same cycles as the oracle, inner mvps = the sum of the lengths used,
+    the oracle's iterate to 1e-8; a first cycle of length 1 from x = 0 is
+    the closed-form minimal-residual step."""
+    c, oop, b = _c1()
+    V, H = _space(oop, (31, 31), 10, 47)
+    op = tg().Operator.const_cd(c["n"], c["beta"])
+    space = tg().defl_from_basis(op, _t(V.T))
+    lengths = [int(v) for v in W.rng(48).integers(1, 41, size=200)]
+    x, reps = tg().solve(op, _t(b), defl=space, method="gmres", m3=40, rtol=1e-10, cycle_lengths=lengths)
+    xo, orep = OG.gmres_proj(oop, b, V=V, H=H, rtol=1e-10, m=40, lengths=lengths)
+    r = reps[0]
+    assert r.status == 0 and orep.status == 0 and r.cycles == orep.cycles
+    assert r.mvp_inner == orep.mvp_inner == sum(lengths[:r.cycles])
+    assert np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo) <= 1e-8
+    x1, r1 = tg().solve(op, _t(b), method="gmres", m3=40, rtol=1e-30, cycle_lengths=[1], max_extra=1)
+    Ab = O.apply(oop, b)
+    np.testing.assert_allclose(x1.cpu().numpy(), (b @ Ab) / (Ab @ Ab) * b, rtol=1e-10)
+    with pytest.raises(tg()._lib.TgdkError):
+        tg().solve(op, _t(b), method="gmres", m3=40, cycle_lengths=[41])
+    with pytest.raises(tg()._lib.TgdkError):
+        tg().solve(op, _t(b), method="gmres", m3=40, cycle_lengths=[0])
