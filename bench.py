@@ -147,7 +147,8 @@ def main():
     def fine_solve(**kw):
         kw.setdefault("ncyc", c["ncyc"])
         kw.setdefault("rtol", c["rtol"])
-        return tg.solve(op, b, x0=x0, defl=space, **kw)
+        kw.setdefault("defl", space)
+        return tg.solve(op, b, x0=x0, **kw)
 
     if a.solve_only and a.method == "idr":
         shadow = torch.tensor(W.shadow_draw(n, 4, 5), device=dev)
@@ -280,6 +281,18 @@ def main():
             log(f"{name}: {dt*1e3:.1f} ms, mvps {rv.mvp_inner}, relres {variants[name]['relres_true']:.2e}")
 
         run_idr("idr4_proj30_fp64", 2)
+
+        # MinRes projection (H = (AV)^T AV, c = (AV)^T r) on the same V
+        space_minres = space.minres()
+        run("bicgstab20_proj30_minres_fp64", 2, defl=space_minres)
+        # variable restarting (Sec. 4.3): GMRES cycle j as long as the headline
+        # BiCGStab's cycle j (capped at 128), and seeded random lengths 1..100
+        lens_b = [min(max(v, 1), 128) for v in head.cycle_mvps]
+        run("gmres_restarted_as_bicgstab_proj30_fp64", 1, method="gmres", m3=128, cycle_lengths=lens_b)
+        variants["gmres_restarted_as_bicgstab_proj30_fp64"]["cycle_lengths"] = lens_b
+        lens_r = [int(v) for v in np.random.default_rng(9).integers(1, 101, size=200)]
+        run("gmres_random_lengths_1to100_proj30_fp64", 1, method="gmres", m3=100, cycle_lengths=lens_r)
+        del space_minres
         # no deflation, from zero: the restarted BiCGStab baseline
         t = time.perf_counter()
         x_nd, r_nd = tg.solve(op, b, rtol=c["rtol"], ncyc=c["ncyc"], max_extra=40)
@@ -394,6 +407,12 @@ def main():
         hrun("bicgstab_proj60_fp64", lambda: tg.solve(oph, bh, **hk))
         hrun("gmres100_proj60_fp64", lambda: tg.solve(oph, bh, x0=x0h, defl=sph, method="gmres", m3=100,
                                                       rtol=ch["rtol"], max_extra=150))
+        sph_m = sph.minres()
+        hrun("idr20_proj60_minres_fp64", lambda: tg.solve_idr(oph, bh, s=20, shadow=shadows[20], x0=x0h, defl=sph_m,
+                                                              rtol=ch["rtol"], ncyc=ch["ncyc"], max_extra=20))
+        hrun("gmres100_proj60_minres_fp64", lambda: tg.solve(oph, bh, x0=x0h, defl=sph_m, method="gmres", m3=100,
+                                                             rtol=ch["rtol"], max_extra=150))
+        del sph_m
         hrun("idr20_no_deflation_10x1000", lambda: tg.solve_idr(oph, bh, s=20, shadow=shadows[20], rtol=ch["rtol"],
                                                                 ncyc=10, max_extra=0, maxit_cycle=1000))
         workloads["helmholtz_511sq_kappa25_k60"] = wh

@@ -61,6 +61,7 @@ extern "C" {
 #define TGDK_MAX_DEFL 128   /* largest GMRES cycle length m (deflation spaces: k <= 64) */
 #define TGDK_NHIST    8     /* recorded BiCGStab scalars of the first iterations */
 #define TGDK_IDR_SMAX 32    /* largest IDR shadow-space dimension s */
+#define TGDK_NCYC_REPORT 64 /* cycles whose inner operator applications are reported */
 
 /* Text of the last non-OK return on the calling thread ("" if none). */
 const char* tgdk_last_error(void);
@@ -263,6 +264,8 @@ typedef struct {
     int branch[4];         /* cycles whose tolerance came from criterion 1, 2, past-ncyc */
     int n_first;           /* recorded (rho, alpha, omega) of the first inner iterations */
     double first_rho[TGDK_NHIST], first_alpha[TGDK_NHIST], first_omega[TGDK_NHIST];
+    int n_cycle_mvps;      /* min(cycles, TGDK_NCYC_REPORT) */
+    int cycle_mvps[TGDK_NCYC_REPORT];  /* inner operator applications of each of the first cycles */
 } tgdk_solve_report;
 
 int tgdk_solve(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int nrhs,

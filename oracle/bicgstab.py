@@ -139,6 +139,7 @@ class SolveReport:
     nu_hist: list = field(default_factory=list)   # ||r|| after each cycle's true residual
     branches: list = field(default_factory=list)  # rticyc branch per cycle
     inner_iters: list = field(default_factory=list)
+    cycle_mvps: list = field(default_factory=list)     # inner operator applications per cycle
     first_scalars: list = field(default_factory=list)  # first 8 inner (rho, alpha, omega), across cycles
 
 
@@ -182,6 +183,7 @@ def bicgstab_proj(op, b, x0=None, V=None, H=None, rtol=1e-8, ncyc=20,
         rep.mvp_inner += inner.mvps
         rep.branches.append(branch)
         rep.inner_iters.append(inner.iters)
+        rep.cycle_mvps.append(inner.mvps)
         if len(rep.first_scalars) < 8:
             rep.first_scalars += inner.scalars[: 8 - len(rep.first_scalars)]
         x = x + inner.e.astype(np.float64)

@@ -72,6 +72,7 @@ class GmresReport:
     relres_true: float = float("nan")
     nu_hist: list = field(default_factory=list)
     lsq_hist: list = field(default_factory=list)
+    cycle_mvps: list = field(default_factory=list)  # steps per cycle
 
 
 def gmres_proj(op, b, x0=None, V=None, H=None, rtol=1e-8, m=50, maxcyc=1000,
@@ -106,6 +107,7 @@ def gmres_proj(op, b, x0=None, V=None, H=None, rtol=1e-8, m=50, maxcyc=1000,
         mc = lengths[icyc - 1] if lengths is not None and icyc <= len(lengths) else m
         e, lsq, steps = gmres_cycle(mv, r, mc)         # (B) one GMRES(mc) cycle
         rep.mvp_inner += steps
+        rep.cycle_mvps.append(steps)
         x = x + e
         r = b - mv(x)
         rep.mvp_boundary += 1

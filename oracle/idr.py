@@ -194,6 +194,7 @@ def idrs_proj(op, b, P, x0=None, V=None, H=None, rtol=1e-8, ncyc=20, max_extra=N
             rep.first_scalars = list(zip(inner.resnorms, inner.coefs, inner.kinds))[:8]
         rep.branches.append(branch)
         rep.inner_iters.append(inner.mvps)
+        rep.cycle_mvps.append(inner.mvps)
         x = x + inner.e.astype(np.float64)
         r = b - mv(x)                                    # true residual, FP64
         rep.mvp_boundary += 1

@@ -21,6 +21,7 @@ FP64, FP32_IR = 0, 1
 MAX_DEFL = 128
 NHIST = 8
 IDR_SMAX = 32
+NCYC_REPORT = 64
 
 STATUS_NAMES = {OK: "ok", NOT_CONVERGED: "not_converged", BREAKDOWN: "breakdown",
                 E_INVALID: "invalid", E_NOMEM: "nomem", E_HIP: "hip", E_SINGULAR: "singular",
@@ -56,7 +57,8 @@ class SolveReport(C.Structure):
                 ("mvp_inner", C.c_longlong), ("mvp_boundary", C.c_longlong),
                 ("relres_true", C.c_double), ("seconds", C.c_double), ("branch", C.c_int * 4),
                 ("n_first", C.c_int), ("first_rho", C.c_double * NHIST),
-                ("first_alpha", C.c_double * NHIST), ("first_omega", C.c_double * NHIST)]
+                ("first_alpha", C.c_double * NHIST), ("first_omega", C.c_double * NHIST),
+                ("n_cycle_mvps", C.c_int), ("cycle_mvps", C.c_int * NCYC_REPORT)]
 
 
 P = C.c_void_p

@@ -229,6 +229,7 @@ class Report:
     seconds: float
     branch: list = field(default_factory=list)
     first_scalars: list = field(default_factory=list)
+    cycle_mvps: list = field(default_factory=list)  # inner operator applications of the first cycles
 
     @property
     def status_name(self):
@@ -257,7 +258,7 @@ def _reports(reps):
     for r in reps:
         fs = [(r.first_rho[i], r.first_alpha[i], r.first_omega[i]) for i in range(r.n_first)]
         out.append(Report(r.status, r.cycles, r.iters_inner, r.mvp_inner, r.mvp_boundary, r.relres_true,
-                          r.seconds, list(r.branch), fs))
+                          r.seconds, list(r.branch), fs, [r.cycle_mvps[i] for i in range(r.n_cycle_mvps)]))
     return out
 
 

@@ -345,8 +345,10 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
     return TGDK_OK;
 }
 
+// cycle_steps: the GMRES driver's steps per cycle (one right-hand side);
+// the other solvers' per-cycle counts come from the device's cycle log.
 static int finish_group(Group& g, const std::vector<ProbSpec>& ps, tgdk_solve_report* reps, double secs,
-                        const std::vector<long long>* extra_inner) {
+                        const std::vector<long long>* extra_inner, const std::vector<int>* cycle_steps = nullptr) {
     hipStream_t s = g.ctx->stream;
     launch(g, K_RESIDUAL, 2);
     TGDK_HIP(hipGetLastError());
@@ -371,6 +373,21 @@ static int finish_group(Group& g, const std::vector<ProbSpec>& ps, tgdk_solve_re
             R.first_alpha[i] = S.hist[3 * i + 1];
             R.first_omega[i] = S.hist[3 * i + 2];
         }
+        // inner operator applications per cycle: BiCGStab two per iteration
+        // (one more when a breakdown follows phase A), IDR its count, GMRES
+        // the host's step count
+        const int nc = std::min(std::min(S.icyc, NCYCLOG), TGDK_NCYC_REPORT);
+        for (int c = 0; c < nc; ++c) {
+            int mv;
+            if (S.method == METHOD_GMRES)
+                mv = cycle_steps && c < (int)cycle_steps->size() ? (*cycle_steps)[c] : 0;
+            else if (S.method == METHOD_IDR)
+                mv = S.cyc_iters[c];
+            else
+                mv = 2 * S.cyc_iters[c] + (S.cyc_end[c] == IN_BREAK_NOUPD ? 1 : 0);
+            R.cycle_mvps[c] = mv;
+        }
+        R.n_cycle_mvps = nc;
         if (R.status == TGDK_E_NONFINITE) set_error("non-finite residual (check b, x0 and the operator)");
         rc = worst(rc, R.status);
     }
@@ -502,6 +519,7 @@ static int gmres_single(tgdk_ctx ctx, const ProbSpec& p, const tgdk_solve_params
     double* Nd = Hd + 2 * hsz;
     rc = ctx->partial.ensure((size_t)gs_blocks(n) * (MAXK + 1) * sizeof(double));
     std::vector<long long> extra(1, 0);
+    std::vector<int> cyc_steps;  // steps of each cycle
     const DevOp op = make_devop(p.op, prm->transpose);
     const int maxcyc = prm->max_extra_cycles > 0 ? prm->max_extra_cycles : 1000;
     std::vector<double> h1(hsz), h2(hsz), nrm(m), Hbar(hsz), rhs(m + 1), y(m), res(m + 1);
@@ -557,6 +575,7 @@ static int gmres_single(tgdk_ctx ctx, const ProbSpec& p, const tgdk_solve_params
         TGDK_HIP(hipMemcpyAsync(dy, y.data(), sizeof(double) * steps, hipMemcpyHostToDevice, s));
         launch_vmul_add(V, n, steps, dy, p.x, n, s);
         extra[0] += steps;
+        cyc_steps.push_back(steps);
         launch(g, K_RESIDUAL, 0);
         TGDK_HIP(hipGetLastError());
         TGDK_HIP(hipStreamSynchronize(s));
@@ -567,7 +586,7 @@ static int gmres_single(tgdk_ctx ctx, const ProbSpec& p, const tgdk_solve_params
     (void)hipFree(dy);
     if (rc) return rc;
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    return finish_group(g, ps, rep, secs, &extra);
+    return finish_group(g, ps, rep, secs, &extra, &cyc_steps);
 }
 
 // IDR(s)(ncyc)-Proj(k): one right-hand side.  The cycle boundary is the

@@ -153,3 +153,33 @@ def test_gmres_variable_cycle_lengths():
         tg().solve(op, _t(b), method="gmres", m3=40, cycle_lengths=[41])
     with pytest.raises(tg()._lib.TgdkError):
         tg().solve(op, _t(b), method="gmres", m3=40, cycle_lengths=[0])
+
+
+def test_cycle_mvps_and_gmres_restarted_as_bicgstab():
+    """The report's per-cycle inner operator applications add up to the
+    total for BiCGStab, IDR and GMRES; the first BiCGStab cycle's count is the
+    oracle's (within one iteration).  GMRES restarted exactly as BiCGStab was
+    (Sec. 4.3, Table 4.3: cycle j as long as BiCGStab's cycle j) follows the
+    oracle's run with the same lengths: same cycles and mvps, iterate to
+    1e-8."""
+    c, oop, b = _c1()
+    V, H = _space(oop, (31, 31), 10, 49)
+    op = tg().Operator.const_cd(c["n"], c["beta"])
+    space = tg().defl_from_basis(op, _t(V.T))
+    x, reps = tg().solve(op, _t(b), defl=space, rtol=1e-10, ncyc=20)
+    r = reps[0]
+    assert len(r.cycle_mvps) == r.cycles and sum(r.cycle_mvps) == r.mvp_inner
+    xo, orep = OB.bicgstab_proj(oop, b, V=V, H=H, rtol=1e-10, ncyc=20)
+    assert sum(orep.cycle_mvps) == orep.mvp_inner
+    assert abs(r.cycle_mvps[0] - orep.cycle_mvps[0]) <= 2
+    draw = W.shadow_draw(oop.n, 4, 50)
+    xi, ri = tg().solve_idr(op, _t(b), s=4, shadow=_t(draw), defl=space, rtol=1e-10)
+    assert len(ri.cycle_mvps) == ri.cycles and sum(ri.cycle_mvps) == ri.mvp_inner
+    lengths = [min(max(v, 1), 128) for v in r.cycle_mvps]
+    xg, rg = tg().solve(op, _t(b), defl=space, method="gmres", m3=128, rtol=1e-10, cycle_lengths=lengths)
+    xo2, og = OG.gmres_proj(oop, b, V=V, H=H, rtol=1e-10, m=128, lengths=lengths)
+    g = rg[0]
+    assert g.status == 0 and og.status == 0
+    assert g.cycles == og.cycles and g.mvp_inner == og.mvp_inner
+    assert g.cycle_mvps == og.cycle_mvps and sum(g.cycle_mvps) == g.mvp_inner
+    assert np.linalg.norm(xg.cpu().numpy() - xo2) / np.linalg.norm(xo2) <= 1e-8
