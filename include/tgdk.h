@@ -208,6 +208,38 @@ int tgdk_defl_from_basis(tgdk_op op, const double* W, int k, int transpose, int 
 #define TGDK_PROJ_GALERKIN 0
 #define TGDK_PROJ_MINRES   1
 int tgdk_defl_minres(tgdk_defl galerkin_space, tgdk_defl* minres_space);
+/* Arnoldi-E(m,k) improvement of a space's vectors on its own grid (step 2
+ * of the Two-grid Deflated GMRES and BiCGStab boxes, Sec. 3 and 4.1; the
+ * Two-grid Arnoldi method of Sec. 2.3).  Starting from the k approximate
+ * eigenvectors spanning the space, each cycle runs m - k Arnoldi steps from
+ * the leading approximate eigenvector whose residual norm exceeds tol, adds
+ * the k kept vectors (orthonormalised against the Krylov basis; a vector
+ * that loses all but 1e-8 of its norm is dropped), and takes Rayleigh-Ritz
+ * on that subspace (dimension <= m + 1), keeping the k pairs of smallest
+ * |theta| (a conjugate pair whole).  Residual norms are
+ * ||A y - theta y|| / ||A||_1 for unit y, formed explicitly.  Stops when the
+ * nev leading pairs are below tol or after maxcyc cycles, and builds a new
+ * Galerkin space (store_dtype) over an orthonormal basis of the kept span.
+ * Each basis vector of a cycle is multiplied by A once. */
+typedef struct {
+    int m;          /* subspace dimension per cycle, k < m <= TGDK_MAX_DEFL */
+    int nev;        /* leading pairs that must converge, 0 <= nev <= k */
+    int maxcyc;     /* >= 0 */
+    double tol;     /* > 0 */
+} tgdk_arnoldie_params;
+
+typedef struct {
+    int cycles, nconv, k_out;
+    long long mvps;
+    double theta_re[TGDK_MAX_DEFL + 1];  /* kept Ritz values, in keeping order */
+    double theta_im[TGDK_MAX_DEFL + 1];
+    double eigres[TGDK_MAX_DEFL + 1];    /* their residual norms at the end */
+    double eigres_start[TGDK_MAX_DEFL + 1];  /* ... before the first cycle */
+    double seconds;
+} tgdk_arnoldie_report;
+
+int tgdk_defl_improve(tgdk_defl space, const tgdk_arnoldie_params* params, int store_dtype,
+                      tgdk_defl* improved, tgdk_arnoldie_report* report);
 /* k and the store type of a space. */
 int tgdk_defl_info(tgdk_defl defl, int* k, int* store_dtype, long long* n);
 /* TGDK_PROJ_GALERKIN or TGDK_PROJ_MINRES. */

@@ -45,6 +45,17 @@ class GmresDrReport(C.Structure):
                 ("eigres", C.c_double * (MAX_DEFL + 1)), ("seconds", C.c_double)]
 
 
+class ArnoldiEParams(C.Structure):
+    _fields_ = [("m", C.c_int), ("nev", C.c_int), ("maxcyc", C.c_int), ("tol", C.c_double)]
+
+
+class ArnoldiEReport(C.Structure):
+    _fields_ = [("cycles", C.c_int), ("nconv", C.c_int), ("k_out", C.c_int), ("mvps", C.c_longlong),
+                ("theta_re", C.c_double * (MAX_DEFL + 1)), ("theta_im", C.c_double * (MAX_DEFL + 1)),
+                ("eigres", C.c_double * (MAX_DEFL + 1)), ("eigres_start", C.c_double * (MAX_DEFL + 1)),
+                ("seconds", C.c_double)]
+
+
 class SolveParams(C.Structure):
     _fields_ = [("method", C.c_int), ("ncyc", C.c_int), ("m3", C.c_int), ("precision", C.c_int),
                 ("x0_given", C.c_int), ("transpose", C.c_int), ("maxit_cycle", C.c_int),
@@ -85,6 +96,7 @@ SIGNATURES = [
     ("tgdk_coarse_setup", I, [P, P, P, C.POINTER(GmresDrParams), PP, C.POINTER(GmresDrReport)]),
     ("tgdk_defl_prolongate", I, [P, P, I, PP]),
     ("tgdk_defl_from_basis", I, [P, P, I, I, I, PP]),
+    ("tgdk_defl_improve", I, [P, C.POINTER(ArnoldiEParams), I, PP, C.POINTER(ArnoldiEReport)]),
     ("tgdk_defl_minres", I, [P, PP]),
     ("tgdk_defl_projection", I, [P]),
     ("tgdk_defl_info", I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(C.c_longlong)]),

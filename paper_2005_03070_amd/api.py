@@ -156,6 +156,23 @@ class DeflationSpace:
         check(lib().tgdk_defl_minres(self.h, C.byref(h)))
         return DeflationSpace(h, self.op, self.transpose)
 
+    def improve(self, m, nev=None, tol=1e-8, maxcyc=100, store=torch.float64):
+        """Arnoldi-E(m, k) improvement of the space's vectors on its grid (see
+        include/tgdk.h, tgdk_defl_improve).  Returns (improved space, report
+        dict with cycles, nconv, k_out, mvps, theta, eigres, eigres_start)."""
+        p = L.ArnoldiEParams(m, self.k if nev is None else nev, maxcyc, tol)
+        r = L.ArnoldiEReport()
+        h = C.c_void_p()
+        check(lib().tgdk_defl_improve(self.h, C.byref(p), L.F64 if store == torch.float64 else L.F32, C.byref(h),
+                                      C.byref(r)))
+        nk = r.k_out
+        cnt = min(len(r.theta_re), nk)
+        theta = np.array([complex(r.theta_re[i], r.theta_im[i]) for i in range(cnt)])
+        rep = {"cycles": r.cycles, "nconv": r.nconv, "k_out": nk, "mvps": r.mvps, "seconds": r.seconds,
+               "theta": theta, "eigres": np.array(r.eigres[:cnt]),
+               "eigres_start": np.array(r.eigres_start[:p.nev])}
+        return DeflationSpace(h, self.op, self.transpose), rep
+
     def basis(self):
         """(V as a (k, n) float64 tensor, H as a k x k numpy array)."""
         V = torch.empty((self.k, self.n), dtype=torch.float64, device=self.op.device)

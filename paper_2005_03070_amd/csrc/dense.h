@@ -2,6 +2,7 @@
 #pragma once
 
 #include <complex>
+#include <vector>
 
 namespace tgdk {
 
@@ -20,5 +21,9 @@ int lstsq(int m, int n, const double* A, const double* b, double* x, double* res
 // Eigenvalues w[n] and unit eigenvectors X (column i at X + i*n) of a real
 // n x n matrix.  Returns 0 on success.
 int eig_real(int n, const double* A, std::complex<double>* w, std::complex<double>* X);
+// Indices of the k values of smallest modulus (ties by real part, then
+// positive imaginary part first); a kept complex value brings its conjugate
+// partner along (listed right after it), so k+1 may be returned.
+std::vector<int> select_smallest(const std::vector<std::complex<double>>& th, int k);
 
 }  // namespace tgdk

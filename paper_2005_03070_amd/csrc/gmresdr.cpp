@@ -51,51 +51,6 @@ static int harmonic_ritz(int m, const std::vector<double>& Hbar, Ritz& out) {
     return TGDK_OK;
 }
 
-// Smallest |theta| first; ties by real part, then positive imaginary part
-// first; a kept complex value brings its conjugate partner along.
-static std::vector<int> select_smallest(const std::vector<cd>& th, int k) {
-    const int m = (int)th.size();
-    auto is_cplx = [&](int i) { return std::fabs(th[i].imag()) > 1e-10 * std::max(std::abs(th[i]), 1e-300); };
-    std::vector<int> order(m);
-    std::iota(order.begin(), order.end(), 0);
-    std::sort(order.begin(), order.end(), [&](int a, int b) {
-        const double aa = std::abs(th[a]), ab = std::abs(th[b]);
-        if (aa != ab) return aa < ab;
-        if (th[a].real() != th[b].real()) return th[a].real() < th[b].real();
-        return th[a].imag() > th[b].imag();
-    });
-    std::vector<int> chosen;
-    std::vector<char> used(m, 0);
-    for (int i : order) {
-        if ((int)chosen.size() >= k) break;
-        if (used[i]) continue;
-        if (is_cplx(i)) {
-            int best = -1;
-            double bd = INFINITY;
-            for (int j = 0; j < m; ++j) {
-                if (used[j] || j == i) continue;
-                const double d = std::abs(th[j] - std::conj(th[i]));
-                if (d < bd) {
-                    bd = d;
-                    best = j;
-                }
-            }
-            int ip = i, jn = best;
-            if (th[i].imag() < 0 && best >= 0) std::swap(ip, jn);
-            chosen.push_back(ip);
-            used[ip] = 1;
-            if (jn >= 0) {
-                chosen.push_back(jn);
-                used[jn] = 1;
-            }
-        } else {
-            chosen.push_back(i);
-            used[i] = 1;
-        }
-    }
-    return chosen;
-}
-
 static double eig_residual(int m, const std::vector<double>& Hbar, const Ritz& R, int i) {
     // ||Hbar g - rho [g; 0]|| with ||g|| = 1 and rho = g^H H_m g
     std::vector<cd> g(m);

@@ -311,4 +311,18 @@ void launch_scale(const double* w, double* v, const double* nrm, long long n, hi
     hipLaunchKernelGGL(k_scale, dim3((int)nb), dim3(256), 0, s, w, v, nrm, n);
 }
 
+// c = a - b over n contiguous values
+__global__ __launch_bounds__(NT) void k_sub(const double* __restrict__ a, const double* __restrict__ b,
+                                            double* __restrict__ c, long long n) {
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
+        c[i] = a[i] - b[i];
+}
+
+void launch_sub(const double* a, const double* b, double* c, long long n, hipStream_t s) {
+    long long nb = (n + NT - 1) / NT;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_sub, dim3((int)nb), dim3(NT), 0, s, a, b, c, n);
+}
+
 }  // namespace tgdk

@@ -83,7 +83,9 @@ void launch_gs_update_dot(const double* V, long long ldv, int p, double* w, cons
 void launch_gs_update_norm(const double* V, long long ldv, int p, double* w, const double* h, long long n,
                            double* nrm, double* partial, unsigned* counter, hipStream_t s);
 void launch_scale(const double* w, double* v, const double* nrm, long long n, hipStream_t s);
-// sum of squares of a vector -> *out (deterministic)
+// c = a - b (n values)
+void launch_sub(const double* a, const double* b, double* c, long long n, hipStream_t s);
+// ||w|| -> *out (deterministic)
 void launch_norm2(const double* w, long long n, double* out, double* partial, unsigned* counter, hipStream_t s);
 
 }  // namespace tgdk
