@@ -282,6 +282,23 @@ def main():
 
         run_idr("idr4_proj30_fp64", 2)
 
+        # phase 2: Arnoldi-E(80,30) on the moved vectors until the 24 leading
+        # pairs are below 1e-4 (the paper's Table 5.1 improves until its first
+        # 80 are below 1e-3), at most 40 cycles; then the same fine solve
+        t = time.perf_counter()
+        space_imp, arep = space.improve(m=c["m"], nev=c["nev"], tol=1e-4, maxcyc=40)
+        torch.cuda.synchronize()
+        imp_s = time.perf_counter() - t
+        log(f"Arnoldi-E({c['m']},{c['k']}): {arep['cycles']} cycles, {arep['mvps']} mvps, {imp_s*1e3:.0f} ms; "
+            f"max eigen-residual of the {c['nev']} leading pairs {arep['eigres_start'].max():.1e} -> "
+            f"{arep['eigres'][:c['nev']].max():.1e}")
+        run("bicgstab20_proj30_after_arnoldie_fp64", 2, defl=space_imp)
+        variants["bicgstab20_proj30_after_arnoldie_fp64"]["arnoldie"] = {
+            "seconds": imp_s, "cycles": arep["cycles"], "mvps": arep["mvps"], "nconv": arep["nconv"],
+            "max_eigres_start": float(arep["eigres_start"].max()),
+            "max_eigres_end": float(arep["eigres"][:c["nev"]].max())}
+        del space_imp
+
         # MinRes projection (H = (AV)^T AV, c = (AV)^T r) on the same V
         space_minres = space.minres()
         run("bicgstab20_proj30_minres_fp64", 2, defl=space_minres)
@@ -407,6 +424,19 @@ def main():
         hrun("bicgstab_proj60_fp64", lambda: tg.solve(oph, bh, **hk))
         hrun("gmres100_proj60_fp64", lambda: tg.solve(oph, bh, x0=x0h, defl=sph, method="gmres", m3=100,
                                                       rtol=ch["rtol"], max_extra=150))
+        t = time.perf_counter()
+        sph_i, arep_h = sph.improve(m=ch["m"], nev=ch["nev"], tol=1e-4, maxcyc=20)
+        torch.cuda.synchronize()
+        wh["arnoldie"] = {"seconds": time.perf_counter() - t, "cycles": arep_h["cycles"], "mvps": arep_h["mvps"],
+                          "nconv": arep_h["nconv"], "max_eigres_start": float(arep_h["eigres_start"].max()),
+                          "max_eigres_end": float(arep_h["eigres"][:ch["nev"]].max())}
+        log(f"  Arnoldi-E({ch['m']},{ch['k']}): {arep_h['cycles']} cycles, {arep_h['mvps']} mvps, "
+            f"{wh['arnoldie']['seconds']*1e3:.0f} ms, eigen-residuals {wh['arnoldie']['max_eigres_start']:.1e} -> "
+            f"{wh['arnoldie']['max_eigres_end']:.1e}")
+        hrun("idr20_proj60_after_arnoldie_fp64", lambda: tg.solve_idr(oph, bh, s=20, shadow=shadows[20], x0=x0h,
+                                                                      defl=sph_i, rtol=ch["rtol"], ncyc=ch["ncyc"],
+                                                                      max_extra=20))
+        del sph_i
         sph_m = sph.minres()
         hrun("idr20_proj60_minres_fp64", lambda: tg.solve_idr(oph, bh, s=20, shadow=shadows[20], x0=x0h, defl=sph_m,
                                                               rtol=ch["rtol"], ncyc=ch["ncyc"], max_extra=20))
