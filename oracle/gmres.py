@@ -76,11 +76,14 @@ class GmresReport:
 
 
 def gmres_proj(op, b, x0=None, V=None, H=None, rtol=1e-8, m=50, maxcyc=1000,
-               transpose=False, projection="galerkin", lengths=None):
+               transpose=False, projection="galerkin", lengths=None, precond=None, Z=None):
     """GMRES(m)-Proj(k) on ``A x = b``; ``V``/``H`` may be None (k = 0);
     ``projection="minres"`` takes the MinRes variant of the projection.
     ``lengths``: variable restarting (Sec. 4.3, Table 4.3): cycle j
     (1-based) has ``lengths[j-1]`` steps while the list lasts, then ``m``.
+    ``precond`` (``v -> M^{-1} v``): right preconditioning, the cycles run on
+    ``A M^{-1}`` and ``x += M^{-1} e``; the projection then needs
+    ``Z = M^{-1} V`` and ``H = V^T A Z`` (``projection.precond_space``).
 
     The overall tolerance is ``tau = rtol * min(||b||, ||r0||)``, as for
     BiCGStab(ncyc)-Proj(k)."""
@@ -96,7 +99,8 @@ def gmres_proj(op, b, x0=None, V=None, H=None, rtol=1e-8, m=50, maxcyc=1000,
     if nu0 <= tau:
         rep.relres_true = nu0 / bnorm if bnorm else 0.0
         return x, rep
-    proj = projector(op, V, H, transpose, projection) if V is not None and V.shape[1] > 0 else None
+    proj = projector(op, V, H, transpose, projection, Z) if V is not None and V.shape[1] > 0 else None
+    mvc = mv if precond is None else (lambda z: mv(precond(z)))
     for icyc in range(1, maxcyc + 1):
         if proj is not None:                          # (A) projection
             x, r, _ = proj(x, r)
@@ -105,10 +109,10 @@ def gmres_proj(op, b, x0=None, V=None, H=None, rtol=1e-8, m=50, maxcyc=1000,
                 rep.cycles = icyc
                 break
         mc = lengths[icyc - 1] if lengths is not None and icyc <= len(lengths) else m
-        e, lsq, steps = gmres_cycle(mv, r, mc)         # (B) one GMRES(mc) cycle
+        e, lsq, steps = gmres_cycle(mvc, r, mc)        # (B) one GMRES(mc) cycle
         rep.mvp_inner += steps
         rep.cycle_mvps.append(steps)
-        x = x + e
+        x = x + (e if precond is None else precond(e))
         r = b - mv(x)
         rep.mvp_boundary += 1
         nu = float(np.linalg.norm(r))

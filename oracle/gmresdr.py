@@ -134,11 +134,18 @@ class DRReport:
 
 
 def gmres_dr(op, b, m, k, nev=None, rtolev=1e-8, rtol=1e-8, maxcyc=300,
-             transpose=False, x0=None):
+             transpose=False, x0=None, precond=None):
     """GMRES-DR(m,k) on ``A x = b``.  Returns ``(x, W, report)`` where ``W``
     (n x k') is an orthonormal basis of the final k harmonic Ritz vectors
-    (k' = k, or k+1 if a conjugate pair straddles position k)."""
-    mv = (lambda z: operators.apply_transpose(op, z)) if transpose else (lambda z: operators.apply(op, z))
+    (k' = k, or k+1 if a conjugate pair straddles position k).
+
+    ``precond`` (a function ``v -> M^{-1} v``): right preconditioning (Sec. 5,
+    Example 5): the cycles run on ``A M^{-1}`` from ``u = 0`` (``x0`` must be
+    None), the kept vectors are harmonic Ritz vectors of ``A M^{-1}`` and the
+    solution is ``x = M^{-1} u``."""
+    mv0 = (lambda z: operators.apply_transpose(op, z)) if transpose else (lambda z: operators.apply(op, z))
+    assert precond is None or x0 is None
+    mv = mv0 if precond is None else (lambda z: mv0(precond(z)))
     nev = k if nev is None else nev
     anorm = operators.norm1(op)
     b = np.asarray(b, dtype=np.float64)
@@ -195,5 +202,7 @@ def gmres_dr(op, b, m, k, nev=None, rtolev=1e-8, rtol=1e-8, maxcyc=300,
         V, Hbar, j = arnoldi(mv, Vn[:, kk], m, V_init=Vn, H_init=Hnew, start=kk)
         rep.mvps += m - kk
         c = cnew
-    rep.relres = float(np.linalg.norm(b - mv(x))) / bnorm
+    if precond is not None:
+        x = precond(x)
+    rep.relres = float(np.linalg.norm(b - mv0(x))) / bnorm
     return x, W, rep

@@ -152,10 +152,14 @@ def idrs_inner(matvec, r0, target, P, maxit, kappa=0.7, dtype=np.float64, check=
 
 
 def idrs_proj(op, b, P, x0=None, V=None, H=None, rtol=1e-8, ncyc=20, max_extra=None, maxit_cycle=100000,
-              precision="fp64", fp32_floor=1e-4, kappa=0.7, transpose=False, projection="galerkin"):
+              precision="fp64", fp32_floor=1e-4, kappa=0.7, transpose=False, projection="galerkin",
+              precond=None, Z=None):
     """IDR(s)(ncyc)-Proj(k) on ``A x = b`` with shadow matrix ``P`` (n x s).
 
     ``V`` (n x k, orthonormal) and ``H = V^T A V`` may be None (k = 0).
+    ``precond`` (``v -> M^{-1} v``): right preconditioning; the inner cycles
+    run on ``A M^{-1}`` and ``x += M^{-1} e``; the projection then needs
+    ``Z = M^{-1} V`` and ``H = V^T A Z`` (``projection.precond_space``).
     Returns ``(x, SolveReport)``; ``first_scalars`` holds, for the first
     updates of r in the first cycle, (||r||, coefficient, 1 at a dimension
     reduction else 0)."""
@@ -175,7 +179,8 @@ def idrs_proj(op, b, P, x0=None, V=None, H=None, rtol=1e-8, ncyc=20, max_extra=N
         return x, rep
     inner_dtype = np.float32 if precision == "fp32_ir" else np.float64
     Pin = np.asarray(P, dtype=inner_dtype)
-    proj = projector(op, V, H, transpose, projection) if V is not None and V.shape[1] > 0 else None
+    proj = projector(op, V, H, transpose, projection, Z) if V is not None and V.shape[1] > 0 else None
+    mvc = mv if precond is None else (lambda z: mv(precond(z)))
     icyc = 0
     while True:
         icyc += 1
@@ -188,14 +193,14 @@ def idrs_proj(op, b, P, x0=None, V=None, H=None, rtol=1e-8, ncyc=20, max_extra=N
         rt, branch = cycle_tolerance(nu, nu0, tau, icyc, ncyc)   # step b)
         if precision == "fp32_ir":
             rt = max(rt, fp32_floor)
-        inner = idrs_inner(mv, r, rt * nu, Pin, maxit_cycle, kappa=kappa, dtype=inner_dtype)  # step c)
+        inner = idrs_inner(mvc, r, rt * nu, Pin, maxit_cycle, kappa=kappa, dtype=inner_dtype)  # step c)
         rep.mvp_inner += inner.mvps
         if icyc == 1:
             rep.first_scalars = list(zip(inner.resnorms, inner.coefs, inner.kinds))[:8]
         rep.branches.append(branch)
         rep.inner_iters.append(inner.mvps)
         rep.cycle_mvps.append(inner.mvps)
-        x = x + inner.e.astype(np.float64)
+        x = x + (inner.e.astype(np.float64) if precond is None else precond(inner.e.astype(np.float64)))
         r = b - mv(x)                                    # true residual, FP64
         rep.mvp_boundary += 1
         nu = float(np.linalg.norm(r))

@@ -60,10 +60,32 @@ def minres_projection(op, V, x, r, transpose=False, W=None, H=None):
     return x + xh, r - Axh, d
 
 
-def projector(op, V, H, transpose=False, projection="galerkin"):
+def precond_space(op, V, precond, transpose=False):
+    """Right preconditioning (Sec. 5, Example 5): the Galerkin projection of
+    ``A M^{-1}`` over ``V`` uses ``c = V^T r`` and ``H = V^T A Z`` with
+    ``Z = M^{-1} V``, and updates ``x += Z d``, ``r -= A Z d``.  Returns
+    ``(Z, H)``."""
+    Z = np.stack([precond(V[:, j]) for j in range(V.shape[1])], axis=1)
+    AZ = operators.apply_transpose(op, Z) if transpose else operators.apply(op, Z)
+    return Z, V.T @ AZ
+
+
+def precond_projection(op, V, Z, H, x, r, transpose=False):
+    """One projection of the preconditioned system (see :func:`precond_space`)."""
+    c = V.T @ r
+    d = np.linalg.solve(H, c)
+    xh = Z @ d
+    Axh = operators.apply_transpose(op, xh) if transpose else operators.apply(op, xh)
+    return x + xh, r - Axh, d
+
+
+def projector(op, V, H, transpose=False, projection="galerkin", Z=None):
     """The projection step of the solvers as a function ``(x, r) -> (x, r, d)``:
-    Galerkin with the given ``H = V^T A V``, or MinRes (its ``W`` and ``H``
-    formed here once)."""
+    Galerkin with the given ``H = V^T A V``, MinRes (its ``W`` and ``H``
+    formed here once), or, with ``Z = M^{-1} V``, the preconditioned one
+    (``H = V^T A Z`` given)."""
+    if Z is not None:
+        return lambda x, r: precond_projection(op, V, Z, H, x, r, transpose)
     if projection == "minres":
         W, Hm = minres_matrix(op, V, transpose)
         return lambda x, r: minres_projection(op, V, x, r, transpose, W, Hm)
