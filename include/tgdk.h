@@ -63,6 +63,12 @@ extern "C" {
 #define TGDK_IDR_SMAX 32    /* largest IDR shadow-space dimension s */
 #define TGDK_NCYC_REPORT 64 /* cycles whose inner operator applications are reported */
 
+/* A right preconditioner as the host-driven solvers call it: out = M^{-1} in
+ * for nrhs device float64 vectors of n (column-major), enqueued on the
+ * context's stream (or completed before returning); in and out do not alias.
+ * Returns TGDK_OK or a negative code. */
+typedef int (*tgdk_precond_fn)(void* user, const double* in, double* out, int nrhs);
+
 /* Text of the last non-OK return on the calling thread ("" if none). */
 const char* tgdk_last_error(void);
 
@@ -165,6 +171,11 @@ int tgdk_restrict(tgdk_op fine, tgdk_op coarse, int dtype, const void* vf, void*
 typedef struct {
     int m, k, nev, maxcyc, transpose;
     double rtolev, rtol;
+    /* optional right preconditioner (Sec. 5, Example 5): GMRES-DR runs on
+     * A M^{-1}, x = M^{-1} u at the end, and the kept vectors are harmonic
+     * Ritz vectors of A M^{-1}; NULL for none */
+    tgdk_precond_fn precond;
+    void* precond_user;
 } tgdk_gmresdr_params;
 
 typedef struct {
@@ -208,6 +219,14 @@ int tgdk_defl_from_basis(tgdk_op op, const double* W, int k, int transpose, int 
 #define TGDK_PROJ_GALERKIN 0
 #define TGDK_PROJ_MINRES   1
 int tgdk_defl_minres(tgdk_defl galerkin_space, tgdk_defl* minres_space);
+/* Deflation with a right preconditioner M (Sec. 5, Example 5): the Galerkin
+ * projection of A M^{-1} over V, i.e. c = V^T r, H = V^T A Z with
+ * Z = M^{-1} V, and the update x += Z d, r -= A Z d.  Builds a new space from
+ * a float64 Galerkin space (V kept, Z stored; precond called once with
+ * nrhs = k).  Only the preconditioned GMRES-Proj and IDR-Proj solves accept
+ * it; tgdk_defl_copy returns V. */
+int tgdk_defl_precond(tgdk_defl galerkin_space, tgdk_precond_fn precond, void* precond_user,
+                      tgdk_defl* precond_space);
 /* Arnoldi-E(m,k) improvement of a space's vectors on its own grid (step 2
  * of the Two-grid Deflated GMRES and BiCGStab boxes, Sec. 3 and 4.1; the
  * Two-grid Arnoldi method of Sec. 2.3).  Starting from the k approximate
@@ -249,6 +268,24 @@ int tgdk_defl_projection(tgdk_defl defl);
 int tgdk_defl_copy(tgdk_defl defl, double* V_out, double* H_out);
 int tgdk_defl_destroy(tgdk_defl defl);
 
+/* ------------------------------------------------------------ multigrid
+ * Geometric multigrid for a constant-coefficient operator (e.g. the
+ * positively shifted Laplacian -Lap(u) + kappa^2 u, which preconditions the
+ * Helmholtz operator in Sec. 5, Example 5).  Levels: the operator's grid and
+ * its rediscretised nested coarse grids (n -> (n-1)/2) while every side is
+ * odd and >= 3.  V-cycle: damped Jacobi with the constant diagonal
+ * (omega = 4/5 in 2-D, 6/7 in 3-D), nu sweeps before and after; full
+ * weighting and linear interpolation; 20 sweeps on the coarsest grid.
+ * tgdk_mg_apply is a tgdk_precond_fn (user = the tgdk_mg): `cycles` V-cycles
+ * from zero, z_1 = V(b), z_(c+1) = z_c + V(b - A z_c) (a fixed linear
+ * operator).  The object keeps per-level work vectors: one apply at a time
+ * per object. */
+typedef struct tgdk_mg_s* tgdk_mg;
+int tgdk_mg_create(tgdk_op op, int cycles, int nu, tgdk_mg* mg);
+int tgdk_mg_apply(void* mg, const double* in, double* out, int nrhs);
+int tgdk_mg_levels(tgdk_mg mg);
+int tgdk_mg_destroy(tgdk_mg mg);
+
 /* ------------------------------------------------------------ fine solve
  * BiCGStab(ncyc)-Proj(k) (Sec. 4.1 algorithm box, step 3 a-d) or
  * GMRES(m3)-Proj(k) (Sec. 2.2 box) on A x = b (A^T x = b if transpose).
@@ -286,6 +323,12 @@ typedef struct {
      * every length in 1..m3.  NULL / 0: every cycle has m3 steps. */
     const int* cycle_lengths;  /* host array */
     int n_cycle_lengths;
+    /* optional right preconditioner for GMRES-Proj and IDR-Proj (FP64 only;
+     * BiCGStab: TGDK_E_INVALID): the inner solver works on A M^{-1} and
+     * x += M^{-1} (correction); a deflation space must then come from
+     * tgdk_defl_precond with the same preconditioner */
+    tgdk_precond_fn precond;
+    void* precond_user;
 } tgdk_solve_params;
 
 typedef struct {

@@ -5,10 +5,10 @@ Krylov method (arXiv 2005.03070) as a HIP library (libtgdk.so, C-ABI in
 include/tgdk.h) with a thin Python binding.
 """
 from . import _lib
-from .api import (DeflationSpace, Operator, Report, SetupReport, coarse_setup, context, defl_from_basis,
+from .api import (DeflationSpace, Multigrid, Operator, Report, SetupReport, coarse_setup, context, defl_from_basis,
                   defl_prolongate, grad_k, prolongate, restrict, solve, solve_idr, solve_instances)
 from .autograd import DeflatedSolve, TwoGridSolver
 
-__all__ = ["Operator", "DeflationSpace", "Report", "SetupReport", "coarse_setup", "context", "defl_from_basis",
+__all__ = ["Operator", "DeflationSpace", "Multigrid", "Report", "SetupReport", "coarse_setup", "context", "defl_from_basis",
            "defl_prolongate", "grad_k", "prolongate", "restrict", "solve", "solve_idr", "solve_instances", "DeflatedSolve",
            "TwoGridSolver"]

@@ -35,7 +35,8 @@ class OpDesc(C.Structure):
 
 class GmresDrParams(C.Structure):
     _fields_ = [("m", C.c_int), ("k", C.c_int), ("nev", C.c_int), ("maxcyc", C.c_int),
-                ("transpose", C.c_int), ("rtolev", C.c_double), ("rtol", C.c_double)]
+                ("transpose", C.c_int), ("rtolev", C.c_double), ("rtol", C.c_double),
+                ("precond", C.c_void_p), ("precond_user", C.c_void_p)]
 
 
 class GmresDrReport(C.Structure):
@@ -60,7 +61,8 @@ class SolveParams(C.Structure):
     _fields_ = [("method", C.c_int), ("ncyc", C.c_int), ("m3", C.c_int), ("precision", C.c_int),
                 ("x0_given", C.c_int), ("transpose", C.c_int), ("maxit_cycle", C.c_int),
                 ("max_extra_cycles", C.c_int), ("rtol", C.c_double), ("fp32_floor", C.c_double),
-                ("cycle_lengths", C.POINTER(C.c_int)), ("n_cycle_lengths", C.c_int)]
+                ("cycle_lengths", C.POINTER(C.c_int)), ("n_cycle_lengths", C.c_int),
+                ("precond", C.c_void_p), ("precond_user", C.c_void_p)]
 
 
 class SolveReport(C.Structure):
@@ -96,8 +98,13 @@ SIGNATURES = [
     ("tgdk_coarse_setup", I, [P, P, P, C.POINTER(GmresDrParams), PP, C.POINTER(GmresDrReport)]),
     ("tgdk_defl_prolongate", I, [P, P, I, PP]),
     ("tgdk_defl_from_basis", I, [P, P, I, I, I, PP]),
+    ("tgdk_mg_create", I, [P, I, I, PP]),
+    ("tgdk_mg_apply", I, [P, P, P, I]),
+    ("tgdk_mg_levels", I, [P]),
+    ("tgdk_mg_destroy", I, [P]),
     ("tgdk_defl_improve", I, [P, C.POINTER(ArnoldiEParams), I, PP, C.POINTER(ArnoldiEReport)]),
     ("tgdk_defl_minres", I, [P, PP]),
+    ("tgdk_defl_precond", I, [P, P, P, PP]),
     ("tgdk_defl_projection", I, [P]),
     ("tgdk_defl_info", I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(C.c_longlong)]),
     ("tgdk_defl_copy", I, [P, P, DP]),

@@ -149,6 +149,14 @@ class DeflationSpace:
         self.k, self.store, self.n = k.value, st.value, n.value
         self.projection = "minres" if lib().tgdk_defl_projection(handle) == L.PROJ_MINRES else "galerkin"
 
+    def precond(self, mg):
+        """The space for right-preconditioned solves with M^{-1} = mg: c = V^T r,
+        H = V^T A M^{-1} V, update with Z = M^{-1} V (tgdk_defl_precond)."""
+        fn, user = _precond(mg)
+        h = C.c_void_p()
+        check(lib().tgdk_defl_precond(self.h, C.c_void_p(fn), C.c_void_p(user), C.byref(h)))
+        return DeflationSpace(h, self.op, self.transpose)
+
     def minres(self):
         """The MinRes-projection space over the same V: H = (AV)^T AV and
         c = (AV)^T r (see include/tgdk.h, tgdk_defl_minres)."""
@@ -202,11 +210,22 @@ class SetupReport:
     seconds: float
 
 
-def coarse_setup(coarse, b_c, m, k, nev=None, rtolev=1e-8, rtol=1e-8, maxcyc=300, transpose=False):
-    """GMRES-DR(m,k) on the coarse grid: returns (x_c, space, SetupReport)."""
+def _precond(pc):
+    """(function pointer, user pointer) of a right preconditioner: a Multigrid."""
+    if pc is None:
+        return None, None
+    if not isinstance(pc, Multigrid):
+        raise TypeError("precond must be a Multigrid")
+    return C.cast(lib().tgdk_mg_apply, C.c_void_p).value, pc.h.value
+
+
+def coarse_setup(coarse, b_c, m, k, nev=None, rtolev=1e-8, rtol=1e-8, maxcyc=300, transpose=False, precond=None):
+    """GMRES-DR(m,k) on the coarse grid (on A M^{-1} with a right
+    preconditioner): returns (x_c, space, SetupReport)."""
     _ptr(b_c, numel=coarse.n, what="b_c")
     x_c = torch.empty_like(b_c)
     p = L.GmresDrParams(m, k, k if nev is None else nev, maxcyc, int(transpose), rtolev, rtol)
+    p.precond, p.precond_user = _precond(precond)
     rep = L.GmresDrReport()
     h = C.c_void_p()
     rc = check(lib().tgdk_coarse_setup(coarse.h, C.c_void_p(b_c.data_ptr()), C.c_void_p(x_c.data_ptr()),
@@ -216,6 +235,33 @@ def coarse_setup(coarse, b_c, m, k, nev=None, rtolev=1e-8, rtol=1e-8, maxcyc=300
     sr = SetupReport(rc, rep.cycles, rep.nconv, kk, rep.mvps, rep.relres, theta, np.array(rep.eigres[:kk]),
                      rep.seconds)
     return x_c, DeflationSpace(h, coarse, transpose), sr
+
+
+class Multigrid:
+    """Geometric multigrid V-cycles for a constant-coefficient operator (see
+    include/tgdk.h, tgdk_mg_create); usable as a right preconditioner."""
+
+    def __init__(self, op, cycles=2, nu=2):
+        h = C.c_void_p()
+        check(lib().tgdk_mg_create(op.h, cycles, nu, C.byref(h)))
+        self.h, self.op = h, op
+        self.levels = lib().tgdk_mg_levels(h)
+
+    def apply(self, x):
+        """M^{-1} x for x of shape (n,) or (nrhs, n), float64 on the device."""
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        _ptr(x, numel=self.op.n * nrhs, what="x")
+        y = torch.empty_like(x)
+        check(lib().tgdk_mg_apply(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nrhs))
+        return y
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None and _lib._lib is not None:
+                lib().tgdk_mg_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
 
 
 def defl_prolongate(space, fine, store=torch.float64):
@@ -280,7 +326,8 @@ def _reports(reps):
 
 
 def solve(op, b, x0=None, defl=None, method="bicgstab", ncyc=20, m3=50, precision="fp64", rtol=1e-8,
-          transpose=False, maxit_cycle=100000, max_extra=None, fp32_floor=1e-4, out=None, cycle_lengths=None):
+          transpose=False, maxit_cycle=100000, max_extra=None, fp32_floor=1e-4, out=None, cycle_lengths=None,
+          precond=None):
     """Fine solve of A x = b (A^T x = b if transpose).  b: (n,) or (nrhs, n)
     float64.  cycle_lengths (GMRES): lengths of the first cycles, each in
     1..m3 (variable restarting).  Returns (x, [Report per right-hand side])."""
@@ -296,6 +343,7 @@ def solve(op, b, x0=None, defl=None, method="bicgstab", ncyc=20, m3=50, precisio
         lens = (C.c_int * len(cycle_lengths))(*[int(v) for v in cycle_lengths])
         p.cycle_lengths = C.cast(lens, C.POINTER(C.c_int))
         p.n_cycle_lengths = len(cycle_lengths)
+    p.precond, p.precond_user = _precond(precond)
     reps = (L.SolveReport * nrhs)()
     check(lib().tgdk_solve(op.h, defl.h if defl is not None else None, C.c_void_p(b.data_ptr()),
                            C.c_void_p(out.data_ptr()), nrhs, C.byref(p), reps))
@@ -303,7 +351,7 @@ def solve(op, b, x0=None, defl=None, method="bicgstab", ncyc=20, m3=50, precisio
 
 
 def solve_idr(op, b, s=4, shadow=None, x0=None, defl=None, ncyc=20, precision="fp64", rtol=1e-8, kappa=0.7,
-              transpose=False, maxit_cycle=100000, max_extra=None, fp32_floor=1e-4, seed=0, out=None):
+              transpose=False, maxit_cycle=100000, max_extra=None, fp32_floor=1e-4, seed=0, out=None, precond=None):
     """IDR(s)(ncyc)-Proj(k) on A x = b (one right-hand side, b of shape (n,)
     float64).  shadow: (s, n) float64 device tensor, the raw columns of the
     shadow space (orthonormalised by the library); None draws s standard
@@ -322,6 +370,7 @@ def solve_idr(op, b, s=4, shadow=None, x0=None, defl=None, ncyc=20, precision="f
     if x0 is not None:
         out.copy_(x0)
     p = _params("idr", ncyc, 0, precision, x0 is not None, transpose, maxit_cycle, max_extra, rtol, fp32_floor)
+    p.precond, p.precond_user = _precond(precond)
     rep = L.SolveReport()
     check(lib().tgdk_solve_idr(op.h, defl.h if defl is not None else None, C.c_void_p(b.data_ptr()),
                                C.c_void_p(out.data_ptr()), s, C.c_void_p(shadow.data_ptr()), kappa, C.byref(p),

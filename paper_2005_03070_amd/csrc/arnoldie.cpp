@@ -168,6 +168,7 @@ using namespace tgdk;
 extern "C" int tgdk_defl_improve(tgdk_defl in, const tgdk_arnoldie_params* prm, int store_dtype, tgdk_defl* out,
                                  tgdk_arnoldie_report* rep) {
     if (!in || !prm || !out) return fail(TGDK_E_INVALID, "NULL argument");
+    if (in->precond) return fail(TGDK_E_INVALID, "improve the Galerkin space, then precondition it");
     const int k = in->k, m = prm->m;
     if (m <= k || m > MAXK) return fail(TGDK_E_INVALID, "need k < m <= 128");
     if (prm->nev < 0 || prm->nev > k || prm->maxcyc < 0 || !(prm->tol > 0.0))

@@ -159,6 +159,35 @@ int cholqr2(tgdk_ctx ctx, double* W, long long n, int k) {
     return rc;
 }
 
+// LU factors, pivots and H^{-1} (column-major, from the LU factors) of d->H,
+// uploaded to the device.  On failure nothing is left allocated.
+static int defl_factor(tgdk_defl d, const char* singular_msg) {
+    const int k = d->k;
+    d->LU = d->H;
+    d->piv.assign(k, 0);
+    if (lu_factor(k, d->LU.data(), d->piv.data()) != 0) return fail(TGDK_E_SINGULAR, singular_msg);
+    std::vector<double> hinv((size_t)k * k, 0.0);
+    for (int j = 0; j < k; ++j) {
+        double* col = hinv.data() + (size_t)j * k;
+        col[j] = 1.0;
+        lu_solve(k, d->LU.data(), d->piv.data(), col);
+    }
+    int rc;
+    if ((rc = dev_alloc(&d->d_lu, (size_t)k * k)) || (rc = dev_alloc(&d->d_piv, (size_t)k)) ||
+        (rc = dev_alloc(&d->d_hinv, (size_t)k * k)) ||
+        hipMemcpy(d->d_lu, d->LU.data(), (size_t)k * k * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d->d_piv, d->piv.data(), (size_t)k * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d->d_hinv, hinv.data(), (size_t)k * k * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        if (d->d_lu) (void)hipFree(d->d_lu);
+        if (d->d_piv) (void)hipFree(d->d_piv);
+        if (d->d_hinv) (void)hipFree(d->d_hinv);
+        d->d_lu = d->d_hinv = nullptr;
+        d->d_piv = nullptr;
+        return rc ? rc : fail(TGDK_E_HIP, "upload of LU failed");
+    }
+    return TGDK_OK;
+}
+
 int defl_finish(tgdk_op op, int transpose, double* V64, int k, int store, tgdk_defl* out, int projection) {
     tgdk_ctx ctx = op->ctx;
     hipStream_t s = ctx->stream;
@@ -219,41 +248,12 @@ int defl_finish(tgdk_op op, int transpose, double* V64, int k, int store, tgdk_d
     d->projection = minres ? TGDK_PROJ_MINRES : TGDK_PROJ_GALERKIN;
     d->W = W;
     d->H = H;
-    d->LU = H;
-    d->piv.assign(k, 0);
-    if (lu_factor(k, d->LU.data(), d->piv.data()) != 0) {
+    if ((rc = defl_factor(d, minres ? "projection matrix H = (AV)^T AV is singular"
+                                    : "projection matrix H = V^T A V is singular"))) {
         if (V32) (void)hipFree(V32);
-        if (W) (void)hipFree(W);
-        delete d;
-        return fail(TGDK_E_SINGULAR, minres ? "projection matrix H = (AV)^T AV is singular"
-                                            : "projection matrix H = V^T A V is singular");
-    }
-    // H^{-1} column by column from the LU factors (column-major)
-    std::vector<double> hinv((size_t)k * k, 0.0);
-    for (int j = 0; j < k; ++j) {
-        double* col = hinv.data() + (size_t)j * k;
-        col[j] = 1.0;
-        lu_solve(k, d->LU.data(), d->piv.data(), col);
-    }
-    if ((rc = dev_alloc(&d->d_lu, (size_t)k * k)) || (rc = dev_alloc(&d->d_piv, (size_t)k)) ||
-        (rc = dev_alloc(&d->d_hinv, (size_t)k * k))) {
-        if (V32) (void)hipFree(V32);
-        if (d->d_lu) (void)hipFree(d->d_lu);
-        if (d->d_piv) (void)hipFree(d->d_piv);
         if (W) (void)hipFree(W);
         delete d;
         return rc;
-    }
-    if (hipMemcpy(d->d_lu, d->LU.data(), (size_t)k * k * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d->d_piv, d->piv.data(), (size_t)k * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d->d_hinv, hinv.data(), (size_t)k * k * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
-        if (V32) (void)hipFree(V32);
-        (void)hipFree(d->d_lu);
-        (void)hipFree(d->d_piv);
-        (void)hipFree(d->d_hinv);
-        if (W) (void)hipFree(W);
-        delete d;
-        return fail(TGDK_E_HIP, "upload of LU failed");
     }
     if (store == TGDK_F32) {
         d->V = V32;
@@ -543,6 +543,7 @@ int tgdk_defl_from_basis(tgdk_op op, const double* W, int k, int transpose, int 
 
 int tgdk_defl_minres(tgdk_defl g, tgdk_defl* out) {
     if (!g || !out) return fail(TGDK_E_INVALID, "NULL argument");
+    if (g->precond) return fail(TGDK_E_INVALID, "a preconditioned space has no MinRes variant");
     TGDK_HIP(hipSetDevice(g->ctx->device));
     double* V = nullptr;
     int rc = dev_alloc(&V, (size_t)g->n * g->k);
@@ -559,6 +560,66 @@ int tgdk_defl_minres(tgdk_defl g, tgdk_defl* out) {
 
 int tgdk_defl_projection(tgdk_defl d) { return d ? d->projection : TGDK_E_INVALID; }
 
+int tgdk_defl_precond(tgdk_defl g, tgdk_precond_fn fn, void* user, tgdk_defl* out) {
+    if (!g || !fn || !out) return fail(TGDK_E_INVALID, "NULL argument");
+    if (g->store != TGDK_F64 || g->W || g->precond)
+        return fail(TGDK_E_INVALID, "a preconditioned space is built from a float64 Galerkin space");
+    tgdk_ctx ctx = g->ctx;
+    TGDK_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const long long n = g->n;
+    const int k = g->k;
+    double *V = nullptr, *Z = nullptr, *AZ = nullptr, *dG = nullptr;
+    int rc;
+    auto release = [&]() {
+        if (V) (void)hipFree(V);
+        if (Z) (void)hipFree(Z);
+        if (AZ) (void)hipFree(AZ);
+        if (dG) (void)hipFree(dG);
+    };
+    if ((rc = dev_alloc(&V, (size_t)n * k)) || (rc = dev_alloc(&Z, (size_t)n * k)) ||
+        (rc = dev_alloc(&AZ, (size_t)n * k)) || (rc = dev_alloc(&dG, (size_t)k * k))) {
+        release();
+        return rc;
+    }
+    TGDK_HIP(hipMemcpyAsync(V, g->V, sizeof(double) * n * k, hipMemcpyDeviceToDevice, s));
+    // Z = M^{-1} V, then H = V^T (A Z)
+    if ((rc = fn(user, V, Z, k)) || (rc = op_apply_internal(g->op, g->transpose, TGDK_F64, Z, AZ, k)) ||
+        (rc = ctx->partial.ensure((size_t)gram_blocks(n) * k * k * sizeof(double)))) {
+        release();
+        return rc < 0 ? rc : fail(TGDK_E_HIP, "preconditioner failed");
+    }
+    std::vector<double> H((size_t)k * k);
+    launch_gram(V, 0, n, k, AZ, 0, n, k, n, dG, (double*)ctx->partial.p, ctx->counters, s);
+    if (hipMemcpyAsync(H.data(), dG, H.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        release();
+        return fail(TGDK_E_HIP, "forming H failed");
+    }
+    (void)hipFree(AZ);
+    (void)hipFree(dG);
+    AZ = dG = nullptr;
+    tgdk_defl d = new tgdk_defl_s();
+    d->ctx = ctx;
+    d->op = g->op;
+    d->transpose = g->transpose;
+    d->k = k;
+    d->n = n;
+    d->store = TGDK_F64;
+    d->projection = TGDK_PROJ_GALERKIN;
+    d->precond = 1;
+    d->V = Z;  // update basis
+    d->W = V;  // basis of c = V^T r
+    d->H = H;
+    if ((rc = defl_factor(d, "projection matrix H = V^T A M^{-1} V is singular"))) {
+        delete d;
+        release();
+        return rc;
+    }
+    *out = d;
+    return TGDK_OK;
+}
+
 int tgdk_defl_info(tgdk_defl d, int* k, int* store, long long* n) {
     if (!d) return fail(TGDK_E_INVALID, "NULL space");
     if (k) *k = d->k;
@@ -572,8 +633,8 @@ int tgdk_defl_copy(tgdk_defl d, double* V_out, double* H_out) {
     TGDK_HIP(hipSetDevice(d->ctx->device));
     if (V_out) {
         if (d->store == TGDK_F64)
-            TGDK_HIP(hipMemcpyAsync(V_out, d->V, (size_t)d->n * d->k * sizeof(double), hipMemcpyDeviceToDevice,
-                                    d->ctx->stream));
+            TGDK_HIP(hipMemcpyAsync(V_out, d->precond ? d->W : d->V, (size_t)d->n * d->k * sizeof(double),
+                                    hipMemcpyDeviceToDevice, d->ctx->stream));
         else
             launch_to_f64((const float*)d->V, V_out, (long long)d->n * d->k, d->ctx->stream);
         TGDK_HIP(hipStreamSynchronize(d->ctx->stream));

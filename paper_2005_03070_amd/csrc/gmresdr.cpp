@@ -103,7 +103,7 @@ extern "C" int tgdk_coarse_setup(tgdk_op op, const double* b, double* x, const t
     };
     if (hipMalloc((void**)&V, sizeof(double) * n * (m + 1)) != hipSuccess ||
         hipMalloc((void**)&Vt, sizeof(double) * n * (m + 1)) != hipSuccess ||
-        hipMalloc((void**)&w, sizeof(double) * n) != hipSuccess ||
+        hipMalloc((void**)&w, sizeof(double) * n * (prm->precond ? 2 : 1)) != hipSuccess ||
         hipMalloc((void**)&Hd, sizeof(double) * (2 * hsz + m + 16)) != hipSuccess ||
         hipMalloc((void**)&dP, sizeof(double) * (m + 1) * (m + 2)) != hipSuccess) {
         cleanup();
@@ -121,9 +121,18 @@ extern "C" int tgdk_coarse_setup(tgdk_op op, const double* b, double* x, const t
     double* part = (double*)ctx->partial.p;
     unsigned* cnt = ctx->counters;
 
+    // right preconditioning (Sec. 5, Example 5): the Arnoldi process runs on
+    // A M^{-1}; x accumulates u and becomes M^{-1} u at the end
+    double* pz = prm->precond ? w + n : nullptr;
+    int prc = TGDK_OK;
     auto arnoldi = [&](int j0) {
         for (int j = j0; j < m; ++j) {
-            launch_apply<double>(dop, V + (size_t)j * n, w, 1, op->tile_id[0], s);
+            if (pz) {
+                if (!prc) prc = prm->precond(prm->precond_user, V + (size_t)j * n, pz, 1);
+                launch_apply<double>(dop, pz, w, 1, op->tile_id[0], s);
+            } else {
+                launch_apply<double>(dop, V + (size_t)j * n, w, 1, op->tile_id[0], s);
+            }
             launch_gs_dot(V, n, j + 1, w, n, H1 + (size_t)j * (m + 1), part, cnt, s);
             launch_gs_update_dot(V, n, j + 1, w, H1 + (size_t)j * (m + 1), n, H2 + (size_t)j * (m + 1), part, cnt, s);
             launch_gs_update_norm(V, n, j + 1, w, H2 + (size_t)j * (m + 1), n, Nd + j, part, cnt, s);
@@ -304,6 +313,16 @@ extern "C" int tgdk_coarse_setup(tgdk_op op, const double* b, double* x, const t
         }
     }
     if (cyc > maxcyc) cyc = maxcyc;
+    if (!rc && prc) rc = prc;
+    if (!rc && pz) {  // x = M^{-1} u
+        if ((rc = prm->precond(prm->precond_user, x, pz, 1)) == TGDK_OK)
+            TGDK_HIP(hipMemcpyAsync(x, pz, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    }
+    if (rc) {
+        cleanup();
+        if (W) (void)hipFree(W);
+        return rc;
+    }
     // final true residual of the coarse solution: ||A x - b||
     launch_apply<double>(dop, x, w, 1, op->tile_id[0], s);
     const double one = 1.0;

@@ -79,7 +79,9 @@ struct tgdk_defl_s {
     int store = TGDK_F64;
     void* V = nullptr;         // n x k column-major (ldv = n)
     int projection = TGDK_PROJ_GALERKIN;
-    void* W = nullptr;         // MinRes: A V (or A^T V), same layout and type as V; else null
+    void* W = nullptr;         // left basis of c when it differs from V: MinRes A V (or A^T V);
+                               // preconditioned: the orthonormal basis (V then holds Z = M^{-1} V)
+    int precond = 0;           // built by tgdk_defl_precond
     std::vector<double> H, LU;
     std::vector<int> piv;
     double* d_lu = nullptr;

@@ -311,9 +311,9 @@ void launch_scale(const double* w, double* v, const double* nrm, long long n, hi
     hipLaunchKernelGGL(k_scale, dim3((int)nb), dim3(256), 0, s, w, v, nrm, n);
 }
 
-// c = a - b over n contiguous values
-__global__ __launch_bounds__(NT) void k_sub(const double* __restrict__ a, const double* __restrict__ b,
-                                            double* __restrict__ c, long long n) {
+// c = a - b over n contiguous values (c may be b: each element is read
+// before it is written by the same thread)
+__global__ __launch_bounds__(NT) void k_sub(const double* __restrict__ a, const double* b, double* c, long long n) {
     for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
         c[i] = a[i] - b[i];
 }
@@ -323,6 +323,33 @@ void launch_sub(const double* a, const double* b, double* c, long long n, hipStr
     if (nb > 4096) nb = 4096;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_sub, dim3((int)nb), dim3(NT), 0, s, a, b, c, n);
+}
+
+// Damped Jacobi with a constant diagonal: z = s v (first sweep, from z = 0)
+// or z += s (v - Az), s = omega / d.
+__global__ __launch_bounds__(NT) void k_jacobi(double* __restrict__ z, const double* __restrict__ v,
+                                               const double* __restrict__ Az, double s, long long n, int first) {
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
+        z[i] = first ? s * v[i] : z[i] + s * (v[i] - Az[i]);
+}
+
+void launch_jacobi(double* z, const double* v, const double* Az, double s, long long n, int first, hipStream_t st) {
+    long long nb = (n + NT - 1) / NT;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_jacobi, dim3((int)nb), dim3(NT), 0, st, z, v, Az, s, n, first);
+}
+
+// a += b over n values
+__global__ __launch_bounds__(NT) void k_add(double* __restrict__ a, const double* __restrict__ b, long long n) {
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) a[i] += b[i];
+}
+
+void launch_add(double* a, const double* b, long long n, hipStream_t st) {
+    long long nb = (n + NT - 1) / NT;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_add, dim3((int)nb), dim3(NT), 0, st, a, b, n);
 }
 
 }  // namespace tgdk

@@ -83,6 +83,10 @@ void launch_gs_update_dot(const double* V, long long ldv, int p, double* w, cons
 void launch_gs_update_norm(const double* V, long long ldv, int p, double* w, const double* h, long long n,
                            double* nrm, double* partial, unsigned* counter, hipStream_t s);
 void launch_scale(const double* w, double* v, const double* nrm, long long n, hipStream_t s);
+// damped Jacobi, constant diagonal: z = s v (first) or z += s (v - Az), s = omega / d
+void launch_jacobi(double* z, const double* v, const double* Az, double s, long long n, int first, hipStream_t st);
+// a += b (n values)
+void launch_add(double* a, const double* b, long long n, hipStream_t st);
 // c = a - b (n values)
 void launch_sub(const double* a, const double* b, double* c, long long n, hipStream_t s);
 // ||w|| -> *out (deterministic)

@@ -502,11 +502,12 @@ static int gmres_single(tgdk_ctx ctx, const ProbSpec& p, const tgdk_solve_params
     const int m = prm->m3;
     const long long n = p.op->N;
     // Krylov basis, w, H columns
-    double *V = nullptr, *w = nullptr, *Hd = nullptr, *dy = nullptr;
+    double *V = nullptr, *w = nullptr, *Hd = nullptr, *dy = nullptr, *pz = nullptr;
     const size_t hsz = (size_t)(m + 1) * m;
+    const bool pre = prm->precond != nullptr;
     if (hipMalloc((void**)&V, sizeof(double) * n * (m + 1)) != hipSuccess)
         return fail(TGDK_E_NOMEM, "GMRES basis allocation failed");
-    if (hipMalloc((void**)&w, sizeof(double) * n) != hipSuccess ||
+    if (hipMalloc((void**)&w, sizeof(double) * n * (pre ? 3 : 1)) != hipSuccess ||
         hipMalloc((void**)&Hd, sizeof(double) * (2 * hsz + m + 8)) != hipSuccess ||
         hipMalloc((void**)&dy, sizeof(double) * (m + 1)) != hipSuccess) {
         (void)hipFree(V);
@@ -517,6 +518,8 @@ static int gmres_single(tgdk_ctx ctx, const ProbSpec& p, const tgdk_solve_params
     double* H1 = Hd;
     double* H2 = Hd + hsz;
     double* Nd = Hd + 2 * hsz;
+    pz = pre ? w + n : nullptr;             // M^{-1} v_j; then M^{-1} (V y)
+    double* pu = pre ? w + 2 * n : nullptr;  // V y
     rc = ctx->partial.ensure((size_t)gs_blocks(n) * (MAXK + 1) * sizeof(double));
     std::vector<long long> extra(1, 0);
     std::vector<int> cyc_steps;  // steps of each cycle
@@ -542,7 +545,12 @@ static int gmres_single(tgdk_ctx ctx, const ProbSpec& p, const tgdk_solve_params
         const int mc = cyc < prm->n_cycle_lengths && prm->cycle_lengths ? prm->cycle_lengths[cyc] : m;
         int steps = mc;
         for (int j = 0; j < mc; ++j) {
-            launch_apply<double>(op, V + (size_t)j * n, w, 1, p.op->tile_id[0], s);
+            if (pre) {  // right preconditioning: w = A M^{-1} v_j
+                if ((rc = prm->precond(prm->precond_user, V + (size_t)j * n, pz, 1))) break;
+                launch_apply<double>(op, pz, w, 1, p.op->tile_id[0], s);
+            } else {
+                launch_apply<double>(op, V + (size_t)j * n, w, 1, p.op->tile_id[0], s);
+            }
             launch_gs_dot(V, n, j + 1, w, n, H1 + (size_t)j * (m + 1), (double*)ctx->partial.p, ctx->counters, s);
             launch_gs_update_dot(V, n, j + 1, w, H1 + (size_t)j * (m + 1), n, H2 + (size_t)j * (m + 1),
                                  (double*)ctx->partial.p, ctx->counters, s);
@@ -550,6 +558,7 @@ static int gmres_single(tgdk_ctx ctx, const ProbSpec& p, const tgdk_solve_params
                                   ctx->counters, s);
             launch_scale(w, V + (size_t)(j + 1) * n, Nd + j, n, s);
         }
+        if (rc) break;
         TGDK_HIP(hipGetLastError());
         TGDK_HIP(hipMemcpyAsync(h1.data(), H1, sizeof(double) * hsz, hipMemcpyDeviceToHost, s));
         TGDK_HIP(hipMemcpyAsync(h2.data(), H2, sizeof(double) * hsz, hipMemcpyDeviceToHost, s));
@@ -573,7 +582,13 @@ static int gmres_single(tgdk_ctx ctx, const ProbSpec& p, const tgdk_solve_params
         rhs[0] = S.nu;
         lstsq(steps + 1, steps, Hs.data(), rhs.data(), y.data(), res.data());
         TGDK_HIP(hipMemcpyAsync(dy, y.data(), sizeof(double) * steps, hipMemcpyHostToDevice, s));
-        launch_vmul_add(V, n, steps, dy, p.x, n, s);
+        if (pre) {  // x += M^{-1} (V y)
+            launch_vmul(V, n, steps, dy, 1, pu, n, n, s);
+            if ((rc = prm->precond(prm->precond_user, pu, pz, 1))) break;
+            launch_add(p.x, pz, n, s);
+        } else {
+            launch_vmul_add(V, n, steps, dy, p.x, n, s);
+        }
         extra[0] += steps;
         cyc_steps.push_back(steps);
         launch(g, K_RESIDUAL, 0);
@@ -611,7 +626,8 @@ static int idr_single(tgdk_ctx ctx, const ProbSpec& p, int s, const double* shad
     const size_t off_u = align256(sn * ies), off_p = off_u + align256(sn * ies);
     const size_t off_p64 = off_p + (f32 ? align256(sn * ies) : 0);
     const size_t off_st = off_p64 + align256(sn * 8);
-    const size_t bytes = off_st + align256(sizeof(IdrState));
+    const size_t off_pz = off_st + align256(sizeof(IdrState));  // preconditioner output
+    const size_t bytes = off_pz + (prm->precond ? align256((size_t)n * 8) : 0);
     char* wk = nullptr;
     if (hipMalloc((void**)&wk, bytes) != hipSuccess) return fail(TGDK_E_NOMEM, "IDR workspace allocation failed");
     double* P64 = (double*)(wk + off_p64);
@@ -660,11 +676,18 @@ static int idr_single(tgdk_ctx ctx, const ProbSpec& p, int s, const double* shad
     const int* gate = &d_st->gate;
     const size_t eln = (size_t)n * ies;
     auto col = [&](void* base, int k) { return (void*)((char*)base + (size_t)k * eln); };
+    const bool pre = prm->precond != nullptr;  // float64 only (checked)
+    double* pz = pre ? (double*)(wk + off_pz) : nullptr;
+    int prc = TGDK_OK;                          // first preconditioner failure
     auto apply = [&](const void* x, void* y) {
-        if (f32)
+        if (pre) {  // right preconditioning: y = A M^{-1} x
+            if (!prc) prc = prm->precond(prm->precond_user, (const double*)x, pz, 1);
+            launch_apply<double>(op, pz, (double*)y, 1, tile, hs, gate);
+        } else if (f32) {
             launch_apply<float>(op, (const float*)x, (float*)y, 1, tile, hs, gate);
-        else
+        } else {
             launch_apply<double>(op, (const double*)x, (double*)y, 1, tile, hs, gate);
+        }
     };
     auto round = [&]() {
         for (int k = 0; k < s; ++k) {
@@ -689,6 +712,7 @@ static int idr_single(tgdk_ctx ctx, const ProbSpec& p, int s, const double* shad
             launch(g, K_PROJ_DOT);
             launch(g, K_PROJ_APPLY);
         }
+        if (pre) launch_fill((double*)a.e, 0.0, n, hs);  // the fold below reads e whatever the cycle did
         launch_idr(IDR_START, f32, a, 0, hs);
         IDR_HIP(hipGetLastError());
         // rounds until the device ends the cycle
@@ -702,6 +726,7 @@ static int idr_single(tgdk_ctx ctx, const ProbSpec& p, int s, const double* shad
             }
             if ((rc = wait_event(ctx->events[head % 2]))) return done(rc);
             ++head;
+            if (prc) return done(prc);
             const Mirror m = read_mirror(g, 0);
             if (m.solve_state != SV_RUNNING || m.inner_state != IN_RUNNING) break;
             if (m.iter == ev_mvps) return done(fail(TGDK_E_HIP, "IDR cycle stopped reporting progress"));
@@ -710,9 +735,14 @@ static int idr_single(tgdk_ctx ctx, const ProbSpec& p, int s, const double* shad
             int rem = s + 1;
             if (rate > 0.0 && rate < 0.9999 && m.rr > 0.0 && m.target2 > 0.0 && m.rr > m.target2)
                 rem = (int)std::ceil(std::log(m.target2 / m.rr) / std::log(rate));
-            nr = std::max(1, std::min(8, (rem + s) / (s + 1)));
+            nr = pre ? 1 : std::max(1, std::min(8, (rem + s) / (s + 1)));
         }
-        launch_idr(IDR_FOLD, f32, a, 0, hs);
+        if (pre) {  // x += M^{-1} e (e is zero if the cycle made no update)
+            if ((rc = prm->precond(prm->precond_user, (const double*)a.e, pz, 1))) return done(rc);
+            launch_add(p.x, pz, n, hs);
+        } else {
+            launch_idr(IDR_FOLD, f32, a, 0, hs);
+        }
         launch(g, K_RESIDUAL, 0);
         IDR_HIP(hipGetLastError());
         IDR_HIP(hipStreamSynchronize(hs));
@@ -741,6 +771,11 @@ static int check_params(const tgdk_solve_params* prm) {
         return fail(TGDK_E_INVALID, "unknown method");
     }
     if (prm->precision != TGDK_FP64 && prm->precision != TGDK_FP32_IR) return fail(TGDK_E_INVALID, "precision");
+    if (prm->precond) {
+        if (prm->method == TGDK_BICGSTAB_PROJ)
+            return fail(TGDK_E_INVALID, "right preconditioning is available for GMRES-Proj and IDR-Proj");
+        if (prm->precision != TGDK_FP64) return fail(TGDK_E_INVALID, "preconditioned solves run in float64");
+    }
     if (!(prm->rtol > 0.0)) return fail(TGDK_E_INVALID, "rtol must be > 0");
     return TGDK_OK;
 }
@@ -752,6 +787,8 @@ static int check_defl(tgdk_op op, tgdk_defl d, const tgdk_solve_params* prm) {
         if (d->op->n[a] != op->n[a]) return fail(TGDK_E_INVALID, "deflation space grid does not match the operator");
     if (d->transpose != (prm->transpose ? 1 : 0))
         return fail(TGDK_E_INVALID, "deflation space was built for the other orientation (A vs A^T)");
+    if ((d->precond != 0) != (prm->precond != nullptr))
+        return fail(TGDK_E_INVALID, "a preconditioned solve needs a space from tgdk_defl_precond, and only it");
     return TGDK_OK;
 }
 
