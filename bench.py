@@ -449,6 +449,57 @@ def main():
         del oph, bh, sph, csh, coarse_h, x0h, shadows
         torch.cuda.empty_cache()
 
+        # Example 5: multigrid-preconditioned Helmholtz, kappa = 100 on 511^2
+        # (each solve once: they take seconds)
+        c5 = W.CONFIGS["H2"]
+        kap2 = -c5["sigma"]
+        op5 = tg.Operator.const_cd(c5["n"], c5["beta"], sigma=c5["sigma"])
+        b5 = torch.tensor(W.rhs(op5.n, c5["seed"]), device=dev)
+        t = time.perf_counter()
+        mg5 = tg.Multigrid(tg.Operator.const_cd(c5["n"], c5["beta"], sigma=kap2), cycles=c5["mg_cycles"],
+                           nu=c5["mg_nu"])
+        coarse5 = op5.coarsen()
+        mg5c = tg.Multigrid(tg.Operator.const_cd(coarse5.dims, c5["beta"], sigma=kap2), cycles=c5["mg_cycles"],
+                            nu=c5["mg_nu"])
+        xc5, cs5, sr5 = tg.coarse_setup(coarse5, tg.restrict(op5, coarse5, b5), c5["m"], c5["k"], c5["nev"],
+                                        c5["rtolev"], c5["rtol"], 300, precond=mg5c)
+        sp5 = tg.defl_prolongate(cs5, op5).precond(mg5)
+        x05 = tg.prolongate(coarse5, op5, xc5)
+        torch.cuda.synchronize()
+        w5 = {"setup_seconds": time.perf_counter() - t, "gmresdr_cycles": sr5.cycles, "nconv": sr5.nconv,
+              "k": sp5.k}
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            mg5.apply(b5)
+        torch.cuda.synchronize()
+        w5["mg_apply_ms"] = (time.perf_counter() - t) / 5 * 1e3
+        log(f"Helmholtz 511^2 kappa 100, multigrid-preconditioned: coarse GMRES-DR({c5['m']},{c5['k']}) on A M^-1 "
+            f"{sr5.cycles} cycles, {sr5.nconv} converged, {w5['setup_seconds']:.2f} s; M^-1 {w5['mg_apply_ms']:.2f} ms")
+        sh5 = torch.tensor(W.shadow_draw(op5.n, c5["s"], c5["seed"] + c5["s"]), device=dev)
+
+        def once(name, fn):
+            torch.cuda.synchronize()
+            t0_ = time.perf_counter()
+            xv, rv = fn()
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0_
+            rr = float(torch.linalg.vector_norm(b5 - op5.apply(xv)) / torch.linalg.vector_norm(b5))
+            w5[name] = {"seconds": sec, "status": rv.status_name, "cycles": rv.cycles, "mvp_inner": rv.mvp_inner,
+                        "relres_true": rr}
+            log(f"  {name}: {sec*1e3:.0f} ms, {rv.status_name}, {rv.cycles} cycles, mvps {rv.mvp_inner}, "
+                f"relres {rr:.2e}")
+
+        once("idr5_5cyc_proj60_mg_fp64", lambda: tg.solve_idr(op5, b5, s=c5["s"], shadow=sh5, x0=x05, defl=sp5,
+                                                               rtol=c5["rtol"], ncyc=c5["ncyc"], max_extra=20,
+                                                               precond=mg5))
+        once("idr5_mg_no_deflation_fp64", lambda: tg.solve_idr(op5, b5, s=c5["s"], shadow=sh5, x0=x05,
+                                                                rtol=c5["rtol"], ncyc=c5["ncyc"], max_extra=20,
+                                                                precond=mg5))
+        workloads["helmholtz_mg_511sq_kappa100_k60"] = w5
+        del op5, b5, mg5, mg5c, coarse5, cs5, sp5, x05, sh5
+        torch.cuda.empty_cache()
+
     # ------------------------------------------ standalone stencil bandwidth
     def stencil_gbs(opx, dtype, rotate_bytes=2 << 30):
         es = torch.tensor([], dtype=dtype).element_size()

@@ -278,10 +278,12 @@ int tgdk_defl_destroy(tgdk_defl defl);
  * weighting and linear interpolation; 20 sweeps on the coarsest grid.
  * tgdk_mg_apply is a tgdk_precond_fn (user = the tgdk_mg): `cycles` V-cycles
  * from zero, z_1 = V(b), z_(c+1) = z_c + V(b - A z_c) (a fixed linear
- * operator).  The object keeps per-level work vectors: one apply at a time
- * per object. */
+ * operator).  By default the kernel sequence is captured into a HIP graph
+ * at the first apply and replayed; in and out are copied around it.  The
+ * object keeps per-level work vectors: one apply at a time per object. */
 typedef struct tgdk_mg_s* tgdk_mg;
-int tgdk_mg_create(tgdk_op op, int cycles, int nu, tgdk_mg* mg);
+#define TGDK_MG_EAGER 1   /* flags: launch the kernels on every apply instead of replaying a HIP graph */
+int tgdk_mg_create(tgdk_op op, int cycles, int nu, int flags, tgdk_mg* mg);
 int tgdk_mg_apply(void* mg, const double* in, double* out, int nrhs);
 int tgdk_mg_levels(tgdk_mg mg);
 int tgdk_mg_destroy(tgdk_mg mg);

@@ -98,7 +98,7 @@ SIGNATURES = [
     ("tgdk_coarse_setup", I, [P, P, P, C.POINTER(GmresDrParams), PP, C.POINTER(GmresDrReport)]),
     ("tgdk_defl_prolongate", I, [P, P, I, PP]),
     ("tgdk_defl_from_basis", I, [P, P, I, I, I, PP]),
-    ("tgdk_mg_create", I, [P, I, I, PP]),
+    ("tgdk_mg_create", I, [P, I, I, I, PP]),
     ("tgdk_mg_apply", I, [P, P, P, I]),
     ("tgdk_mg_levels", I, [P]),
     ("tgdk_mg_destroy", I, [P]),

@@ -241,9 +241,9 @@ class Multigrid:
     """Geometric multigrid V-cycles for a constant-coefficient operator (see
     include/tgdk.h, tgdk_mg_create); usable as a right preconditioner."""
 
-    def __init__(self, op, cycles=2, nu=2):
+    def __init__(self, op, cycles=2, nu=2, graph=True):
         h = C.c_void_p()
-        check(lib().tgdk_mg_create(op.h, cycles, nu, C.byref(h)))
+        check(lib().tgdk_mg_create(op.h, cycles, nu, 0 if graph else 1, C.byref(h)))
         self.h, self.op = h, op
         self.levels = lib().tgdk_mg_levels(h)
 
