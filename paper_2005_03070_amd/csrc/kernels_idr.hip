@@ -33,6 +33,7 @@ namespace tgdk {
 
 constexpr int IDR_BLOCKS = 1024;  // cap on the workgroups of the vector kernels
 constexpr int IDR_CH = 8;         // products with P accumulated per pass
+static_assert(IDR_BLOCKS % 64 == 0, "the epilogue gives every lane IDR_BLOCKS / 64 partials");
 
 int idr_blocks(long long n) {
     long long b = (n + 2 * NT - 1) / (2 * NT);
@@ -56,6 +57,7 @@ __device__ __forceinline__ void dots_with_P(const IdrArgs& a, Y&& y) {
 #pragma unroll
         for (int j = 0; j <= IDR_CH; ++j) acc[j] = 0.0;
         const int nc = min(IDR_CH, a.s - c0);
+#pragma unroll 2
         for (long long i = i0; i < n; i += stride) {
             const double yv = y(i, first);
 #pragma unroll
@@ -100,6 +102,7 @@ __global__ __launch_bounds__(NT) void k_idr_dir(IdrArgs a, int k) {
     if (threadIdx.x < m) cs[threadIdx.x] = st->c[threadIdx.x];
     __syncthreads();
     const double om = st->om;
+#pragma unroll 2
     for (long long i = i0; i < n; i += stride) {
         double gc = 0.0, uc = 0.0;
         for (int j = 0; j < m; ++j) {
@@ -109,6 +112,56 @@ __global__ __launch_bounds__(NT) void k_idr_dir(IdrArgs a, int k) {
         const TI v = (TI)((double)r[i] - gc);
         uk[i] = (TI)(uc + om * (double)v);
     }
+}
+
+// Steps k-1 and k fused (k >= 1): the update of step k-1,
+// r -= beta g_(k-1), e += beta u_(k-1) (e = beta u_(k-1) on the cycle's first
+// update), with r . r into value slot s; then the direction of step k from the
+// updated r.  The convergence test of that update happens in step k's alpha
+// epilogue; beta's effect on f and the coefficients c of step k were formed in
+// step k-1's M epilogue (they do not depend on r . r).
+template <class TI>
+__global__ __launch_bounds__(NT) void k_idr_dirupd(IdrArgs a, int k) {
+    __shared__ double cs[IDR_SMAX];
+    __shared__ double sh[NWAVE];
+    const IdrState* st = a.st;
+    if (st->gate) return;
+    TI* r = vp<TI>(a.r);
+    TI* e = vp<TI>(a.e);
+    const TI* __restrict__ G = vp<TI>(a.G);
+    TI* U = vp<TI>(a.U);
+    const long long n = a.n;
+    const TI* gp = G + (long long)(k - 1) * n;
+    const TI* up = U + (long long)(k - 1) * n;
+    TI* uk = U + (long long)k * n;
+    const int m = a.s - k;
+    const bool round0 = st->round0;
+    if (!round0 && threadIdx.x < m) cs[threadIdx.x] = st->c[threadIdx.x];
+    __syncthreads();
+    const double beta = st->beta, om = st->om;
+    const bool efirst = st->efirst;
+    const long long stride = (long long)gridDim.x * NT;
+    double acc = 0.0;
+#pragma unroll 2
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
+        const TI rv = (TI)((double)r[i] - beta * (double)gp[i]);
+        r[i] = rv;
+        e[i] = efirst ? (TI)(beta * (double)up[i]) : (TI)((double)e[i] + beta * (double)up[i]);
+        acc += (double)rv * (double)rv;
+        if (round0) {
+            uk[i] = rv;
+        } else {
+            double gc = 0.0, uc = 0.0;
+            for (int j = 0; j < m; ++j) {
+                gc += (double)G[(long long)(k + j) * n + i] * cs[j];
+                uc += (double)U[(long long)(k + j) * n + i] * cs[j];
+            }
+            const TI v = (TI)((double)rv - gc);
+            uk[i] = (TI)(uc + om * (double)v);
+        }
+    }
+    const double tot = block_sum_one(acc, sh);
+    if (threadIdx.x == 0) a.part[(long long)a.s * a.nb + blockIdx.x] = tot;
 }
 
 // m = P^T g_k before the orthogonalisation (k > 0).
@@ -162,6 +215,7 @@ __global__ __launch_bounds__(NT) void k_idr_upd(IdrArgs a, int k) {
     const bool efirst = st->efirst;
     const long long stride = (long long)gridDim.x * NT;
     double acc = 0.0;
+#pragma unroll 4
     for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
         const TI rv = (TI)((double)r[i] - beta * (double)g[i]);
         r[i] = rv;
@@ -181,6 +235,7 @@ __global__ __launch_bounds__(NT) void k_idr_tdot(IdrArgs a) {
     const TI* __restrict__ t = vp<TI>(a.t);
     const long long stride = (long long)gridDim.x * NT;
     double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll 4
     for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < a.n; i += stride) {
         const double tv = (double)t[i], rv = (double)r[i];
         acc[0] += tv * tv;
@@ -314,6 +369,25 @@ __device__ void idr_decide(const IdrArgs& a, int which, int k, const double* v, 
             break;
         }
         case E_ALPHA: {
+            // the update of step k-1 (fused into step k's direction): its tests
+            const double rr = v[s], beta = st->beta;
+            const int mvps = st->mvps;
+            st->rr = rr;
+            st->efirst = 0;
+            idr_hist(a, rr, beta, 0);
+            if (rr <= st->target2) {
+                idr_end(a, IN_CONVERGED);
+                break;
+            }
+            if (!isfinite(rr)) {
+                idr_end(a, IN_BREAK_NOUPD);
+                break;
+            }
+            if (mvps >= st->maxit) {
+                idr_end(a, IN_MAXIT);
+                break;
+            }
+            idr_progress(a, rr, mvps);
             // forward substitution with the leading k x k block of M
             for (int i = 0; i < k; ++i) {
                 double x = v[i];
@@ -331,6 +405,12 @@ __device__ void idr_decide(const IdrArgs& a, int which, int k, const double* v, 
                 break;
             }
             st->beta = L.f[k] / mkk;
+            // f and the next step's coefficients (the update itself and its
+            // tests follow in the next step's kernels)
+            if (k + 1 < s) {
+                for (int i = k + 1; i < s; ++i) L.f[i] -= st->beta * L.M[i * s + k];
+                idr_coeffs(L, s, k + 1);
+            }
             break;
         }
         case E_UPD: {
@@ -404,9 +484,20 @@ __global__ __launch_bounds__(NT) void k_idr_epi(IdrArgs a, int which, int k, int
     if (which == E_START ? a.ss->solve_state != SV_RUNNING : st->gate != 0) return;
     const int s = a.s;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // each lane's IDR_BLOCKS / 64 partials of a value are loaded together
+    // (clamped addresses, masked values), then added in a fixed order
+    constexpr int PER_LANE = IDR_BLOCKS / 64;
     for (int q = w; q < nv; q += NWAVE) {
+        const double* pq = a.part + (long long)q * a.nb;
+        double x[PER_LANE];
+#pragma unroll
+        for (int i = 0; i < PER_LANE; ++i) {
+            const int b = lane + 64 * i;
+            x[i] = pq[b < a.nb ? b : 0];
+        }
         double acc = 0.0;
-        for (int b = lane; b < a.nb; b += 64) acc += a.part[(long long)q * a.nb + b];
+#pragma unroll
+        for (int i = 0; i < PER_LANE; ++i) acc += (lane + 64 * i < a.nb) ? x[i] : 0.0;
         acc = wave_sum(acc);
         if (lane == 0) v[q] = acc;
     }
@@ -448,7 +539,10 @@ static void idr_launch_t(int what, const IdrArgs& a, int k, hipStream_t s) {
             break;
         case IDR_ALPHA:
             hipLaunchKernelGGL(k_idr_gdot<TI>, grid, block, 0, s, a, k);
-            hipLaunchKernelGGL(k_idr_epi, dim3(1), block, 0, s, a, (int)E_ALPHA, k, a.s);
+            hipLaunchKernelGGL(k_idr_epi, dim3(1), block, 0, s, a, (int)E_ALPHA, k, a.s + 1);
+            break;
+        case IDR_DIRUPD:
+            hipLaunchKernelGGL(k_idr_dirupd<TI>, grid, block, 0, s, a, k);
             break;
         case IDR_ORTH:
             hipLaunchKernelGGL(k_idr_orth<TI>, grid, block, 0, s, a, k);

@@ -54,6 +54,7 @@ enum : int {
     IDR_OMEGA = 5,  // omega from t = A r
     IDR_RED = 6,    // e += omega r, r -= omega t; f = P^T r; convergence; next c
     IDR_FOLD = 7,   // x += e
+    IDR_DIRUPD = 8,  // the update of step k-1 fused with the direction of step k (k >= 1)
 };
 int idr_blocks(long long n);
 void launch_idr(int what, int inner_f32, const IdrArgs& a, int k, hipStream_t s);

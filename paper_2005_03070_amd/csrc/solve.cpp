@@ -689,14 +689,17 @@ static int idr_single(tgdk_ctx ctx, const ProbSpec& p, int s, const double* shad
             launch_apply<double>(op, (const double*)x, (double*)y, 1, tile, hs, gate);
         }
     };
+    // a round: step 0's direction, then for k >= 1 the update of step k-1
+    // fused with step k's direction, the last step's update on its own, and
+    // the dimension reduction
     auto round = [&]() {
         for (int k = 0; k < s; ++k) {
-            launch_idr(IDR_DIR, f32, a, k, hs);
+            launch_idr(k == 0 ? IDR_DIR : IDR_DIRUPD, f32, a, k, hs);
             apply(col(a.U, k), col(a.G, k));
             if (k > 0) launch_idr(IDR_ALPHA, f32, a, k, hs);
             launch_idr(IDR_ORTH, f32, a, k, hs);
-            launch_idr(IDR_UPD, f32, a, k, hs);
         }
+        launch_idr(IDR_UPD, f32, a, s - 1, hs);
         apply(a.r, a.t);
         launch_idr(IDR_OMEGA, f32, a, 0, hs);
         launch_idr(IDR_RED, f32, a, 0, hs);
