@@ -325,21 +325,6 @@ void launch_sub(const double* a, const double* b, double* c, long long n, hipStr
     hipLaunchKernelGGL(k_sub, dim3((int)nb), dim3(NT), 0, s, a, b, c, n);
 }
 
-// Damped Jacobi with a constant diagonal: z = s v (first sweep, from z = 0)
-// or z += s (v - Az), s = omega / d.
-__global__ __launch_bounds__(NT) void k_jacobi(double* __restrict__ z, const double* __restrict__ v,
-                                               const double* __restrict__ Az, double s, long long n, int first) {
-    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
-        z[i] = first ? s * v[i] : z[i] + s * (v[i] - Az[i]);
-}
-
-void launch_jacobi(double* z, const double* v, const double* Az, double s, long long n, int first, hipStream_t st) {
-    long long nb = (n + NT - 1) / NT;
-    if (nb > 4096) nb = 4096;
-    if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_jacobi, dim3((int)nb), dim3(NT), 0, st, z, v, Az, s, n, first);
-}
-
 // a += b over n values
 __global__ __launch_bounds__(NT) void k_add(double* __restrict__ a, const double* __restrict__ b, long long n) {
     for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) a[i] += b[i];

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "idr_shared.h"
+#include "mg_shared.h"
 #include "tgdk_shared.h"
 
 namespace tgdk {
@@ -84,12 +85,20 @@ void launch_gs_update_dot(const double* V, long long ldv, int p, double* w, cons
 void launch_gs_update_norm(const double* V, long long ldv, int p, double* w, const double* h, long long n,
                            double* nrm, double* partial, unsigned* counter, hipStream_t s);
 void launch_scale(const double* w, double* v, const double* nrm, long long n, hipStream_t s);
-// damped Jacobi, constant diagonal: z = s v (first) or z += s (v - Az), s = omega / d
-void launch_jacobi(double* z, const double* v, const double* Az, double s, long long n, int first, hipStream_t st);
 // a += b (n values)
 void launch_add(double* a, const double* b, long long n, hipStream_t st);
 // c = a - b (n values)
 void launch_sub(const double* a, const double* b, double* c, long long n, hipStream_t s);
+
+// multigrid (kernels_mg.hip): one pass over a level (mode: MG_FIRST ...
+// MG_RESID, optionally | MG_ACC; zc the coarser level's z for MG_PSWEEP),
+// the restricted residual of a level, and one V-cycle of the coarse tail in
+// one workgroup (P: the tail description in device memory)
+void launch_mg_pass(int dim, const MgLvl& L, const double* z, const double* v, const double* zc, double* out,
+                    int mode, hipStream_t s);
+void launch_mg_resid_restrict(int dim, const MgLvl& F, const double* z, const double* v, double* vc,
+                              hipStream_t s);
+void launch_mg_tail(int dim, const MgTail* P, const double* vin, double* out, int acc, hipStream_t s);
 // ||w|| -> *out (deterministic)
 void launch_norm2(const double* w, long long n, double* out, double* partial, unsigned* counter, hipStream_t s);
 

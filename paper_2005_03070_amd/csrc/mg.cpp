@@ -1,18 +1,25 @@
 // Geometric multigrid V-cycles for a constant-coefficient operator: the
 // preconditioner of Sec. 5, Example 5 (solutions with the positively shifted
 // Laplacian precondition the Helmholtz operator).  Levels are the operator's
-// grid and its rediscretised nested coarse grids down to sides of 1; damped
-// Jacobi smoothing (omega 4/5 in 2-D, 6/7 in 3-D) around a full-weighting /
-// linear-interpolation coarse correction; 20 sweeps on the coarsest grid.
-// The host walks the levels and enqueues the grid kernels; the
-// preconditioner is a fixed number of V-cycles from zero, a fixed linear
-// operator.  That kernel sequence (about 150 small launches per V-cycle on a
-// 511^2 grid, latency-bound) is captured once into a HIP graph on a private
-// stream and replayed on the context's stream; the caller's vectors are
-// copied in and out around it, so the graph only touches the object's own
+// grid and its rediscretised nested coarse grids while every side is odd and
+// at least 3; damped Jacobi smoothing (omega 4/5 in 2-D, 6/7 in 3-D) around a
+// full-weighting / linear-interpolation coarse correction; 20 sweeps on the
+// coarsest grid.  The preconditioner is a fixed number of V-cycles from zero,
+// a fixed linear operator.
+//
+// The host walks the fine levels and enqueues one kernel per pass (the first
+// two sweeps fused, the residual fused into the restriction, the coarse
+// correction fused into the first post-sweep: 4 passes per level with two
+// sweeps); the coarse tail of the hierarchy (the levels whose z, v and sweep
+// temporary fit in the LDS budget) is one single-workgroup launch
+// (kernels_mg.hip).  A 511^2 V-cycle is 17 launches.
+// The kernel sequence of one application is captured once into a HIP graph on
+// a private stream and replayed on the context's stream; the caller's vectors
+// are copied in and out around it, so the graph only touches the object's own
 // buffers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -21,11 +28,14 @@
 struct tgdk_mg_s {
     tgdk_ctx ctx = nullptr;
     std::vector<tgdk_op> ops;       // level 0: the caller's operator (not owned)
-    std::vector<double*> z, v, t;   // per level; t: A z, residual, prolongation scratch
+    std::vector<tgdk::MgLvl> lv;    // per level: sides, stencil, Jacobi factor
+    std::vector<double*> z, v, t;   // per level: z and t ping-pong, v the right-hand side
     double* acc = nullptr;          // level 0: the accumulated solution
     double* bin = nullptr;          // level 0: the right-hand side, copied in
     int cycles = 2, nu = 2;
     double omega = 0.8;
+    int tail = 0;                   // first level of the single-workgroup tail (ops.size(): none)
+    tgdk::MgTail* tail_dev = nullptr;
     int use_graph = 1;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -35,53 +45,80 @@ namespace tgdk {
 
 constexpr int MG_COARSEST_SWEEPS = 20;
 
-// One V-cycle for A_l z_l = vin (vin: v_l, or the input on level 0).
-static void vcycle(tgdk_mg mg, int l, const double* vin, hipStream_t s) {
-    tgdk_op op = mg->ops[l];
-    const DevOp d = make_devop(op, 0);
-    const long long n = op->N;
-    const double sc = mg->omega / op->cc[0];
-    double *z = mg->z[l], *t = mg->t[l];
-    const double* v = vin;
-    auto sweeps = [&](int count, bool from_zero) {
-        for (int i = 0; i < count; ++i) {
-            if (from_zero && i == 0) {
-                launch_jacobi(z, v, nullptr, sc, n, 1, s);
-            } else {
-                launch_apply<double>(d, z, t, 1, op->tile_id[0], s);
-                launch_jacobi(z, v, t, sc, n, 0, s);
-            }
-        }
-    };
-    if (l + 1 == (int)mg->ops.size()) {
-        sweeps(MG_COARSEST_SWEEPS, true);
-        return;
+// One V-cycle for A_l z_l = v from z = 0.  Returns the buffer holding z_l;
+// with dst set (level 0) the last pass writes dst instead (added to it if
+// acc).
+static const double* vcycle(tgdk_mg mg, int l, const double* v, double* dst, int acc, hipStream_t s) {
+    const int dim = mg->ops[0]->dim;
+    if (l == mg->tail) {
+        double* out = dst ? dst : mg->z[l];
+        launch_mg_tail(dim, mg->tail_dev, v, out, dst ? acc : 0, s);
+        return out;
     }
-    tgdk_op c = mg->ops[l + 1];
-    const int cz = op->dim == 3 ? c->n[2] : 1;
-    sweeps(mg->nu, true);
-    launch_apply<double>(d, z, t, 1, op->tile_id[0], s);
-    launch_sub(v, t, t, n, s);
-    launch_restrict(op->dim, c->n[0], c->n[1], cz, t, mg->v[l + 1], 1, s);
-    vcycle(mg, l + 1, mg->v[l + 1], s);
-    launch_prolong(op->dim, c->n[0], c->n[1], cz, mg->z[l + 1], t, 1, s);
-    launch_add(z, t, n, s);
-    sweeps(mg->nu, false);
+    const MgLvl& L = mg->lv[l];
+    double *a = mg->z[l], *b = mg->t[l];
+    // count sweeps, from z = 0 (start null: the first two fused) or after the
+    // coarse correction (zc set: the first one fused with it), ping-ponging
+    // between a and b
+    auto smooth = [&](int count, const double* start, const double* zc, bool last_to_dst) {
+        const double* cur = start;
+        const int passes = !start && count >= 2 ? count - 1 : count;
+        for (int i = 0; i < passes; ++i) {
+            const bool fin = last_to_dst && dst && i == passes - 1;
+            double* o = fin ? dst : (cur == a ? b : a);
+            int mode = MG_SWEEP;
+            if (i == 0 && !start) mode = count >= 2 ? MG_FIRST2 : MG_FIRST;
+            if (i == 0 && zc) mode = MG_PSWEEP;
+            if (fin && acc) mode |= MG_ACC;
+            launch_mg_pass(dim, L, cur, v, i == 0 ? zc : nullptr, o, mode, s);
+            cur = o;
+        }
+        return cur;
+    };
+    if (l + 1 == (int)mg->ops.size()) return smooth(MG_COARSEST_SWEEPS, nullptr, nullptr, true);
+    const double* zs = smooth(mg->nu, nullptr, nullptr, false);
+    launch_mg_resid_restrict(dim, L, zs, v, mg->v[l + 1], s);
+    const double* zc = vcycle(mg, l + 1, mg->v[l + 1], nullptr, 0, s);
+    return smooth(mg->nu, zs, zc, true);
 }
 
 // The whole preconditioner on bin -> acc: z_1 = V(b), z_(c+1) = z_c + V(b - A z_c).
 static void mg_body(tgdk_mg mg, hipStream_t s) {
-    tgdk_op op = mg->ops[0];
-    const DevOp d = make_devop(op, 0);
-    const long long n = op->N;
-    vcycle(mg, 0, mg->bin, s);
-    launch_copy(mg->z[0], mg->acc, n, s);
+    vcycle(mg, 0, mg->bin, mg->acc, 0, s);
     for (int c = 1; c < mg->cycles; ++c) {
-        launch_apply<double>(d, mg->acc, mg->t[0], 1, op->tile_id[0], s);
-        launch_sub(mg->bin, mg->t[0], mg->v[0], n, s);
-        vcycle(mg, 0, mg->v[0], s);
-        launch_add(mg->acc, mg->z[0], n, s);
+        launch_mg_pass(mg->ops[0]->dim, mg->lv[0], mg->acc, mg->bin, nullptr, mg->v[0], MG_RESID, s);
+        vcycle(mg, 0, mg->v[0], mg->acc, 1, s);
     }
+}
+
+// The tail: the longest run of coarsest levels (at most MG_TAIL_MAXLEV)
+// whose z, v and sweep temporary fit in MG_TAIL_LDS doubles.
+static int plan_tail(tgdk_mg mg, MgTail& P) {
+    const int L = (int)mg->ops.size();
+    int first = L;
+    long long used = 0;
+    for (int l = L - 1; l >= 0 && L - l <= MG_TAIL_MAXLEV; --l) {
+        used += 3 * mg->ops[l]->N;
+        if (used > MG_TAIL_LDS) break;
+        first = l;
+    }
+    P = MgTail{};
+    P.dim = mg->ops[0]->dim;
+    P.nlev = L - first;
+    P.nu = mg->nu;
+    P.coarsest_sweeps = MG_COARSEST_SWEEPS;
+    P.wave_from = P.nlev;
+    for (int l = L - 1; l >= first && mg->ops[l]->N <= 64; --l) P.wave_from = l - first;
+    int off = 0;
+    for (int l = first; l < L; ++l) {
+        const int n = (int)mg->ops[l]->N;
+        P.lv[l - first] = mg->lv[l];
+        P.zoff[l - first] = off;
+        P.voff[l - first] = off + n;
+        P.toff[l - first] = off + 2 * n;
+        off += 3 * n;
+    }
+    return first;
 }
 
 // Captures mg_body into a graph on a private stream (once per object).
@@ -148,6 +185,30 @@ int tgdk_mg_create(tgdk_op op, int cycles, int nu, int flags, tgdk_mg* out) {
             mg->bin = p + 4 * n;
         }
     }
+    for (size_t l = 0; l < mg->ops.size() && !rc; ++l) {
+        tgdk_op o = mg->ops[l];
+        if (o->N > (1LL << 30)) {
+            rc = fail(TGDK_E_INVALID, "multigrid grids are limited to 2^30 points");
+            break;
+        }
+        MgLvl L{};
+        L.nx = (int)o->n[0];
+        L.ny = (int)o->n[1];
+        L.nz = o->dim == 3 ? (int)o->n[2] : 1;
+        for (int i = 0; i < 2 * o->dim + 1; ++i) L.cc[i] = o->cc[i];
+        L.sc = mg->omega / o->cc[0];
+        mg->lv.push_back(L);
+    }
+    if (!rc) {
+        MgTail P;
+        mg->tail = plan_tail(mg, P);
+        if (mg->tail < (int)mg->ops.size()) {
+            if (hipMalloc((void**)&mg->tail_dev, sizeof(MgTail)) != hipSuccess)
+                rc = fail(TGDK_E_NOMEM, "multigrid tail allocation failed");
+            else if (hipMemcpy(mg->tail_dev, &P, sizeof(MgTail), hipMemcpyHostToDevice) != hipSuccess)
+                rc = fail(TGDK_E_HIP, "multigrid tail upload failed");
+        }
+    }
     if (rc) {
         tgdk_mg_destroy(mg);
         return rc;
@@ -188,6 +249,7 @@ int tgdk_mg_destroy(tgdk_mg mg) {
     if (mg->exec) (void)hipGraphExecDestroy(mg->exec);
     if (mg->graph) (void)hipGraphDestroy(mg->graph);
     for (double* p : mg->z) (void)hipFree(p);  // one allocation per level
+    if (mg->tail_dev) (void)hipFree(mg->tail_dev);
     for (size_t l = 1; l < mg->ops.size(); ++l) tgdk_op_destroy(mg->ops[l]);
     delete mg;
     return TGDK_OK;

@@ -30,8 +30,16 @@ def _t(a, dtype=torch.float64):
     return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
 
 
+# grids whose coarse tail runs in one workgroup from level 1 (63^2, 15^3,
+# 31 x 15 x 7 with an odd sweep count), from level 0 (31^2: the whole
+# hierarchy; 7^2: every level small enough for the single-wave passes), after
+# a non-square fine level (65 x 33 -> 32 x 16, no single-wave levels), and
+# not at all (64^2: one level, too large for the tail, 20 sweeps as global
+# passes)
 @pytest.mark.parametrize("dims,sigma,cycles,nu", [((63, 63), 400.0, 2, 2), ((31, 31), 900.0, 1, 1),
-                                                  ((15, 15, 15), 100.0, 3, 2)])
+                                                  ((15, 15, 15), 100.0, 3, 2), ((31, 15, 7), 50.0, 2, 3),
+                                                  ((65, 33), 400.0, 2, 1), ((64, 64), 300.0, 2, 2),
+                                                  ((7, 7), 100.0, 2, 2)])
 def test_multigrid_matches_oracle(dims, sigma, cycles, nu):
     oop = O.const_cd(dims, (0.0,) * len(dims), sigma=sigma)
     ops = MG.levels(oop)
