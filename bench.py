@@ -42,8 +42,10 @@ def _args():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--solve-only", action="store_true",
                     help="setup, warm-up and timed solves only (for hardware-counter runs)")
-    ap.add_argument("--workload", choices=("2d", "3d"), default="2d",
-                    help="with --solve-only: 2d = 1023^2 FP64 (the headline), 3d = 255^3 FP32 inner + FP64 refinement")
+    ap.add_argument("--workload", choices=("2d", "3d", "mg"), default="2d",
+                    help="with --solve-only: 2d = 1023^2 FP64 (the headline), 3d = 255^3 FP32 inner + FP64 "
+                         "refinement, mg = the multigrid preconditioner of the kappa = 100 Helmholtz workload "
+                         "alone (--steps applications)")
     ap.add_argument("--method", choices=("bicgstab", "idr"), default="bicgstab",
                     help="with --solve-only --workload 2d: the inner solver (idr = IDR(4), FP64)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -107,6 +109,24 @@ def main():
         torch.cuda.synchronize()
         log(f"255^3 fp32_ir: {(time.perf_counter() - t0) / a.steps * 1e3:.1f} ms/solve, mvps {r3[0].mvp_inner}, "
             f"relres {r3[0].relres_true:.2e}")
+        return
+
+    if a.solve_only and a.workload == "mg":
+        import paper_2005_03070_amd as tg
+        import workloads as W
+        c5 = W.CONFIGS["H2"]
+        shifted = tg.Operator.const_cd(c5["n"], c5["beta"], sigma=-c5["sigma"])
+        mg = tg.Multigrid(shifted, cycles=c5["mg_cycles"], nu=c5["mg_nu"])
+        b5 = torch.tensor(W.rhs(shifted.n, c5["seed"]), device="cuda:0")
+        for _ in range(a.warmup):
+            mg.apply(b5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            mg.apply(b5)
+        torch.cuda.synchronize()
+        log(f"multigrid {c5['n'][0]}^2, {mg.levels} levels, {c5['mg_cycles']} V-cycles: "
+            f"{(time.perf_counter() - t0) / a.steps * 1e3:.3f} ms per application")
         return
 
     if a.copy_calibration:
