@@ -1,7 +1,8 @@
 """Edge cases of the solvers on the GPU through the C-ABI: degenerate grids
 (1 x 1, 3 x 1, 1 x 5, 1 x 1 x 1), an exact initial guess, the largest
-deflation space (63 vectors) with the longest GMRES cycle (128), and IDR(s)
-with a zero or non-finite right-hand side."""
+deflation space (63 vectors) with the longest GMRES cycle (128), a GMRES
+cycle longer than the system, and IDR(s) with a zero or non-finite
+right-hand side."""
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spl
@@ -79,6 +80,21 @@ def test_largest_space_and_longest_gmres_cycle():
         assert np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs) <= 1e-7
     with pytest.raises(tg()._lib.TgdkError):
         tg().defl_from_basis(op, _t(W.rng(9).standard_normal((65, oop.n))))
+
+
+def test_gmres_cycle_longer_than_the_system():
+    """GMRES(40) on a 5 x 5 grid (n = 25): the Krylov space fills the whole
+    space within the first cycle, the later steps orthogonalise a remainder at
+    rounding level (the cycle stops early only at an exact zero), and the
+    least-squares solution is still the direct solution."""
+    dims, beta = (5, 5), (10.0, 5.0)
+    oop = O.const_cd(dims, beta)
+    b = W.rhs(oop.n, 5)
+    xs = spl.spsolve(O.to_csr(oop).tocsc(), b)
+    op = tg().Operator.const_cd(dims, beta)
+    x, reps = tg().solve(op, _t(b), method="gmres", m3=40, rtol=1e-12)
+    assert reps[0].status == 0
+    assert np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs) <= 1e-10
 
 
 def test_idr_zero_and_nonfinite_rhs():

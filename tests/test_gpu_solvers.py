@@ -174,14 +174,18 @@ def test_gmres_proj_matches_oracle():
     assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-7
 
 
-def test_gmres_first_cycle_equals_oracle_cycle():
-    """One GMRES(20) cycle (CGS2 on the GPU, MGS2 in the oracle) gives the same
+# one cycle runs every basis width p = 1 .. m + 1 through the Gram-Schmidt
+# passes: m = 128 covers 1 to 32 columns per wave and the chunked kernel
+# beyond 128 columns; n = 1457 is not a multiple of the 64-row blocks
+@pytest.mark.parametrize("m", [20, 64, 128])
+def test_gmres_first_cycle_equals_oracle_cycle(m):
+    """One GMRES(m) cycle (CGS2 on the GPU, MGS2 in the oracle) gives the same
     iterate to rounding."""
     oop = O.const_cd((47, 31), (30.0, 10.0))
     b = W.rhs(oop.n, 12)
     op = tg().Operator.const_cd((47, 31), (30.0, 10.0))
-    x, reps = tg().solve(op, _t(b), method="gmres", m3=20, rtol=1e-30, max_extra=1)
-    xo, _ = OG.gmres_proj(oop, b, rtol=1e-30, m=20, maxcyc=1)
+    x, reps = tg().solve(op, _t(b), method="gmres", m3=m, rtol=1e-30, max_extra=1)
+    xo, _ = OG.gmres_proj(oop, b, rtol=1e-30, m=m, maxcyc=1)
     assert reps[0].status == 1  # not converged after the single allowed cycle
     assert np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo) <= 1e-10
 
