@@ -32,7 +32,6 @@
 namespace tgdk {
 
 constexpr int IDR_BLOCKS = 1024;  // cap on the workgroups of the vector kernels
-constexpr int IDR_CH = 8;         // products with P accumulated per pass
 static_assert(IDR_BLOCKS % 64 == 0, "the epilogue gives every lane IDR_BLOCKS / 64 partials");
 
 int idr_blocks(long long n) {
@@ -42,42 +41,52 @@ int idr_blocks(long long n) {
 
 // Per-workgroup sums of P_j . y (j in [0, s)) and, with SELF, y . y as value
 // s, written to part.  y(i, first) returns entry i of y; first is true on
-// the first pass only (where y may be formed and stored).  Columns beyond
-// IDR_CH take further passes that read y back.
-template <class TI, bool SELF, class Y>
+// the first pass only (where y may be formed and stored).  A pass takes CH
+// columns of P (CH = s up to 8: the launcher picks 1, 2, 4 or 8); columns
+// beyond CH take further passes that read y back.  Every column load of a
+// pass is issued unconditionally (a column past s re-reads the pass's first
+// column, a cache hit, and is masked), so a row's loads are all in flight
+// together: a guarded load compiles to a branch that waits at its join.
+template <class TI, bool SELF, int CH, class Y>
 __device__ __forceinline__ void dots_with_P(const IdrArgs& a, Y&& y) {
-    __shared__ double sh[NWAVE * (IDR_CH + 1)];
+    __shared__ double sh[NWAVE * (CH + 1)];
     const TI* __restrict__ P = vp<TI>(a.P);
     const long long n = a.n;
     const long long stride = (long long)gridDim.x * NT;
     const long long i0 = (long long)blockIdx.x * NT + threadIdx.x;
-    for (int c0 = 0; c0 < a.s; c0 += IDR_CH) {
+    for (int c0 = 0; c0 < a.s; c0 += CH) {
         const bool first = c0 == 0;
-        double acc[IDR_CH + 1];
+        double acc[CH + 1];
 #pragma unroll
-        for (int j = 0; j <= IDR_CH; ++j) acc[j] = 0.0;
-        const int nc = min(IDR_CH, a.s - c0);
+        for (int j = 0; j <= CH; ++j) acc[j] = 0.0;
+        const int nc = min(CH, a.s - c0);
+        const TI* Pc[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) Pc[j] = P + (long long)(c0 + (j < nc ? j : 0)) * n;
 #pragma unroll 2
         for (long long i = i0; i < n; i += stride) {
             const double yv = y(i, first);
 #pragma unroll
-            for (int j = 0; j < IDR_CH; ++j)
-                if (j < nc) acc[j] += (double)P[(long long)(c0 + j) * n + i] * yv;
-            if (SELF && first) acc[IDR_CH] += yv * yv;
+            for (int j = 0; j < CH; ++j) {
+                // the mask on the factor keeps the multiply-add fused
+                const double pv = (double)Pc[j][i];
+                acc[j] += (j < nc ? pv : 0.0) * yv;
+            }
+            if (SELF && first) acc[CH] += yv * yv;
         }
         double tot;
-        block_sum<IDR_CH + 1>(acc, sh, tot);
+        block_sum<CH + 1>(acc, sh, tot);
         if (threadIdx.x < nc) a.part[(long long)(c0 + threadIdx.x) * a.nb + blockIdx.x] = tot;
-        if (SELF && first && threadIdx.x == IDR_CH) a.part[(long long)a.s * a.nb + blockIdx.x] = tot;
+        if (SELF && first && threadIdx.x == CH) a.part[(long long)a.s * a.nb + blockIdx.x] = tot;
     }
 }
 
 // Cycle start: f = P^T r, r . r (values 0..s-1, s).
-template <class TI>
+template <class TI, int CH>
 __global__ __launch_bounds__(NT) void k_idr_start(IdrArgs a) {
     if (a.ss->solve_state != SV_RUNNING) return;
     const TI* __restrict__ r = vp<TI>(a.r);
-    dots_with_P<TI, true>(a, [&](long long i, bool) { return (double)r[i]; });
+    dots_with_P<TI, true, CH>(a, [&](long long i, bool) { return (double)r[i]; });
 }
 
 // Direction of step k: u_k = U_(k:) c + omega (r - G_(k:) c); in the first
@@ -165,15 +174,17 @@ __global__ __launch_bounds__(NT) void k_idr_dirupd(IdrArgs a, int k) {
 }
 
 // m = P^T g_k before the orthogonalisation (k > 0).
-template <class TI>
+template <class TI, int CH>
 __global__ __launch_bounds__(NT) void k_idr_gdot(IdrArgs a, int k) {
     if (a.st->gate) return;
     const TI* __restrict__ g = vp<TI>(a.G) + (long long)k * a.n;
-    dots_with_P<TI, false>(a, [&](long long i, bool) { return (double)g[i]; });
+    dots_with_P<TI, false, CH>(a, [&](long long i, bool) { return (double)g[i]; });
 }
 
 // g_k -= G_(:k) alpha, u_k -= U_(:k) alpha, then P^T g_k (values 0..s-1).
-template <class TI>
+// The columns of G and U are taken CH at a time with unconditional loads (a
+// column past k re-reads column 0 and is masked: 0 * G adds an exact zero).
+template <class TI, int CH>
 __global__ __launch_bounds__(NT) void k_idr_orth(IdrArgs a, int k) {
     __shared__ double al[IDR_SMAX];
     const IdrState* st = a.st;
@@ -185,12 +196,19 @@ __global__ __launch_bounds__(NT) void k_idr_orth(IdrArgs a, int k) {
     const long long n = a.n;
     TI* g = G + (long long)k * n;
     TI* u = U + (long long)k * n;
-    dots_with_P<TI, false>(a, [&](long long i, bool first) {
+    dots_with_P<TI, false, CH>(a, [&](long long i, bool first) {
         if (!first || k == 0) return (double)g[i];
         double gs = (double)g[i], us = (double)u[i];
-        for (int j = 0; j < k; ++j) {
-            gs -= al[j] * (double)G[(long long)j * n + i];
-            us -= al[j] * (double)U[(long long)j * n + i];
+        for (int j0 = 0; j0 < k; j0 += CH) {
+#pragma unroll
+            for (int jj = 0; jj < CH; ++jj) {
+                const int j = j0 + jj;
+                const int jc = j < k ? j : 0;
+                const double gv = (double)G[(long long)jc * n + i], uv = (double)U[(long long)jc * n + i];
+                const double aj = j < k ? al[jc] : 0.0;
+                gs -= aj * gv;
+                us -= aj * uv;
+            }
         }
         const TI gt = (TI)gs;
         g[i] = gt;
@@ -249,7 +267,7 @@ __global__ __launch_bounds__(NT) void k_idr_tdot(IdrArgs a) {
 
 // Dimension reduction, second half: e += omega r, r -= omega t; then
 // f = P^T r, r . r (values 0..s-1, s) for the next round.
-template <class TI>
+template <class TI, int CH>
 __global__ __launch_bounds__(NT) void k_idr_red(IdrArgs a) {
     const IdrState* st = a.st;
     if (st->gate) return;
@@ -258,7 +276,7 @@ __global__ __launch_bounds__(NT) void k_idr_red(IdrArgs a) {
     const TI* __restrict__ t = vp<TI>(a.t);
     const double om = st->om;
     const bool efirst = st->efirst;
-    dots_with_P<TI, true>(a, [&](long long i, bool first) {
+    dots_with_P<TI, true, CH>(a, [&](long long i, bool first) {
         if (!first) return (double)r[i];
         const double rv = (double)r[i];
         e[i] = efirst ? (TI)(om * rv) : (TI)((double)e[i] + om * rv);
@@ -526,26 +544,26 @@ __global__ __launch_bounds__(NT) void k_idr_epi(IdrArgs a, int which, int k, int
 }
 
 // ------------------------------------------------------------- launchers
-template <class TI>
-static void idr_launch_t(int what, const IdrArgs& a, int k, hipStream_t s) {
+template <class TI, int CH>
+static void idr_launch_ch(int what, const IdrArgs& a, int k, hipStream_t s) {
     const dim3 grid(a.nb), block(NT);
     switch (what) {
         case IDR_START:
-            hipLaunchKernelGGL(k_idr_start<TI>, grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_idr_start<TI, CH>), grid, block, 0, s, a);
             hipLaunchKernelGGL(k_idr_epi, dim3(1), block, 0, s, a, (int)E_START, 0, a.s + 1);
             break;
         case IDR_DIR:
             hipLaunchKernelGGL(k_idr_dir<TI>, grid, block, 0, s, a, k);
             break;
         case IDR_ALPHA:
-            hipLaunchKernelGGL(k_idr_gdot<TI>, grid, block, 0, s, a, k);
+            hipLaunchKernelGGL((k_idr_gdot<TI, CH>), grid, block, 0, s, a, k);
             hipLaunchKernelGGL(k_idr_epi, dim3(1), block, 0, s, a, (int)E_ALPHA, k, a.s + 1);
             break;
         case IDR_DIRUPD:
             hipLaunchKernelGGL(k_idr_dirupd<TI>, grid, block, 0, s, a, k);
             break;
         case IDR_ORTH:
-            hipLaunchKernelGGL(k_idr_orth<TI>, grid, block, 0, s, a, k);
+            hipLaunchKernelGGL((k_idr_orth<TI, CH>), grid, block, 0, s, a, k);
             hipLaunchKernelGGL(k_idr_epi, dim3(1), block, 0, s, a, (int)E_M, k, a.s);
             break;
         case IDR_UPD:
@@ -557,13 +575,26 @@ static void idr_launch_t(int what, const IdrArgs& a, int k, hipStream_t s) {
             hipLaunchKernelGGL(k_idr_epi, dim3(1), block, 0, s, a, (int)E_OM, 0, 3);
             break;
         case IDR_RED:
-            hipLaunchKernelGGL(k_idr_red<TI>, grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_idr_red<TI, CH>), grid, block, 0, s, a);
             hipLaunchKernelGGL(k_idr_epi, dim3(1), block, 0, s, a, (int)E_RED, 0, a.s + 1);
             break;
         case IDR_FOLD:
             hipLaunchKernelGGL(k_idr_fold<TI>, grid, block, 0, s, a);
             break;
     }
+}
+
+// the column chunk of the products with P: s columns up to 8 in one pass
+template <class TI>
+static void idr_launch_t(int what, const IdrArgs& a, int k, hipStream_t s) {
+    if (a.s <= 1)
+        idr_launch_ch<TI, 1>(what, a, k, s);
+    else if (a.s <= 2)
+        idr_launch_ch<TI, 2>(what, a, k, s);
+    else if (a.s <= 4)
+        idr_launch_ch<TI, 4>(what, a, k, s);
+    else
+        idr_launch_ch<TI, 8>(what, a, k, s);
 }
 
 void launch_idr(int what, int inner_f32, const IdrArgs& a, int k, hipStream_t s) {
