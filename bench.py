@@ -46,8 +46,9 @@ def _args():
                     help="with --solve-only: 2d = 1023^2 FP64 (the headline), 3d = 255^3 FP32 inner + FP64 "
                          "refinement, mg = the multigrid preconditioner of the kappa = 100 Helmholtz workload "
                          "alone (--steps applications)")
-    ap.add_argument("--method", choices=("bicgstab", "idr"), default="bicgstab",
-                    help="with --solve-only --workload 2d: the inner solver (idr = IDR(4), FP64)")
+    ap.add_argument("--method", choices=("bicgstab", "idr", "gmres"), default="bicgstab",
+                    help="with --solve-only --workload 2d: the fine solver (idr = IDR(4), gmres = GMRES(50); "
+                         "FP64)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB device buffer three times (counter scale of a plain copy)")
     return ap.parse_args()
@@ -182,6 +183,19 @@ def main():
         dt = (time.perf_counter() - t0) / a.steps
         log(f"fp64 IDR(4)(20)-Proj(30): {dt*1e3:.1f} ms/solve, mvps {ri.mvp_inner}, cycles {ri.cycles}, "
             f"relres {ri.relres_true:.2e}, {dt*1e6/max(ri.mvp_inner, 1):.1f} us per inner mvp")
+        return
+
+    if a.solve_only and a.method == "gmres":
+        for _ in range(a.warmup):
+            fine_solve(method="gmres", m3=c["m3"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            xg, rg = fine_solve(method="gmres", m3=c["m3"])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.steps
+        log(f"fp64 GMRES(50)-Proj(30): {dt*1e3:.1f} ms/solve, mvps {rg[0].mvp_inner}, cycles {rg[0].cycles}, "
+            f"relres {rg[0].relres_true:.2e}, {dt*1e6/max(rg[0].mvp_inner, 1):.1f} us per inner mvp")
         return
 
     def true_relres(x):
