@@ -272,21 +272,22 @@ __global__ __launch_bounds__(NT) void k_gs(const double* __restrict__ V, long lo
     (void)hout;
 }
 
-// The same passes with the columns split over the waves, for p <= 4 CPW:
-// wave w of a workgroup holds columns w, w + 4, ..., w + 4 (CPW - 1) of a
-// 64-row block (64 consecutive rows per column load), so every pass reads V
-// once and the row loop has no per-chunk reductions.  The update w -= V h of
-// a row needs all columns: the waves exchange their partial sums of V h
-// through LDS (double-buffered, one barrier per row block) and every wave
-// forms the same updated rows (wave 0 stores them), whose dot products then
-// use the V values already in registers.  The next row block's loads are
-// issued before the barrier, which does not wait for them.  Columns past p
-// are read at column 0 (a cache hit) and masked.
-template <int MODE, int CPW, bool PREF>
-__global__ __launch_bounds__(NT) void k_gsc(const double* __restrict__ V, long long ldv, int p, double* w,
-                                            const double* __restrict__ h, long long n,
-                                            double* __restrict__ partial) {
-    __shared__ double xs[2][NWAVE][64];
+// The same passes with the columns split over the waves, for p <= NW CPW
+// (NW waves of 64 threads per workgroup): wave w holds columns w, w + NW, ...,
+// w + NW (CPW - 1) of a 64-row block (64 consecutive rows per column load),
+// so every pass reads V once and the row loop has no per-chunk reductions.
+// The update w -= V h of a row needs all columns: the waves exchange their
+// partial sums of V h through LDS (double-buffered, one barrier per row
+// block; summed over the waves in order) and every wave forms the same
+// updated rows (wave 0 stores them), whose dot products then use the V values
+// already in registers.  The next row block's loads are issued before the
+// barrier, which does not wait for them.  Columns past p are read at column 0
+// (a cache hit) and masked.
+template <int MODE, int CPW, int NW>
+__global__ __launch_bounds__(64 * NW) void k_gsc(const double* __restrict__ V, long long ldv, int p, double* w,
+                                                 const double* __restrict__ h, long long n,
+                                                 double* __restrict__ partial) {
+    __shared__ double xs[2][NW][64];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const double* vc[CPW];
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(NT) void k_gsc(const double* __restrict__ V, long l
     bool cok[CPW];
 #pragma unroll
     for (int i = 0; i < CPW; ++i) {
-        const int c = wv + NWAVE * i;
+        const int c = wv + NW * i;
         cok[i] = c < p;
         vc[i] = V + (long long)(cok[i] ? c : 0) * ldv;
         hc[i] = (MODE >= 1 && cok[i]) ? h[c] : 0.0;
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(NT) void k_gsc(const double* __restrict__ V, long l
         double nv[CPW], nw = 0.0;
 #pragma unroll
         for (int i = 0; i < CPW; ++i) nv[i] = 0.0;
-        if (PREF && rb + step < nrb) load(rb + step, nv, nw);
+        if (rb + step < nrb) load(rb + step, nv, nw);
         const long long row = rb * 64 + lane;
         const bool ok = row < n;
         double x = wr;
@@ -331,7 +332,9 @@ __global__ __launch_bounds__(NT) void k_gsc(const double* __restrict__ V, long l
             for (int i = 0; i < CPW; ++i) u += cok[i] ? vv[i] * hc[i] : 0.0;
             xs[par][wv][lane] = u;
             __syncthreads();
-            const double t = ((xs[par][0][lane] + xs[par][1][lane]) + xs[par][2][lane]) + xs[par][3][lane];
+            double t = xs[par][0][lane];
+#pragma unroll
+            for (int q = 1; q < NW; ++q) t += xs[par][q][lane];
             x = wr - t;
             if (wv == 0 && ok) w[row] = x;
             par ^= 1;
@@ -342,20 +345,16 @@ __global__ __launch_bounds__(NT) void k_gsc(const double* __restrict__ V, long l
         } else if (wv == 0) {
             nacc += ok ? x * x : 0.0;
         }
-        if (PREF) {
 #pragma unroll
-            for (int i = 0; i < CPW; ++i) vv[i] = nv[i];
-            wr = nw;
-        } else if (rb + step < nrb) {
-            load(rb + step, vv, wr);
-        }
+        for (int i = 0; i < CPW; ++i) vv[i] = nv[i];
+        wr = nw;
     }
     const long long pstride = MAXK + 1;
     if (MODE <= 1) {
 #pragma unroll
         for (int i = 0; i < CPW; ++i) {
             const double t = wave_sum(acc[i]);
-            if (lane == 0 && cok[i]) partial[(long long)blockIdx.x * pstride + wv + NWAVE * i] = t;
+            if (lane == 0 && cok[i]) partial[(long long)blockIdx.x * pstride + wv + NW * i] = t;
         }
     } else if (wv == 0) {
         const double t = wave_sum(nacc);
@@ -363,48 +362,57 @@ __global__ __launch_bounds__(NT) void k_gsc(const double* __restrict__ V, long l
     }
 }
 
-// k_gsc for 1 <= p <= 4 * 32 (columns per wave 1 ... 32; the widest
-// without the next block's loads in flight, for registers); false if p is
-// out of that range
+// k_gsc for 1 <= p <= 128: 4 waves with 1 ... 16 columns each up to 64
+// columns; beyond, 8 waves with 16 each in half as many workgroups (the same
+// threads).  Returns the number of workgroups (of partials) launched, or 0 if
+// p is out of range.
 template <int MODE>
-static bool launch_gsc(const double* V, long long ldv, int p, double* w, const double* h, long long n,
-                       double* partial, int nb, hipStream_t s) {
-    if (p < 1 || p > NWAVE * 32) return false;
-    const dim3 g(nb), b(NT);
-    if (p <= NWAVE)
-        hipLaunchKernelGGL((k_gsc<MODE, 1, true>), g, b, 0, s, V, ldv, p, w, h, n, partial);
-    else if (p <= 2 * NWAVE)
-        hipLaunchKernelGGL((k_gsc<MODE, 2, true>), g, b, 0, s, V, ldv, p, w, h, n, partial);
-    else if (p <= 4 * NWAVE)
-        hipLaunchKernelGGL((k_gsc<MODE, 4, true>), g, b, 0, s, V, ldv, p, w, h, n, partial);
-    else if (p <= 8 * NWAVE)
-        hipLaunchKernelGGL((k_gsc<MODE, 8, true>), g, b, 0, s, V, ldv, p, w, h, n, partial);
-    else if (p <= 16 * NWAVE)
-        hipLaunchKernelGGL((k_gsc<MODE, 16, true>), g, b, 0, s, V, ldv, p, w, h, n, partial);
-    else
-        hipLaunchKernelGGL((k_gsc<MODE, 32, false>), g, b, 0, s, V, ldv, p, w, h, n, partial);
-    return true;
+static int launch_gsc(const double* V, long long ldv, int p, double* w, const double* h, long long n,
+                      double* partial, int nb, hipStream_t s) {
+    if (p < 1 || p > 8 * 16) return 0;
+    const dim3 g(nb), b4(256);
+    if (p <= 4)
+        hipLaunchKernelGGL((k_gsc<MODE, 1, 4>), g, b4, 0, s, V, ldv, p, w, h, n, partial);
+    else if (p <= 8)
+        hipLaunchKernelGGL((k_gsc<MODE, 2, 4>), g, b4, 0, s, V, ldv, p, w, h, n, partial);
+    else if (p <= 16)
+        hipLaunchKernelGGL((k_gsc<MODE, 4, 4>), g, b4, 0, s, V, ldv, p, w, h, n, partial);
+    else if (p <= 32)
+        hipLaunchKernelGGL((k_gsc<MODE, 8, 4>), g, b4, 0, s, V, ldv, p, w, h, n, partial);
+    else if (p <= 64)
+        hipLaunchKernelGGL((k_gsc<MODE, 16, 4>), g, b4, 0, s, V, ldv, p, w, h, n, partial);
+    else {
+        nb = nb > 1 ? nb / 2 : 1;
+        hipLaunchKernelGGL((k_gsc<MODE, 16, 8>), dim3(nb), dim3(512), 0, s, V, ldv, p, w, h, n, partial);
+    }
+    return nb;
 }
 
 void launch_gs_dot(const double* V, long long ldv, int p, const double* w, long long n, double* hout,
                    double* partial, unsigned* counter, hipStream_t s) {
-    const int nb = gs_blocks(n);
-    if (!launch_gsc<0>(V, ldv, p, const_cast<double*>(w), nullptr, n, partial, nb, s))
+    int nb = gs_blocks(n);
+    if (const int used = launch_gsc<0>(V, ldv, p, const_cast<double*>(w), nullptr, n, partial, nb, s))
+        nb = used;
+    else
         hipLaunchKernelGGL((k_gs<0>), dim3(nb), dim3(NT), 0, s, V, ldv, p, const_cast<double*>(w),
                            (const double*)nullptr, n, hout, partial, counter);
     if (p > 0) hipLaunchKernelGGL(k_sum_partials, dim3(p), dim3(NT), 0, s, partial, nb, (long long)(MAXK + 1), hout, 0);
 }
 void launch_gs_update_dot(const double* V, long long ldv, int p, double* w, const double* h, long long n,
                           double* hout, double* partial, unsigned* counter, hipStream_t s) {
-    const int nb = gs_blocks(n);
-    if (!launch_gsc<1>(V, ldv, p, w, h, n, partial, nb, s))
+    int nb = gs_blocks(n);
+    if (const int used = launch_gsc<1>(V, ldv, p, w, h, n, partial, nb, s))
+        nb = used;
+    else
         hipLaunchKernelGGL((k_gs<1>), dim3(nb), dim3(NT), 0, s, V, ldv, p, w, h, n, hout, partial, counter);
     if (p > 0) hipLaunchKernelGGL(k_sum_partials, dim3(p), dim3(NT), 0, s, partial, nb, (long long)(MAXK + 1), hout, 0);
 }
 void launch_gs_update_norm(const double* V, long long ldv, int p, double* w, const double* h, long long n,
                            double* nrm, double* partial, unsigned* counter, hipStream_t s) {
-    const int nb = gs_blocks(n);
-    if (!launch_gsc<2>(V, ldv, p, w, h, n, partial, nb, s))
+    int nb = gs_blocks(n);
+    if (const int used = launch_gsc<2>(V, ldv, p, w, h, n, partial, nb, s))
+        nb = used;
+    else
         hipLaunchKernelGGL((k_gs<2>), dim3(nb), dim3(NT), 0, s, V, ldv, p, w, h, n, nrm, partial, counter);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(NT), 0, s, partial, nb, (long long)(MAXK + 1), nrm, 1);
 }
