@@ -1,5 +1,5 @@
 """GPU checks at the full sizes of the workloads (the 1023^2 two-grid
-pipeline the benchmark times, 3-D 255^3, 32 batched right-hand sides and 16
+pipeline the benchmark times, the two 511^2 Helmholtz workloads, 3-D 255^3, 32 batched right-hand sides and 16
 uneven instances, the 1023^2 adjoint).  The oracle
 cannot solve these sizes in seconds, so each check uses properties that hold
 at any size: the true residual recomputed by the oracle's operator on the
@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import workloads as W
-from oracle import operators as O, adjoint as ADJ, transfer as T
+from oracle import operators as O, adjoint as ADJ, transfer as T, multigrid as MG
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
@@ -63,6 +63,45 @@ def test_headline_pipeline_full_size():
     rr = _relres(oop, b, x.cpu().numpy())
     assert reps[0].status == 0 and rr <= c["rtol"]
     assert abs(rr - reps[0].relres_true) <= 1e-3 * rr
+
+
+def test_helmholtz_workloads_full_size():
+    """The 511^2 Helmholtz workloads as the benchmark runs them.  kappa = 25:
+    coarse GMRES-DR(128,60), IDR(20)(20)-Proj(60).  kappa = 100: the
+    multigrid on -Lap + 100^2 equals the oracle's V-cycles element by element
+    at full size (1e-11); GMRES-DR(128,60) on A_c M_c^-1 and the
+    preconditioned IDR(5)(5)-Proj(60).  Both solves: the true residual
+    recomputed by the oracle meets 1e-10."""
+    for name in ("H1", "H2"):
+        c = W.CONFIGS[name]
+        oop = O.const_cd(c["n"], c["beta"], sigma=c["sigma"])
+        b = W.rhs(oop.n, c["seed"])
+        op = tg().Operator.const_cd(c["n"], c["beta"], sigma=c["sigma"])
+        cop = op.coarsen()
+        bt = _t(b)
+        mg = mgc = None
+        if name == "H2":
+            shifted = O.const_cd(c["n"], c["beta"], sigma=-c["sigma"])
+            mg = tg().Multigrid(tg().Operator.const_cd(c["n"], c["beta"], sigma=-c["sigma"]),
+                                cycles=c["mg_cycles"], nu=c["mg_nu"])
+            ref = MG.mg_apply(MG.levels(shifted), b, cycles=c["mg_cycles"], nu=c["mg_nu"])
+            got = mg.apply(bt).cpu().numpy()
+            np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+            mgc = tg().Multigrid(tg().Operator.const_cd(cop.dims, c["beta"], sigma=-c["sigma"]),
+                                 cycles=c["mg_cycles"], nu=c["mg_nu"])
+        xc, cspace, srep = tg().coarse_setup(cop, tg().restrict(op, cop, bt), c["m"], c["k"], c["nev"],
+                                             c["rtolev"], c["rtol"], 300, precond=mgc)
+        assert srep.nconv >= c["nev"]
+        space = tg().defl_prolongate(cspace, op)
+        if mg is not None:
+            space = space.precond(mg)
+        x0 = tg().prolongate(cop, op, xc)
+        s = c["s"]
+        shadow = _t(W.shadow_draw(op.n, s, c["seed"] + s))
+        x, rep = tg().solve_idr(op, bt, s=s, shadow=shadow, x0=x0, defl=space, rtol=c["rtol"], ncyc=c["ncyc"],
+                                max_extra=20, precond=mg)
+        rr = _relres(oop, b, x.cpu().numpy())
+        assert rep.status == 0 and rr <= c["rtol"], (name, rep.status, rr)
 
 
 def test_3d_255_fp32_inner_with_fp32_stored_vectors():
