@@ -280,7 +280,12 @@ int tgdk_defl_destroy(tgdk_defl defl);
  * from zero, z_1 = V(b), z_(c+1) = z_c + V(b - A z_c) (a fixed linear
  * operator).  By default the kernel sequence is captured into a HIP graph
  * at the first apply and replayed; in and out are copied around it.  The
- * object keeps per-level work vectors: one apply at a time per object. */
+ * object keeps per-level work vectors: one apply at a time per object.
+ * tgdk_mg_create returns TGDK_E_INVALID for an operator that is not
+ * constant-coefficient, a non-positive diagonal or cycles, nu < 1, and
+ * TGDK_E_NOMEM when the level vectors cannot be allocated; tgdk_mg_apply
+ * returns TGDK_E_INVALID for NULL or aliasing in/out or nrhs < 1 and
+ * TGDK_E_HIP if the graph capture fails. */
 typedef struct tgdk_mg_s* tgdk_mg;
 #define TGDK_MG_EAGER 1   /* flags: launch the kernels on every apply instead of replaying a HIP graph */
 int tgdk_mg_create(tgdk_op op, int cycles, int nu, int flags, tgdk_mg* mg);
@@ -294,8 +299,8 @@ int tgdk_mg_destroy(tgdk_mg mg);
  *  - defl may be NULL (k = 0: plain restarted BiCGStab / GMRES(m3)).
  *  - b, x: device float64, nrhs columns of n; x is the initial guess when
  *    x0_given = 1, otherwise it is zeroed first.  The nrhs systems share A,
- *    V and H and advance cycle by cycle together; each keeps its own scalars
- *    and stops on its own.
+ *    V and H and run in the same launches, each with its own state machine:
+ *    its own scalars, cycle boundaries and stopping.
  *  - The overall tolerance is tau = rtol * min(||b||, ||b - A x0||) on the
  *    true residual, recomputed in float64 after every cycle.
  *  - Cycle tolerance (BiCGStab): the smaller of
