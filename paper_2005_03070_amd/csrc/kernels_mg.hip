@@ -1,9 +1,9 @@
 // Multigrid V-cycle kernels for a constant-coefficient operator (the
 // preconditioner of Sec. 5, Example 5).  A V-cycle on a 511^2 grid visits nine
 // levels, most of them a few thousand points or fewer, and every dependent
-// pass over a level costs a kernel boundary (about 3 us on this chip, where
-// the eight L2 caches are made coherent between kernels), so the cost is the
-// number of passes, not bytes.  Two things cut the passes:
+// pass over a level costs a kernel boundary (measured: 2.5 to 4.5 us per
+// pass whatever the level's size), so the cost is the number of passes, not
+// bytes.  Two things cut the passes:
 //
 //  * fused passes: the first two sweeps from z = 0 are one pass (the first
 //    sweep's values s v are formed where the second needs them), the residual
