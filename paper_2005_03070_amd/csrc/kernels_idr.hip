@@ -295,6 +295,75 @@ __global__ __launch_bounds__(NT) void k_idr_fold(IdrArgs a) {
     for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < a.n; i += stride) a.x[i] += (double)e[i];
 }
 
+// ------------------------------------------- stencil fused with products
+// y = A x on 2-D tiles (x staged with its halo in LDS, as k_apply), the tiles
+// grid-strided over the nb workgroups of the vector kernels, with the step's
+// products formed from the outputs in registers: MODE 0, P^T y (values
+// 0..s-1, CH columns of P, s <= CH, unconditional loads masked on the
+// factor); MODE 1, y.y, y.r, r.r (values 0, 1, 2; r read at the tile's own
+// points).  Per-workgroup partials in the vector kernels' layout, so the
+// epilogue reads them as it reads theirs.
+template <class Cfg, class TI, int MODE, int CH>
+__global__ __launch_bounds__(NT) void k_idr_apply_dots(DevOp op, IdrArgs a, const TI* __restrict__ x,
+                                                       TI* __restrict__ y, int tx, int ty, int ntiles) {
+    constexpr int NV = MODE == 0 ? CH : 3;
+    __shared__ TI L[Cfg::BOX];
+    __shared__ double sh[NWAVE * NV];
+    if (a.st->gate) return;
+    const TI* __restrict__ P = vp<TI>(a.P);
+    const TI* __restrict__ r = vp<TI>(a.r);
+    const long long n = a.n;
+    const TI* Pc[MODE == 0 ? CH : 1];
+    if (MODE == 0) {
+#pragma unroll
+        for (int j = 0; j < CH; ++j) Pc[j] = P + (long long)(j < a.s ? j : 0) * n;
+    }
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int tile = xcd_remap(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
+        const TilePos tp = tile_pos<Cfg>(tile, tx, ty);
+        long long gq[Cfg::PPT];
+        int cq[Cfg::PPT];
+        bool okq[Cfg::PPT];
+#pragma unroll
+        for (int q = 0; q < Cfg::PPT; ++q) {
+            int gx, gy, gz;
+            point_coords<Cfg>(q, tp, gx, gy, gz, cq[q]);
+            okq[q] = inside(op, gx, gy, gz);
+            gq[q] = okq[q] ? gidx(op, gx, gy, gz) : 0;
+            L[cq[q]] = okq[q] ? x[gq[q]] : TI(0);
+        }
+        fill_halo<Cfg, 2, TI>(L, tp, op, [&](long long g) { return x[g]; });
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Cfg::PPT; ++q) {
+            if (!okq[q]) continue;
+            const long long g = gq[q];
+            const TI yv = stencil_row<Cfg, 2, TI>(op, L, cq[q], g);
+            st_stream<2>(&y[g], yv);
+            const double yd = (double)yv;
+            if (MODE == 0) {
+#pragma unroll
+                for (int j = 0; j < CH; ++j) {
+                    const double pv = (double)Pc[j][g];
+                    acc[j] += (j < a.s ? pv : 0.0) * yd;
+                }
+            } else {
+                const double rv = (double)r[g];
+                acc[0] += yd * yd;
+                acc[1] += yd * rv;
+                acc[2] += rv * rv;
+            }
+        }
+        __syncthreads();  // L is rewritten by the next tile
+    }
+    double tot;
+    block_sum<NV>(acc, sh, tot);
+    const int nv = MODE == 0 ? a.s : 3;
+    if (threadIdx.x < nv) a.part[(long long)threadIdx.x * a.nb + blockIdx.x] = tot;
+}
+
 // ------------------------------------------------------------ epilogues
 // One workgroup: the waves sum the partials of each value in a fixed order,
 // the cycle's small arrays (M, f, c, alpha) are staged in LDS, thread 0 takes
@@ -595,6 +664,52 @@ static void idr_launch_t(int what, const IdrArgs& a, int k, hipStream_t s) {
         idr_launch_ch<TI, 4>(what, a, k, s);
     else
         idr_launch_ch<TI, 8>(what, a, k, s);
+}
+
+template <class TI, int CH>
+static void idr_fused_t(int what, const IdrArgs& a, const DevOp& op, int tile_id, const void* x, void* y, int k,
+                        hipStream_t s) {
+    with_tile<2>(tile_id, [&](auto cfg) {
+        using Cfg = decltype(cfg);
+        const int tx = (op.nx + Cfg::TX - 1) / Cfg::TX, ty = (op.ny + Cfg::TY - 1) / Cfg::TY;
+        const dim3 grid(a.nb), block(NT);
+        if (what == IDR_ALPHA)
+            hipLaunchKernelGGL((k_idr_apply_dots<Cfg, TI, 0, CH>), grid, block, 0, s, op, a, (const TI*)x, (TI*)y,
+                               tx, ty, tx * ty);
+        else
+            hipLaunchKernelGGL((k_idr_apply_dots<Cfg, TI, 1, 1>), grid, block, 0, s, op, a, (const TI*)x, (TI*)y,
+                               tx, ty, tx * ty);
+    });
+    const dim3 block(NT);
+    if (what == IDR_OMEGA)
+        hipLaunchKernelGGL(k_idr_epi, dim3(1), block, 0, s, a, (int)E_OM, 0, 3);
+    else if (k > 0)
+        hipLaunchKernelGGL(k_idr_epi, dim3(1), block, 0, s, a, (int)E_ALPHA, k, a.s + 1);
+    else
+        hipLaunchKernelGGL(k_idr_epi, dim3(1), block, 0, s, a, (int)E_M, 0, a.s);
+}
+
+template <class TI>
+static void idr_fused_s(int what, const IdrArgs& a, const DevOp& op, int tile_id, const void* x, void* y, int k,
+                        hipStream_t s) {
+    if (a.s <= 1)
+        idr_fused_t<TI, 1>(what, a, op, tile_id, x, y, k, s);
+    else if (a.s <= 2)
+        idr_fused_t<TI, 2>(what, a, op, tile_id, x, y, k, s);
+    else if (a.s <= 4)
+        idr_fused_t<TI, 4>(what, a, op, tile_id, x, y, k, s);
+    else
+        idr_fused_t<TI, 8>(what, a, op, tile_id, x, y, k, s);
+}
+
+bool launch_idr_fused(int what, int inner_f32, const IdrArgs& a, const DevOp& op, int tile_id, const void* x,
+                      void* y, int k, hipStream_t s) {
+    if (op.dim != 2 || a.s > 8 || (what != IDR_ALPHA && what != IDR_OMEGA)) return false;
+    if (inner_f32)
+        idr_fused_s<float>(what, a, op, tile_id, x, y, k, s);
+    else
+        idr_fused_s<double>(what, a, op, tile_id, x, y, k, s);
+    return true;
 }
 
 void launch_idr(int what, int inner_f32, const IdrArgs& a, int k, hipStream_t s) {

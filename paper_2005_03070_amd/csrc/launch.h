@@ -59,6 +59,14 @@ enum : int {
 };
 int idr_blocks(long long n);
 void launch_idr(int what, int inner_f32, const IdrArgs& a, int k, hipStream_t s);
+// 2-D grids with s <= 8: the stencil of a step fused with its products,
+// y = A x and the step's partials, then the step's epilogue.  what =
+// IDR_ALPHA: x = u_k (or M^-1 u_k), y = g_k, P^T g_k, then alpha (k > 0) or,
+// for k = 0, M_(:,0) and beta (the orthogonalisation of step 0 has nothing
+// to remove); IDR_OMEGA: x = r (or M^-1 r), y = t, t.t, t.r, r.r (r from
+// a.r), then omega.  false if the fused form does not apply (3-D, s > 8).
+bool launch_idr_fused(int what, int inner_f32, const IdrArgs& a, const DevOp& op, int tile_id, const void* x,
+                      void* y, int k, hipStream_t s);
 
 // tall-skinny products (column-major blocks, leading dimensions in elements)
 // G (p x q, row-major, device) = A^T B, A: n x p, B: n x q; partial workspace

@@ -689,19 +689,40 @@ static int idr_single(tgdk_ctx ctx, const ProbSpec& p, int s, const double* shad
             launch_apply<double>(op, (const double*)x, (double*)y, 1, tile, hs, gate);
         }
     };
+    // 2-D grids with s <= 8: each stencil forms its step's products too
+    // (P^T g_k, or t.t, t.r, r.r), so no separate pass re-reads g_k or t, and
+    // step 0 needs no orthogonalisation pass (its products are P^T g_0)
+    const bool fused = op.dim == 2 && s <= 8;
+    auto fused_apply = [&](int what, void* x, void* y, int k) {
+        const void* in = x;
+        if (pre) {  // right preconditioning: the stencil takes M^{-1} x
+            if (!prc) prc = prm->precond(prm->precond_user, (const double*)x, pz, 1);
+            in = pz;
+        }
+        launch_idr_fused(what, f32, a, op, tile, in, y, k, hs);
+    };
     // a round: step 0's direction, then for k >= 1 the update of step k-1
     // fused with step k's direction, the last step's update on its own, and
     // the dimension reduction
     auto round = [&]() {
         for (int k = 0; k < s; ++k) {
             launch_idr(k == 0 ? IDR_DIR : IDR_DIRUPD, f32, a, k, hs);
-            apply(col(a.U, k), col(a.G, k));
-            if (k > 0) launch_idr(IDR_ALPHA, f32, a, k, hs);
-            launch_idr(IDR_ORTH, f32, a, k, hs);
+            if (fused) {
+                fused_apply(IDR_ALPHA, col(a.U, k), col(a.G, k), k);
+                if (k > 0) launch_idr(IDR_ORTH, f32, a, k, hs);
+            } else {
+                apply(col(a.U, k), col(a.G, k));
+                if (k > 0) launch_idr(IDR_ALPHA, f32, a, k, hs);
+                launch_idr(IDR_ORTH, f32, a, k, hs);
+            }
         }
         launch_idr(IDR_UPD, f32, a, s - 1, hs);
-        apply(a.r, a.t);
-        launch_idr(IDR_OMEGA, f32, a, 0, hs);
+        if (fused) {
+            fused_apply(IDR_OMEGA, a.r, a.t, 0);
+        } else {
+            apply(a.r, a.t);
+            launch_idr(IDR_OMEGA, f32, a, 0, hs);
+        }
         launch_idr(IDR_RED, f32, a, 0, hs);
     };
     const int maxcyc = prm->ncyc + (prm->max_extra_cycles >= 0 ? prm->max_extra_cycles : prm->ncyc) + 2;
