@@ -23,6 +23,33 @@
 
 namespace tgdk {
 
+// Global-memory pointers.  The vectors reach the kernels inside descriptors
+// read from memory, so the compiler cannot tell their address space and
+// emits flat accesses, which count against the LDS counter as well as the
+// memory counter: every LDS wait (each barrier, each LDS read of a
+// reduction) then also waits for the loads and stores in flight.  gptr<T>
+// is a pointer the compiler knows to be global; gp() converts a descriptor
+// pointer (device memory from hipMalloc) to one.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> gp(const void* p) {
+    return (gptr<T>)const_cast<void*>(p);
+}
+// A copy of a struct in global memory, read as 8-byte words through a
+// global pointer (a struct copy through a generic pointer compiles to flat
+// loads).
+template <class T>
+__device__ __forceinline__ T load_global(const T* p) {
+    static_assert(sizeof(T) % 8 == 0, "8-byte words");
+    T v;
+    const gptr<const unsigned long long> s = gp<const unsigned long long>(p);
+    unsigned long long* d = reinterpret_cast<unsigned long long*>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 8); ++i) d[i] = s[i];
+    return v;
+}
+
 constexpr int NT = 256;         // threads per workgroup of the tile kernels
 constexpr int NWAVE = NT / 64;
 constexpr int NXCD = 8;         // XCDs on MI355X
@@ -204,6 +231,14 @@ __device__ __forceinline__ void point_coords(int q, const TilePos& tp, int& gx, 
 // measured slightly faster.
 template <int DIM, class T>
 __device__ __forceinline__ void st_stream(T* p, T v) {
+    if (DIM == 2)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+template <int DIM, class T>
+__device__ __forceinline__ void st_stream(gptr<T> p, T v) {
     if (DIM == 2)
         __builtin_nontemporal_store(v, p);
     else
@@ -419,7 +454,8 @@ __device__ __forceinline__ void sum_partial_columns(const double* __restrict__ p
 // receives the totals, and every workgroup that calls this on the same array
 // gets the same bits.  sh needs NWAVE*NV doubles.
 template <int NV>
-__device__ __forceinline__ void sum_values(const double* __restrict__ part, int nwg, double (&out)[NV], double* sh) {
+__device__ __forceinline__ void sum_values(const double* __restrict__ part_in, int nwg, double (&out)[NV], double* sh) {
+    const gptr<const double> part = gp<const double>(part_in);
     double a[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) a[v] = 0.0;
@@ -459,6 +495,7 @@ template <class T>
 __device__ __forceinline__ T* vp(void* p) {
     return reinterpret_cast<T*>(p);
 }
+
 template <class T>
 __device__ __forceinline__ const T* vp(const void* p) {
     return reinterpret_cast<const T*>(p);
