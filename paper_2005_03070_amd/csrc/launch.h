@@ -36,7 +36,7 @@ void tile_shape(int dim, int tile_id, int* ty, int* tz);
 
 // BiCGStab step kernel: one launch advances every running problem of the
 // group by one step of its state machine.  wg_prob maps a workgroup id to its
-// problem; gslot is the launch number within the solve; var: the operator has
+// problem (null: every workgroup belongs to problem 0); gslot is the launch number within the solve; var: the operator has
 // per-row coefficient arrays.
 void launch_step(int dim, int inner_f32, int var, int tile_id, const DevProb* probs, const int* wg_prob,
                  int total_wg, int gslot, hipStream_t s);

@@ -97,7 +97,10 @@ static void launch(const Group& g, int which, int flag = 0) {
 // One step launch (with measurement on, the kernel stamps its start and end).
 static int launch_step_timed(Group& g) {
     const int slot = g.gslot++;
-    launch_step(g.dim, g.inner_f32, g.var, g.tile_id, g.d_probs, g.d_wgprob, g.total_wg, slot, g.ctx->stream);
+    // a group of one system needs no workgroup-to-system map (one load less
+    // on the dependent chain at the start of every launch)
+    launch_step(g.dim, g.inner_f32, g.var, g.tile_id, g.d_probs, g.nprob == 1 ? nullptr : g.d_wgprob, g.total_wg,
+                slot, g.ctx->stream);
     return TGDK_OK;
 }
 

@@ -1063,7 +1063,7 @@ __global__ __launch_bounds__(NT) void k_step(const DevProb* __restrict__ probs, 
     __shared__ double sh[NWAVE * 16];
     __shared__ double ysh[MAXK + 1];
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const DevProb& P = probs[wg_prob[wg]];
+    const DevProb& P = probs[wg_prob ? wg_prob[wg] : 0];
     const int lw = wg - P.wg_begin;
     const bool lead = lw == 0;
     const bool scribe = lead && threadIdx.x == 0;
