@@ -601,7 +601,7 @@ def main():
                    "n": n, "k": space.k, "ncyc": c["ncyc"], "seed": c["seed"]},
         "roofline": {"bound": "hbm", "achieved": ach_step, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach_step / HBM_PEAK_GBS, "traffic": traffic_from_profiles(),
-                     "kernel": "k_step (BiCGStab step: phase A / phase B / cycle boundary), f64, one solve",
+                     "kernel": "k_step1 (BiCGStab step kernel of a one-system group: phase A / phase B / cycle boundary), f64, one solve",
                      "algorithmic_bytes_per_launch": step_bytes, "avg_launch_us": step_us,
                      "launches_timed": tot_cnt, "timing": "device wall clock per launch",
                      "step_kernel_ms": tot_ms, "solve_ms_hip_events": solve_event_ms},

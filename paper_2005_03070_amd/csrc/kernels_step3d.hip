@@ -4,6 +4,7 @@
 
 namespace tgdk {
 
-template void launch_step_dim<3>(int, int, int, const DevProb*, const int*, int, int, hipStream_t);
+template void launch_step_dim<3>(int, int, int, const DevProb*, const int*, int, int, hipStream_t,
+                                 const DevProb*);
 
 }  // namespace tgdk

@@ -36,13 +36,15 @@ void tile_shape(int dim, int tile_id, int* ty, int* tz);
 
 // BiCGStab step kernel: one launch advances every running problem of the
 // group by one step of its state machine.  wg_prob maps a workgroup id to its
-// problem (null: every workgroup belongs to problem 0); gslot is the launch number within the solve; var: the operator has
-// per-row coefficient arrays.
+// problem (null: every workgroup belongs to problem 0); gslot is the launch
+// number within the solve; var: the operator has per-row coefficient arrays;
+// single: for a group of one problem, a host copy of its descriptor (passed
+// in the kernel arguments), else null.
 void launch_step(int dim, int inner_f32, int var, int tile_id, const DevProb* probs, const int* wg_prob,
-                 int total_wg, int gslot, hipStream_t s);
+                 int total_wg, int gslot, hipStream_t s, const DevProb* single);
 template <int DIM>
 void launch_step_dim(int inner_f32, int var, int tile_id, const DevProb* probs, const int* wg_prob, int total_wg,
-                     int gslot, hipStream_t s);
+                     int gslot, hipStream_t s, const DevProb* single);
 
 // IDR(s) inner cycles (kernels_idr.hip): what = one of the IDR_* actions,
 // k = the step of the round for IDR_DIR, IDR_ALPHA, IDR_ORTH, IDR_UPD.

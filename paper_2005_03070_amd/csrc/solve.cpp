@@ -97,10 +97,11 @@ static void launch(const Group& g, int which, int flag = 0) {
 // One step launch (with measurement on, the kernel stamps its start and end).
 static int launch_step_timed(Group& g) {
     const int slot = g.gslot++;
-    // a group of one system needs no workgroup-to-system map (one load less
-    // on the dependent chain at the start of every launch)
-    launch_step(g.dim, g.inner_f32, g.var, g.tile_id, g.d_probs, g.nprob == 1 ? nullptr : g.d_wgprob, g.total_wg,
-                slot, g.ctx->stream);
+    // a group of one system passes its descriptor in the kernel arguments
+    // and needs no workgroup-to-system map
+    const bool one = g.nprob == 1;
+    launch_step(g.dim, g.inner_f32, g.var, g.tile_id, g.d_probs, one ? nullptr : g.d_wgprob, g.total_wg, slot,
+                g.ctx->stream, one ? &g.probs[0] : nullptr);
     return TGDK_OK;
 }
 

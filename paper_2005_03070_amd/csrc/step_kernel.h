@@ -1055,15 +1055,11 @@ __device__ __forceinline__ void march_apply(const DevProb& P, int lw, int gslot,
 
 // ------------------------------------------------------------- kernel
 template <class Cfg, int DIM, bool VAR, class TI>
-__global__ __launch_bounds__(NT) void k_step(const DevProb* __restrict__ probs, const int* __restrict__ wg_prob,
-                                             int gslot) {
-    const unsigned long long t_begin = (unsigned long long)wall_clock64();
+__device__ __forceinline__ void step_run(const DevProb& P, int wg, int gslot, unsigned long long t_begin) {
     constexpr int NBOX = (DIM == 3 && StepMarch<TI>::PLANE > Cfg::BOX) ? StepMarch<TI>::PLANE : Cfg::BOX;
     __shared__ double Lbox[NBOX];
     __shared__ double sh[NWAVE * 16];
     __shared__ double ysh[MAXK + 1];
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const DevProb& P = probs[wg_prob ? wg_prob[wg] : 0];
     const int lw = wg - P.wg_begin;
     const bool lead = lw == 0;
     const bool scribe = lead && threadIdx.x == 0;
@@ -1153,13 +1149,54 @@ __global__ __launch_bounds__(NT) void k_step(const DevProb* __restrict__ probs, 
     }
 }
 
+// Groups of several systems: the descriptors in device memory, wg_prob maps
+// a workgroup to its system (null: all belong to system 0).
+template <class Cfg, int DIM, bool VAR, class TI>
+__global__ __launch_bounds__(NT) void k_step(const DevProb* __restrict__ probs, const int* __restrict__ wg_prob,
+                                             int gslot) {
+    const unsigned long long t_begin = (unsigned long long)wall_clock64();
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    step_run<Cfg, DIM, VAR, TI>(probs[wg_prob ? wg_prob[wg] : 0], wg, gslot, t_begin);
+}
+
+// A group of one system: its descriptor travels in the kernel arguments, so
+// its fields are read from the argument segment at once instead of after a
+// pointer load (one memory round trip fewer at the start of every launch).
+template <class Cfg, int DIM, bool VAR, class TI>
+__global__ __launch_bounds__(NT) void k_step1(const DevProb P, int gslot) {
+    const unsigned long long t_begin = (unsigned long long)wall_clock64();
+    step_run<Cfg, DIM, VAR, TI>(P, xcd_remap(blockIdx.x, gridDim.x), gslot, t_begin);
+}
+
 // ------------------------------------------------------------ launcher
 template <int DIM>
 void launch_step_dim(int inner_f32, int var, int tile_id, const DevProb* probs, const int* wg_prob, int total_wg,
-                     int gslot, hipStream_t s) {
+                     int gslot, hipStream_t s, const DevProb* single) {
     with_tile<DIM>(tile_id, [&](auto cfg) {
         using Cfg = decltype(cfg);
         const dim3 grid(total_wg), block(NT);
+        // 2-D tiles up to 16 rows only: in the 3-D kernels and the 32-row
+        // 2-D tiles with per-row coefficients the argument-segment
+        // descriptor is copied to scratch (392 bytes a lane)
+        bool launched = false;
+        if constexpr (DIM == 2 && Cfg::TY <= 16) {
+            if (single) {
+                launched = true;
+                const DevProb& P = *single;
+                if (inner_f32) {
+                    if (var)
+                        hipLaunchKernelGGL((k_step1<Cfg, DIM, true, float>), grid, block, 0, s, P, gslot);
+                    else
+                        hipLaunchKernelGGL((k_step1<Cfg, DIM, false, float>), grid, block, 0, s, P, gslot);
+                } else {
+                    if (var)
+                        hipLaunchKernelGGL((k_step1<Cfg, DIM, true, double>), grid, block, 0, s, P, gslot);
+                    else
+                        hipLaunchKernelGGL((k_step1<Cfg, DIM, false, double>), grid, block, 0, s, P, gslot);
+                }
+            }
+        }
+        if (launched) return;
         if (inner_f32) {
             if (var)
                 hipLaunchKernelGGL((k_step<Cfg, DIM, true, float>), grid, block, 0, s, probs, wg_prob, gslot);
