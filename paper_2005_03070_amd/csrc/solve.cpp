@@ -310,6 +310,7 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
             S.max_extra = prm->max_extra_cycles > 0 ? prm->max_extra_cycles : 1000;
         }
         S.maxit = prm->maxit_cycle > 0 ? prm->maxit_cycle : 100000;
+        P.maxit = S.maxit;
         S.k = P.k;
         S.precision = g.inner_f32;
         S.solve_state = SV_RUNNING;

@@ -111,11 +111,22 @@ __device__ __forceinline__ void boundary_tests(const StepHot& H, StepHot& N, con
     if (N.solve_state == SV_RUNNING) N.icyc = H.icyc + 1;
 }
 
+// Report counters of the inner iterations, read by the scribe in one batch
+// before the decision: read-modify-writes through the state pointer inside
+// the decision were ordered behind the scribe's other state stores (they may
+// alias), one memory round trip each, and the lead workgroup ended last.
+struct ScribeCnt {
+    long long mvp_inner, iters_total;
+    int nhist;
+};
+
 // The scalar part of a step.  Every workgroup of the problem evaluates it on
 // the same inputs; only the scribe (thread 0 of the lead workgroup) writes
-// the report counters.  Returns the action of this launch.
+// the report counters (C: their values before this launch, scribe only).
+// maxit: the inner iteration cap.  Returns the action of this launch.
 __device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* st, int k, int dim, int gslot,
-                           bool scribe, StepHot& N, Upd& U, double& rr_out, double& rr0_out) {
+                           bool scribe, int maxit, const ScribeCnt& C, StepHot& N, Upd& U, double& rr_out,
+                           double& rr0_out) {
     N = H;
     U = Upd{H.upd_a, H.upd_w, H.upd_any, H.pbuf};
     const int after_res = k > 0 ? M_REDUCE : M_APPLY0;
@@ -136,7 +147,7 @@ __device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* s
         case M_B: {  // phase A partials: r^.v, ||r_i||^2
             const double sig = s[0];
             if (scribe) {
-                st->mvp_inner += 1;
+                st->mvp_inner = C.mvp_inner + 1;
                 st->sigma = sig;
                 st->rr_last = s[1];
             }
@@ -149,10 +160,10 @@ __device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* s
             const double ss = s[0], ts = s[1], tt = s[2], rs = s[3], rt = s[4];
             N.iter = H.iter + 1;
             const int pb = ((gslot - 2) >> 1) & 1;  // p of the iteration just finished
-            const int hi = scribe ? st->nhist : NHIST;
+            const int hi = scribe ? C.nhist : NHIST;
             if (scribe) {
-                st->mvp_inner += 1;
-                st->iters_total += 1;
+                st->mvp_inner = C.mvp_inner + 1;
+                st->iters_total = C.iters_total + 1;
             }
             if (ss <= H.target2) {
                 if (hi < NHIST) {
@@ -179,7 +190,7 @@ __device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* s
             const double rho_new = rs - omega * rt;
             if (rr <= H.target2) return end_cycle(IN_CONVERGED, H.alpha, omega, 1, pb);
             if (rho_new == 0.0 || !isfinite(rho_new)) return end_cycle(IN_BREAK_FULL, H.alpha, omega, 1, pb);
-            if (N.iter >= st->maxit) return end_cycle(IN_MAXIT, H.alpha, omega, 1, pb);
+            if (N.iter >= maxit) return end_cycle(IN_MAXIT, H.alpha, omega, 1, pb);
             N.rho_old = H.rho;
             N.rho = rho_new;
             N.mode = M_B;
@@ -1066,12 +1077,19 @@ __device__ __forceinline__ void step_run(const DevProb& P, int wg, int gslot, un
     const int cur = gslot & 1;
     SolveState* st = P.st;
     const StepHot H = load_global(&st->hot[cur ^ 1]);
+    const int maxit = P.maxit;
     double s5[5];
     sum_values<5>(P.partial + (long long)(cur ^ 1) * P.pslot, P.nwg, s5, sh);
+    ScribeCnt C{0, 0, 0};
+    if (scribe) {
+        C.mvp_inner = *gp<const long long>(&st->mvp_inner);
+        C.iters_total = *gp<const long long>(&st->iters_total);
+        C.nhist = *gp<const int>(&st->nhist);
+    }
     StepHot N;
     Upd U;
     double rr = -1.0, rr0 = -1.0;
-    const int act = step_decide(H, s5, st, P.k, DIM, gslot, scribe, N, U, rr, rr0);
+    const int act = step_decide(H, s5, st, P.k, DIM, gslot, scribe, maxit, C, N, U, rr, rr0);
     if (scribe) {
         st->hot[cur] = N;
         st->solve_state = N.solve_state;

@@ -113,6 +113,7 @@ struct DevProb {
     DevOp op;
     int tx, ty, tz, ntiles, tile_begin;
     int k;
+    int maxit;               // step kernel: inner iteration cap (the state's maxit)
     const double* b;
     double* x;
     double* r;               // outer residual, float64
