@@ -480,14 +480,26 @@ __device__ __forceinline__ void c_partials(const DevProb& P, const TilePos& tp, 
                                            const double* __restrict__ L, double* csum) {
     const DevOp& op = P.op;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int R = Cfg::PTS / 64;
+    constexpr int RB = R < 8 ? R : 8;  // rows in flight (register budget)
+    static_assert(R % RB == 0, "tile rows");
+    const gptr<const TV> zero = gp<const TV>(op.zero);
     for (int j = w; j < P.k; j += NWAVE) {
-        const TV* __restrict__ Vj = V + (long long)j * P.ldv;
+        const gptr<const TV> Vj = gp<const TV>(V) + (long long)j * P.ldv;
+        // RB rows of the column issued before their sum: points outside the
+        // domain read the zero page (and their L entry is zero), so no load
+        // is guarded (a guarded load compiles to a branch and a full wait)
         double a = 0.0;
-#pragma unroll 8
-        for (int m = 0; m < Cfg::PTS / 64; ++m) {
-            const int l = lane + 64 * m;
-            const int gx = tp.x0 + lane, gy = tp.y0 + (l / 64) % Cfg::TY, gz = tp.z0 + l / (64 * Cfg::TY);
-            if (inside(op, gx, gy, gz)) a += (double)Vj[gidx(op, gx, gy, gz)] * L[l];
+        for (int m0 = 0; m0 < R; m0 += RB) {
+            TV v[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const int l = lane + 64 * (m0 + u);
+                const int gx = tp.x0 + lane, gy = tp.y0 + (l / 64) % Cfg::TY, gz = tp.z0 + l / (64 * Cfg::TY);
+                v[u] = *(inside(op, gx, gy, gz) ? Vj + gidx(op, gx, gy, gz) : zero);
+            }
+#pragma unroll
+            for (int u = 0; u < RB; ++u) a += (double)v[u] * L[lane + 64 * (m0 + u)];
         }
         a = wave_sum(a);
         if (lane == 0) csum[j] += a;
