@@ -933,15 +933,18 @@ __device__ __forceinline__ void chunk_columns(const DevProb& P, const Chunk& c, 
         const TV* __restrict__ Vj[4];
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) Vj[jj] = V + (long long)(j0 + jj < k ? j0 + jj : j0) * P.ldv;
+        // no guarded loads (a guarded load compiles to a branch and a full
+        // wait): points outside the domain read the zero page for r and V
+        const gptr<const double> zr = gp<const double>(op.zero);
+        const gptr<const TV> zv = gp<const TV>(op.zero);
 #pragma unroll 4
         for (int l = threadIdx.x; l < npts; l += NT) {
             const int gx = c.x0 + (l & 63), gy = c.y0 + ((l >> 6) % M::MY), z = c.z0 + l / (64 * M::MY);
-            if (gx < op.nx && gy < op.ny) {
-                const long long g = z * plane + (long long)gy * op.nx + gx;
-                const double rv = r[g];
+            const bool in = gx < op.nx && gy < op.ny;
+            const long long g = z * plane + (long long)gy * op.nx + gx;
+            const double rv = *(in ? gp<const double>(r) + g : zr);
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) a[jj] += (double)Vj[jj][g] * rv;
-            }
+            for (int jj = 0; jj < 4; ++jj) a[jj] += (double)*(in ? gp<const TV>(Vj[jj]) + g : zv) * rv;
         }
         double tot;
         block_sum<4>(a, sh, tot);
