@@ -356,14 +356,51 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// One data-parallel-primitive move of a double (two 32-bit halves): lane i
+// receives the source lane that CTRL selects; lanes of rows outside ROWMASK
+// receive 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_move(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWMASK, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWMASK, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wave through lane moves instead of LDS
+// permutes: pairs, quads (quad permutations), eight and sixteen lanes (half-
+// row and row mirrors), then the rows combined by the row broadcasts of
+// lanes 15 and 31 into row 3; lane 63's total is returned to every lane.
+// A fixed order: every wave that sums the same values gets the same bits.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_move<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+    v += dpp_move<0x141, 0xf>(v);  // row_half_mirror
+    v += dpp_move<0x140, 0xf>(v);  // row_mirror
+    v += dpp_move<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <bool DPP>
+__device__ __forceinline__ double wave_sum_t(double v) {
+    if constexpr (DPP)
+        return wave_sum_dpp(v);
+    else
+        return wave_sum(v);
+}
+
 // Sums a[0..NR) over the workgroup; the totals land in out[0..NR) of thread
 // i < NR (other threads' out is undefined).  sh needs NWAVE*NR doubles.
-template <int NR>
+template <int NR, bool DPP = false>
 __device__ __forceinline__ void block_sum(const double (&a)[NR], double* sh, double& out) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-        const double s = wave_sum(a[i]);
+        const double s = wave_sum_t<DPP>(a[i]);
         if (lane == 0) sh[w * NR + i] = s;
     }
     __syncthreads();
@@ -453,7 +490,7 @@ __device__ __forceinline__ void sum_partial_columns(const double* __restrict__ p
 // at part[v * nwg + t]) over t = 0..nwg-1 in a fixed order; every thread
 // receives the totals, and every workgroup that calls this on the same array
 // gets the same bits.  sh needs NWAVE*NV doubles.
-template <int NV>
+template <int NV, bool DPP = false>
 __device__ __forceinline__ void sum_values(const double* __restrict__ part_in, int nwg, double (&out)[NV], double* sh) {
     const gptr<const double> part = gp<const double>(part_in);
     double a[NV];
@@ -478,7 +515,7 @@ __device__ __forceinline__ void sum_values(const double* __restrict__ part_in, i
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        const double s = wave_sum(a[v]);
+        const double s = wave_sum_t<DPP>(a[v]);
         if (lane == 0) sh[w * NV + v] = s;
     }
     __syncthreads();

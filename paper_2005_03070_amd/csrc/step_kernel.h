@@ -397,7 +397,7 @@ __device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, boo
         __syncthreads();
     }
     double tot;
-    block_sum<2>(acc, sh, tot);
+    block_sum<2, true>(acc, sh, tot);
     if (threadIdx.x < 2) *part_at(P, gslot & 1, threadIdx.x, lw) = tot;
 }
 
@@ -469,7 +469,7 @@ __device__ __forceinline__ void phase_b(const DevProb& P, int lw, int gslot, con
         __syncthreads();
     }
     double tot;
-    block_sum<5>(acc, sh, tot);
+    block_sum<5, true>(acc, sh, tot);
     if (threadIdx.x < 5) *part_at(P, gslot & 1, threadIdx.x, lw) = tot;
 }
 
@@ -501,7 +501,7 @@ __device__ __forceinline__ void c_partials(const DevProb& P, const TilePos& tp, 
 #pragma unroll
             for (int u = 0; u < RB; ++u) a += (double)v[u] * L[lane + 64 * (m0 + u)];
         }
-        a = wave_sum(a);
+        a = wave_sum_dpp(a);
         if (lane == 0) csum[j] += a;
     }
 }
@@ -575,7 +575,7 @@ __device__ __forceinline__ void true_residual(const DevProb& P, int lw, int gslo
         __syncthreads();
     }
     double tot;
-    block_sum<3>(acc, sh, tot);
+    block_sum<3, true>(acc, sh, tot);
     const int slot = gslot & 1;
     if (threadIdx.x < 3) *part_at(P, slot, threadIdx.x, lw) = tot;
     for (int i = threadIdx.x; i < k; i += NT) *part_at(P, slot, 3 + i, lw) = csum[i];
@@ -597,7 +597,7 @@ __device__ __forceinline__ void projection_coefficients(const DevProb& P, int gs
         double a = 0.0;
 #pragma unroll 4
         for (int t = lane; t < nwg; t += 64) a += col[t];
-        a = wave_sum(a);
+        a = wave_sum_dpp(a);
         if (lane == 0) y[c] = a;
     }
     __syncthreads();
@@ -666,7 +666,7 @@ __device__ __forceinline__ void apply_projection(const DevProb& P, int lw, int g
         __syncthreads();
     }
     double tot;
-    block_sum<2>(acc, sh, tot);
+    block_sum<2, true>(acc, sh, tot);
     if (threadIdx.x < 2) *part_at(P, gslot & 1, threadIdx.x, lw) = tot;
 }
 
@@ -826,7 +826,7 @@ __device__ __forceinline__ void march_phase(const DevProb& P, int lw, int gslot,
         march_chunk<M, VAR, TI>(P.op, k, L, ph);
     }
     double tot;
-    block_sum<NV>(ph.acc, sh, tot);
+    block_sum<NV, true>(ph.acc, sh, tot);
     if (threadIdx.x < NV) *part_at(P, gslot & 1, threadIdx.x, lw) = tot;
 }
 
@@ -947,7 +947,7 @@ __device__ __forceinline__ void chunk_columns(const DevProb& P, const Chunk& c, 
             for (int jj = 0; jj < 4; ++jj) a[jj] += (double)*(in ? gp<const TV>(Vj[jj]) + g : zv) * rv;
         }
         double tot;
-        block_sum<4>(a, sh, tot);
+        block_sum<4, true>(a, sh, tot);
         if (threadIdx.x < 4 && j0 + threadIdx.x < k) csum[j0 + threadIdx.x] = tot;
     }
 }
@@ -982,7 +982,7 @@ __device__ __forceinline__ void march_res(const DevProb& P, int lw, int gslot, c
     }
     __syncthreads();
     double tot;
-    block_sum<3>(ph.acc, sh, tot);
+    block_sum<3, true>(ph.acc, sh, tot);
     const int slot = gslot & 1;
     if (threadIdx.x < 3) *part_at(P, slot, threadIdx.x, lw) = tot;
     for (int i = threadIdx.x; i < k; i += NT) *part_at(P, slot, 3 + i, lw) = csum[i];
@@ -1075,7 +1075,7 @@ __device__ __forceinline__ void march_apply(const DevProb& P, int lw, int gslot,
         march_chunk<M, VAR, double>(P.op, c, Lbox, ph);
     }
     double tot;
-    block_sum<2>(ph.acc, sh, tot);
+    block_sum<2, true>(ph.acc, sh, tot);
     if (threadIdx.x < 2) *part_at(P, gslot & 1, threadIdx.x, lw) = tot;
 }
 
@@ -1094,7 +1094,7 @@ __device__ __forceinline__ void step_run(const DevProb& P, int wg, int gslot, un
     const StepHot H = load_global(&st->hot[cur ^ 1]);
     const int maxit = P.maxit;
     double s5[5];
-    sum_values<5>(P.partial + (long long)(cur ^ 1) * P.pslot, P.nwg, s5, sh);
+    sum_values<5, true>(P.partial + (long long)(cur ^ 1) * P.pslot, P.nwg, s5, sh);
     ScribeCnt C{0, 0, 0};
     if (scribe) {
         C.mvp_inner = *gp<const long long>(&st->mvp_inner);

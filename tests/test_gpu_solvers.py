@@ -255,15 +255,21 @@ def test_adjoint_gradients_against_oracle():
 
 
 def test_breakdown_on_skew_operator():
-    """Pure centred convection (skew-symmetric): status breakdown, no hang."""
+    """Pure centred convection (skew-symmetric): status breakdown, no hang.
+    r^.A r0 vanishes for a skew-symmetric A; with integer right-hand-side
+    entries and coefficients (45 = 10 / (2h)) every product and partial sum
+    is an exact integer, so sigma is exactly zero in any summation order."""
     dims = (8, 8)
     h = 1 / 9
     n = 64
     coef = np.zeros((5, n))
     coef[1] = -10 / (2 * h)
     coef[2] = 10 / (2 * h)
+    assert coef[2, 0] == 45.0
     op = tg().Operator.var_stencil(dims, _t(coef))
-    x, reps = tg().solve(op, _t(W.rhs(n, 3)), rtol=1e-8, ncyc=5)
+    b = np.round(2.0 * W.rhs(n, 3))
+    assert np.any(b != 0.0)
+    x, reps = tg().solve(op, _t(b), rtol=1e-8, ncyc=5)
     assert reps[0].status == 2
 
 
