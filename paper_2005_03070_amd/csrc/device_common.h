@@ -415,9 +415,10 @@ __device__ __forceinline__ void block_sum(const double (&a)[NR], double* sh, dou
 
 // Runtime-width variant: a[i] for i < nr held in shared memory rows; used
 // by the projection kernels.  vals[t * stride + i] contains thread t's value i.
+template <bool DPP = false>
 __device__ __forceinline__ double block_sum_one(double v, double* sh) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    v = wave_sum(v);
+    v = wave_sum_t<DPP>(v);
     if (lane == 0) sh[w] = v;
     __syncthreads();
     double s = sh[0];

@@ -75,7 +75,7 @@ __device__ __forceinline__ void dots_with_P(const IdrArgs& a, Y&& y) {
             if (SELF && first) acc[CH] += yv * yv;
         }
         double tot;
-        block_sum<CH + 1>(acc, sh, tot);
+        block_sum<CH + 1, true>(acc, sh, tot);
         if (threadIdx.x < nc) a.part[(long long)(c0 + threadIdx.x) * a.nb + blockIdx.x] = tot;
         if (SELF && first && threadIdx.x == CH) a.part[(long long)a.s * a.nb + blockIdx.x] = tot;
     }
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(NT) void k_idr_dirupd(IdrArgs a, int k) {
             uk[i] = (TI)(uc + om * (double)v);
         }
     }
-    const double tot = block_sum_one(acc, sh);
+    const double tot = block_sum_one<true>(acc, sh);
     if (threadIdx.x == 0) a.part[(long long)a.s * a.nb + blockIdx.x] = tot;
 }
 
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(NT) void k_idr_upd(IdrArgs a, int k) {
         e[i] = efirst ? (TI)(beta * (double)u[i]) : (TI)((double)e[i] + beta * (double)u[i]);
         acc += (double)rv * (double)rv;
     }
-    const double tot = block_sum_one(acc, sh);
+    const double tot = block_sum_one<true>(acc, sh);
     if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
 }
 
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(NT) void k_idr_tdot(IdrArgs a) {
         acc[2] += rv * rv;
     }
     double tot;
-    block_sum<3>(acc, sh, tot);
+    block_sum<3, true>(acc, sh, tot);
     if (threadIdx.x < 3) a.part[(long long)threadIdx.x * a.nb + blockIdx.x] = tot;
 }
 
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(NT) void k_idr_apply_dots(DevOp op, IdrArgs a, cons
         __syncthreads();  // L is rewritten by the next tile
     }
     double tot;
-    block_sum<NV>(acc, sh, tot);
+    block_sum<NV, true>(acc, sh, tot);
     const int nv = MODE == 0 ? a.s : 3;
     if (threadIdx.x < nv) a.part[(long long)threadIdx.x * a.nb + blockIdx.x] = tot;
 }
@@ -585,7 +585,7 @@ __global__ __launch_bounds__(NT) void k_idr_epi(IdrArgs a, int which, int k, int
         double acc = 0.0;
 #pragma unroll
         for (int i = 0; i < PER_LANE; ++i) acc += (lane + 64 * i < a.nb) ? x[i] : 0.0;
-        acc = wave_sum(acc);
+        acc = wave_sum_dpp(acc);
         if (lane == 0) v[q] = acc;
     }
     // stage what the decisions read
