@@ -193,7 +193,9 @@ def test_gmres_first_cycle_equals_oracle_cycle(m):
 def test_batched_rhs_independent_of_grouping():
     """Right-hand sides on one deflation space solved in one group: every
     system runs its own state machine with its own reductions, so a column is
-    bit-identical whichever group it is solved in, including a group of one."""
+    bit-identical whichever group it is solved in, including a group of one
+    (which launches the step kernel with its descriptor in the kernel
+    arguments instead of the device-side descriptor table)."""
     dims, beta = (127, 127), (100.0, 0.0)
     op = tg().Operator.const_cd(dims, beta)
     oop = O.const_cd(dims, beta)
