@@ -336,6 +336,22 @@ typedef struct {
      * tgdk_defl_precond with the same preconditioner */
     tgdk_precond_fn precond;
     void* precond_user;
+    /* Resuming a solve at a cycle boundary (Sec. 4.1 box, step 3: the
+     * schedule of cycle tolerances depends on the cycle number icyc and on
+     * ||r0||).  icyc0 >= 0: cycles already completed by earlier calls on
+     * this system; this call's first cycle is cycle icyc0 + 1 of the
+     * schedule and the cycle limit ncyc + max_extra_cycles counts them.
+     * nu0 > 0: ||r0|| of the solve's original initial guess (the report's
+     * nu0 of the first call); tau = rtol min(||b||, nu0).  0 takes this
+     * call's starting residual.  Pass the interrupted iterate as x with
+     * x0_given = 1: the resumed solve then repeats, bit for bit, what the
+     * uninterrupted one computes from that cycle boundary on.
+     * max_cycles_call > 0: stop after that many cycles of this call with
+     * TGDK_NOT_CONVERGED (outputs valid, x is the iterate at that cycle
+     * boundary); 0 for no limit. */
+    int icyc0;
+    int max_cycles_call;
+    double nu0;
 } tgdk_solve_params;
 
 typedef struct {
@@ -348,16 +364,21 @@ typedef struct {
     double first_rho[TGDK_NHIST], first_alpha[TGDK_NHIST], first_omega[TGDK_NHIST];
     int n_cycle_mvps;      /* min(cycles, TGDK_NCYC_REPORT) */
     int cycle_mvps[TGDK_NCYC_REPORT];  /* inner operator applications of each of the first cycles */
+    int cycle_branch[TGDK_NCYC_REPORT];  /* criterion (1, 2, 3 = past ncyc) that set each cycle's
+                                            tolerance; 0 for a cycle that did not start */
+    double nu0;            /* ||r0|| of the schedule (pass it back as params.nu0 to resume) */
+    /* Cost in the paper's terms (Sec. 3, Example 1: cost = nnz * mvps + vops).
+     * mvp_setup: fine-grid operator applications spent building the
+     * deflation space used (A V for H = V^T A V; paid once per space, not by
+     * this call).  vops: length-n vector operations of this call (a dot
+     * product, a norm or an update y += a x counts one; formed from the
+     * iteration counts, see DESIGN). */
+    long long mvp_setup, vops;
 } tgdk_solve_report;
 
 int tgdk_solve(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int nrhs,
                const tgdk_solve_params* params, tgdk_solve_report* reports);
 
-/* Several independent instances (each its own operator, deflation space or
- * NULL, right-hand side and solution, all on one context and of one
- * dimension) solved together: every kernel launch covers the tiles of all
- * instances, so small and uneven grids fill the device in one launch per
- * step.  Same parameters and reports (one per instance) as tgdk_solve. */
 /* IDR(s)(ncyc)-Proj(k) on one right-hand side: the same cycles, projection
  * and cycle tolerance as BiCGStab(ncyc)-Proj(k) (Sec. 4.1 box, step 3 a-d),
  * with IDR(s) as the inner solver of step c (the paper runs s = 4 by
@@ -389,7 +410,14 @@ int tgdk_solve(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int nrh
 int tgdk_solve_idr(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int s, const double* shadow,
                    double kappa, const tgdk_solve_params* params, tgdk_solve_report* report);
 
-int tgdk_solve_instances(int ninst, const tgdk_op* ops, const tgdk_defl* defls,
+/* Several independent instances (each its own operator, deflation space or
+ * NULL, right-hand side and solution, all on the context ctx -- every
+ * operator must belong to it -- and of one dimension) solved together:
+ * every kernel launch covers the tiles of all instances, so small and uneven
+ * grids fill the device in one launch per step.  BiCGStab(ncyc)-Proj(k)
+ * only.  Same parameters and reports (one per instance) as tgdk_solve;
+ * TGDK_E_INVALID for an operator of another context or dimension. */
+int tgdk_solve_instances(tgdk_ctx ctx, int ninst, const tgdk_op* ops, const tgdk_defl* defls,
                          const double* const* b, double* const* x,
                          const tgdk_solve_params* params, tgdk_solve_report* reports);
 
@@ -408,8 +436,9 @@ int tgdk_adjoint_grad_k(tgdk_op fine, const double* lambda, const double* u, dou
  * operator and element type and keeps the fastest for later launches on
  * operators of the same shape.  Results are cached in the file named by the
  * environment variable TGDK_TUNE_CACHE (if set).  Returns the chosen tile
- * height in *tile_y (may be NULL). */
-int tgdk_tune(tgdk_op op, int dtype, int nrhs, int* tile_y);
+ * height in *tile_y (may be NULL).  ctx must be the operator's context
+ * (NULL: the operator's own); kernels are timed on its stream. */
+int tgdk_tune(tgdk_ctx ctx, tgdk_op op, int dtype, int nrhs, int* tile_y);
 
 #ifdef __cplusplus
 }

@@ -32,6 +32,8 @@ Modules and the part of the paper each follows:
   (Sec. 2.2 step 1-2, Sec. 3 phase 1).
 * ``adjoint``    -- gradient of a least-squares loss through a solve, by an
   adjoint solve with ``A^T`` (extension of the method; not in the paper).
+* ``direct``     -- ``x = A^{-1} b`` by a sparse LU factorisation (the plain
+  definition every solve converges to; pins full-size solutions).
 
 Functions whose result has no independent pin are marked "parity unpinned"
 in their docstring.

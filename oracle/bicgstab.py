@@ -76,6 +76,7 @@ class InnerResult:
     mvps: int
     status: str  # "converged", "half", "breakdown", "maxit"
     scalars: list = field(default_factory=list)  # (rho, alpha, omega) per iteration
+    resid: np.ndarray = None  # the recursive residual at exit (s after a half step, else r)
 
 
 def bicgstab_inner(matvec, r0, target, maxit, dtype=np.float64):
@@ -97,7 +98,7 @@ def bicgstab_inner(matvec, r0, target, maxit, dtype=np.float64):
     for it in range(maxit):
         rho = dot(rhat, r)
         if rho == 0.0 or not math.isfinite(rho):
-            return InnerResult(e, it, mvps, "breakdown", scalars)
+            return InnerResult(e, it, mvps, "breakdown", scalars, r)
         if it == 0:
             p = r.copy()
         else:
@@ -107,13 +108,13 @@ def bicgstab_inner(matvec, r0, target, maxit, dtype=np.float64):
         mvps += 1
         sigma = dot(rhat, v)
         if sigma == 0.0 or not math.isfinite(sigma):
-            return InnerResult(e, it, mvps, "breakdown", scalars)
+            return InnerResult(e, it, mvps, "breakdown", scalars, r)
         alpha = rho / sigma
         s = (r - dtype(alpha) * v).astype(dtype)
         if math.sqrt(dot(s, s)) <= target:
             e = (e + dtype(alpha) * p).astype(dtype)
             scalars.append((rho, alpha, float("nan")))
-            return InnerResult(e, it + 1, mvps, "half", scalars)
+            return InnerResult(e, it + 1, mvps, "half", scalars, s)
         t = matvec(s).astype(dtype)
         mvps += 1
         tt = dot(t, t)
@@ -123,10 +124,10 @@ def bicgstab_inner(matvec, r0, target, maxit, dtype=np.float64):
         r = (s - dtype(omega) * t).astype(dtype)
         rho_old = rho
         if omega == 0.0 or not math.isfinite(omega):
-            return InnerResult(e, it + 1, mvps, "breakdown", scalars)
+            return InnerResult(e, it + 1, mvps, "breakdown", scalars, r)
         if math.sqrt(dot(r, r)) <= target:
-            return InnerResult(e, it + 1, mvps, "converged", scalars)
-    return InnerResult(e, maxit, mvps, "maxit", scalars)
+            return InnerResult(e, it + 1, mvps, "converged", scalars, r)
+    return InnerResult(e, maxit, mvps, "maxit", scalars, r)
 
 
 @dataclass

@@ -6,15 +6,12 @@ the fine grid; the projection box of Sec. 2.2 needs an orthonormal ``V``
 spanning them (step 1) and ``H = V^T A V`` (step 2).  ``V`` is the Q factor
 of the thin QR of ``P W_c`` with a positive diagonal in R (the unique thin QR,
 so any correct orthonormalisation with that sign convention agrees with it).
-
-``ritz_report`` is the Rayleigh-Ritz check of Sec. 3, Example 1: the Ritz
-pairs of ``A`` in ``range(V)`` and their residual norms on the fine grid.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import operators, transfer
+from . import transfer
 from .projection import projection_matrix
 
 
@@ -32,18 +29,3 @@ def deflation_space(fine_op, Wc, coarse_dims, transpose=False):
     V = orthonormalize(PW)
     H = projection_matrix(fine_op, V, transpose=transpose)
     return V, H
-
-
-def ritz_report(op, V):
-    """Ritz values of ``A`` in ``range(V)`` and ``||A y - theta y||`` for unit
-    Ritz vectors ``y``, sorted by ``|theta|``."""
-    AV = operators.apply(op, V)
-    H = V.T @ AV
-    theta, G = np.linalg.eig(H)
-    order = np.argsort(np.abs(theta))
-    res = []
-    for i in order:
-        y = V @ G[:, i]
-        ny = np.linalg.norm(y)
-        res.append(float(np.linalg.norm(AV @ G[:, i] - theta[i] * y) / ny))
-    return theta[order], np.array(res)

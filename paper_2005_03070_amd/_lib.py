@@ -62,7 +62,8 @@ class SolveParams(C.Structure):
                 ("x0_given", C.c_int), ("transpose", C.c_int), ("maxit_cycle", C.c_int),
                 ("max_extra_cycles", C.c_int), ("rtol", C.c_double), ("fp32_floor", C.c_double),
                 ("cycle_lengths", C.POINTER(C.c_int)), ("n_cycle_lengths", C.c_int),
-                ("precond", C.c_void_p), ("precond_user", C.c_void_p)]
+                ("precond", C.c_void_p), ("precond_user", C.c_void_p),
+                ("icyc0", C.c_int), ("max_cycles_call", C.c_int), ("nu0", C.c_double)]
 
 
 class SolveReport(C.Structure):
@@ -71,7 +72,9 @@ class SolveReport(C.Structure):
                 ("relres_true", C.c_double), ("seconds", C.c_double), ("branch", C.c_int * 4),
                 ("n_first", C.c_int), ("first_rho", C.c_double * NHIST),
                 ("first_alpha", C.c_double * NHIST), ("first_omega", C.c_double * NHIST),
-                ("n_cycle_mvps", C.c_int), ("cycle_mvps", C.c_int * NCYC_REPORT)]
+                ("n_cycle_mvps", C.c_int), ("cycle_mvps", C.c_int * NCYC_REPORT),
+                ("cycle_branch", C.c_int * NCYC_REPORT), ("nu0", C.c_double),
+                ("mvp_setup", C.c_longlong), ("vops", C.c_longlong)]
 
 
 P = C.c_void_p
@@ -111,9 +114,9 @@ SIGNATURES = [
     ("tgdk_defl_destroy", I, [P]),
     ("tgdk_solve", I, [P, P, P, P, I, C.POINTER(SolveParams), C.POINTER(SolveReport)]),
     ("tgdk_solve_idr", I, [P, P, P, P, I, P, D, C.POINTER(SolveParams), C.POINTER(SolveReport)]),
-    ("tgdk_solve_instances", I, [I, PP, PP, PP, PP, C.POINTER(SolveParams), C.POINTER(SolveReport)]),
+    ("tgdk_solve_instances", I, [P, I, PP, PP, PP, PP, C.POINTER(SolveParams), C.POINTER(SolveReport)]),
     ("tgdk_adjoint_grad_k", I, [P, P, P, P]),
-    ("tgdk_tune", I, [P, I, I, C.POINTER(I)]),
+    ("tgdk_tune", I, [P, P, I, I, C.POINTER(I)]),
     # include/tgdk_host.h
     ("tgdk_host_eig", I, [I, DP, DP, DP, DP, DP]),
     ("tgdk_host_lstsq", I, [I, I, DP, DP, DP, DP]),

@@ -109,12 +109,12 @@ class Operator:
 
     def tune(self, dtype=torch.float64, nrhs=1):
         ty = C.c_int()
-        check(lib().tgdk_tune(self.h, L.F64 if dtype == torch.float64 else L.F32, nrhs, C.byref(ty)))
+        check(lib().tgdk_tune(self.ctx, self.h, L.F64 if dtype == torch.float64 else L.F32, nrhs, C.byref(ty)))
         return ty.value
 
     def __del__(self):
         try:
-            if getattr(self, "h", None) is not None and _lib._lib is not None:
+            if getattr(self, "h", None) is not None and L._lib is not None:
                 lib().tgdk_op_destroy(self.h)
                 self.h = None
         except Exception:
@@ -190,7 +190,7 @@ class DeflationSpace:
 
     def __del__(self):
         try:
-            if getattr(self, "h", None) is not None and _lib._lib is not None:
+            if getattr(self, "h", None) is not None and L._lib is not None:
                 lib().tgdk_defl_destroy(self.h)
                 self.h = None
         except Exception:
@@ -257,7 +257,7 @@ class Multigrid:
 
     def __del__(self):
         try:
-            if getattr(self, "h", None) is not None and _lib._lib is not None:
+            if getattr(self, "h", None) is not None and L._lib is not None:
                 lib().tgdk_mg_destroy(self.h)
                 self.h = None
         except Exception:
@@ -293,14 +293,28 @@ class Report:
     branch: list = field(default_factory=list)
     first_scalars: list = field(default_factory=list)
     cycle_mvps: list = field(default_factory=list)  # inner operator applications of the first cycles
+    cycle_branch: list = field(default_factory=list)  # tolerance criterion of each of the first cycles
+    nu0: float = 0.0       # ||r0|| of the schedule (pass back as nu0= to resume)
+    mvp_setup: int = 0     # fine operator applications that built the deflation space
+    vops: int = 0          # length-n vector operations of this call (the paper's cost model)
+
+    @property
+    def cost(self):
+        """The paper's cost (Sec. 3, Example 1) without the nnz factor: the
+        caller multiplies mvps by the operator's nonzeros per row."""
+        return {"mvps": self.mvp_inner + self.mvp_boundary, "vops": self.vops}
 
     @property
     def status_name(self):
         return L.STATUS_NAMES.get(self.status, str(self.status))
 
 
-def _params(method, ncyc, m3, precision, x0_given, transpose, maxit_cycle, max_extra, rtol, fp32_floor):
+def _params(method, ncyc, m3, precision, x0_given, transpose, maxit_cycle, max_extra, rtol, fp32_floor,
+            icyc0=0, nu0=0.0, max_cycles_call=0):
     p = L.SolveParams()
+    p.icyc0 = int(icyc0)
+    p.nu0 = float(nu0)
+    p.max_cycles_call = int(max_cycles_call)
     p.method = {"gmres": L.GMRES_PROJ, "idr": L.IDRS_PROJ}.get(method, L.BICGSTAB_PROJ)
     p.ncyc = ncyc
     p.m3 = m3
@@ -321,16 +335,19 @@ def _reports(reps):
     for r in reps:
         fs = [(r.first_rho[i], r.first_alpha[i], r.first_omega[i]) for i in range(r.n_first)]
         out.append(Report(r.status, r.cycles, r.iters_inner, r.mvp_inner, r.mvp_boundary, r.relres_true,
-                          r.seconds, list(r.branch), fs, [r.cycle_mvps[i] for i in range(r.n_cycle_mvps)]))
+                          r.seconds, list(r.branch), fs, [r.cycle_mvps[i] for i in range(r.n_cycle_mvps)],
+                          [r.cycle_branch[i] for i in range(r.n_cycle_mvps)], r.nu0, r.mvp_setup, r.vops))
     return out
 
 
 def solve(op, b, x0=None, defl=None, method="bicgstab", ncyc=20, m3=50, precision="fp64", rtol=1e-8,
           transpose=False, maxit_cycle=100000, max_extra=None, fp32_floor=1e-4, out=None, cycle_lengths=None,
-          precond=None):
+          precond=None, icyc0=0, nu0=0.0, max_cycles_call=0):
     """Fine solve of A x = b (A^T x = b if transpose).  b: (n,) or (nrhs, n)
     float64.  cycle_lengths (GMRES): lengths of the first cycles, each in
-    1..m3 (variable restarting).  Returns (x, [Report per right-hand side])."""
+    1..m3 (variable restarting).  icyc0, nu0, max_cycles_call: resuming at a
+    cycle boundary (see include/tgdk.h, tgdk_solve_params).  Returns
+    (x, [Report per right-hand side])."""
     nrhs = 1 if b.dim() == 1 else b.shape[0]
     _ptr(b, numel=op.n * nrhs, what="b")
     if out is None:
@@ -338,7 +355,8 @@ def solve(op, b, x0=None, defl=None, method="bicgstab", ncyc=20, m3=50, precisio
     _ptr(out, numel=op.n * nrhs, what="x")
     if x0 is not None:
         out.copy_(x0)
-    p = _params(method, ncyc, m3, precision, x0 is not None, transpose, maxit_cycle, max_extra, rtol, fp32_floor)
+    p = _params(method, ncyc, m3, precision, x0 is not None, transpose, maxit_cycle, max_extra, rtol, fp32_floor,
+                icyc0, nu0, max_cycles_call)
     if cycle_lengths is not None:
         lens = (C.c_int * len(cycle_lengths))(*[int(v) for v in cycle_lengths])
         p.cycle_lengths = C.cast(lens, C.POINTER(C.c_int))
@@ -351,7 +369,8 @@ def solve(op, b, x0=None, defl=None, method="bicgstab", ncyc=20, m3=50, precisio
 
 
 def solve_idr(op, b, s=4, shadow=None, x0=None, defl=None, ncyc=20, precision="fp64", rtol=1e-8, kappa=0.7,
-              transpose=False, maxit_cycle=100000, max_extra=None, fp32_floor=1e-4, seed=0, out=None, precond=None):
+              transpose=False, maxit_cycle=100000, max_extra=None, fp32_floor=1e-4, seed=0, out=None, precond=None,
+              icyc0=0, nu0=0.0, max_cycles_call=0):
     """IDR(s)(ncyc)-Proj(k) on A x = b (one right-hand side, b of shape (n,)
     float64).  shadow: (s, n) float64 device tensor, the raw columns of the
     shadow space (orthonormalised by the library); None draws s standard
@@ -369,7 +388,8 @@ def solve_idr(op, b, s=4, shadow=None, x0=None, defl=None, ncyc=20, precision="f
     _ptr(out, numel=op.n, what="x")
     if x0 is not None:
         out.copy_(x0)
-    p = _params("idr", ncyc, 0, precision, x0 is not None, transpose, maxit_cycle, max_extra, rtol, fp32_floor)
+    p = _params("idr", ncyc, 0, precision, x0 is not None, transpose, maxit_cycle, max_extra, rtol, fp32_floor,
+                icyc0, nu0, max_cycles_call)
     p.precond, p.precond_user = _precond(precond)
     rep = L.SolveReport()
     check(lib().tgdk_solve_idr(op.h, defl.h if defl is not None else None, C.c_void_p(b.data_ptr()),
@@ -389,12 +409,13 @@ def solve_instances(ops, defls, bs, x0s=None, ncyc=20, precision="fp64", rtol=1e
         if x0s is not None:
             outs[j].copy_(x0s[j])
     p = _params("bicgstab", ncyc, 0, precision, x0s is not None, False, maxit_cycle, max_extra, rtol, fp32_floor)
+    ctx = ops[0].ctx
     oph = (C.c_void_p * ni)(*[o.h.value for o in ops])
     dh = (C.c_void_p * ni)(*[(d.h.value if d is not None else None) for d in defls]) if defls else None
     bp = (C.c_void_p * ni)(*[b.data_ptr() for b in bs])
     xp = (C.c_void_p * ni)(*[x.data_ptr() for x in outs])
     reps = (L.SolveReport * ni)()
-    check(lib().tgdk_solve_instances(ni, oph, dh, bp, xp, C.byref(p), reps))
+    check(lib().tgdk_solve_instances(ctx, ni, oph, dh, bp, xp, C.byref(p), reps))
     return outs, _reports(reps)
 
 

@@ -248,6 +248,7 @@ int defl_finish(tgdk_op op, int transpose, double* V64, int k, int store, tgdk_d
     d->projection = minres ? TGDK_PROJ_MINRES : TGDK_PROJ_GALERKIN;
     d->W = W;
     d->H = H;
+    d->mvp_build = k;
     if ((rc = defl_factor(d, minres ? "projection matrix H = (AV)^T AV is singular"
                                     : "projection matrix H = V^T A V is singular"))) {
         if (V32) (void)hipFree(V32);
@@ -611,6 +612,7 @@ int tgdk_defl_precond(tgdk_defl g, tgdk_precond_fn fn, void* user, tgdk_defl* ou
     d->V = Z;  // update basis
     d->W = V;  // basis of c = V^T r
     d->H = H;
+    d->mvp_build = k;  // A Z (plus k applications of the preconditioner)
     if ((rc = defl_factor(d, "projection matrix H = V^T A M^{-1} V is singular"))) {
         delete d;
         release();
@@ -664,8 +666,9 @@ int tgdk_adjoint_grad_k(tgdk_op op, const double* lambda, const double* u, doubl
     return TGDK_OK;
 }
 
-int tgdk_tune(tgdk_op op, int dtype, int nrhs, int* tile_y) {
+int tgdk_tune(tgdk_ctx ctx, tgdk_op op, int dtype, int nrhs, int* tile_y) {
     if (!op || nrhs < 1 || (dtype != TGDK_F64 && dtype != TGDK_F32)) return fail(TGDK_E_INVALID, "bad argument");
+    if (ctx && ctx != op->ctx) return fail(TGDK_E_INVALID, "the operator belongs to another context");
     TGDK_HIP(hipSetDevice(op->ctx->device));
     const char* cache = getenv("TGDK_TUNE_CACHE");
     char key[160];

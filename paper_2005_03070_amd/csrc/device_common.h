@@ -245,6 +245,36 @@ __device__ __forceinline__ void st_stream(gptr<T> p, T v) {
         *p = v;
 }
 
+// Sec. 4.1, step 3 b): the relative tolerance rt of inner cycle icyc
+// (1-based, of ncyc requested) that starts from a residual of norm nu, given
+// the initial residual norm nu0 and the overall tolerance tau (rtol ||r0||
+// in the paper).  Criterion 1 shares the remaining orders of magnitude
+// equally over the cycles left; criterion 2 asks the cycle to reach at
+// least the geometric schedule's value for icyc; the smaller one is taken
+// (ties count as criterion 1).  Past ncyc the cycle aims straight at tau.
+// float32 inner cycles are floored at fp32_floor.  Returns the criterion
+// (1, 2, or 3 past ncyc).  The one definition for every solver driver.
+__device__ __forceinline__ int cycle_tolerance(double nu, double nu0, double tau, int icyc, int ncyc, int fp32,
+                                               double fp32_floor, double& rt) {
+    int branch;
+    if (icyc > ncyc) {
+        rt = tau / nu;
+        branch = 3;
+    } else {
+        const double t1 = pow(tau / nu, 1.0 / (double)(ncyc - icyc + 1));
+        const double t2 = (nu0 / nu) * pow(tau / nu0, (double)icyc / (double)ncyc);
+        if (t1 <= t2) {
+            rt = t1;
+            branch = 1;
+        } else {
+            rt = t2;
+            branch = 2;
+        }
+    }
+    if (fp32 == 1 && rt < fp32_floor) rt = fp32_floor;
+    return branch;
+}
+
 __device__ __forceinline__ bool inside(const DevOp& op, int gx, int gy, int gz) {
     return gx >= 0 && gx < op.nx && gy >= 0 && gy < op.ny && gz >= 0 && gz < op.nz;
 }

@@ -87,6 +87,7 @@ struct tgdk_defl_s {
     double* d_lu = nullptr;
     int* d_piv = nullptr;
     double* d_hinv = nullptr;  // H^{-1}, column-major
+    long long mvp_build = 0;   // fine-grid operator applications spent building it (A V for H)
 };
 
 namespace tgdk {

@@ -21,28 +21,15 @@ __device__ __forceinline__ void mirror_out(const DevProb& P, const SolveState* s
     }
 }
 
-// Sec. 4.1 step 3 b): tolerance of the cycle that starts with residual nu.
+// Start of an inner cycle from a residual of norm nu: its tolerance
+// (Sec. 4.1 step 3 b, cycle_tolerance) and fresh scalars.
 __device__ void start_cycle(SolveState* st, double nu, double rho0) {
     double rt;
-    int branch;
-    if (st->icyc > st->ncyc) {
-        rt = st->tau / nu;
-        branch = 3;
-    } else {
-        const double t1 = pow(st->tau / nu, 1.0 / (double)(st->ncyc - st->icyc + 1));
-        const double t2 = (st->nu0 / nu) * pow(st->tau / st->nu0, (double)st->icyc / (double)st->ncyc);
-        if (t1 <= t2) {
-            rt = t1;
-            branch = 1;
-        } else {
-            rt = t2;
-            branch = 2;
-        }
-    }
-    if (st->precision == 1 && rt < st->fp32_floor) rt = st->fp32_floor;
+    const int branch = cycle_tolerance(nu, st->nu0, st->tau, st->icyc, st->ncyc, st->precision, st->fp32_floor, rt);
     st->rt = rt;
     st->target2 = (rt * nu) * (rt * nu);
     st->branch[branch] += 1;
+    if (st->icyc >= 1 && st->icyc <= NCYCLOG) st->cyc_branch[st->icyc - 1] = branch;
     st->rho = rho0;
     st->rho_old = 1.0;
     st->alpha = 1.0;
@@ -131,13 +118,17 @@ __global__ __launch_bounds__(NT) void k_epi_residual(const DevProb* __restrict__
     const double nu = sqrt(rr);
     st->nu = nu;
     if (first) {
+        // a resumed solve keeps its first call's nu0 and tau (st->icyc
+        // starts at icyc0)
         st->bnorm = sqrt(bb);
-        st->nu0 = nu;
-        st->tau = st->rtol * fmin(st->bnorm, nu);
+        st->nu0 = st->nu0_in > 0.0 ? st->nu0_in : nu;
+        st->tau = st->rtol * fmin(st->bnorm, st->nu0);
         if (!isfinite(nu))
             st->solve_state = SV_NONFINITE;
         else if (nu <= st->tau || nu == 0.0)
             st->solve_state = SV_CONVERGED;
+        else if (st->icyc > 0 && st->icyc >= st->ncyc + st->max_extra)
+            st->solve_state = SV_NOT_CONVERGED;
     } else {
         if (st->icyc >= 1 && st->icyc <= NCYCLOG) {
             st->cyc_iters[st->icyc - 1] = st->iter;
@@ -152,6 +143,8 @@ __global__ __launch_bounds__(NT) void k_epi_residual(const DevProb* __restrict__
                            (st->method == METHOD_IDR && st->iter <= 1)))
             st->solve_state = SV_BREAKDOWN;
         else if (st->icyc >= st->ncyc + st->max_extra)
+            st->solve_state = SV_NOT_CONVERGED;
+        else if (st->maxcyc_call > 0 && st->icyc - st->icyc0 >= st->maxcyc_call)
             st->solve_state = SV_NOT_CONVERGED;
     }
     if (st->solve_state == SV_RUNNING) {
@@ -327,6 +320,7 @@ __global__ __launch_bounds__(NT) void k_epi_proj_apply(const DevProb* __restrict
     const double rr = sums[0], ri = sums[1];
     if (threadIdx.x != 0) return;
     st->mvp_boundary += 1;
+    st->nproj += 1;
     const double nu = sqrt(rr);
     st->nu = nu;
     if (!isfinite(nu))

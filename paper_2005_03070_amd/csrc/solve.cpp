@@ -315,11 +315,17 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
         S.precision = g.inner_f32;
         S.solve_state = SV_RUNNING;
         S.inner_state = IN_CONVERGED;
+        // resuming at a cycle boundary: the cycle count continues from icyc0
+        S.icyc0 = prm->icyc0;
+        S.icyc = prm->icyc0;
+        S.maxcyc_call = prm->max_cycles_call;
+        S.nu0_in = prm->nu0;
         // the step kernel starts with the true residual of x0
         StepHot h;
         memset(&h, 0, sizeof(h));
         h.mode = M_RES;
         h.first = 1;
+        h.icyc = prm->icyc0;
         h.solve_state = SV_RUNNING;
         h.inner_state = IN_CONVERGED;
         S.hot[0] = h;
@@ -350,10 +356,47 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
     return TGDK_OK;
 }
 
+// Length-n vector operations of a solve in the paper's cost model (Sec. 3,
+// Example 1: cost = nnz * mvps + vops; a dot product, a norm or an update
+// y += a x counts one), from the counts of the run:
+//  - BiCGStab iteration: rho, p (two updates), sigma, s, ||s||, t.s, t.t,
+//    e (two updates), r, ||r||: 12; a half-step exit: rho, p, sigma, s,
+//    ||s||, e: 7;
+//  - GMRES cycle of j steps (CGS2): step i has two passes of i products and
+//    i updates, the norm and the scaling (4i + 2), then r / ||r|| and
+//    x += V y (j): 2 j^2 + 5 j + 1;
+//  - IDR(s) (biorthogonal), per round of s + 1 operator applications: step k
+//    forms u_k (2 (s - k) + 1), P^T g_k (s), orthogonalises g_k and u_k
+//    against the earlier ones (2 k), forms M's column (s - k) and updates r,
+//    e and ||r|| (3); the dimension reduction takes t.t, t.r, r.r, updates
+//    e and r, forms P^T r and ||r|| (s + 6);
+//  - every true residual r = b - A x with its norm and the x update: 3;
+//    every projection: c = V^T r (k), V d (k), x, r and ||r|| (3).
+static long long count_vops(const SolveState& S, int k, int idr_s, const std::vector<int>* cycle_steps) {
+    const long long nres = S.mvp_boundary - S.nproj;
+    long long v = 3 * nres + (2LL * k + 3) * S.nproj;
+    if (S.method == METHOD_BICGSTAB) {
+        long long half = 0;
+        const int nc = std::min(S.icyc, NCYCLOG);
+        for (int c = S.icyc0; c < nc; ++c) half += S.cyc_end[c] == IN_HALF ? 1 : 0;
+        v += 12 * (S.iters_total - half) + 7 * half;
+    } else if (S.method == METHOD_GMRES && cycle_steps) {
+        for (int j : *cycle_steps) v += 2LL * j * j + 5LL * j + 1;
+    } else if (S.method == METHOD_IDR && idr_s > 0) {
+        const long long s = idr_s;
+        long long round = s + 6;
+        for (long long q = 0; q < s; ++q) round += 2 * (s - q) + 1 + s + 2 * q + (s - q) + 3;
+        v += (round * S.mvp_inner) / (s + 1);
+    }
+    return v;
+}
+
 // cycle_steps: the GMRES driver's steps per cycle (one right-hand side);
 // the other solvers' per-cycle counts come from the device's cycle log.
+// idr_s: the shadow-space dimension of an IDR(s) solve (0 otherwise).
 static int finish_group(Group& g, const std::vector<ProbSpec>& ps, tgdk_solve_report* reps, double secs,
-                        const std::vector<long long>* extra_inner, const std::vector<int>* cycle_steps = nullptr) {
+                        const std::vector<long long>* extra_inner, const std::vector<int>* cycle_steps = nullptr,
+                        int idr_s = 0) {
     hipStream_t s = g.ctx->stream;
     launch(g, K_RESIDUAL, 2);
     TGDK_HIP(hipGetLastError());
@@ -385,7 +428,9 @@ static int finish_group(Group& g, const std::vector<ProbSpec>& ps, tgdk_solve_re
         for (int c = 0; c < nc; ++c) {
             int mv;
             if (S.method == METHOD_GMRES)
-                mv = cycle_steps && c < (int)cycle_steps->size() ? (*cycle_steps)[c] : 0;
+                mv = cycle_steps && c >= S.icyc0 && c - S.icyc0 < (int)cycle_steps->size()
+                         ? (*cycle_steps)[c - S.icyc0]
+                         : 0;
             else if (S.method == METHOD_IDR)
                 mv = S.cyc_iters[c];
             else
@@ -393,10 +438,13 @@ static int finish_group(Group& g, const std::vector<ProbSpec>& ps, tgdk_solve_re
             R.cycle_mvps[c] = mv;
         }
         R.n_cycle_mvps = nc;
+        for (int c = 0; c < nc; ++c) R.cycle_branch[c] = c >= S.icyc0 ? S.cyc_branch[c] : 0;
+        R.nu0 = S.nu0;
+        R.mvp_setup = ps[j].defl ? ps[j].defl->mvp_build : 0;
+        R.vops = count_vops(S, g.probs[j].k, idr_s, cycle_steps);
         if (R.status == TGDK_E_NONFINITE) set_error("non-finite residual (check b, x0 and the operator)");
         rc = worst(rc, R.status);
     }
-    (void)ps;
     return rc;
 }
 
@@ -777,7 +825,7 @@ static int idr_single(tgdk_ctx ctx, const ProbSpec& p, int s, const double* shad
         IDR_HIP(hipStreamSynchronize(hs));
     }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    rc = finish_group(g, ps, rep, secs, nullptr);
+    rc = finish_group(g, ps, rep, secs, nullptr, nullptr, s);
     return done(rc);
 #undef IDR_HIP
 }
@@ -806,6 +854,9 @@ static int check_params(const tgdk_solve_params* prm) {
         if (prm->precision != TGDK_FP64) return fail(TGDK_E_INVALID, "preconditioned solves run in float64");
     }
     if (!(prm->rtol > 0.0)) return fail(TGDK_E_INVALID, "rtol must be > 0");
+    if (prm->icyc0 < 0 || prm->max_cycles_call < 0 || !(prm->nu0 >= 0.0))
+        return fail(TGDK_E_INVALID, "icyc0, max_cycles_call and nu0 must be >= 0");
+    if (prm->icyc0 > 0 && !prm->x0_given) return fail(TGDK_E_INVALID, "a resumed solve (icyc0 > 0) needs x0_given");
     return TGDK_OK;
 }
 
@@ -858,23 +909,23 @@ int tgdk_solve_idr(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int
     return idr_single(fine->ctx, ProbSpec{fine, defl, b, x}, s, shadow, kappa, prm, report);
 }
 
-int tgdk_solve_instances(int ninst, const tgdk_op* ops, const tgdk_defl* defls, const double* const* b,
+int tgdk_solve_instances(tgdk_ctx ctx, int ninst, const tgdk_op* ops, const tgdk_defl* defls, const double* const* b,
                          double* const* x, const tgdk_solve_params* prm, tgdk_solve_report* reports) {
-    if (ninst < 1 || !ops || !b || !x || !reports) return fail(TGDK_E_INVALID, "bad argument");
+    if (!ctx || ninst < 1 || !ops || !b || !x || !reports) return fail(TGDK_E_INVALID, "bad argument");
     int rc = check_params(prm);
     if (rc) return rc;
     if (prm->method != TGDK_BICGSTAB_PROJ) return fail(TGDK_E_INVALID, "instances use BiCGStab-Proj");
     std::vector<ProbSpec> ps(ninst);
     for (int j = 0; j < ninst; ++j) {
         if (!ops[j] || !b[j] || !x[j]) return fail(TGDK_E_INVALID, "NULL instance");
-        if (ops[j]->ctx != ops[0]->ctx || ops[j]->dim != ops[0]->dim)
-            return fail(TGDK_E_INVALID, "instances must share a context and a dimension");
+        if (ops[j]->ctx != ctx || ops[j]->dim != ops[0]->dim)
+            return fail(TGDK_E_INVALID, "instances must belong to the context and share a dimension");
         tgdk_defl d = defls ? defls[j] : nullptr;
         if ((rc = check_defl(ops[j], d, prm))) return rc;
         ps[j] = ProbSpec{ops[j], d, b[j], x[j]};
     }
-    TGDK_HIP(hipSetDevice(ops[0]->ctx->device));
-    return bicgstab_group(ops[0]->ctx, ps, prm, reports);
+    TGDK_HIP(hipSetDevice(ctx->device));
+    return bicgstab_group(ctx, ps, prm, reports);
 }
 
 }  // extern "C"

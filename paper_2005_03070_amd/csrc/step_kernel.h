@@ -52,26 +52,11 @@ struct Upd {
     int any, pbuf;
 };
 
-// Sec. 4.1 step 3 b): the relative tolerance of the inner cycle that starts
-// from a residual of norm nu; returns the branch taken (1, 2 or 3).
+// Start of an inner cycle from a residual of norm nu: its tolerance
+// (Sec. 4.1 step 3 b, cycle_tolerance) and fresh BiCGStab scalars; returns
+// the criterion taken (1, 2 or 3).
 __device__ __forceinline__ int cycle_start(StepHot& N, const SolveState* st, double nu, double rho0, double& rt) {
-    int branch;
-    const int ncyc = st->ncyc;
-    if (N.icyc > ncyc) {
-        rt = N.tau / nu;
-        branch = 3;
-    } else {
-        const double t1 = pow(N.tau / nu, 1.0 / (double)(ncyc - N.icyc + 1));
-        const double t2 = (N.nu0 / nu) * pow(N.tau / N.nu0, (double)N.icyc / (double)ncyc);
-        if (t1 <= t2) {
-            rt = t1;
-            branch = 1;
-        } else {
-            rt = t2;
-            branch = 2;
-        }
-    }
-    if (st->precision == 1 && rt < st->fp32_floor) rt = st->fp32_floor;
+    const int branch = cycle_tolerance(nu, N.nu0, N.tau, N.icyc, st->ncyc, st->precision, st->fp32_floor, rt);
     N.target2 = (rt * nu) * (rt * nu);
     N.rho = rho0;
     N.rho_old = 1.0;
@@ -89,13 +74,18 @@ __device__ __forceinline__ int cycle_start(StepHot& N, const SolveState* st, dou
 __device__ __forceinline__ void boundary_tests(const StepHot& H, StepHot& N, const SolveState* st, double nu,
                                                double bb) {
     if (H.first) {
+        // a resumed solve keeps the schedule of its first call: nu0 and
+        // tau = rtol min(||b||, nu0) come from there, and it starts at cycle
+        // icyc0 + 1 (H.icyc = icyc0)
         N.bnorm = sqrt(bb);
-        N.nu0 = nu;
-        N.tau = st->rtol * fmin(N.bnorm, nu);
+        N.nu0 = st->nu0_in > 0.0 ? st->nu0_in : nu;
+        N.tau = st->rtol * fmin(N.bnorm, N.nu0);
         if (!isfinite(nu))
             N.solve_state = SV_NONFINITE;
         else if (nu <= N.tau || nu == 0.0)
             N.solve_state = SV_CONVERGED;
+        else if (H.icyc > 0 && H.icyc >= st->ncyc + st->max_extra)
+            N.solve_state = SV_NOT_CONVERGED;
     } else {
         const bool broke = H.inner_state == IN_BREAK_NOUPD || H.inner_state == IN_BREAK_FULL;
         if (!isfinite(nu))
@@ -105,6 +95,8 @@ __device__ __forceinline__ void boundary_tests(const StepHot& H, StepHot& N, con
         else if (broke && H.iter == 0)
             N.solve_state = SV_BREAKDOWN;
         else if (H.icyc >= st->ncyc + st->max_extra)
+            N.solve_state = SV_NOT_CONVERGED;
+        else if (st->maxcyc_call > 0 && H.icyc - st->icyc0 >= st->maxcyc_call)
             N.solve_state = SV_NOT_CONVERGED;
     }
     N.first = 0;
@@ -220,6 +212,7 @@ __device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* s
             const int br = cycle_start(N, st, nu, s[2], rt);
             if (scribe) {
                 st->branch[br] += 1;
+                if (N.icyc >= 1 && N.icyc <= NCYCLOG) st->cyc_branch[N.icyc - 1] = br;
                 st->rt = rt;
             }
             rr0_out = rr_out = s[0];
@@ -238,6 +231,7 @@ __device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* s
             const double nu = sqrt(s[0]);
             if (scribe) {
                 st->mvp_boundary += 1;
+                st->nproj += 1;
                 st->nu = nu;
             }
             if (!isfinite(nu))
@@ -252,6 +246,7 @@ __device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* s
             const int br = cycle_start(N, st, nu, s[1], rt);
             if (scribe) {
                 st->branch[br] += 1;
+                if (N.icyc >= 1 && N.icyc <= NCYCLOG) st->cyc_branch[N.icyc - 1] = br;
                 st->rt = rt;
             }
             rr0_out = rr_out = s[0];

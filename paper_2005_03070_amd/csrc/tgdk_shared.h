@@ -92,9 +92,14 @@ struct SolveState {
     int nhist;
     int branch[4];
     long long iters_total, mvp_inner, mvp_boundary;
+    long long nproj;         // projections applied (each one boundary operator application)
     double hist[3 * NHIST];
     int cyc_iters[NCYCLOG];  // inner iterations of each finished cycle
     int cyc_end[NCYCLOG];    // inner state that ended it
+    int cyc_branch[NCYCLOG];  // cycle tolerance criterion of each started cycle (1, 2, 3)
+    int icyc0;               // cycles completed by earlier calls (resume); the first cycle here is icyc0 + 1
+    int maxcyc_call;         // > 0: stop after this many cycles in this call
+    double nu0_in;           // > 0: the initial residual norm of the resumed solve
     double d[MAXK + 1];      // projection coefficients (H d = c)
     double cvec[MAXK + 1];
 };

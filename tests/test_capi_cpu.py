@@ -42,16 +42,20 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header(tmp_path):
     src = tmp_path / "sizes.c"
     src.write_text('#include "tgdk.h"\n#include <stdio.h>\n#include <stddef.h>\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(tgdk_op_desc),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(tgdk_op_desc),'
                    ' sizeof(tgdk_gmresdr_params), sizeof(tgdk_gmresdr_report), sizeof(tgdk_solve_params),'
                    ' sizeof(tgdk_solve_report), offsetof(tgdk_solve_report, first_rho),'
-                   ' offsetof(tgdk_gmresdr_report, seconds)); return 0;}\n')
+                   ' offsetof(tgdk_gmresdr_report, seconds), offsetof(tgdk_solve_params, nu0),'
+                   ' offsetof(tgdk_solve_params, icyc0), offsetof(tgdk_solve_report, cycle_branch),'
+                   ' offsetof(tgdk_solve_report, vops)); return 0;}\n')
     exe = tmp_path / "sizes"
     subprocess.run(["gcc", "-I", INCLUDE, str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     L = _lib()
     want = [C.sizeof(L.OpDesc), C.sizeof(L.GmresDrParams), C.sizeof(L.GmresDrReport), C.sizeof(L.SolveParams),
-            C.sizeof(L.SolveReport), L.SolveReport.first_rho.offset, L.GmresDrReport.seconds.offset]
+            C.sizeof(L.SolveReport), L.SolveReport.first_rho.offset, L.GmresDrReport.seconds.offset,
+            L.SolveParams.nu0.offset, L.SolveParams.icyc0.offset, L.SolveReport.cycle_branch.offset,
+            L.SolveReport.vops.offset]
     assert got == want
 
 

@@ -77,10 +77,14 @@ def test_inner_bicgstab_invariants():
     t = mv(s)
     r1 = s - omega * t
     assert abs(t @ r1) < 1e-12 * np.linalg.norm(t) * np.linalg.norm(r1)
-    # true vs recursive residual after 6 iterations
-    e = res.e
-    full = B.bicgstab_inner(mv, r0, 0.0, 6)
-    assert np.allclose(full.e, e)
+    # the recursive residual after 6 iterations equals the true one r0 - A e
+    assert res.status == "maxit" and res.iters == 6
+    drift = np.linalg.norm(res.resid - (r0 - mv(res.e)))
+    assert drift <= 1e-12 * np.linalg.norm(r0)
+    # and after a half-step exit (the residual is s)
+    half = B.bicgstab_inner(mv, r0, 1.001 * np.linalg.norm(s), 6)
+    assert half.status == "half" and half.iters == 1
+    assert np.linalg.norm(half.resid - (r0 - mv(half.e))) <= 1e-12 * np.linalg.norm(r0)
 
 
 def test_bicgstab_scalar_operator_one_half_step():
