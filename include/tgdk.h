@@ -83,15 +83,21 @@ int tgdk_ctx_create(tgdk_ctx* out, int device, void* hip_stream);
 int tgdk_ctx_destroy(tgdk_ctx ctx);
 /* Number of compute units of the context's device (for launch sizing). */
 int tgdk_ctx_num_cus(tgdk_ctx ctx);
-/* Measurement hook.  on = 1 makes every launch of the BiCGStab step kernel
- * inside tgdk_solve / tgdk_solve_instances (first 4096 launches of a call)
- * record its duration -- last end minus first start of the workgroups of the
- * group's first problem, on the device's constant-rate wall clock -- and what
- * that problem did in it; on = 0 switches it off.  Both calls clear the
- * totals.  tgdk_ctx_kernel_time returns, for one action
+/* Measurement hook for the BiCGStab step kernel inside tgdk_solve /
+ * tgdk_solve_instances (the first 4096 launches of a call): each launch's
+ * duration is added to the total of what the group's first problem did in it.
+ *  on = 2: durations from HIP timing events, one recorded on the context's
+ *          stream before the first launch and one after every launch (the
+ *          time between two events: the launch plus the gap before it);
+ *  on = 1: durations from the device's constant-rate wall clock, last end
+ *          minus first start of the first problem's workgroups;
+ *  on = 0: off.
+ * Every call clears the totals.  tgdk_ctx_kernel_time returns, for one action
  * (TGDK_STEP_*), the summed duration in ms of the launches in which the first
- * problem did it and their number; TGDK_STEP_ANY sums every launch in which it
- * did work.  Actions: */
+ * problem did it and their number; TGDK_STEP_ANY sums the launches in which it
+ * did work, TGDK_STEP_ALL every launch (including those queued past the end of
+ * its solve).  Actions: */
+#define TGDK_STEP_NONE   0  /* nothing (the problem had finished, or another problem's launch) */
 #define TGDK_STEP_A      1  /* phase A of iteration i > 0: r, e, p updates, v = A p, r^.v and ||r||^2 partials */
 #define TGDK_STEP_A0     2  /* phase A of iteration 0 of a cycle (p = r) */
 #define TGDK_STEP_B      3  /* phase B: s = r - alpha v, t = A s, five dot-product partials */
@@ -102,6 +108,7 @@ int tgdk_ctx_num_cus(tgdk_ctx ctx);
 #define TGDK_STEP_FIN_A0 8  /* update folded into x and phase A of iteration 0 (no deflation) */
 #define TGDK_STEP_APPLYW 9  /* 3-D: w = V d and x += update + w (APPLY then does r -= A w) */
 #define TGDK_STEP_ANY   -1
+#define TGDK_STEP_ALL   -2
 int tgdk_ctx_time_kernel(tgdk_ctx ctx, int on);
 int tgdk_ctx_kernel_time(tgdk_ctx ctx, int action, double* total_ms, long long* launches);
 

@@ -142,6 +142,7 @@ class SolveReport:
     inner_iters: list = field(default_factory=list)
     cycle_mvps: list = field(default_factory=list)     # inner operator applications per cycle
     first_scalars: list = field(default_factory=list)  # first 8 inner (rho, alpha, omega), across cycles
+    cycle_nu: list = field(default_factory=list)   # (nu, nu0, tau, icyc, ncyc) at each cycle start
 
 
 def bicgstab_proj(op, b, x0=None, V=None, H=None, rtol=1e-8, ncyc=20,
@@ -178,6 +179,7 @@ def bicgstab_proj(op, b, x0=None, V=None, H=None, rtol=1e-8, ncyc=20,
         if nu <= tau:                                   # step d) (after projection)
             break
         rt, branch = cycle_tolerance(nu, nu0, tau, icyc, ncyc)   # step b)
+        rep.cycle_nu.append((nu, nu0, tau, icyc, ncyc))          # what decided the branch
         if precision == "fp32_ir":
             rt = max(rt, fp32_floor)
         inner = bicgstab_inner(mv, r, rt * nu, maxit_cycle, dtype=inner_dtype)  # step c)

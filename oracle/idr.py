@@ -191,6 +191,7 @@ def idrs_proj(op, b, P, x0=None, V=None, H=None, rtol=1e-8, ncyc=20, max_extra=N
         if nu <= tau:
             break
         rt, branch = cycle_tolerance(nu, nu0, tau, icyc, ncyc)   # step b)
+        rep.cycle_nu.append((nu, nu0, tau, icyc, ncyc))          # what decided the branch
         if precision == "fp32_ir":
             rt = max(rt, fp32_floor)
         inner = idrs_inner(mvc, r, rt * nu, Pin, maxit_cycle, kappa=kappa, dtype=inner_dtype)  # step c)

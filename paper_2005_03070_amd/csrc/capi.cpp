@@ -307,19 +307,28 @@ int tgdk_ctx_destroy(tgdk_ctx c) {
     if (c->zero) (void)hipFree(c->zero);
     if (c->mirror) (void)hipHostFree(c->mirror);
     for (auto e : c->events) (void)hipEventDestroy(e);
+    for (auto e : c->tevents) (void)hipEventDestroy(e);
     delete c;
     return TGDK_OK;
 }
 
 int tgdk_ctx_num_cus(tgdk_ctx c) { return c ? c->num_cus : 0; }
 
-static_assert(TGDK_STEP_A == ACT_A && TGDK_STEP_A0 == ACT_A0 && TGDK_STEP_B == ACT_B && TGDK_STEP_RES == ACT_RES &&
+static_assert(TGDK_STEP_NONE == ACT_NONE && TGDK_STEP_A == ACT_A && TGDK_STEP_A0 == ACT_A0 && TGDK_STEP_B == ACT_B && TGDK_STEP_RES == ACT_RES &&
                   TGDK_STEP_REDUCE == ACT_REDUCE && TGDK_STEP_APPLY == ACT_APPLY && TGDK_STEP_FIN == ACT_FIN &&
                   TGDK_STEP_FIN_A0 == ACT_FIN_A0 && TGDK_STEP_APPLYW == ACT_APPLYW && NACT == 10,
               "step action codes");
 
 int tgdk_ctx_time_kernel(tgdk_ctx c, int on) {
-    if (!c || on < 0 || on > 1) return fail(TGDK_E_INVALID, "bad argument");
+    if (!c || on < 0 || on > 2) return fail(TGDK_E_INVALID, "bad argument");
+    if (on == 2 && c->tevents.empty()) {
+        TGDK_HIP(hipSetDevice(c->device));
+        for (int i = 0; i <= NTSLOG; ++i) {
+            hipEvent_t e;
+            TGDK_HIP(hipEventCreate(&e));
+            c->tevents.push_back(e);
+        }
+    }
     c->time_which = on;
     for (int a = 0; a < NACT; ++a) {
         c->act_ms[a] = 0.0;
@@ -330,11 +339,12 @@ int tgdk_ctx_time_kernel(tgdk_ctx c, int on) {
 
 int tgdk_ctx_kernel_time(tgdk_ctx c, int action, double* total_ms, long long* launches) {
     if (!c) return fail(TGDK_E_INVALID, "NULL context");
-    if (action != TGDK_STEP_ANY && (action < 1 || action >= NACT)) return fail(TGDK_E_INVALID, "unknown action");
+    if (action != TGDK_STEP_ANY && action != TGDK_STEP_ALL && (action < 0 || action >= NACT))
+        return fail(TGDK_E_INVALID, "unknown action");
     double ms = 0.0;
     long long cnt = 0;
-    for (int a = 1; a < NACT; ++a)
-        if (action == TGDK_STEP_ANY || action == a) {
+    for (int a = 0; a < NACT; ++a)
+        if (action == TGDK_STEP_ALL || (action == TGDK_STEP_ANY && a > 0) || action == a) {
             ms += c->act_ms[a];
             cnt += c->act_count[a];
         }

@@ -120,10 +120,15 @@ double cond_estimate_lu(int n, const double* LU) {
 
 int cholesky_upper(int n, double* G) {
     // G (row-major, symmetric) -> upper triangular R with G = R^T R; lower part zeroed.
+    // A pivot below 64 eps of its diagonal entry (the column keeps less than
+    // about 1.2e-7 of its norm outside the span of the earlier ones) counts
+    // as rank deficient: exact duplicates leave a rounding-size positive
+    // pivot, and a Cholesky QR of such a basis would not be orthonormal.
     for (int j = 0; j < n; ++j) {
-        double d = G[j * n + j];
+        const double g0 = G[j * n + j];
+        double d = g0;
         for (int k = 0; k < j; ++k) d -= G[k * n + j] * G[k * n + j];
-        if (!(d > 0.0) || !std::isfinite(d)) return j + 1;
+        if (!(d > 64.0 * 2.220446049250313e-16 * g0) || !std::isfinite(d)) return j + 1;
         const double r = std::sqrt(d);
         G[j * n + j] = r;
         for (int c = j + 1; c < n; ++c) {

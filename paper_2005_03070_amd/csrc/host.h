@@ -47,8 +47,10 @@ struct tgdk_ctx_s {
     tgdk::Mirror* mirror = nullptr;  // host-mapped
     int mirror_cap = 0;
     std::vector<hipEvent_t> events;
-    // step-kernel timing for measurement (0 off, 1 on)
+    // step-kernel timing for measurement: 0 off, 1 device-clock stamps,
+    // 2 a HIP timing event after every step launch (tevents)
     int time_which = 0;
+    std::vector<hipEvent_t> tevents;
     double act_ms[tgdk::NACT] = {0};          // summed duration per action of the first problem
     long long act_count[tgdk::NACT] = {0};
 };

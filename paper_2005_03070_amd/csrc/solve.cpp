@@ -94,14 +94,19 @@ static void launch(const Group& g, int which, int flag = 0) {
                         g.ctx->stream);
 }
 
-// One step launch (with measurement on, the kernel stamps its start and end).
+// One step launch (with measurement on, the kernel stamps its start and end,
+// or a timing event follows it on the stream).
 static int launch_step_timed(Group& g) {
     const int slot = g.gslot++;
+    tgdk_ctx ctx = g.ctx;
+    const bool ev = ctx->time_which == 2 && slot < NTSLOG;
+    if (ev && slot == 0) TGDK_HIP(hipEventRecord(ctx->tevents[0], ctx->stream));
     // a group of one system passes its descriptor in the kernel arguments
     // and needs no workgroup-to-system map
     const bool one = g.nprob == 1;
     launch_step(g.dim, g.inner_f32, g.var, g.tile_id, g.d_probs, one ? nullptr : g.d_wgprob, g.total_wg, slot,
-                g.ctx->stream, one ? &g.probs[0] : nullptr);
+                ctx->stream, one ? &g.probs[0] : nullptr);
+    if (ev) TGDK_HIP(hipEventRecord(ctx->tevents[slot + 1], ctx->stream));
     return TGDK_OK;
 }
 
@@ -111,12 +116,23 @@ static int launch_step_timed(Group& g) {
 // device's action log).
 static int collect_timing(Group& g) {
     tgdk_ctx ctx = g.ctx;
-    if (!g.d_ts || !g.d_actlog) return TGDK_OK;
+    if (!g.d_actlog) return TGDK_OK;
     const int nl = std::min(g.gslot, NTSLOG);
-    const size_t nwg = (size_t)g.probs[0].nwg;
     std::vector<unsigned char> act((size_t)nl, 0);
-    std::vector<unsigned long long> ts(2 * (size_t)nl * nwg, 0);
     TGDK_HIP(hipMemcpy(act.data(), g.d_actlog, (size_t)nl, hipMemcpyDeviceToHost));
+    if (ctx->time_which == 2) {
+        for (int l = 0; l < nl; ++l) {
+            float ms = 0.0f;
+            TGDK_HIP(hipEventElapsedTime(&ms, ctx->tevents[l], ctx->tevents[l + 1]));
+            const int a = act[(size_t)l];
+            ctx->act_ms[a] += (double)ms;
+            ctx->act_count[a] += 1;
+        }
+        return TGDK_OK;
+    }
+    if (!g.d_ts) return TGDK_OK;
+    const size_t nwg = (size_t)g.probs[0].nwg;
+    std::vector<unsigned long long> ts(2 * (size_t)nl * nwg, 0);
     TGDK_HIP(hipMemcpy(ts.data(), g.d_ts, sizeof(unsigned long long) * ts.size(), hipMemcpyDeviceToHost));
     int khz = 0;
     TGDK_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device));
@@ -238,7 +254,8 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
     const size_t off_actlog = off;
     if (ctx->time_which) off += align256(NSLOTLOG);
     const size_t off_ts = off;
-    if (ctx->time_which) off += align256(sizeof(unsigned long long) * 2 * NTSLOG * (size_t)g.probs[0].nwg);
+    const bool stamps = ctx->time_which == 1;
+    if (stamps) off += align256(sizeof(unsigned long long) * 2 * NTSLOG * (size_t)g.probs[0].nwg);
     int rc = ctx->solve_ws.ensure(off);
     if (rc) return rc;
     rc = ensure_mirror(ctx, g.nprob);
@@ -248,7 +265,7 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
     g.d_states = (SolveState*)(base + off_states);
     g.d_wgprob = (int*)(base + off_wgprob);
     g.d_actlog = ctx->time_which ? (unsigned char*)(base + off_actlog) : nullptr;
-    g.d_ts = ctx->time_which ? (unsigned long long*)(base + off_ts) : nullptr;
+    g.d_ts = stamps ? (unsigned long long*)(base + off_ts) : nullptr;
     unsigned* counters = (unsigned*)(base + off_counters);
     g.mirror = ctx->mirror;
     g.states.assign(g.nprob, SolveState());

@@ -66,7 +66,7 @@ CONFIGS = {
     "C2": dict(dim=2, n=(1023, 1023), beta=(100.0, 0.0), sigma=0.0, seed=2,
                m=80, k=30, nev=24, rtolev=1e-8, ncyc=20, rtol=1e-8, m3=50),
     "C3": dict(dim=3, n=(255, 255, 255), beta=(50.0, 20.0, 10.0), sigma=0.0, seed=3,
-               m=90, k=40, nev=32, rtolev=1e-8, ncyc=20, rtol=1e-8),
+               m=90, k=40, nev=32, rtolev=1e-8, maxcyc=300, ncyc=20, rtol=1e-8, max_extra=40),
     "C4": dict(dim=2, n=(511, 511), beta=(100.0, 0.0), sigma=0.0, seeds=list(range(100, 132)),
                m=80, k=30, nev=24, rtolev=1e-8, ncyc=20, rtol=1e-8),
     "C5": dict(dim=2, n=(1023, 1023), beta=(60.0, 0.0), sigma=0.0, kseed=5, bstar_seed=6,
