@@ -52,12 +52,17 @@ class TwoGridSolver:
 
 
 class DeflatedSolve(torch.autograd.Function):
-    """u = A(k)^{-1} b for the 2-D operator -div(k grad u) + beta.grad(u)."""
+    """u = A(k)^{-1} b for the 2-D operator -div(k grad u) + beta.grad(u).
+
+    cfg: TwoGridSolver arguments, plus "solve" (fine-solve keywords of both
+    solves) and optionally "solve_adjoint" (keywords of the backward solve
+    alone)."""
 
     @staticmethod
     def forward(ctx, b, kcell, dims, beta, cfg):
         cfg = dict(cfg or {})
         solve_kw = cfg.pop("solve", {})
+        adjoint_kw = cfg.pop("solve_adjoint", solve_kw)  # the backward solve's own settings, if given
         op = api.Operator.div_k(tuple(dims), kcell.detach(), tuple(beta))
         fwd = TwoGridSolver(op, **cfg)
         u, reps = fwd.solve(b.detach().contiguous(), **solve_kw)
@@ -65,7 +70,7 @@ class DeflatedSolve(torch.autograd.Function):
             raise RuntimeError(f"forward solve ended with status {reps[0].status_name}")
         ctx.op = op
         ctx.cfg = cfg
-        ctx.solve_kw = solve_kw
+        ctx.solve_kw = adjoint_kw
         ctx.reports = {"forward": reps[0], "forward_setup": fwd.setup_report}
         ctx.save_for_backward(u)
         return u
