@@ -417,6 +417,28 @@ int tgdk_solve(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int nrh
 int tgdk_solve_idr(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int s, const double* shadow,
                    double kappa, const tgdk_solve_params* params, tgdk_solve_report* report);
 
+/* For callers that cannot allocate device memory during a solve (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * tgdk_solve for params.method = TGDK_BICGSTAB_PROJ, with the same kernels,
+ * launches and results, that allocates nothing.  Its workspace (descriptors,
+ * solver states, the float64 residual and inner vectors of every system,
+ * partial sums) lives in one fixed device array of TGDK_NOALLOC_SCRATCH_MB
+ * MiB per GPU, held by the library until the process ends; the status
+ * mirror and events come from tgdk_ctx_create.  The caller passes inputs and
+ * outputs as for tgdk_solve.
+ *  - Capacity: about 72 n bytes per right-hand side with TGDK_FP64 inner
+ *    cycles, 44 n with TGDK_FP32_IR (8 n more on 3-D grids with a deflation
+ *    space), plus partial sums; at most 64 right-hand sides.  A call that
+ *    needs more returns TGDK_E_INVALID (the message gives the bytes needed)
+ *    without touching x.  Step-kernel timing (tgdk_ctx_time_kernel) must be
+ *    off.
+ *  - Every call on a GPU uses that GPU's one array, and the array keeps the
+ *    last call's contents (the solve clears what must start at zero): calls
+ *    that overlap on one GPU, from any context or thread, race. */
+#define TGDK_NOALLOC_SCRATCH_MB 64
+int tgdk_solve_noalloc(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int nrhs,
+                       const tgdk_solve_params* params, tgdk_solve_report* reports);
+
 /* Several independent instances (each its own operator, deflation space or
  * NULL, right-hand side and solution, all on the context ctx -- every
  * operator must belong to it -- and of one dimension) solved together:

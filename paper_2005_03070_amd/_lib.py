@@ -113,6 +113,7 @@ SIGNATURES = [
     ("tgdk_defl_copy", I, [P, P, DP]),
     ("tgdk_defl_destroy", I, [P]),
     ("tgdk_solve", I, [P, P, P, P, I, C.POINTER(SolveParams), C.POINTER(SolveReport)]),
+    ("tgdk_solve_noalloc", I, [P, P, P, P, I, C.POINTER(SolveParams), C.POINTER(SolveReport)]),
     ("tgdk_solve_idr", I, [P, P, P, P, I, P, D, C.POINTER(SolveParams), C.POINTER(SolveReport)]),
     ("tgdk_solve_instances", I, [P, I, PP, PP, PP, PP, C.POINTER(SolveParams), C.POINTER(SolveReport)]),
     ("tgdk_adjoint_grad_k", I, [P, P, P, P]),

@@ -368,6 +368,28 @@ def solve(op, b, x0=None, defl=None, method="bicgstab", ncyc=20, m3=50, precisio
     return out, _reports(reps)
 
 
+def solve_noalloc(op, b, x0=None, defl=None, ncyc=20, precision="fp64", rtol=1e-8, transpose=False,
+                  maxit_cycle=100000, max_extra=None, fp32_floor=1e-4, out=None, icyc0=0, nu0=0.0,
+                  max_cycles_call=0):
+    """BiCGStab(ncyc)-Proj(k) through tgdk_solve_noalloc: the same solve as
+    solve(method="bicgstab"), with the library's workspace in its fixed
+    per-device scratch (no device allocation inside the call; `out` may be
+    passed preallocated).  Returns (x, [Report per right-hand side])."""
+    nrhs = 1 if b.dim() == 1 else b.shape[0]
+    _ptr(b, numel=op.n * nrhs, what="b")
+    if out is None:
+        out = torch.empty_like(b)
+    _ptr(out, numel=op.n * nrhs, what="x")
+    if x0 is not None:
+        out.copy_(x0)
+    p = _params("bicgstab", ncyc, 0, precision, x0 is not None, transpose, maxit_cycle, max_extra, rtol, fp32_floor,
+                icyc0, nu0, max_cycles_call)
+    reps = (L.SolveReport * nrhs)()
+    check(lib().tgdk_solve_noalloc(op.h, defl.h if defl is not None else None, C.c_void_p(b.data_ptr()),
+                                   C.c_void_p(out.data_ptr()), nrhs, C.byref(p), reps))
+    return out, _reports(reps)
+
+
 def solve_idr(op, b, s=4, shadow=None, x0=None, defl=None, ncyc=20, precision="fp64", rtol=1e-8, kappa=0.7,
               transpose=False, maxit_cycle=100000, max_extra=None, fp32_floor=1e-4, seed=0, out=None, precond=None,
               icyc0=0, nu0=0.0, max_cycles_call=0):

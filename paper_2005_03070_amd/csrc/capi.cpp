@@ -290,9 +290,26 @@ int tgdk_ctx_create(tgdk_ctx* out, int device, void* hip_stream) {
     if (hipMalloc((void**)&c->counters, 64 * sizeof(unsigned)) != hipSuccess ||
         hipMemset(c->counters, 0, 64 * sizeof(unsigned)) != hipSuccess ||
         hipMalloc((void**)&c->dscal, 4096 * sizeof(double)) != hipSuccess ||
-        hipMalloc((void**)&c->zero, 4096) != hipSuccess || hipMemset(c->zero, 0, 4096) != hipSuccess) {
-        delete c;
+        hipMalloc((void**)&c->zero, 4096) != hipSuccess || hipMemset(c->zero, 0, 4096) != hipSuccess ||
+        hipHostMalloc((void**)&c->mirror, sizeof(Mirror) * MIRROR_PREALLOC, hipHostMallocMapped) != hipSuccess) {
+        (void)tgdk_ctx_destroy(c);
         return fail(TGDK_E_NOMEM, "context allocation failed");
+    }
+    c->mirror_cap = MIRROR_PREALLOC;
+    // the solve's host-wait events and the no-allocation scratch's address,
+    // set up here so that tgdk_solve_noalloc allocates nothing
+    for (int i = 0; i < 2; ++i) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            (void)tgdk_ctx_destroy(c);
+            return fail(TGDK_E_HIP, "context event creation failed");
+        }
+        c->events.push_back(e);
+    }
+    int rc = noalloc_init(device);
+    if (rc) {
+        (void)tgdk_ctx_destroy(c);
+        return rc;
     }
     *out = c;
     return TGDK_OK;

@@ -102,5 +102,15 @@ int defl_finish(tgdk_op op, int transpose, double* V64, int k, int store, tgdk_d
 // Orthonormalise W (n x k, device float64) in place by CholQR2.
 int cholqr2(tgdk_ctx ctx, double* W, long long n, int k);
 int op_apply_internal(tgdk_op op, int transpose, int dtype, const void* x, void* y, int nrhs);
+// BiCGStab(ncyc)-Proj(k) with its workspace laid out in [base, base + cap)
+// (no allocation; solve.cpp).
+int solve_bicgstab_in(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int nrhs,
+                      const tgdk_solve_params* prm, tgdk_solve_report* reports, void* base, size_t cap);
+// Address of the no-allocation scratch on the current device (taken once
+// per device; solve_noalloc.hip).  Called by tgdk_ctx_create.
+int noalloc_init(int device);
+// Systems a context's preallocated status mirror holds (the no-allocation
+// solve takes at most this many right-hand sides).
+constexpr int MIRROR_PREALLOC = 64;
 
 }  // namespace tgdk

@@ -176,8 +176,17 @@ static int wait_event(hipEvent_t e) {
     }
 }
 
-// Allocates and fills the device-side group description and workspaces.
-static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk_solve_params* prm, Group& g) {
+// A caller-provided device workspace (base, capacity in bytes) used in place
+// of the context's grow-only one; nothing is allocated when it is given.
+struct ExtWs {
+    void* base;
+    size_t cap;
+};
+
+// Fills the device-side group description and workspaces (allocated in the
+// context's grow-only buffer, or laid out in ext).
+static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk_solve_params* prm, Group& g,
+                       const ExtWs* ext = nullptr) {
     g.ctx = ctx;
     g.nprob = (int)ps.size();
     g.dim = ps[0].op->dim;
@@ -256,11 +265,23 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
     const size_t off_ts = off;
     const bool stamps = ctx->time_which == 1;
     if (stamps) off += align256(sizeof(unsigned long long) * 2 * NTSLOG * (size_t)g.probs[0].nwg);
-    int rc = ctx->solve_ws.ensure(off);
-    if (rc) return rc;
-    rc = ensure_mirror(ctx, g.nprob);
-    if (rc) return rc;
-    char* base = (char*)ctx->solve_ws.p;
+    int rc;
+    char* base;
+    if (ext) {
+        if (off > ext->cap) {
+            char msg[160];
+            snprintf(msg, sizeof(msg), "the solve needs %zu bytes of workspace; the fixed scratch holds %zu", off,
+                     ext->cap);
+            return fail(TGDK_E_INVALID, msg);
+        }
+        if (ctx->mirror_cap < g.nprob || (int)ctx->events.size() < 2)
+            return fail(TGDK_E_INVALID, "more systems than the context's preallocated status mirror holds");
+        base = (char*)ext->base;
+    } else {
+        if ((rc = ctx->solve_ws.ensure(off))) return rc;
+        if ((rc = ensure_mirror(ctx, g.nprob))) return rc;
+        base = (char*)ctx->solve_ws.p;
+    }
     g.d_probs = (DevProb*)(base + off_probs);
     g.d_states = (SolveState*)(base + off_states);
     g.d_wgprob = (int*)(base + off_wgprob);
@@ -498,13 +519,12 @@ static int predict_steps(const Mirror& m, Predict& pr) {
 // predicted to need (steps past the end of a solve return at once but still
 // cost a dispatch each).
 static int bicgstab_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk_solve_params* prm,
-                          tgdk_solve_report* reps) {
+                          tgdk_solve_report* reps, const ExtWs* ext = nullptr) {
     const auto t0 = std::chrono::steady_clock::now();
     Group g;
-    int rc = build_group(ctx, ps, prm, g);
+    int rc = build_group(ctx, ps, prm, g, ext);
     if (rc) return rc;
-    rc = ensure_events(ctx, 2);
-    if (rc) return rc;
+    if (!ext && (rc = ensure_events(ctx, 2))) return rc;
     hipStream_t s = ctx->stream;
     const int S_MAX = 24;  // largest batch of steps enqueued at once
     const long long max_cycles = prm->ncyc + (prm->max_extra_cycles >= 0 ? prm->max_extra_cycles : prm->ncyc) + 2;
@@ -887,6 +907,23 @@ static int check_defl(tgdk_op op, tgdk_defl d, const tgdk_solve_params* prm) {
     if ((d->precond != 0) != (prm->precond != nullptr))
         return fail(TGDK_E_INVALID, "a preconditioned solve needs a space from tgdk_defl_precond, and only it");
     return TGDK_OK;
+}
+
+// BiCGStab(ncyc)-Proj(k) on nrhs systems with the workspace laid out in the
+// caller's scratch (base, cap bytes): the no-allocation entry point.
+int solve_bicgstab_in(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int nrhs,
+                      const tgdk_solve_params* prm, tgdk_solve_report* reports, void* base, size_t cap) {
+    if (!fine || !b || !x || nrhs < 1 || !reports) return fail(TGDK_E_INVALID, "bad argument");
+    int rc = check_params(prm);
+    if (rc) return rc;
+    if (prm->method != TGDK_BICGSTAB_PROJ) return fail(TGDK_E_INVALID, "the no-allocation solve is BiCGStab-Proj");
+    if ((rc = check_defl(fine, defl, prm))) return rc;
+    if (fine->ctx->time_which) return fail(TGDK_E_INVALID, "switch the step-kernel timing off for this call");
+    TGDK_HIP(hipSetDevice(fine->ctx->device));
+    std::vector<ProbSpec> ps(nrhs);
+    for (int j = 0; j < nrhs; ++j) ps[j] = ProbSpec{fine, defl, b + (size_t)j * fine->N, x + (size_t)j * fine->N};
+    const ExtWs ext{base, cap};
+    return bicgstab_group(fine->ctx, ps, prm, reports, &ext);
 }
 
 }  // namespace tgdk
