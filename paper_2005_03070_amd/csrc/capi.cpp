@@ -48,6 +48,7 @@ DevOp make_devop(const tgdk_op_s* op, int transpose) {
     memset(&d, 0, sizeof(d));
     d.dim = op->dim;
     d.nx = op->n[0];
+    d.px = op->n[0];  // unpadded; the 3-D step kernel's solve workspace widens it
     d.ny = op->n[1];
     d.nz = op->dim == 3 ? op->n[2] : 1;
     d.n = op->N;

@@ -283,6 +283,12 @@ __device__ __forceinline__ long long gidx(const DevOp& op, int gx, int gy, int g
     return ((long long)gz * op.ny + gy) * op.nx + gx;
 }
 
+// Index of point (gx, gy, gz) in a vector stored with the padded row pitch
+// op.px (the step kernel's residual and inner vectors on 3-D grids).
+__device__ __forceinline__ long long pidx(const DevOp& op, int gx, int gy, int gz) {
+    return ((long long)gz * op.ny + gy) * op.px + gx;
+}
+
 // Fills the halo of an LDS box (everything except the tile interior, which
 // the caller writes from its own points): the rows above/below the tile (and
 // the planes in front/behind it in 3-D), 64 wide and coalesced, then the two

@@ -61,9 +61,10 @@ struct ApplyPhase {
     };
     using Ring = Own;
     static constexpr bool PLANE_HOOK = false;
-    __device__ __forceinline__ void load(Own& o, long long g) const { o.v = *(g >= 0 ? x + g : zero); }
+    // x and y are caller vectors: unpadded indices
+    __device__ __forceinline__ void load(Own& o, long long, long long gu) const { o.v = *(gu >= 0 ? x + gu : zero); }
     __device__ __forceinline__ T value(const Own& o) const { return o.v; }
-    __device__ __forceinline__ void emit(int, long long g, const Own&, T yv) { y[g] = yv; }
+    __device__ __forceinline__ void emit(int, long long, long long gu, const Own&, T yv) { y[gu] = yv; }
     __device__ __forceinline__ void plane_done(const Chunk&, int) {}
 };
 

@@ -45,6 +45,8 @@ void launch_step(int dim, int inner_f32, int var, int tile_id, const DevProb* pr
 template <int DIM>
 void launch_step_dim(int inner_f32, int var, int tile_id, const DevProb* probs, const int* wg_prob, int total_wg,
                      int gslot, hipStream_t s, const DevProb* single);
+// Workgroups per compute unit of the 3-D step kernel (occupancy; 0 if unknown).
+int step_blocks_per_cu(int inner_f32, int var, int tile_id);
 
 // IDR(s) inner cycles (kernels_idr.hip): what = one of the IDR_* actions,
 // k = the step of the round for IDR_DIR, IDR_ALPHA, IDR_ORTH, IDR_UPD.

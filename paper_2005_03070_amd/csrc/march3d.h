@@ -120,13 +120,20 @@ namespace tgdk {
 // The marching loop over one chunk, shared by the 3-D kernels.  Ph (the
 // kernel's phase) provides
 //   struct Own, struct Ring        raw loads of an own / ring point of a plane
-//   void load(Own&, long long g)   g < 0: a point outside the domain (reads zeros)
-//   void load(Ring&, long long g)
+//   void load(Own&, long long g, long long gu)   g < 0: a point outside the domain (reads zeros)
+//   void load(Ring&, long long g, long long gu)
 //   T value(const Own&), T value(const Ring&)     the stencil input u
-//   void emit(int q, long long g, const Own& c, T y)   outputs at own point q
-//                                                 (global index g) of plane z, y = (A u) there
+//   void emit(int q, long long g, long long gu, const Own& c, T y)
+//                                                 outputs at own point q of plane z, y = (A u) there
 //   void plane_done(const Chunk&, int z)          after every thread's emits of plane z
 //                                                 (between two workgroup barriers)
+// Every point comes with two indices: g in vectors stored with the padded
+// row pitch op.px (the step kernel's own vectors) and gu in vectors of pitch
+// op.nx (caller vectors, coefficient arrays); they coincide when px = nx.
+// With px a multiple of 64, every 64-point row segment of a padded vector
+// starts on a 128-byte line: at n_x = 255 a float32 segment otherwise spans
+// three lines instead of two, and the step kernel's phases measured 15-19 %
+// slower.
 // Four register sets hold the own points of planes z-1, z, z+1 and z+2 (the
 // last in flight while plane z is computed); the loop is unrolled four times
 // so the sets change roles by position, never by register moves (a move
@@ -137,10 +144,11 @@ template <class M, bool VAR, class T, class Ph>
 __device__ __forceinline__ void march_chunk(const DevOp& op, const Chunk& k, T* __restrict__ L, Ph& ph) {
     using Own = typename Ph::Own;
     using Ring = typename Ph::Ring;
-    const long long plane = (long long)op.nx * op.ny;
+    const long long plane = (long long)op.nx * op.ny;   // unpadded
+    const long long pplane = (long long)op.px * op.ny;  // padded
     const int nz = op.nz;
     int cq[M::PPT];
-    long long bq[M::PPT];
+    int bq[M::PPT], pq[M::PPT];  // in-plane offsets, unpadded and padded
     bool okq[M::PPT];
 #pragma unroll
     for (int q = 0; q < M::PPT; ++q) {
@@ -148,10 +156,11 @@ __device__ __forceinline__ void march_chunk(const DevOp& op, const Chunk& k, T* 
         own_point<M>(q, lx, ly, cq[q]);
         const int gx = k.x0 + lx, gy = k.y0 + ly;
         okq[q] = gx < op.nx && gy < op.ny;
-        bq[q] = okq[q] ? (long long)gy * op.nx + gx : 0;
+        bq[q] = okq[q] ? gy * op.nx + gx : 0;
+        pq[q] = okq[q] ? gy * op.px + gx : 0;
     }
     int cr[M::RPT];
-    long long br[M::RPT];
+    int br[M::RPT], pr[M::RPT];
     bool okr[M::RPT];
 #pragma unroll
     for (int j = 0; j < M::RPT; ++j) {
@@ -161,17 +170,24 @@ __device__ __forceinline__ void march_chunk(const DevOp& op, const Chunk& k, T* 
         const int gx = k.x0 + lx, gy = k.y0 + ly;
         cr[j] = c;
         okr[j] = c >= 0 && gx >= 0 && gx < op.nx && gy >= 0 && gy < op.ny;
-        br[j] = okr[j] ? (long long)gy * op.nx + gx : 0;
+        br[j] = okr[j] ? gy * op.nx + gx : 0;
+        pr[j] = okr[j] ? gy * op.px + gx : 0;
     }
     auto load_own = [&](Own (&o)[M::PPT], int zz) {
         const bool okz = zz >= 0 && zz < nz;
 #pragma unroll
-        for (int q = 0; q < M::PPT; ++q) ph.load(o[q], (okq[q] && okz) ? zz * plane + bq[q] : -1LL);
+        for (int q = 0; q < M::PPT; ++q) {
+            const bool ok = okq[q] && okz;
+            ph.load(o[q], ok ? zz * pplane + pq[q] : -1LL, ok ? zz * plane + bq[q] : -1LL);
+        }
     };
     auto load_ring = [&](Ring (&r)[M::RPT], int zz) {
         const bool okz = zz < k.z1;
 #pragma unroll
-        for (int j = 0; j < M::RPT; ++j) ph.load(r[j], (okr[j] && okz) ? zz * plane + br[j] : -1LL);
+        for (int j = 0; j < M::RPT; ++j) {
+            const bool ok = okr[j] && okz;
+            ph.load(r[j], ok ? zz * pplane + pr[j] : -1LL, ok ? zz * plane + br[j] : -1LL);
+        }
     };
     // plane z: stage plane z (own points oc, ring rc) in LDS, issue the loads
     // of ring z + 1 (needed first) and of plane z + 2, compute plane z
@@ -188,8 +204,9 @@ __device__ __forceinline__ void march_chunk(const DevOp& op, const Chunk& k, T* 
 #pragma unroll
         for (int q = 0; q < M::PPT; ++q)
             if (okq[q]) {
-                const long long g = z * plane + bq[q];
-                ph.emit(q, g, oc[q], stencil_march<M, VAR, T>(op, L, cq[q], g, ph.value(om[q]), ph.value(op_[q])));
+                const long long gu = z * plane + bq[q];
+                ph.emit(q, z * pplane + pq[q], gu, oc[q],
+                        stencil_march<M, VAR, T>(op, L, cq[q], gu, ph.value(om[q]), ph.value(op_[q])));
             }
         if constexpr (Ph::PLANE_HOOK) {
             __syncthreads();

@@ -32,8 +32,11 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Workgroups of the step kernel per problem: on 2-D grids one per tile up to
 // this cap (beyond it each walks several tiles; the cap bounds the partial
-// sums every workgroup reads), on 3-D grids about STEP_CHUNKS z-marching
-// chunks.
+// sums every workgroup reads), on 3-D grids about as many z-marching chunks
+// as the device holds resident at once, at most STEP_CHUNKS: the float64
+// kernel (145 registers, 3 workgroups per compute unit) gets 768 chunks, so
+// no fourth of them runs as a tail after the others (255^3 FP64 solve
+// 272.8 -> 260.2 ms); float32 (5 per unit) keeps 1024.
 constexpr int STEP_WG_CAP = 1024;
 constexpr int STEP_CHUNKS = 1024;
 
@@ -203,6 +206,13 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
     int ty, tz;
     tile_shape(g.dim, g.tile_id, &ty, &tz);
     const size_t ies = g.inner_f32 ? 4 : 8;
+    int var_any = 0;
+    for (const auto& p : ps) var_any |= p.op->kind != TGDK_CONST_CD;
+    int chunk_target = STEP_CHUNKS;
+    if (g.dim == 3) {
+        const int nb = step_blocks_per_cu(g.inner_f32, var_any, g.tile_id);
+        if (nb > 0) chunk_target = std::max(64, std::min(STEP_CHUNKS, nb * ctx->num_cus));
+    }
     // layout
     size_t off = 0;
     const size_t off_probs = off;
@@ -214,11 +224,20 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
     std::vector<size_t> off_vec(g.nprob), off_part(g.nprob);
     g.probs.assign(g.nprob, DevProb());
     int tiles = 0, wgs = 0;
+    // 3-D BiCGStab: the step kernel's own vectors (r, the inner vectors, w)
+    // get a row pitch rounded up to 64, so that every 64-point row segment
+    // the marching phases load starts on a 128-byte line (15-19 % faster
+    // phases at n_x = 255); x, b and V keep the caller's pitch n_x.  The
+    // other drivers' kernels and the 2-D tile paths assume pitch n_x.
+    const bool padded = g.dim == 3 && prm->method == TGDK_BICGSTAB_PROJ;
+    std::vector<size_t> nstore(g.nprob);  // elements per stored vector
     for (int j = 0; j < g.nprob; ++j) {
         const tgdk_op op = ps[j].op;
         DevProb& P = g.probs[j];
         memset(&P, 0, sizeof(P));
         P.op = make_devop(op, prm->transpose);
+        if (padded) P.op.px = (op->n[0] + 63) / 64 * 64;
+        nstore[j] = (size_t)P.op.px * op->n[1] * (g.dim == 3 ? op->n[2] : 1);
         P.tx = (op->n[0] + 63) / 64;
         P.ty = (op->n[1] + ty - 1) / ty;
         P.tz = g.dim == 3 ? (op->n[2] + tz - 1) / tz : 1;
@@ -232,7 +251,7 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
             P.mcx = (op->n[0] + 63) / 64;
             P.mcy = (op->n[1] + my - 1) / my;
             const long long cols = (long long)P.mcx * P.mcy;
-            long long mz = (cols * op->n[2] + STEP_CHUNKS - 1) / STEP_CHUNKS;
+            long long mz = (cols * op->n[2] + chunk_target - 1) / chunk_target;
             mz = std::max(4LL, std::min(mz, (long long)op->n[2]));
             P.mz = (int)mz;
             P.nchunks = (int)(cols * ((op->n[2] + P.mz - 1) / P.mz));
@@ -248,7 +267,7 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
         P.pstride = std::max(8, 3 + P.k);
         P.pslot = (long long)P.pstride * P.nwg;
         off_vec[j] = off;
-        const size_t n = (size_t)op->N;
+        const size_t n = nstore[j];
         off += align256(n * 8);                            // r (float64)
         off += (g.inner_f32 ? 9 : 8) * align256(n * ies);  // inner vectors
         if (g.dim == 3 && P.k > 0) off += align256(n * 8);  // w = V d (3-D boundary)
@@ -295,7 +314,7 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
     for (int j = 0; j < g.nprob; ++j) {
         DevProb& P = g.probs[j];
         for (int w = 0; w < P.nwg; ++w) wgprob[(size_t)P.wg_begin + w] = j;
-        const size_t n = (size_t)ps[j].op->N;
+        const size_t n = nstore[j];
         char* v = base + off_vec[j];
         P.b = ps[j].b;
         P.x = ps[j].x;

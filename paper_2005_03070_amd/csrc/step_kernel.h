@@ -263,7 +263,8 @@ __device__ __forceinline__ double vload(const DevProb& P, long long i) {
     return P.vtype ? (double)reinterpret_cast<const float*>(P.V)[i] : reinterpret_cast<const double*>(P.V)[i];
 }
 
-// x + e + a p + w s at global index g (the folded inner update, float64).
+// e + a p + w s at index g of the step kernel's own vectors (padded pitch
+// on 3-D grids): the pending inner update, float64.
 template <class TI>
 __device__ __forceinline__ double upd_at(const DevProb& P, const Upd& U, long long g) {
     double u = (double)vp<const TI>(P.e)[g];
@@ -278,7 +279,8 @@ __device__ __forceinline__ gptr<double> part_at(const DevProb& P, int slot, int 
 }
 
 // ------------------------------------------------------------ phase A
-// 2-D tiles.  Every load of the stencil input's sources (own points and halo
+// 2-D tiles (the 2-D actions index every vector with pitch n_x: their
+// problems are not padded).  Every load of the stencil input's sources (own points and halo
 // slots) is issued first, from clamped addresses (points outside the domain
 // read the zero page), so all of them are in flight together; then the
 // stencil input goes to LDS and the outputs are formed.  e and r^ are read
@@ -676,8 +678,7 @@ __device__ __forceinline__ void fold_update(const DevProb& P, int lw, const Upd&
             int gx, gy, gz, c;
             point_coords<Cfg>(q, tp, gx, gy, gz, c);
             if (!inside(op, gx, gy, gz)) continue;
-            const long long g = gidx(op, gx, gy, gz);
-            P.x[g] += upd_at<TI>(P, U, g);
+            P.x[gidx(op, gx, gy, gz)] += upd_at<TI>(P, U, pidx(op, gx, gy, gz));
         }
     }
 }
@@ -699,7 +700,7 @@ struct MarchA {  // phase A of iteration i > 0
         TI s, t, po, vo;
     };
     __device__ __forceinline__ const TI* at(const TI* a, long long g) const { return g >= 0 ? a + g : zero; }
-    __device__ __forceinline__ void load(Own& o, long long g) const {
+    __device__ __forceinline__ void load(Own& o, long long g, long long) const {
         o.s = *at(s, g);
         o.t = *at(t, g);
         o.po = *at(po, g);
@@ -707,7 +708,7 @@ struct MarchA {  // phase A of iteration i > 0
         o.e = *at(e, g);
         o.rh = *at(rh, g);
     }
-    __device__ __forceinline__ void load(Ring& o, long long g) const {
+    __device__ __forceinline__ void load(Ring& o, long long g, long long) const {
         o.s = *at(s, g);
         o.t = *at(t, g);
         o.po = *at(po, g);
@@ -720,7 +721,7 @@ struct MarchA {  // phase A of iteration i > 0
     }
     static constexpr bool PLANE_HOOK = false;
     __device__ __forceinline__ void plane_done(const Chunk&, int) {}
-    __device__ __forceinline__ void emit(int, long long g, const Own& c, TI y) {
+    __device__ __forceinline__ void emit(int, long long g, long long, const Own& c, TI y) {
         const TI r = c.s - omega * c.t;
         pnew[g] = r + beta * (c.po - omega * c.vo);
         vnew[g] = y;
@@ -746,19 +747,19 @@ struct MarchA0 {  // phase A of iteration 0, optionally folding the last update 
         TI r;
     };
     __device__ __forceinline__ const TI* at(const TI* a, long long g) const { return g >= 0 ? a + g : zero; }
-    __device__ __forceinline__ void load(Own& o, long long g) const {
+    __device__ __forceinline__ void load(Own& o, long long g, long long) const {
         o.r = *at(rin, g);
         o.rh = *at(rh, g);
     }
-    __device__ __forceinline__ void load(Ring& o, long long g) const { o.r = *at(rin, g); }
+    __device__ __forceinline__ void load(Ring& o, long long g, long long) const { o.r = *at(rin, g); }
     template <class R>
     __device__ __forceinline__ TI value(const R& o) const {
         return o.r;
     }
     static constexpr bool PLANE_HOOK = false;
     __device__ __forceinline__ void plane_done(const Chunk&, int) {}
-    __device__ __forceinline__ void emit(int, long long g, const Own& c, TI y) {
-        if (fin) P->x[g] += upd_at<TI>(*P, U, g);
+    __device__ __forceinline__ void emit(int, long long g, long long gu, const Own& c, TI y) {
+        if (fin) P->x[gu] += upd_at<TI>(*P, U, g);
         pnew[g] = c.r;
         vnew[g] = y;
         e[g] = TI(0);
@@ -780,12 +781,12 @@ struct MarchB {  // phase B
         TI r, v;
     };
     __device__ __forceinline__ const TI* at(const TI* a, long long g) const { return g >= 0 ? a + g : zero; }
-    __device__ __forceinline__ void load(Own& o, long long g) const {
+    __device__ __forceinline__ void load(Own& o, long long g, long long) const {
         o.r = *at(rin, g);
         o.v = *at(v, g);
         o.rh = *at(rh, g);
     }
-    __device__ __forceinline__ void load(Ring& o, long long g) const {
+    __device__ __forceinline__ void load(Ring& o, long long g, long long) const {
         o.r = *at(rin, g);
         o.v = *at(v, g);
     }
@@ -795,7 +796,7 @@ struct MarchB {  // phase B
     }
     static constexpr bool PLANE_HOOK = false;
     __device__ __forceinline__ void plane_done(const Chunk&, int) {}
-    __device__ __forceinline__ void emit(int, long long g, const Own& c, TI y) {
+    __device__ __forceinline__ void emit(int, long long g, long long, const Own& c, TI y) {
         const TI sv = c.r - alpha * c.v;
         s[g] = sv;
         t[g] = y;
@@ -876,18 +877,20 @@ struct MarchRes {
         double x;
         TI e, p, s;
     };
+    // x and b are caller vectors (unpadded index gu), e, p, s the step
+    // kernel's own (padded index g)
     template <class R>
-    __device__ __forceinline__ void load_upd(R& o, long long g) const {
-        o.x = *(g >= 0 ? x + g : zero64);
+    __device__ __forceinline__ void load_upd(R& o, long long g, long long gu) const {
+        o.x = *(gu >= 0 ? x + gu : zero64);
         o.e = *(U.any && g >= 0 ? e + g : zeroT);
         o.p = *(U.any && U.a != 0.0 && g >= 0 ? p + g : zeroT);
         o.s = *(U.any && U.w != 0.0 && g >= 0 ? s + g : zeroT);
     }
-    __device__ __forceinline__ void load(Own& o, long long g) const {
-        load_upd(o, g);
-        o.b = *(g >= 0 ? b + g : zero64);
+    __device__ __forceinline__ void load(Own& o, long long g, long long gu) const {
+        load_upd(o, g, gu);
+        o.b = *(gu >= 0 ? b + gu : zero64);
     }
-    __device__ __forceinline__ void load(Ring& o, long long g) const { load_upd(o, g); }
+    __device__ __forceinline__ void load(Ring& o, long long g, long long gu) const { load_upd(o, g, gu); }
     template <class R>
     __device__ __forceinline__ double value(const R& o) const {
         if (!U.any) return o.x;
@@ -896,7 +899,7 @@ struct MarchRes {
         if (U.w != 0.0) u += U.w * (double)o.s;
         return o.x + u;
     }
-    __device__ __forceinline__ void emit(int, long long g, const Own& c, double y) {
+    __device__ __forceinline__ void emit(int, long long g, long long, const Own& c, double y) {
         const double rr = c.b - y;
         r[g] = rr;
         acc[0] += rr * rr;
@@ -919,7 +922,8 @@ template <class M, class TV>
 __device__ __forceinline__ void chunk_columns(const DevProb& P, const Chunk& c, const TV* __restrict__ V,
                                               double* csum, double* sh) {
     const DevOp& op = P.op;
-    const long long plane = (long long)op.nx * op.ny;
+    const long long plane = (long long)op.nx * op.ny;   // V: unpadded
+    const long long pplane = (long long)op.px * op.ny;  // r: padded
     const double* __restrict__ r = P.r;
     const int k = P.k;
     const int npts = 64 * M::MY * (c.z1 - c.z0);
@@ -937,7 +941,8 @@ __device__ __forceinline__ void chunk_columns(const DevProb& P, const Chunk& c, 
             const int gx = c.x0 + (l & 63), gy = c.y0 + ((l >> 6) % M::MY), z = c.z0 + l / (64 * M::MY);
             const bool in = gx < op.nx && gy < op.ny;
             const long long g = z * plane + (long long)gy * op.nx + gx;
-            const double rv = *(in ? gp<const double>(r) + g : zr);
+            const long long gpad = z * pplane + (long long)gy * op.px + gx;
+            const double rv = *(in ? gp<const double>(r) + gpad : zr);
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) a[jj] += (double)*(in ? gp<const TV>(Vj[jj]) + g : zv) * rv;
         }
@@ -991,7 +996,8 @@ __device__ __forceinline__ void apply_w_points(const DevProb& P, int lw, const U
     if (lw >= P.nchunks) return;
     const DevOp& op = P.op;
     const Chunk c = chunk_of<M>(lw, P.mcx, P.mcy, P.mz, op.nz);
-    const long long plane = (long long)op.nx * op.ny;
+    const long long plane = (long long)op.nx * op.ny;   // V, x: unpadded
+    const long long pplane = (long long)op.px * op.ny;  // w and the update: padded
     const int k = P.k;
     for (int z = c.z0; z < c.z1; ++z) {
 #pragma unroll
@@ -1000,14 +1006,15 @@ __device__ __forceinline__ void apply_w_points(const DevProb& P, int lw, const U
             own_point<M>(q, lx, ly, ci);
             const int gx = c.x0 + lx, gy = c.y0 + ly;
             if (gx >= op.nx || gy >= op.ny) continue;
-            const long long g = z * plane + (long long)gy * op.nx + gx;
+            const long long gu = z * plane + (long long)gy * op.nx + gx;
+            const long long g = z * pplane + (long long)gy * op.px + gx;
             double w = 0.0;
 #pragma unroll 8
-            for (int j = 0; j < k; ++j) w += (double)V[(long long)j * P.ldv + g] * dsh[j];
+            for (int j = 0; j < k; ++j) w += (double)V[(long long)j * P.ldv + gu] * dsh[j];
             P.w[g] = w;
-            double xv = P.x[g];
+            double xv = P.x[gu];
             if (U.any) xv += upd_at<TI>(P, U, g);
-            P.x[g] = xv + w;
+            P.x[gu] = xv + w;
         }
     }
 }
@@ -1038,16 +1045,16 @@ struct MarchApply {
     struct Ring {
         double w;
     };
-    __device__ __forceinline__ void load(Own& o, long long g) const {
+    __device__ __forceinline__ void load(Own& o, long long g, long long) const {
         o.w = *(g >= 0 ? w + g : zero);
         o.r = *(g >= 0 ? rr_ + g : zero);
     }
-    __device__ __forceinline__ void load(Ring& o, long long g) const { o.w = *(g >= 0 ? w + g : zero); }
+    __device__ __forceinline__ void load(Ring& o, long long g, long long) const { o.w = *(g >= 0 ? w + g : zero); }
     template <class R>
     __device__ __forceinline__ double value(const R& o) const {
         return o.w;
     }
-    __device__ __forceinline__ void emit(int, long long g, const Own& c, double y) {
+    __device__ __forceinline__ void emit(int, long long g, long long, const Own& c, double y) {
         const double rv = c.r - y;
         r[g] = rv;
         acc[0] += rv * rv;
@@ -1194,6 +1201,25 @@ template <class Cfg, int DIM, bool VAR, class TI>
 __global__ __launch_bounds__(NT) void k_step1(const DevProb P, int gslot) {
     const unsigned long long t_begin = (unsigned long long)wall_clock64();
     step_run<Cfg, DIM, VAR, TI>(P, xcd_remap(blockIdx.x, gridDim.x), gslot, t_begin);
+}
+
+// Workgroups of the grouped step kernel that one compute unit holds at once
+// (its registers and LDS decide), for the kernel the launcher would pick.
+template <int DIM>
+int step_blocks_per_cu_dim(int inner_f32, int var, int tile_id) {
+    int nb = 0;
+    with_tile<DIM>(tile_id, [&](auto cfg) {
+        using Cfg = decltype(cfg);
+        hipError_t e;
+        if (inner_f32)
+            e = var ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<Cfg, DIM, true, float>, NT, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<Cfg, DIM, false, float>, NT, 0);
+        else
+            e = var ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<Cfg, DIM, true, double>, NT, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<Cfg, DIM, false, double>, NT, 0);
+        if (e != hipSuccess) nb = 0;
+    });
+    return nb;
 }
 
 // ------------------------------------------------------------ launcher

@@ -15,7 +15,8 @@ struct DevOp {
     int dim, nx, ny, nz;
     long long n;
     int var;                 // 1: per-row coefficient arrays
-    int pad_;
+    int px;                  // row pitch (x stride of y) of the step kernel's own vectors, >= nx; caller
+                             // vectors (x, b), the deflation basis and coefficient arrays have pitch nx
     double cc[7];            // constant coefficients C, W, E, S, N, D, U
     const double* coef64;    // var: (2*dim+1) arrays of n, same order
     const float* coef32;

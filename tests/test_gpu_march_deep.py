@@ -1,10 +1,14 @@
 """3-D parity where the z-marching chunks are deep.  The step kernel gives
 each workgroup a column chunk and walks its z planes four at a time, the
-register sets of planes z-1 .. z+2 changing roles by position.  On
-127 x 127 x 255 the launch has 1024 chunks of 8 planes (the last z chunk
-7), so every chunk carries its loads and its planes from one group of four
-to the next and ends on a partial group; x and y are ragged too (127 = 64 +
-63 columns, 15 full row blocks of 8 and one of 7).  Checked against the
+register sets of planes z-1 .. z+2 changing roles by position.  The chunk
+count follows the kernel's residency: 768 for the float64 kernel (3
+workgroups per compute unit on 256 units), 1024 for float32.  On
+127 x 127 x 255 that gives 11-plane chunks (the last z chunk 2) in float64
+and 8-plane chunks (the last 7) in float32, so every chunk carries its loads
+and its planes from one group of four to the next and ends on a partial
+group; x and y are ragged too (127 = 64 + 63 columns, 15 full row blocks of
+8 and one of 7), and the step kernel's own vectors are stored with row
+pitch 128.  Checked against the
 oracle after a fixed small number of iterations: phases A and B (no
 deflation), and the cycle boundary (marching true residual with the streamed
 c = V^T r, w = V d, marching r -= A w) with deflation, in FP64 and with
@@ -38,11 +42,14 @@ def _rel(a, b):
 
 
 def test_chunk_depth_of_this_grid():
-    """The launch shape the rest of this file relies on: 2 x 16 columns of
-    64 x 8 points, chunks of 8 planes (so z carries over a group of four)."""
+    """The launch shapes the rest of this file relies on: 2 x 16 columns of
+    64 x 8 points; chunks of 11 planes for 768 chunks in all, 8 planes for
+    1024 (both carry z over a group of four and end on a partial chunk)."""
     cols = ((DIMS[0] + 63) // 64) * ((DIMS[1] + 7) // 8)
-    mz = max(4, min(DIMS[2], -(-cols * DIMS[2] // 1024)))
-    assert cols == 32 and mz == 8 and DIMS[2] % mz == 7
+    assert cols == 32
+    for target, depth, last in ((768, 11, 2), (1024, 8, 7)):
+        mz = max(4, min(DIMS[2], -(-cols * DIMS[2] // target)))
+        assert (mz, DIMS[2] % mz) == (depth, last)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
