@@ -58,7 +58,7 @@ extern "C" {
 #define TGDK_FP64          0
 #define TGDK_FP32_IR       1
 
-#define TGDK_MAX_DEFL 128   /* largest GMRES cycle length m (deflation spaces: k <= 64) */
+#define TGDK_MAX_DEFL 256   /* largest GMRES(-DR) cycle length m and deflation space k (k < m for GMRES-DR) */
 #define TGDK_NHIST    8     /* recorded BiCGStab scalars of the first iterations */
 #define TGDK_IDR_SMAX 32    /* largest IDR shadow-space dimension s */
 #define TGDK_NCYC_REPORT 64 /* cycles whose inner operator applications are reported */

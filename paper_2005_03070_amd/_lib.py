@@ -18,7 +18,7 @@ CONST_CD, VAR_STENCIL, DIV_K = 0, 1, 2
 BICGSTAB_PROJ, GMRES_PROJ, IDRS_PROJ = 0, 1, 2
 PROJ_GALERKIN, PROJ_MINRES = 0, 1
 FP64, FP32_IR = 0, 1
-MAX_DEFL = 128
+MAX_DEFL = 256
 NHIST = 8
 IDR_SMAX = 32
 NCYC_REPORT = 64

@@ -170,7 +170,7 @@ extern "C" int tgdk_defl_improve(tgdk_defl in, const tgdk_arnoldie_params* prm, 
     if (!in || !prm || !out) return fail(TGDK_E_INVALID, "NULL argument");
     if (in->precond) return fail(TGDK_E_INVALID, "improve the Galerkin space, then precondition it");
     const int k = in->k, m = prm->m;
-    if (m <= k || m > MAXK) return fail(TGDK_E_INVALID, "need k < m <= 128");
+    if (m <= k || m > MAXK) return fail(TGDK_E_INVALID, "need k < m <= 256");
     if (prm->nev < 0 || prm->nev > k || prm->maxcyc < 0 || !(prm->tol > 0.0))
         return fail(TGDK_E_INVALID, "need 0 <= nev <= k, maxcyc >= 0, tol > 0");
     if (store_dtype != TGDK_F64 && store_dtype != TGDK_F32) return fail(TGDK_E_INVALID, "store dtype");

@@ -109,7 +109,7 @@ int op_apply_internal(tgdk_op op, int transpose, int dtype, const void* x, void*
 
 // W (n x k) <- W R^{-1} twice, with R from the Cholesky factor of W^T W.
 int cholqr2(tgdk_ctx ctx, double* W, long long n, int k) {
-    if (k > 64) return fail(TGDK_E_INVALID, "deflation spaces are limited to 64 vectors");
+    if (k < 1 || k > MAXK) return fail(TGDK_E_INVALID, "deflation spaces hold 1 to 256 vectors");
     hipStream_t s = ctx->stream;
     double* tmp = nullptr;
     double* dY = nullptr;
@@ -128,7 +128,7 @@ int cholqr2(tgdk_ctx ctx, double* W, long long n, int k) {
     std::vector<double> G((size_t)k * k), Rinv((size_t)k * k), Y((size_t)k * k);
     rc = TGDK_OK;
     for (int pass = 0; pass < 2 && rc == TGDK_OK; ++pass) {
-        const size_t need = (size_t)gram_blocks(n) * k * k * sizeof(double);
+        const size_t need = gram_partial_bytes(n, k, k);
         if ((rc = ctx->partial.ensure(need))) break;
         launch_gram(W, 0, n, k, W, 0, n, k, n, dG, (double*)ctx->partial.p, ctx->counters, s);
         if (hipMemcpyAsync(G.data(), dG, G.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -218,7 +218,7 @@ int defl_finish(tgdk_op op, int transpose, double* V64, int k, int store, tgdk_d
     std::vector<double> H((size_t)k * k);
     double* dG = nullptr;
     if (!rc) rc = dev_alloc(&dG, (size_t)k * k);
-    if (!rc) rc = ctx->partial.ensure((size_t)gram_blocks(n) * k * k * sizeof(double));
+    if (!rc) rc = ctx->partial.ensure(gram_partial_bytes(n, k, k));
     if (!rc) {
         // Galerkin H = V^T (A V); MinRes H = (A V)^T (A V)
         launch_gram(minres ? AV : V64, 0, n, k, AV, 0, n, k, n, dG, (double*)ctx->partial.p, ctx->counters, s);
@@ -614,7 +614,7 @@ int tgdk_defl_precond(tgdk_defl g, tgdk_precond_fn fn, void* user, tgdk_defl* ou
     TGDK_HIP(hipMemcpyAsync(V, g->V, sizeof(double) * n * k, hipMemcpyDeviceToDevice, s));
     // Z = M^{-1} V, then H = V^T (A Z)
     if ((rc = fn(user, V, Z, k)) || (rc = op_apply_internal(g->op, g->transpose, TGDK_F64, Z, AZ, k)) ||
-        (rc = ctx->partial.ensure((size_t)gram_blocks(n) * k * k * sizeof(double)))) {
+        (rc = ctx->partial.ensure(gram_partial_bytes(n, k, k)))) {
         release();
         return rc < 0 ? rc : fail(TGDK_E_HIP, "preconditioner failed");
     }

@@ -79,8 +79,8 @@ extern "C" int tgdk_coarse_setup(tgdk_op op, const double* b, double* x, const t
                                  tgdk_defl* out, tgdk_gmresdr_report* rep) {
     if (!op || !b || !x || !prm || !out) return fail(TGDK_E_INVALID, "NULL argument");
     const int m = prm->m, k = prm->k, nev = prm->nev;
-    if (k < 1 || k >= m || m > MAXK || nev < 0 || nev > k || k > 63)
-        return fail(TGDK_E_INVALID, "need 1 <= k < m <= 128, k <= 63, nev <= k");
+    if (k < 1 || k >= m || m > MAXK || nev < 0 || nev > k)
+        return fail(TGDK_E_INVALID, "need 1 <= k < m <= 256, nev <= k");
     const auto t0 = std::chrono::steady_clock::now();
     TGDK_HIP(hipSetDevice(op->ctx->device));
     tgdk_ctx ctx = op->ctx;
@@ -217,8 +217,8 @@ extern "C" int tgdk_coarse_setup(tgdk_op op, const double* b, double* x, const t
             if (cyc % 5 == 1 || done) {  // loss of orthogonality of the basis
                 std::vector<double> G((size_t)(m + 1) * (m + 1));
                 double* dG = nullptr;
-                if (m + 1 <= 64 && hipMalloc((void**)&dG, sizeof(double) * G.size()) == hipSuccess &&
-                    ctx->partial.ensure((size_t)gram_blocks(n) * G.size() * sizeof(double)) == TGDK_OK) {
+                if (hipMalloc((void**)&dG, sizeof(double) * G.size()) == hipSuccess &&
+                    ctx->partial.ensure(gram_partial_bytes(n, m + 1, m + 1)) == TGDK_OK) {
                     launch_gram(V, 0, n, m + 1, V, 0, n, m + 1, n, dG, (double*)ctx->partial.p, ctx->counters, s);
                     (void)hipMemcpy(G.data(), dG, sizeof(double) * G.size(), hipMemcpyDeviceToHost);
                     for (int i = 0; i <= m; ++i)

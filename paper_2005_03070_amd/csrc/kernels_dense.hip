@@ -116,24 +116,52 @@ __global__ __launch_bounds__(NT) void k_gram(const void* A_, long long lda, int 
     (void)G;
 }
 
-// Sums the per-block Gram partials: one workgroup per entry (k_sum_partials).
+// Entry e = i * qb + j of the summed partials goes to out[i * ldo + j] (a
+// GRAM_MAX x GRAM_MAX block of a larger row-major Gram matrix).
+__global__ __launch_bounds__(NT) void k_sum_gram_block(const double* __restrict__ partial, int nblocks,
+                                                       int npair, int qb, double* __restrict__ out, int ldo) {
+    __shared__ double sh[NWAVE];
+    const int e = blockIdx.x;
+    double a = 0.0;
+#pragma unroll 8
+    for (int b = threadIdx.x; b < nblocks; b += NT) a += partial[(long long)b * npair + e];
+    const double v = block_sum_one(a, sh);
+    if (threadIdx.x == 0) out[(long long)(e / qb) * ldo + e % qb] = v;
+}
+
+// G (p x q, row-major) = A^T B in blocks of at most GRAM_MAX x GRAM_MAX (the
+// kernel's tile limit), each block's per-workgroup partials summed into its
+// place in G; the blocks run one after another on the stream and share the
+// partial workspace (gram_blocks(n) * GRAM_MAX^2 doubles suffice).
 void launch_gram(const void* A, int atype, long long lda, int p, const void* B, int btype, long long ldb, int q,
                  long long n, double* G, double* partial, unsigned* counter, hipStream_t s) {
     const int nb = gram_blocks(n);
-    if (atype == 0 && btype == 0)
-        hipLaunchKernelGGL((k_gram<double, double>), dim3(nb), dim3(NT), 0, s, A, lda, p, B, ldb, q, n, G, partial,
-                           counter);
-    else if (atype == 1 && btype == 1)
-        hipLaunchKernelGGL((k_gram<float, float>), dim3(nb), dim3(NT), 0, s, A, lda, p, B, ldb, q, n, G, partial,
-                           counter);
-    else if (atype == 1 && btype == 0)
-        hipLaunchKernelGGL((k_gram<float, double>), dim3(nb), dim3(NT), 0, s, A, lda, p, B, ldb, q, n, G, partial,
-                           counter);
-    else
-        hipLaunchKernelGGL((k_gram<double, float>), dim3(nb), dim3(NT), 0, s, A, lda, p, B, ldb, q, n, G, partial,
-                           counter);
-    const int npair = p * q;
-    hipLaunchKernelGGL(k_sum_partials, dim3(npair), dim3(NT), 0, s, partial, nb, (long long)npair, G, 0);
+    const size_t ea = atype ? 4 : 8, eb = btype ? 4 : 8;
+    for (int i0 = 0; i0 < p; i0 += GRAM_MAX)
+        for (int j0 = 0; j0 < q; j0 += GRAM_MAX) {
+            const int pb = p - i0 < GRAM_MAX ? p - i0 : GRAM_MAX, qb = q - j0 < GRAM_MAX ? q - j0 : GRAM_MAX;
+            const void* Ab = (const char*)A + (size_t)i0 * lda * ea;
+            const void* Bb = (const char*)B + (size_t)j0 * ldb * eb;
+            if (atype == 0 && btype == 0)
+                hipLaunchKernelGGL((k_gram<double, double>), dim3(nb), dim3(NT), 0, s, Ab, lda, pb, Bb, ldb, qb, n, G,
+                                   partial, counter);
+            else if (atype == 1 && btype == 1)
+                hipLaunchKernelGGL((k_gram<float, float>), dim3(nb), dim3(NT), 0, s, Ab, lda, pb, Bb, ldb, qb, n, G,
+                                   partial, counter);
+            else if (atype == 1 && btype == 0)
+                hipLaunchKernelGGL((k_gram<float, double>), dim3(nb), dim3(NT), 0, s, Ab, lda, pb, Bb, ldb, qb, n, G,
+                                   partial, counter);
+            else
+                hipLaunchKernelGGL((k_gram<double, float>), dim3(nb), dim3(NT), 0, s, Ab, lda, pb, Bb, ldb, qb, n, G,
+                                   partial, counter);
+            hipLaunchKernelGGL(k_sum_gram_block, dim3(pb * qb), dim3(NT), 0, s, partial, nb, pb * qb, qb,
+                               G + (size_t)i0 * q + j0, q);
+        }
+}
+
+size_t gram_partial_bytes(long long n, int p, int q) {
+    const int pb = p < GRAM_MAX ? p : GRAM_MAX, qb = q < GRAM_MAX ? q : GRAM_MAX;
+    return (size_t)gram_blocks(n) * pb * qb * sizeof(double);
 }
 
 // ---------------------------------------------------------------- V * Y
@@ -185,11 +213,19 @@ __global__ __launch_bounds__(NT) void k_vmul(const TV* __restrict__ V, long long
     }
 }
 
+// Out = V Y in column blocks of at most 16 * VMUL_MAXQT (the kernel's limit):
+// block j0 takes Y's columns j0.. (column-major, leading dimension p) and
+// writes Out's.
 void launch_vmul(const double* V, long long ldv, int p, const double* Y, int q, double* Out, long long ldo,
                  long long n, hipStream_t s) {
     long long nb = ((n + 15) / 16 + NWAVE - 1) / NWAVE;
     if (nb > 8192) nb = 8192;
-    hipLaunchKernelGGL(k_vmul<double>, dim3((int)nb), dim3(NT), 0, s, V, ldv, p, Y, q, Out, ldo, n);
+    constexpr int QB = 16 * VMUL_MAXQT;
+    for (int j0 = 0; j0 < q; j0 += QB) {
+        const int qb = q - j0 < QB ? q - j0 : QB;
+        hipLaunchKernelGGL(k_vmul<double>, dim3((int)nb), dim3(NT), 0, s, V, ldv, p, Y + (size_t)j0 * p, qb,
+                           Out + (size_t)j0 * ldo, ldo, n);
+    }
 }
 
 __global__ __launch_bounds__(NT) void k_vmul_add(const double* __restrict__ V, long long ldv, int p,

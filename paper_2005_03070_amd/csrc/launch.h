@@ -76,6 +76,8 @@ bool launch_idr_fused(int what, int inner_f32, const IdrArgs& a, const DevOp& op
 // G (p x q, row-major, device) = A^T B, A: n x p, B: n x q; partial workspace
 // of gram_partial_size(n) doubles * p*q and one counter.
 int gram_blocks(long long n);
+// partial workspace launch_gram needs for a p x q product (any p, q)
+size_t gram_partial_bytes(long long n, int p, int q);
 void launch_gram(const void* A, int atype, long long lda, int p, const void* B, int btype, long long ldb, int q,
                  long long n, double* G, double* partial, unsigned* counter, hipStream_t s);
 // Out (n x q, col-major, ldo) = V (n x p, ldv) * Y (p x q, col-major, device)

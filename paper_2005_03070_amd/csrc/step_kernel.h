@@ -599,8 +599,7 @@ __device__ __forceinline__ void projection_coefficients(const DevProb& P, int gs
     }
     __syncthreads();
     const double* __restrict__ X = P.hinv;  // column-major k x k
-    if (threadIdx.x < k) {
-        const int i = threadIdx.x;
+    for (int i = threadIdx.x; i < k; i += NT) {
         double di = 0.0;
         for (int j = 0; j < k; ++j) di += X[(long long)j * k + i] * y[j];
         st->d[i] = di;

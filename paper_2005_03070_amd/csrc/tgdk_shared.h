@@ -5,7 +5,7 @@
 
 namespace tgdk {
 
-constexpr int MAXK = 128;   // largest deflation space / GMRES cycle length
+constexpr int MAXK = 256;   // largest deflation space / GMRES cycle length
 constexpr int NHIST = 8;    // recorded first BiCGStab scalars
 constexpr int NCYCLOG = 512;  // cycles whose inner iteration counts are logged
 constexpr int NTILE_IDS = 4;  // tile shapes of the grid kernels (ids 0..3)

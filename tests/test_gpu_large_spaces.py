@@ -1,0 +1,109 @@
+"""Deflation spaces and GMRES cycles beyond 64 and 128 vectors: the sizes of
+the paper's own setups (GMRES-DR(150,100) and 100 moved vectors in Sec. 3,
+Example 1 and Sec. 4.1, Example 2; GMRES-DR(200,150) in Sec. 5).  Cholesky
+QR and H = V^T A V over Gram blocks of 64 x 64, V Y in column blocks of 144,
+the step kernel's projection with k > 128."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spl
+import torch
+
+import workloads as W
+from oracle import operators as O, deflation as OD, projection as OP, transfer as T
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+
+
+def tg():
+    import paper_2005_03070_amd as m
+    return m
+
+
+def _t(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def _direct(oop, b):
+    return spl.spsolve(O.to_csr(oop).tocsc(), b)
+
+
+@pytest.mark.parametrize("k,store", [(100, torch.float64), (150, torch.float64), (150, torch.float32)])
+def test_orthonormal_basis_and_H_beyond_64_vectors(k, store):
+    """The library's Cholesky QR of a random n x k basis equals the oracle's
+    unique thin QR (positive diagonal) column by column, and H = V^T A V the
+    oracle's; with float32 storage V is rounded once and H formed from the
+    rounded V."""
+    oop = O.const_cd((127, 127), (40.0, 0.0))
+    Wb = W.rng(61).standard_normal((oop.n, k))
+    op = tg().Operator.const_cd((127, 127), (40.0, 0.0))
+    space = tg().defl_from_basis(op, _t(Wb.T), store=store)
+    Vg, Hg = space.basis()
+    Vg = Vg.cpu().numpy().T
+    V = OD.orthonormalize(Wb)
+    if store == torch.float32:
+        V = V.astype(np.float32).astype(np.float64)
+        assert np.abs(Vg - V).max() <= 1e-7
+    else:
+        assert np.abs(Vg - V).max() <= 1e-12
+        assert np.abs(Vg.T @ Vg - np.eye(k)).max() <= 1e-13
+    H = OP.projection_matrix(oop, Vg)
+    assert np.abs(Hg - H).max() <= 1e-11 * np.abs(H).max()
+
+
+def test_gmres_dr_150_100_closed_form_eigenvalues():
+    """GMRES-DR(150,100) on the 63^2 coarse grid of -Lap(u) + 40 u_x: the
+    converged harmonic Ritz values (80 of the 100 kept, relative eigen-
+    residual <= 1e-8) are eigenvalues of the closed form
+    lambda_j(T_x) + lambda_l(T_y), the coarse solution meets 1e-8 and the
+    basis is orthonormal."""
+    n, beta = 63, 40.0
+    op = tg().Operator.const_cd((n, n), (beta, 0.0))
+    oop = O.const_cd((n, n), (beta, 0.0))
+    b = W.rhs(oop.n, 62)
+    xc, space, rep = tg().coarse_setup(op, _t(b), 150, 100, nev=80, rtolev=1e-8, rtol=1e-8, maxcyc=300)
+    assert rep.status == 0 and rep.nconv >= 80 and rep.k_out >= 100
+    h = 1.0 / (n + 1)
+    jj = np.arange(1, n + 1)
+    lx = 2 / h**2 - 2 * np.sqrt(1 / h**4 - beta**2 / (4 * h * h)) * np.cos(jj * np.pi * h)
+    ly = 2 / h**2 - 2 / h**2 * np.cos(jj * np.pi * h)
+    exact = np.sort((lx[:, None] + ly[None, :]).reshape(-1))
+    conv = rep.theta[:rep.k_out][rep.eigres[:rep.k_out] <= 1e-8]
+    assert len(conv) >= 80
+    for th in conv:
+        assert abs(th.imag) <= 1e-6 * abs(th)
+        assert np.min(np.abs(exact - th.real)) <= 1e-7 * th.real, th
+    assert np.linalg.norm(b - O.apply(oop, xc.cpu().numpy())) <= 1e-8 * np.linalg.norm(b)
+    Vg, _ = space.basis()
+    Vg = Vg.cpu().numpy().T
+    assert np.abs(Vg.T @ Vg - np.eye(Vg.shape[1])).max() <= 1e-12
+
+
+@pytest.mark.parametrize("method,precision", [("bicgstab", "fp64"), ("bicgstab", "fp32_ir"), ("gmres", "fp64"),
+                                              ("idr", "fp64")])
+def test_two_grid_solves_with_100_vectors(method, precision):
+    """The two-grid pipeline with 100 moved vectors (GMRES-DR(150,100) on
+    63^2, BiCGStab(20)-Proj(100), GMRES(50)-Proj(100) or IDR(4)-Proj(100) on
+    127^2) reaches the direct solution."""
+    oop = O.const_cd((127, 127), (40.0, 0.0))
+    b = W.rhs(oop.n, 63)
+    op = tg().Operator.const_cd((127, 127), (40.0, 0.0))
+    solver = tg().TwoGridSolver(op, m=150, k=100, nev=80, rtolev=1e-8, maxcyc=300)
+    x0 = solver.setup(_t(b))
+    assert solver.defl.k >= 100
+    kw = dict(x0=x0, defl=solver.defl, rtol=1e-10)
+    if method == "bicgstab":
+        x, reps = tg().solve(op, _t(b), ncyc=20, precision=precision, **kw)
+        rep = reps[0]
+    elif method == "gmres":
+        x, reps = tg().solve(op, _t(b), method="gmres", m3=50, **kw)
+        rep = reps[0]
+    else:
+        x, rep = tg().solve_idr(op, _t(b), s=4, shadow=_t(W.shadow_draw(oop.n, 4, 64)), ncyc=20, **kw)
+    xg = x.cpu().numpy()
+    assert rep.status == 0
+    assert np.linalg.norm(b - O.apply(oop, xg)) <= 1e-10 * np.linalg.norm(b)
+    xs = _direct(oop, b)
+    assert np.linalg.norm(xg - xs) / np.linalg.norm(xs) <= 1e-7
