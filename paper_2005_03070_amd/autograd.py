@@ -22,10 +22,22 @@ from . import api
 
 
 class TwoGridSolver:
+    """levels: how many times the fine grid is coarsened for the coarse phase
+    (1: h_c = 2 h; the paper's Examples 1-2 coarsen 511^2 to 63^2, three
+    levels, and Example 4 to 127^2, two).  The coarse right-hand side is
+    restricted and the coarse solution and vectors prolongated one level at a
+    time; at each intermediate grid the moved vectors are orthonormalised, so
+    the fine space spans P...P W_c (only the span enters the projection)."""
+
     def __init__(self, op, m=30, k=10, nev=None, rtolev=1e-8, coarse_rtol=1e-8, maxcyc=300,
-                 store=torch.float64, transpose=False):
+                 store=torch.float64, transpose=False, levels=1, grids=None):
         self.op = op
-        self.coarse = op.coarsen()
+        # grids: the operators from fine to coarse (for operators that cannot
+        # coarsen themselves, e.g. per-row coefficient arrays); else coarsened
+        self.grids = list(grids) if grids is not None else [op]
+        while len(self.grids) < levels + 1:
+            self.grids.append(self.grids[-1].coarsen())
+        self.coarse = self.grids[-1]
         self.m, self.k, self.nev = m, k, (k if nev is None else nev)
         self.rtolev, self.coarse_rtol, self.maxcyc = rtolev, coarse_rtol, maxcyc
         self.store = store
@@ -36,12 +48,18 @@ class TwoGridSolver:
     def setup(self, b):
         """Phase 1: GMRES-DR on the restricted right-hand side; returns the
         prolongated coarse solution (the fine initial guess)."""
-        bc = api.restrict(self.op, self.coarse, b)
+        g = self.grids
+        bc = b
+        for lv in range(len(g) - 1):
+            bc = api.restrict(g[lv], g[lv + 1], bc)
         xc, space, rep = api.coarse_setup(self.coarse, bc, self.m, self.k, self.nev, self.rtolev,
                                           self.coarse_rtol, self.maxcyc, self.transpose)
         self.setup_report = rep
-        self.defl = api.defl_prolongate(space, self.op, self.store)
-        return api.prolongate(self.coarse, self.op, xc)
+        for lv in range(len(g) - 2, -1, -1):
+            space = api.defl_prolongate(space, g[lv], self.store if lv == 0 else torch.float64)
+            xc = api.prolongate(g[lv + 1], g[lv], xc)
+        self.defl = space
+        return xc
 
     def solve(self, b, x0=None, **kw):
         """Phase 3 with the current deflation space (set up on the first call)."""

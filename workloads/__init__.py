@@ -71,16 +71,15 @@ CONFIGS = {
                m=80, k=30, nev=24, rtolev=1e-8, ncyc=20, rtol=1e-8),
     "C5": dict(dim=2, n=(1023, 1023), beta=(60.0, 0.0), sigma=0.0, kseed=5, bstar_seed=6,
                bseed=7, dir_seed=8, m=80, k=30, nev=24, rtolev=1e-8, ncyc=20, rtol=1e-8),
-    # Indefinite Helmholtz -Lap(u) - kappa^2 u, kappa = 25 (about 40 negative
-    # eigenvalues), on the 511^2 grid of the paper's Example 4 with a random
-    # normal right-hand side; the wavenumber is scaled down from 100 so that
-    # the 60 vectors the deflation spaces hold here cover the eigenvalues
-    # nearest zero (Example 4 deflates 150 of about 800 negative ones).
-    "H1": dict(dim=2, n=(511, 511), beta=(0.0, 0.0), sigma=-625.0, seed=4,
-               m=128, k=60, nev=48, rtolev=1e-8, ncyc=20, rtol=1e-10, s=20),
-    # The paper's Example 5: -Lap(u) - 100^2 u on 511^2 preconditioned on both
-    # grids by multigrid on -Lap(u) + 100^2 u; IDR(5)(5)-Proj; 60 vectors
-    # here (Example 5 keeps 100, 80 converged).
-    "H2": dict(dim=2, n=(511, 511), beta=(0.0, 0.0), sigma=-1.0e4, seed=4, mg_cycles=2, mg_nu=2,
-               m=128, k=60, nev=48, rtolev=1e-8, ncyc=5, rtol=1e-10, s=5),
+    # The paper's Example 4 as printed: -Lap(u) - 100^2 u on 511^2 with a
+    # random normal right-hand side, coarse grid 127^2 (two levels),
+    # GMRES-DR(200,150) until 120 pairs converge, then IDR(20)-Proj(150) and
+    # GMRES(100)-Proj(150) on the fine grid, rtol 1e-10.
+    "H1": dict(dim=2, n=(511, 511), beta=(0.0, 0.0), sigma=-1.0e4, seed=4, levels=2,
+               m=200, k=150, nev=120, rtolev=1e-8, maxcyc=400, ncyc=20, rtol=1e-10, s=20, m3=100),
+    # The paper's Example 5: the same problem preconditioned on both grids by
+    # multigrid on -Lap(u) + 100^2 u; GMRES-DR(150,100) on A_c M_c^{-1} until
+    # 80 pairs converge, IDR(5)(5)-Proj(100) on the fine grid.
+    "H2": dict(dim=2, n=(511, 511), beta=(0.0, 0.0), sigma=-1.0e4, seed=4, mg_cycles=2, mg_nu=2, levels=2,
+               m=150, k=100, nev=80, rtolev=1e-8, maxcyc=400, ncyc=5, rtol=1e-10, s=5, m3=100),
 }
