@@ -101,12 +101,13 @@ int tgdk_ctx_num_cus(tgdk_ctx ctx);
 #define TGDK_STEP_A      1  /* phase A of iteration i > 0: r, e, p updates, v = A p, r^.v and ||r||^2 partials */
 #define TGDK_STEP_A0     2  /* phase A of iteration 0 of a cycle (p = r) */
 #define TGDK_STEP_B      3  /* phase B: s = r - alpha v, t = A s, five dot-product partials */
-#define TGDK_STEP_RES    4  /* end of a cycle: r = b - A (x + update), ||r||^2 and c = V^T r partials */
+#define TGDK_STEP_RES    4  /* end of a cycle: r = b - A (x + update), ||r||^2 (2-D, and 3-D with a float32 V: and c = V^T r) partials */
 #define TGDK_STEP_REDUCE 5  /* c summed and H d = c solved (one workgroup) */
 #define TGDK_STEP_APPLY  6  /* x += update + V d, r -= A V d, new shadow vector (3-D: r -= A w only) */
 #define TGDK_STEP_FIN    7  /* final update folded into x */
 #define TGDK_STEP_FIN_A0 8  /* update folded into x and phase A of iteration 0 (no deflation) */
 #define TGDK_STEP_APPLYW 9  /* 3-D: w = V d and x += update + w (APPLY then does r -= A w) */
+#define TGDK_STEP_CDOT   10 /* 3-D with a float64 V: c = V^T r partials (after the boundary decisions; REDUCE follows) */
 #define TGDK_STEP_ANY   -1
 #define TGDK_STEP_ALL   -2
 int tgdk_ctx_time_kernel(tgdk_ctx ctx, int on);

@@ -334,7 +334,8 @@ int tgdk_ctx_num_cus(tgdk_ctx c) { return c ? c->num_cus : 0; }
 
 static_assert(TGDK_STEP_NONE == ACT_NONE && TGDK_STEP_A == ACT_A && TGDK_STEP_A0 == ACT_A0 && TGDK_STEP_B == ACT_B && TGDK_STEP_RES == ACT_RES &&
                   TGDK_STEP_REDUCE == ACT_REDUCE && TGDK_STEP_APPLY == ACT_APPLY && TGDK_STEP_FIN == ACT_FIN &&
-                  TGDK_STEP_FIN_A0 == ACT_FIN_A0 && TGDK_STEP_APPLYW == ACT_APPLYW && NACT == 10,
+                  TGDK_STEP_FIN_A0 == ACT_FIN_A0 && TGDK_STEP_APPLYW == ACT_APPLYW && TGDK_STEP_CDOT == ACT_CDOT &&
+                  NACT == 11,
               "step action codes");
 
 int tgdk_ctx_time_kernel(tgdk_ctx c, int on) {

@@ -116,9 +116,9 @@ struct ScribeCnt {
 // the same inputs; only the scribe (thread 0 of the lead workgroup) writes
 // the report counters (C: their values before this launch, scribe only).
 // maxit: the inner iteration cap.  Returns the action of this launch.
-__device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* st, int k, int dim, int gslot,
-                           bool scribe, int maxit, const ScribeCnt& C, StepHot& N, Upd& U, double& rr_out,
-                           double& rr0_out) {
+__device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* st, int k, int dim, bool cdot,
+                           int gslot, bool scribe, int maxit, const ScribeCnt& C, StepHot& N, Upd& U,
+                           double& rr_out, double& rr0_out) {
     N = H;
     U = Upd{H.upd_a, H.upd_w, H.upd_any, H.pbuf};
     const int after_res = k > 0 ? M_REDUCE : M_APPLY0;
@@ -205,6 +205,10 @@ __device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* s
                 return H.upd_any ? ACT_FIN : ACT_NONE;
             }
             if (H.mode == M_REDUCE) {
+                if (cdot) {  // c partials in this launch, summed in the next
+                    N.mode = M_SUMC;
+                    return ACT_CDOT;
+                }
                 N.mode = dim == 3 ? M_APPLYW : M_APPLY;
                 return ACT_REDUCE;
             }
@@ -219,6 +223,9 @@ __device__ int step_decide(const StepHot& H, const double (&s)[5], SolveState* s
             N.mode = M_B;
             return H.upd_any ? ACT_FIN_A0 : ACT_A0;
         }
+        case M_SUMC:
+            N.mode = M_APPLYW;
+            return ACT_REDUCE;
         case M_APPLYW:
             N.mode = M_APPLY;
             N.upd_any = 0;
@@ -854,8 +861,13 @@ __device__ __forceinline__ void march_b(const DevProb& P, int lw, int gslot, con
 
 // --------------------------------------- 3-D cycle boundary by z marching
 // True residual r = b - A x' with x' = x + e + a p + w s formed on the fly,
-// with its partials; then, in a second pass over the workgroup's own chunk
-// (r read back after a workgroup barrier), c = V^T r (chunk_columns).
+// with its partials.  c = V^T r: a float32 V is read in a second pass over
+// the workgroup's own chunk (r read back after a workgroup barrier,
+// chunk_columns); a float64 V in the next launch over contiguous ranges
+// (flat_cdot).  Measured at 255^3 with 41 vectors: the chunk pass costs
+// about 1.2 ms per boundary with a float64 V and 0.76 ms with a float32 V,
+// the contiguous pass 1.09 ms and 1.35 ms; the float32 contiguous pass
+// issues half-width loads and re-reads r once per column group.
 template <class TI>
 struct MarchRes {
     const double *x, *b;
@@ -913,12 +925,12 @@ struct MarchRes {
     __device__ __forceinline__ void plane_done(const Chunk&, int) {}
 };
 
-// c partial of one chunk: the workgroup streams the chunk's points (thread
-// t takes points t, t + 256, ... in x-y-z order, coalesced) against four
-// columns of V at a time, reading r once per group of columns; per-thread
-// sums are combined by block_sum, so the order is fixed.
-template <class M, class TV>
-__device__ __forceinline__ void chunk_columns(const DevProb& P, const Chunk& c, const TV* __restrict__ V,
+// c partial of one chunk (float32 V): the workgroup streams the chunk's
+// points (thread t takes points t, t + 256, ... in x-y-z order, coalesced)
+// against four columns of V at a time, reading r once per group of columns;
+// per-thread sums are combined by block_sum, so the order is fixed.
+template <class M>
+__device__ __forceinline__ void chunk_columns(const DevProb& P, const Chunk& c, const float* __restrict__ V,
                                               double* csum, double* sh) {
     const DevOp& op = P.op;
     const long long plane = (long long)op.nx * op.ny;   // V: unpadded
@@ -928,13 +940,13 @@ __device__ __forceinline__ void chunk_columns(const DevProb& P, const Chunk& c, 
     const int npts = 64 * M::MY * (c.z1 - c.z0);
     for (int j0 = 0; j0 < k; j0 += 4) {
         double a[4] = {0.0, 0.0, 0.0, 0.0};
-        const TV* __restrict__ Vj[4];
+        const float* __restrict__ Vj[4];
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) Vj[jj] = V + (long long)(j0 + jj < k ? j0 + jj : j0) * P.ldv;
         // no guarded loads (a guarded load compiles to a branch and a full
         // wait): points outside the domain read the zero page for r and V
         const gptr<const double> zr = gp<const double>(op.zero);
-        const gptr<const TV> zv = gp<const TV>(op.zero);
+        const gptr<const float> zv = gp<const float>(op.zero);
 #pragma unroll 4
         for (int l = threadIdx.x; l < npts; l += NT) {
             const int gx = c.x0 + (l & 63), gy = c.y0 + ((l >> 6) % M::MY), z = c.z0 + l / (64 * M::MY);
@@ -943,7 +955,7 @@ __device__ __forceinline__ void chunk_columns(const DevProb& P, const Chunk& c, 
             const long long gpad = z * pplane + (long long)gy * op.px + gx;
             const double rv = *(in ? gp<const double>(r) + gpad : zr);
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) a[jj] += (double)*(in ? gp<const TV>(Vj[jj]) + g : zv) * rv;
+            for (int jj = 0; jj < 4; ++jj) a[jj] += (double)*(in ? gp<const float>(Vj[jj]) + g : zv) * rv;
         }
         double tot;
         block_sum<4, true>(a, sh, tot);
@@ -956,7 +968,9 @@ __device__ __forceinline__ void march_res(const DevProb& P, int lw, int gslot, c
                                           double* sh, double* csum) {
     using M = StepMarch<TI>;
     const int k = P.k;
-    for (int i = threadIdx.x; i < k; i += NT) csum[i] = 0.0;
+    const bool fused_c = k > 0 && P.vtype;
+    if (fused_c)
+        for (int i = threadIdx.x; i < k; i += NT) csum[i] = 0.0;
     TI* rin = vp<TI>(P.rin);
     MarchRes<TI> ph{P.x, P.b, vp<const TI>(P.e), vp<const TI>(P.p[U.pbuf]), vp<const TI>(P.s),
                     reinterpret_cast<const double*>(P.op.zero), reinterpret_cast<const TI*>(P.op.zero), U, P.r,
@@ -971,12 +985,9 @@ __device__ __forceinline__ void march_res(const DevProb& P, int lw, int gslot, c
         march_chunk<MH, VAR, double>(P.op, h, Lbox, ph);
         h.y0 += MH::MY;
         if (h.y0 < P.op.ny) march_chunk<MH, VAR, double>(P.op, h, Lbox, ph);
-        __syncthreads();  // r of the chunk, written above, is read back below
-        if (k > 0) {
-            if (P.vtype)
-                chunk_columns<M>(P, c, reinterpret_cast<const float*>(P.Vl), csum, sh);
-            else
-                chunk_columns<M>(P, c, reinterpret_cast<const double*>(P.Vl), csum, sh);
+        if (fused_c) {
+            __syncthreads();  // r of the chunk, written above, is read back below
+            chunk_columns<M>(P, c, reinterpret_cast<const float*>(P.Vl), csum, sh);
         }
     }
     __syncthreads();
@@ -984,37 +995,77 @@ __device__ __forceinline__ void march_res(const DevProb& P, int lw, int gslot, c
     block_sum<3, true>(ph.acc, sh, tot);
     const int slot = gslot & 1;
     if (threadIdx.x < 3) *part_at(P, slot, threadIdx.x, lw) = tot;
-    for (int i = threadIdx.x; i < k; i += NT) *part_at(P, slot, 3 + i, lw) = csum[i];
+    if (fused_c)
+        for (int i = threadIdx.x; i < k; i += NT) *part_at(P, slot, 3 + i, lw) = csum[i];
 }
 
-// w = V d and x <- (x + e + a p + w s) + w on this workgroup's chunk (pointwise).
-template <class TI, class TV>
-__device__ __forceinline__ void apply_w_points(const DevProb& P, int lw, const Upd& U, const TV* __restrict__ V,
-                                               const double* __restrict__ dsh) {
-    using M = StepMarch<TI>;
-    if (lw >= P.nchunks) return;
+// ------------- 3-D c = V^T r over contiguous ranges (ACT_CDOT, float64 V)
+// Workgroup lw takes the points [lw L, (lw + 1) L) of the unpadded index
+// (L a multiple of 64), so every column load of a wave is 64 consecutive
+// entries of V (512 bytes); r, stored with the padded pitch, is read at
+// index g + (g / n_x)(px - n_x).  CH columns per pass over the range (r
+// re-read from cache by later passes); a column past k re-reads the pass's
+// first and is masked on its factor, so every load of a point is issued
+// unconditionally.
+__device__ __forceinline__ void flat_cdot(const DevProb& P, int lw, int gslot, double* sh) {
+    using TV = double;
+    constexpr int CH = 8;
     const DevOp& op = P.op;
-    const Chunk c = chunk_of<M>(lw, P.mcx, P.mcy, P.mz, op.nz);
-    const long long plane = (long long)op.nx * op.ny;   // V, x: unpadded
-    const long long pplane = (long long)op.px * op.ny;  // w and the update: padded
+    const long long n = op.n;
+    const long long L = ((n + P.nwg - 1) / P.nwg + 63) / 64 * 64;
+    const long long g0 = (long long)lw * L, g1 = g0 + L < n ? g0 + L : n;
+    const gptr<const TV> V = gp<const TV>(P.Vl);
+    const gptr<const double> r = gp<const double>(P.r);
     const int k = P.k;
-    for (int z = c.z0; z < c.z1; ++z) {
+    const double nx = (double)op.nx;
+    const long long pad = op.px - op.nx;
+    for (int j0 = 0; j0 < k; j0 += CH) {
+        const int nc = k - j0 < CH ? k - j0 : CH;
+        double a[CH];
 #pragma unroll
-        for (int q = 0; q < M::PPT; ++q) {
-            int lx, ly, ci;
-            own_point<M>(q, lx, ly, ci);
-            const int gx = c.x0 + lx, gy = c.y0 + ly;
-            if (gx >= op.nx || gy >= op.ny) continue;
-            const long long gu = z * plane + (long long)gy * op.nx + gx;
-            const long long g = z * pplane + (long long)gy * op.px + gx;
-            double w = 0.0;
-#pragma unroll 8
-            for (int j = 0; j < k; ++j) w += (double)V[(long long)j * P.ldv + gu] * dsh[j];
-            P.w[g] = w;
-            double xv = P.x[gu];
-            if (U.any) xv += upd_at<TI>(P, U, g);
-            P.x[gu] = xv + w;
+        for (int jj = 0; jj < CH; ++jj) a[jj] = 0.0;
+        gptr<const TV> Vj[CH];
+#pragma unroll
+        for (int jj = 0; jj < CH; ++jj) Vj[jj] = V + (long long)(j0 + (jj < nc ? jj : 0)) * P.ldv;
+#pragma unroll 2
+        for (long long g = g0 + threadIdx.x; g < g1; g += NT) {
+            // the row (y, z) of g: a double division is exact here (g < 2^53
+            // and g / n_x lies at least 1 / n_x away from the next integer)
+            const long long row = (long long)((double)g / nx);
+            const double rv = r[g + row * pad];
+#pragma unroll
+            for (int jj = 0; jj < CH; ++jj) a[jj] += (jj < nc ? (double)Vj[jj][g] : 0.0) * rv;
         }
+        double tot;
+        block_sum<CH, true>(a, sh, tot);
+        if (threadIdx.x < nc) *part_at(P, gslot & 1, 3 + j0 + threadIdx.x, lw) = tot;
+    }
+}
+
+// w = V d and x <- (x + e + a p + w s) + w over the workgroup's contiguous
+// range of the unpadded index (as in flat_cdot): V and x are read at g, w and
+// the update's vectors at the padded index.  All k columns of a point are
+// summed in one pass, eight loads in flight.
+template <class TI, class TV>
+__device__ __forceinline__ void apply_w_flat(const DevProb& P, int lw, const Upd& U, const TV* __restrict__ V_,
+                                             const double* __restrict__ dsh) {
+    const DevOp& op = P.op;
+    const long long n = op.n;
+    const long long L = ((n + P.nwg - 1) / P.nwg + 63) / 64 * 64;
+    const long long g0 = (long long)lw * L, g1 = g0 + L < n ? g0 + L : n;
+    const gptr<const TV> V = gp<const TV>(V_);
+    const double nx = (double)op.nx;
+    const long long pad = op.px - op.nx;
+    const int k = P.k;
+    for (long long g = g0 + threadIdx.x; g < g1; g += NT) {
+        const long long gpad = g + (long long)((double)g / nx) * pad;
+        double w = 0.0;
+#pragma unroll 8
+        for (int j = 0; j < k; ++j) w += (double)V[(long long)j * P.ldv + g] * dsh[j];
+        P.w[gpad] = w;
+        double xv = P.x[g];
+        if (U.any) xv += upd_at<TI>(P, U, gpad);
+        P.x[g] = xv + w;
     }
 }
 
@@ -1023,9 +1074,9 @@ __device__ __forceinline__ void apply_w(const DevProb& P, int lw, const Upd& U, 
     for (int i = threadIdx.x; i < P.k; i += NT) dsh[i] = st->d[i];
     __syncthreads();
     if (P.vtype)
-        apply_w_points<TI>(P, lw, U, reinterpret_cast<const float*>(P.V), dsh);
+        apply_w_flat<TI>(P, lw, U, reinterpret_cast<const float*>(P.V), dsh);
     else
-        apply_w_points<TI>(P, lw, U, reinterpret_cast<const double*>(P.V), dsh);
+        apply_w_flat<TI>(P, lw, U, reinterpret_cast<const double*>(P.V), dsh);
 }
 
 // r <- r - A w; the new cycle's inner residual and shadow vector; partials
@@ -1105,7 +1156,7 @@ __device__ __forceinline__ void step_run(const DevProb& P, int wg, int gslot, un
     StepHot N;
     Upd U;
     double rr = -1.0, rr0 = -1.0;
-    const int act = step_decide(H, s5, st, P.k, DIM, gslot, scribe, maxit, C, N, U, rr, rr0);
+    const int act = step_decide(H, s5, st, P.k, DIM, DIM == 3 && !P.vtype, gslot, scribe, maxit, C, N, U, rr, rr0);
     if (scribe) {
         st->hot[cur] = N;
         st->solve_state = N.solve_state;
@@ -1155,6 +1206,9 @@ __device__ __forceinline__ void step_run(const DevProb& P, int wg, int gslot, un
             break;
         case ACT_APPLYW:
             apply_w<TI>(P, lw, U, st, ysh);
+            break;
+        case ACT_CDOT:
+            if constexpr (DIM == 3) flat_cdot(P, lw, gslot, sh);
             break;
         case ACT_REDUCE:
             if (lead) projection_coefficients(P, gslot, st, ysh, sh);

@@ -47,6 +47,7 @@ enum : int {
     M_START = 6,    // decisions after the projection, then phase A of iteration 0
     M_APPLY0 = 7,   // no deflation: decisions, x += upd, phase A of iteration 0
     M_APPLYW = 8,   // 3-D: w = V d, x += upd + w (then M_APPLY: r -= A w)
+    M_SUMC = 9,     // 3-D, float64 V: c summed and H d = c solved (the c partials came from ACT_CDOT)
 };
 // ... and what a launch did for it (logged for measurement)
 enum : int {
@@ -60,7 +61,8 @@ enum : int {
     ACT_FIN = 7,     // last inner update folded into x
     ACT_FIN_A0 = 8,  // x update and phase A of iteration 0 (no deflation)
     ACT_APPLYW = 9,  // 3-D: w = V d and x += upd + w (the stencil part follows as ACT_APPLY)
-    NACT = 10,
+    ACT_CDOT = 10,   // 3-D, float64 V: c = V^T r partials over contiguous ranges (after the boundary decisions)
+    NACT = 11,
 };
 
 // Scalars of the step kernel's state machine, double-buffered by launch
