@@ -51,8 +51,9 @@ def _args():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle's inner-iteration sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--cpu-full-c2", action="store_true",
-                    help="only run the oracle in full on the 1023^2 workload (setup and fine solve), then exit")
+    ap.add_argument("--cpu-full", default=None, metavar="LIST",
+                    help="only run the oracle in full (setup and solves, one core) on the listed workloads "
+                         "(comma-separated from c1, c2, c5: 63^2, 1023^2, the 1023^2 adjoint workload), then exit")
     ap.add_argument("--solve-only", action="store_true",
                     help="setup, warm-up and timed solves only (for profiler runs)")
     ap.add_argument("--workload", choices=("c3", "c3f32", "c2", "c2f32", "mg"), default="c3",
@@ -136,8 +137,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): this build measures one GPU's share; "
               "the multi-GPU design is documented but not built", file=sys.stderr)
         sys.exit(2)
-    if a.cpu_full_c2:
-        return cpu_full_c2()
+    if a.cpu_full:
+        return cpu_full(a.cpu_full.split(","))
     import numpy as np
     import torch
 
@@ -435,6 +436,30 @@ def other_workloads(tg, W, dev, timed, relres, cost, step_timing, log_timing, np
     del space_m
     s, (x, r) = timed(lambda: tg.solve(op, b, rtol=c["rtol"], ncyc=c["ncyc"], max_extra=40), reps=1)
     w2["bicgstab20_no_deflation_fp64"] = {"seconds": s, "relres_true": relres(op, b, x), **cost(r[0], 2)}
+    # variable restarts (Sec. 4.3): GMRES with the cycle lengths of the
+    # BiCGStab(20)-Proj run (each capped at 128), and seeded random lengths
+    _, rb = fine()
+    lens_b = [min(max(v, 1), 128) for v in rb[0].cycle_mvps]
+    lens_r = [int(v) for v in W.rng(43).integers(1, 101, size=400)]
+    for name, lens, m3 in (("gmres_restarted_as_bicgstab_proj30_fp64", lens_b, 128),
+                           ("gmres_random_lengths_1_100_proj30_fp64", lens_r, 100)):
+        s, (x, r) = timed(lambda: fine(method="gmres", m3=m3, cycle_lengths=lens, max_extra=1000), reps=1)
+        w2[name] = {"seconds": s, "relres_true": relres(op, b, x), "status": r[0].status_name, **cost(r[0], 2)}
+        tg_log(f"1023^2 {name}: {s*1e3:.1f} ms, mvps {r[0].mvp_inner}, cycles {r[0].cycles}")
+    # Arnoldi-E(80,30) on the moved space (phase 2), then the same fine solve
+    t = time.perf_counter()
+    space_e, rep_e = space.improve(80, nev=24, tol=1e-4, maxcyc=20)
+    torch.cuda.synchronize()
+    se = time.perf_counter() - t
+    s, (x, r) = timed(lambda: fine(defl=space_e), reps=3)
+    w2["arnoldi_e_80_30_then_bicgstab20_proj30_fp64"] = {
+        "improve_seconds": se, "improve_cycles": rep_e["cycles"], "improve_mvps": rep_e["mvps"],
+        "improve_nconv": rep_e["nconv"], "eigres_max_before": float(np.max(rep_e["eigres_start"])),
+        "eigres_max_after": float(np.max(rep_e["eigres"][:24])),
+        "seconds": s, "relres_true": relres(op, b, x), **cost(r[0], 2)}
+    tg_log(f"1023^2 Arnoldi-E(80,30): {se*1e3:.0f} ms, {rep_e['cycles']} cycles, {rep_e['mvps']} mvps; "
+           f"then {s*1e3:.1f} ms, mvps {r[0].mvp_inner}")
+    del space_e
     out["c2_1023sq_k30"] = w2
     del op, b, cop, cs, space, x0, shadow
     torch.cuda.empty_cache()
@@ -706,33 +731,74 @@ def cpu_sample(a, head, k, x0):
     return {"value": est, "unit": "s", "cores": 1, "kind": "oracle", "extrapolated": True, "sample": sample}
 
 
-def cpu_full_c2():
-    """The oracle in full on the 1023^2 workload: coarse GMRES-DR(80,30) on
-    511^2, the moved space, BiCGStab(20)-Proj(30) to true relative residual
-    1e-8.  Prints one JSON line with the times (setup and fine solve)."""
+def cpu_full(names):
+    """The oracle in full, one core (BLAS held to one thread), on the small
+    case (63^2), the 1023^2 workload and the 1023^2 adjoint workload: coarse
+    GMRES-DR, the moved space, BiCGStab(20)-Proj to true relative residual
+    1e-8 (the adjoint workload: u* by a direct solve, the forward solve, the
+    left space from GMRES-DR on the coarse transpose, the adjoint solve and
+    dL/dk).  Progress goes to stderr after every coarse and fine cycle; one
+    JSON line with the times goes to stdout."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     import workloads as W
-    from oracle import bicgstab as OB, operators as OO, transfer as OT, gmresdr as ODR, deflation as OD
-    c = W.CONFIGS["C2"]
-    oop = OO.const_cd(c["n"], c["beta"])
-    b = W.rhs(oop.n, c["seed"])
-    with threadpool_limits(1):
+    from oracle import (adjoint as OA, bicgstab as OB, deflation as OD, direct as ODS, gmresdr as ODR,
+                        operators as OO, transfer as OT)
+
+    def setup(tag, op, b, c, transpose=False):
         t = time.perf_counter()
-        opc = OO.coarsen(oop)
-        xc, Wc, grep = ODR.gmres_dr(opc, OT.restrict(b, oop.dims), c["m"], c["k"], nev=c["nev"],
-                                    rtolev=c["rtolev"])
-        V, H = OD.deflation_space(oop, Wc, opc.dims)
+        opc = OO.coarsen(op)
+        xc, Wc, rep = ODR.gmres_dr(opc, OT.restrict(b, op.dims), c["m"], c["k"], nev=c["nev"], rtolev=c["rtolev"],
+                                   transpose=transpose,
+                                   progress=lambda cyc, nc: log(f"oracle {tag} GMRES-DR cycle {cyc}: {nc} converged"))
+        V, H = OD.deflation_space(op, Wc, opc.dims, transpose=transpose)
         x0 = OT.prolongate(xc, opc.dims)
-        t_setup = time.perf_counter() - t
-        log(f"oracle setup {t_setup:.0f} s")
+        dt = time.perf_counter() - t
+        log(f"oracle {tag} setup {dt:.1f} s ({rep.cycles} cycles, k = {V.shape[1]})")
+        return x0, V, H, dt, rep
+
+    def fine(tag, op, b, x0, V, H, c, transpose=False):
         t = time.perf_counter()
-        x, rep = OB.bicgstab_proj(oop, b, x0=x0, V=V, H=H, rtol=c["rtol"], ncyc=c["ncyc"])
-        t_solve = time.perf_counter() - t
-    out = {"oracle_c2_full": {"setup_seconds": t_setup, "solve_seconds": t_solve, "status": rep.status,
-                              "relres_true": rep.relres_true, "mvp_inner": rep.mvp_inner,
-                              "mvp_boundary": rep.mvp_boundary, "cycles": rep.cycles, "k": V.shape[1],
-                              "cpu": cpu_model(), "logical_cores": os.cpu_count(), "threads_used": 1}}
+        x, rep = OB.bicgstab_proj(op, b, x0=x0, V=V, H=H, rtol=c["rtol"], ncyc=c["ncyc"], transpose=transpose,
+                                  progress=lambda cyc, nu: log(f"oracle {tag} cycle {cyc}: ||r|| {nu:.3e}"))
+        dt = time.perf_counter() - t
+        log(f"oracle {tag} solve {dt:.1f} s, {rep.mvp_inner} inner mvps")
+        return x, {"solve_seconds": dt, "status": rep.status, "relres_true": rep.relres_true,
+                   "mvp_inner": rep.mvp_inner, "mvp_boundary": rep.mvp_boundary, "cycles": rep.cycles}
+
+    out = {"cpu": cpu_model(), "logical_cores": os.cpu_count(), "threads_used": 1, "kind": "oracle"}
+    with threadpool_limits(1):
+        for name in names:
+            if name in ("c1", "c2"):
+                c = W.CONFIGS[name.upper()]
+                op = OO.const_cd(c["n"], c["beta"])
+                b = W.rhs(op.n, c["seed"])
+                x0, V, H, t_setup, grep = setup(name, op, b, c)
+                _, res = fine(name, op, b, x0, V, H, c)
+                out[f"oracle_{name}_full"] = {"setup_seconds": t_setup, "gmresdr_cycles": grep.cycles,
+                                              "k": V.shape[1], **res}
+            elif name == "c5":
+                c = W.CONFIGS["C5"]
+                dims = c["n"]
+                op = OO.div_k(dims, W.kfield(dims, c["kseed"]), c["beta"])
+                t = time.perf_counter()
+                ustar = ODS.solve(op, W.rhs(op.n, c["bstar_seed"]))
+                t_star = time.perf_counter() - t
+                log(f"oracle c5 u* direct solve {t_star:.1f} s")
+                b = W.rhs(op.n, c["bseed"])
+                x0, V, H, t_sf, _ = setup("c5 forward", op, b, c)
+                u, res_f = fine("c5 forward", op, b, x0, V, H, c)
+                g = u - ustar
+                x0, V, H, t_sa, _ = setup("c5 adjoint", op, g, c, transpose=True)
+                lam, res_a = fine("c5 adjoint", op, g, x0, V, H, c, transpose=True)
+                t = time.perf_counter()
+                OA.grad_k(lam, u, dims)
+                t_g = time.perf_counter() - t
+                out["oracle_c5_full"] = {"ustar_direct_seconds": t_star, "setup_seconds_forward": t_sf,
+                                         "forward": res_f, "setup_seconds_adjoint": t_sa, "adjoint": res_a,
+                                         "grad_k_seconds": t_g}
+            else:
+                raise SystemExit(f"--cpu-full: unknown workload {name!r} (c1, c2, c5)")
     print(json.dumps(out))
 
 

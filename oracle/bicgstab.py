@@ -147,12 +147,14 @@ class SolveReport:
 
 def bicgstab_proj(op, b, x0=None, V=None, H=None, rtol=1e-8, ncyc=20,
                   max_extra=None, maxit_cycle=100000, precision="fp64",
-                  fp32_floor=1e-4, transpose=False, projection="galerkin"):
+                  fp32_floor=1e-4, transpose=False, projection="galerkin", progress=None):
     """BiCGStab(ncyc)-Proj(k) on ``A x = b`` (or ``A^T x = b``).
 
     ``V`` (n x k, orthonormal) and ``H = V^T A V`` may be None (k = 0);
     ``projection="minres"`` takes the MinRes variant of step a) (``H`` is then
-    not used).  Returns ``(x, SolveReport)``."""
+    not used).  ``progress`` (optional, ``f(cycle, ||r||)``) is called after
+    every cycle's true residual and changes nothing.  Returns
+    ``(x, SolveReport)``."""
     mv = (lambda z: operators.apply_transpose(op, z)) if transpose else (lambda z: operators.apply(op, z))
     if max_extra is None:
         max_extra = ncyc
@@ -195,6 +197,8 @@ def bicgstab_proj(op, b, x0=None, V=None, H=None, rtol=1e-8, ncyc=20,
         nu = float(np.linalg.norm(r))
         rep.nu_hist.append(nu)
         rep.cycles = icyc
+        if progress is not None:
+            progress(icyc, nu)
         if nu <= tau:                                   # step d)
             break
         if inner.status == "breakdown" and inner.iters == 0:

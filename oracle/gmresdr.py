@@ -134,7 +134,7 @@ class DRReport:
 
 
 def gmres_dr(op, b, m, k, nev=None, rtolev=1e-8, rtol=1e-8, maxcyc=300,
-             transpose=False, x0=None, precond=None):
+             transpose=False, x0=None, precond=None, progress=None):
     """GMRES-DR(m,k) on ``A x = b``.  Returns ``(x, W, report)`` where ``W``
     (n x k') is an orthonormal basis of the final k harmonic Ritz vectors
     (k' = k, or k+1 if a conjugate pair straddles position k).
@@ -142,7 +142,10 @@ def gmres_dr(op, b, m, k, nev=None, rtolev=1e-8, rtol=1e-8, maxcyc=300,
     ``precond`` (a function ``v -> M^{-1} v``): right preconditioning (Sec. 5,
     Example 5): the cycles run on ``A M^{-1}`` from ``u = 0`` (``x0`` must be
     None), the kept vectors are harmonic Ritz vectors of ``A M^{-1}`` and the
-    solution is ``x = M^{-1} u``."""
+    solution is ``x = M^{-1} u``.
+
+    ``progress`` (optional, ``f(cycle, nconv)``) is called after every
+    cycle; it sees the counts only and changes nothing."""
     mv0 = (lambda z: operators.apply_transpose(op, z)) if transpose else (lambda z: operators.apply(op, z))
     assert precond is None or x0 is None
     mv = mv0 if precond is None else (lambda z: mv0(precond(z)))
@@ -176,6 +179,8 @@ def gmres_dr(op, b, m, k, nev=None, rtolev=1e-8, rtol=1e-8, maxcyc=300,
         rep.theta = theta[chosen]
         rep.eigres = eigen_residuals(Hbar, m, theta, G, chosen) / anorm
         done = (np.linalg.norm(q) <= rtol * bnorm) and nconv >= nev
+        if progress is not None:
+            progress(cyc, nconv)
         # restart (also done after the last cycle to form W)
         Gr = real_basis(theta, G, chosen)
         kk = Gr.shape[1]
