@@ -46,7 +46,8 @@
 
 namespace tgdk {
 
-// pending x update: x += e + a p + w s (p from buffer pbuf)
+// pending x update: x += e + a p + w s (p, and on 3-D grids r_i and v_i for
+// s = r_i - a v_i, from buffer pbuf)
 struct Upd {
     double a, w;
     int any, pbuf;
@@ -270,13 +271,26 @@ __device__ __forceinline__ double vload(const DevProb& P, long long i) {
     return P.vtype ? (double)reinterpret_cast<const float*>(P.V)[i] : reinterpret_cast<const double*>(P.V)[i];
 }
 
+// s = r_i - alpha v_i of the iteration whose update is pending, at index g:
+// stored by phase B on 2-D grids; on 3-D grids formed from r_i and v_i with
+// phase B's own expression (a = alpha whenever w != 0), so the same bits.
+template <int DIM, class TI>
+__device__ __forceinline__ TI s_at(const DevProb& P, const Upd& U, long long g) {
+    if constexpr (DIM == 3) {
+        const TI a = (TI)U.a;
+        return vp<const TI>(P.r2[U.pbuf])[g] - a * vp<const TI>(P.v[U.pbuf])[g];
+    } else {
+        return vp<const TI>(P.s)[g];
+    }
+}
+
 // e + a p + w s at index g of the step kernel's own vectors (padded pitch
 // on 3-D grids): the pending inner update, float64.
-template <class TI>
+template <int DIM, class TI>
 __device__ __forceinline__ double upd_at(const DevProb& P, const Upd& U, long long g) {
     double u = (double)vp<const TI>(P.e)[g];
     if (U.a != 0.0) u += U.a * (double)vp<const TI>(P.p[U.pbuf])[g];
-    if (U.w != 0.0) u += U.w * (double)vp<const TI>(P.s)[g];
+    if (U.w != 0.0) u += U.w * (double)s_at<DIM, TI>(P, U, g);
     return u;
 }
 
@@ -355,7 +369,7 @@ __device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, boo
         if (fin) {
 #pragma unroll
             for (int q = 0; q < Cfg::PPT; ++q)
-                if (gq[q] >= 0) P.x[gq[q]] += upd_at<TI>(P, U, gq[q]);
+                if (gq[q] >= 0) P.x[gq[q]] += upd_at<DIM, TI>(P, U, gq[q]);
         }
         // stencil input p_i on the tile and its halo
         TI rq[Cfg::PPT];
@@ -527,7 +541,7 @@ __device__ __forceinline__ void true_residual(const DevProb& P, int lw, int gslo
     const long long ldv = P.ldv;
     const double* __restrict__ x = P.x;
     const double* __restrict__ b = P.b;
-    auto xval = [&](long long g) -> double { return U.any ? x[g] + upd_at<TI>(P, U, g) : x[g]; };
+    auto xval = [&](long long g) -> double { return U.any ? x[g] + upd_at<DIM, TI>(P, U, g) : x[g]; };
     for (int i = threadIdx.x; i < k; i += NT) csum[i] = 0.0;
     double acc[3] = {0.0, 0.0, 0.0};
     for (int tile = lw; tile < P.ntiles; tile += P.nwg) {
@@ -656,7 +670,7 @@ __device__ __forceinline__ void apply_projection(const DevProb& P, int lw, int g
             const long long g = gq[q];
             const int c = cq[q];
             double xv = P.x[g];
-            if (U.any) xv += upd_at<TI>(P, U, g);
+            if (U.any) xv += upd_at<DIM, TI>(P, U, g);
             P.x[g] = xv + L[c];
             const double rv = P.r[g] - stencil_row_t<Cfg, DIM, VAR, double>(op, L, c, g);
             P.r[g] = rv;
@@ -674,7 +688,7 @@ __device__ __forceinline__ void apply_projection(const DevProb& P, int lw, int g
 }
 
 // x <- x + e + a p + w s on this workgroup's tiles (the solve stops here).
-template <class Cfg, class TI>
+template <class Cfg, int DIM, class TI>
 __device__ __forceinline__ void fold_update(const DevProb& P, int lw, const Upd& U) {
     const DevOp& op = P.op;
     for (int tile = lw; tile < P.ntiles; tile += P.nwg) {
@@ -684,7 +698,7 @@ __device__ __forceinline__ void fold_update(const DevProb& P, int lw, const Upd&
             int gx, gy, gz, c;
             point_coords<Cfg>(q, tp, gx, gy, gz, c);
             if (!inside(op, gx, gy, gz)) continue;
-            P.x[gidx(op, gx, gy, gz)] += upd_at<TI>(P, U, pidx(op, gx, gy, gz));
+            P.x[gidx(op, gx, gy, gz)] += upd_at<DIM, TI>(P, U, pidx(op, gx, gy, gz));
         }
     }
 }
@@ -692,22 +706,26 @@ __device__ __forceinline__ void fold_update(const DevProb& P, int lw, const Upd&
 // ------------------------------------------------ 3-D phases by z marching
 // The same arithmetic as phase_a / phase_b (same expressions, same order),
 // written as march_chunk phases: raw loads per point and plane, the stencil
-// input, and the outputs at the plane being computed.
+// input, and the outputs at the plane being computed.  Unlike the 2-D
+// phases, phase B stores t but not s: phase A forms s = r_i - alpha v_i
+// again from r_i and v_i, which it reads in place of s (r_i kept in two
+// buffers alternating with p and v, since phase A reads the old one on the
+// ring while writing the new one).  One vector write fewer per iteration.
 template <class TI>
 struct MarchA {  // phase A of iteration i > 0
-    const TI *s, *t, *po, *vo, *rh, *zero;
-    TI *pnew, *vnew, *rin, *e;
+    const TI *ro, *t, *po, *vo, *rh, *zero;
+    TI *pnew, *vnew, *rnew, *e;
     TI alpha, omega, beta;
     double acc[2] = {0.0, 0.0};
     struct Own {
-        TI s, t, po, vo, e, rh;
+        TI ro, t, po, vo, e, rh;
     };
     struct Ring {
-        TI s, t, po, vo;
+        TI ro, t, po, vo;
     };
     __device__ __forceinline__ const TI* at(const TI* a, long long g) const { return g >= 0 ? a + g : zero; }
     __device__ __forceinline__ void load(Own& o, long long g, long long) const {
-        o.s = *at(s, g);
+        o.ro = *at(ro, g);
         o.t = *at(t, g);
         o.po = *at(po, g);
         o.vo = *at(vo, g);
@@ -715,33 +733,35 @@ struct MarchA {  // phase A of iteration i > 0
         o.rh = *at(rh, g);
     }
     __device__ __forceinline__ void load(Ring& o, long long g, long long) const {
-        o.s = *at(s, g);
+        o.ro = *at(ro, g);
         o.t = *at(t, g);
         o.po = *at(po, g);
         o.vo = *at(vo, g);
     }
     template <class R>
     __device__ __forceinline__ TI value(const R& o) const {
-        const TI r = o.s - omega * o.t;
+        const TI s = o.ro - alpha * o.vo;  // phase B's s
+        const TI r = s - omega * o.t;
         return r + beta * (o.po - omega * o.vo);
     }
     static constexpr bool PLANE_HOOK = false;
     __device__ __forceinline__ void plane_done(const Chunk&, int) {}
     __device__ __forceinline__ void emit(int, long long g, long long, const Own& c, TI y) {
-        const TI r = c.s - omega * c.t;
+        const TI s = c.ro - alpha * c.vo;
+        const TI r = s - omega * c.t;
         pnew[g] = r + beta * (c.po - omega * c.vo);
         vnew[g] = y;
-        rin[g] = r;
-        e[g] = c.e + alpha * c.po + omega * c.s;
+        rnew[g] = r;
+        e[g] = c.e + alpha * c.po + omega * s;
         acc[0] += (double)c.rh * (double)y;
         acc[1] += (double)r * (double)r;
     }
 };
 
 template <class TI>
-struct MarchA0 {  // phase A of iteration 0, optionally folding the last update into x
+struct MarchA0 {  // phase A of iteration 0 (r_0 copied into r2), optionally folding the last update into x
     const TI *rin, *rh, *zero;
-    TI *pnew, *vnew, *e;
+    TI *pnew, *vnew, *rnew, *e;
     const DevProb* P;
     Upd U;
     bool fin;
@@ -765,9 +785,10 @@ struct MarchA0 {  // phase A of iteration 0, optionally folding the last update 
     static constexpr bool PLANE_HOOK = false;
     __device__ __forceinline__ void plane_done(const Chunk&, int) {}
     __device__ __forceinline__ void emit(int, long long g, long long gu, const Own& c, TI y) {
-        if (fin) P->x[gu] += upd_at<TI>(*P, U, g);
+        if (fin) P->x[gu] += upd_at<3, TI>(*P, U, g);
         pnew[g] = c.r;
         vnew[g] = y;
+        rnew[g] = c.r;
         e[g] = TI(0);
         acc[0] += (double)c.rh * (double)y;
         acc[1] += (double)c.r * (double)c.r;
@@ -775,9 +796,9 @@ struct MarchA0 {  // phase A of iteration 0, optionally folding the last update 
 };
 
 template <class TI>
-struct MarchB {  // phase B
+struct MarchB {  // phase B (s is not stored: phase A forms it again)
     const TI *rin, *v, *rh, *zero;
-    TI *s, *t;
+    TI* t;
     TI alpha;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     struct Own {
@@ -804,7 +825,6 @@ struct MarchB {  // phase B
     __device__ __forceinline__ void plane_done(const Chunk&, int) {}
     __device__ __forceinline__ void emit(int, long long g, long long, const Own& c, TI y) {
         const TI sv = c.r - alpha * c.v;
-        s[g] = sv;
         t[g] = y;
         const double rh = (double)c.rh, sd = (double)sv, td = (double)y;
         acc[0] += sd * sd;
@@ -839,14 +859,14 @@ __device__ __forceinline__ void march_a(const DevProb& P, int lw, int gslot, boo
     const TI* zero = reinterpret_cast<const TI*>(P.op.zero);
     if (first) {
         MarchA0<TI> ph{vp<const TI>(P.rin), vp<const TI>(P.rhat), zero, vp<TI>(P.p[pb]), vp<TI>(P.v[pb]),
-                       vp<TI>(P.e), &P, U, fin};
+                       vp<TI>(P.r2[pb]), vp<TI>(P.e), &P, U, fin};
         march_phase<VAR, TI, MarchA0<TI>, 2>(P, lw, gslot, ph, L, sh);
     } else {
         const TI alpha = (TI)N.alpha, omega = (TI)N.omega;
         const TI beta = (TI)((N.rho / N.rho_old) * (N.alpha / N.omega));
-        MarchA<TI> ph{vp<const TI>(P.s), vp<const TI>(P.t), vp<const TI>(P.p[pb ^ 1]), vp<const TI>(P.v[pb ^ 1]),
-                      vp<const TI>(P.rhat), zero, vp<TI>(P.p[pb]), vp<TI>(P.v[pb]), vp<TI>(P.rin), vp<TI>(P.e),
-                      alpha, omega, beta};
+        MarchA<TI> ph{vp<const TI>(P.r2[pb ^ 1]), vp<const TI>(P.t), vp<const TI>(P.p[pb ^ 1]),
+                      vp<const TI>(P.v[pb ^ 1]), vp<const TI>(P.rhat), zero, vp<TI>(P.p[pb]), vp<TI>(P.v[pb]),
+                      vp<TI>(P.r2[pb]), vp<TI>(P.e), alpha, omega, beta};
         march_phase<VAR, TI, MarchA<TI>, 2>(P, lw, gslot, ph, L, sh);
     }
 }
@@ -854,8 +874,8 @@ __device__ __forceinline__ void march_a(const DevProb& P, int lw, int gslot, boo
 template <bool VAR, class TI>
 __device__ __forceinline__ void march_b(const DevProb& P, int lw, int gslot, const StepHot& N, TI* L, double* sh) {
     const int pb = ((gslot - 1) >> 1) & 1;
-    MarchB<TI> ph{vp<const TI>(P.rin), vp<const TI>(P.v[pb]), vp<const TI>(P.rhat),
-                  reinterpret_cast<const TI*>(P.op.zero), vp<TI>(P.s), vp<TI>(P.t), (TI)N.alpha};
+    MarchB<TI> ph{vp<const TI>(P.r2[pb]), vp<const TI>(P.v[pb]), vp<const TI>(P.rhat),
+                  reinterpret_cast<const TI*>(P.op.zero), vp<TI>(P.t), (TI)N.alpha};
     march_phase<VAR, TI, MarchB<TI>, 5>(P, lw, gslot, ph, L, sh);
 }
 
@@ -871,7 +891,7 @@ __device__ __forceinline__ void march_b(const DevProb& P, int lw, int gslot, con
 template <class TI>
 struct MarchRes {
     const double *x, *b;
-    const TI *e, *p, *s;
+    const TI *e, *p, *ri, *vi;  // pending update: e + a p + w (r_i - a v_i)
     const double* zero64;
     const TI* zeroT;
     Upd U;
@@ -882,20 +902,22 @@ struct MarchRes {
     static constexpr bool PLANE_HOOK = false;
     struct Own {
         double x, b;
-        TI e, p, s;
+        TI e, p, ri, vi;
     };
     struct Ring {
         double x;
-        TI e, p, s;
+        TI e, p, ri, vi;
     };
-    // x and b are caller vectors (unpadded index gu), e, p, s the step
-    // kernel's own (padded index g)
+    // x and b are caller vectors (unpadded index gu), e, p, r_i, v_i the
+    // step kernel's own (padded index g)
     template <class R>
     __device__ __forceinline__ void load_upd(R& o, long long g, long long gu) const {
         o.x = *(gu >= 0 ? x + gu : zero64);
         o.e = *(U.any && g >= 0 ? e + g : zeroT);
         o.p = *(U.any && U.a != 0.0 && g >= 0 ? p + g : zeroT);
-        o.s = *(U.any && U.w != 0.0 && g >= 0 ? s + g : zeroT);
+        const bool sw = U.any && U.w != 0.0 && g >= 0;
+        o.ri = *(sw ? ri + g : zeroT);
+        o.vi = *(sw ? vi + g : zeroT);
     }
     __device__ __forceinline__ void load(Own& o, long long g, long long gu) const {
         load_upd(o, g, gu);
@@ -907,7 +929,10 @@ struct MarchRes {
         if (!U.any) return o.x;
         double u = (double)o.e;
         if (U.a != 0.0) u += U.a * (double)o.p;
-        if (U.w != 0.0) u += U.w * (double)o.s;
+        if (U.w != 0.0) {
+            const TI a = (TI)U.a;
+            u += U.w * (double)(o.ri - a * o.vi);  // s, as s_at forms it
+        }
         return o.x + u;
     }
     __device__ __forceinline__ void emit(int, long long g, long long, const Own& c, double y) {
@@ -972,7 +997,8 @@ __device__ __forceinline__ void march_res(const DevProb& P, int lw, int gslot, c
     if (fused_c)
         for (int i = threadIdx.x; i < k; i += NT) csum[i] = 0.0;
     TI* rin = vp<TI>(P.rin);
-    MarchRes<TI> ph{P.x, P.b, vp<const TI>(P.e), vp<const TI>(P.p[U.pbuf]), vp<const TI>(P.s),
+    MarchRes<TI> ph{P.x, P.b, vp<const TI>(P.e), vp<const TI>(P.p[U.pbuf]), vp<const TI>(P.r2[U.pbuf]),
+                    vp<const TI>(P.v[U.pbuf]),
                     reinterpret_cast<const double*>(P.op.zero), reinterpret_cast<const TI*>(P.op.zero), U, P.r,
                     rin, vp<TI>(P.rhat), k == 0, (void*)rin != (void*)P.r};
     if (lw < P.nchunks) {
@@ -1064,7 +1090,7 @@ __device__ __forceinline__ void apply_w_flat(const DevProb& P, int lw, const Upd
         for (int j = 0; j < k; ++j) w += (double)V[(long long)j * P.ldv + g] * dsh[j];
         P.w[gpad] = w;
         double xv = P.x[g];
-        if (U.any) xv += upd_at<TI>(P, U, gpad);
+        if (U.any) xv += upd_at<3, TI>(P, U, gpad);
         P.x[g] = xv + w;
     }
 }
@@ -1220,7 +1246,7 @@ __device__ __forceinline__ void step_run(const DevProb& P, int wg, int gslot, un
                 apply_projection<Cfg, DIM, VAR, TI>(P, lw, gslot, U, st, Lbox, sh, ysh);
             break;
         case ACT_FIN:
-            fold_update<Cfg, TI>(P, lw, U);
+            fold_update<Cfg, DIM, TI>(P, lw, U);
             break;
         default:
             break;
@@ -1237,10 +1263,14 @@ __device__ __forceinline__ void step_run(const DevProb& P, int wg, int gslot, un
     }
 }
 
+// Both step kernels ask the register allocator for at least three waves per
+// SIMD (168 registers): without it the 3-D float64 kernel with per-row
+// coefficients came to 179 and two waves, with it 167 and no spills.
+
 // Groups of several systems: the descriptors in device memory, wg_prob maps
 // a workgroup to its system (null: all belong to system 0).
 template <class Cfg, int DIM, bool VAR, class TI>
-__global__ __launch_bounds__(NT) void k_step(const DevProb* __restrict__ probs, const int* __restrict__ wg_prob,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_step(const DevProb* __restrict__ probs, const int* __restrict__ wg_prob,
                                              int gslot) {
     const unsigned long long t_begin = (unsigned long long)wall_clock64();
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
@@ -1251,7 +1281,7 @@ __global__ __launch_bounds__(NT) void k_step(const DevProb* __restrict__ probs, 
 // its fields are read from the argument segment at once instead of after a
 // pointer load (one memory round trip fewer at the start of every launch).
 template <class Cfg, int DIM, bool VAR, class TI>
-__global__ __launch_bounds__(NT) void k_step1(const DevProb P, int gslot) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_step1(const DevProb P, int gslot) {
     const unsigned long long t_begin = (unsigned long long)wall_clock64();
     step_run<Cfg, DIM, VAR, TI>(P, xcd_remap(blockIdx.x, gridDim.x), gslot, t_begin);
 }
