@@ -139,6 +139,6 @@ def test_phase2_improvement_makes_the_deflated_solve_cheaper():
 def test_improve_argument_errors():
     op = tg().Operator.const_cd((15, 13), (5.0, 0.0))
     space = tg().defl_from_basis(op, _t(W.rng(4).standard_normal((5, op.n))))
-    for kw in (dict(m=5), dict(m=129), dict(m=20, nev=6), dict(m=20, tol=0.0), dict(m=20, maxcyc=-1)):
+    for kw in (dict(m=5), dict(m=257), dict(m=20, nev=6), dict(m=20, tol=0.0), dict(m=20, maxcyc=-1)):
         with pytest.raises(tg()._lib.TgdkError):
             space.improve(**kw)

@@ -63,23 +63,24 @@ def test_exact_initial_guess_takes_no_cycle():
 
 
 def test_largest_space_and_longest_gmres_cycle():
-    """A 63-vector deflation space (the limit) and GMRES(128)-Proj(63) and
-    BiCGStab(20)-Proj(63) on the small workload: the direct solution."""
+    """A 256-vector deflation space (the limit, TGDK_MAX_DEFL) and
+    GMRES(256)-Proj(256) and BiCGStab(20)-Proj(256) on the small workload:
+    the direct solution; a 257-vector basis is refused."""
     c = W.CONFIGS["C1"]
     oop = O.const_cd(c["n"], c["beta"])
     b = W.rhs(oop.n, c["seed"])
     xs = spl.spsolve(O.to_csr(oop).tocsc(), b)
-    V, H = OD.deflation_space(oop, W.rng(8).standard_normal((31 * 31, 63)), (31, 31))
+    V, H = OD.deflation_space(oop, W.rng(8).standard_normal((31 * 31, 256)), (31, 31))
     op = tg().Operator.const_cd(c["n"], c["beta"])
     space = tg().defl_from_basis(op, _t(V.T))
-    assert space.k == 63
-    x1, r1 = tg().solve(op, _t(b), defl=space, method="gmres", m3=128, rtol=1e-10)
+    assert space.k == 256
+    x1, r1 = tg().solve(op, _t(b), defl=space, method="gmres", m3=256, rtol=1e-10)
     x2, r2 = tg().solve(op, _t(b), defl=space, rtol=1e-10)
     for x, r in ((x1, r1[0]), (x2, r2[0])):
         assert r.status == 0
         assert np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs) <= 1e-7
     with pytest.raises(tg()._lib.TgdkError):
-        tg().defl_from_basis(op, _t(W.rng(9).standard_normal((65, oop.n))))
+        tg().defl_from_basis(op, _t(W.rng(9).standard_normal((257, oop.n))))
 
 
 def test_gmres_cycle_longer_than_the_system():
