@@ -64,6 +64,10 @@ def _args():
                     help="with --solve-only --workload c2: the fine solver (idr = IDR(4), gmres = GMRES(50))")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB device buffer three times (counter scale of a plain copy)")
+    ap.add_argument("--stream-ceiling", action="store_true",
+                    help="only measure the streaming ceilings of the step kernel's stream mixes (a copy, phase B's "
+                         "3 reads + 1 write, phase A's 6 + 4) in copy order and in the marching phases' order, "
+                         "then print one JSON line")
     return ap.parse_args()
 
 
@@ -171,6 +175,9 @@ def main():
     from paper_2005_03070_amd.api import context
     import workloads as W
     import ctypes as C
+
+    if a.stream_ceiling:
+        return stream_ceiling(tg)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -744,6 +751,31 @@ def cpu_sample(a, head, k, x0):
               f"columns; setup not included; host CPU {cpu_model()}, {os.cpu_count()} logical cores, 1 used")
     log(f"cpu oracle: {t_it:.2f} s per iteration -> {est:.0f} s per solve (extrapolated)")
     return {"value": est, "unit": "s", "cores": 1, "kind": "oracle", "extrapolated": True, "sample": sample}
+
+
+def stream_ceiling(tg):
+    """What plain kernels stream with the step kernel's mixes of float64
+    streams: a copy (1 read + 1 write, 511^3 arrays of 1.07 GB, past the MALL),
+    phase B of the 3-D step kernel (3 + 1) and phase A (6 + 4) on 255^3
+    arrays, each in copy order (grid-strided; best of 768..8192 workgroups)
+    and in the marching phases' order (64 x 8 column chunks walked plane by
+    plane; best of about 768, 1024 and 2048 chunks).  One JSON line."""
+    out = {}
+    for tag, nr, nw, dims in (("copy_1r1w_511cube", 1, 1, (511, 511, 511)), ("phaseB_3r1w_255cube", 3, 1, (255, 255, 255)),
+                              ("phaseA_6r4w_255cube", 6, 4, (255, 255, 255))):
+        row = {}
+        for pattern, blocks_list in (("contiguous", (768, 1024, 2048, 4096, 8192)), ("march", (768, 1024, 2048))):
+            best = None
+            for blocks in blocks_list:
+                ms, nbytes = tg.stream_probe(pattern, nr, nw, dims, blocks=blocks, reps=10)
+                tbs = nbytes / (ms * 1e-3) / 1e12
+                if best is None or tbs > best["TBs"]:
+                    best = {"TBs": tbs, "us": ms * 1e3, "blocks": blocks, "bytes": nbytes}
+            row[pattern] = best
+            log(f"stream ceiling {tag} {pattern}: {best['TBs']:.2f} TB/s ({best['us']:.1f} us, {best['blocks']} "
+                f"workgroups/chunks)")
+        out[tag] = row
+    print(json.dumps({"stream_ceiling": out, "peak_TBs": 8.0}))
 
 
 def cpu_full(names):

@@ -112,6 +112,20 @@ int tgdk_ctx_num_cus(tgdk_ctx ctx);
 #define TGDK_STEP_ALL   -2
 int tgdk_ctx_time_kernel(tgdk_ctx ctx, int on);
 int tgdk_ctx_kernel_time(tgdk_ctx ctx, int action, double* total_ms, long long* launches);
+/* Measurement utility, not a step of the method: the streaming rate a plain
+ * kernel reaches with nreads read streams and nwrites write streams of
+ * float64 (mixes 1+1, 3+1 and 6+4: a copy, the 3-D phase B, the 3-D phase A),
+ * the ceilings the step kernel's phases are compared with.  The arrays are
+ * dims[0] x dims[1] x dims[2] grids with the row pitch rounded up to 64 (as
+ * the step kernel's own vectors), allocated and freed by the call.
+ * pattern 0: each array walked grid-strided by `blocks` workgroups (copy
+ * order); pattern 1: one workgroup per 64 x 8 column chunk walking its planes
+ * (the marching phases' order, about `blocks` chunks, no LDS or stencil).
+ * Runs one untimed and `reps` timed launches on the context's stream;
+ * *ms_per_launch = their average (HIP events).  Returns TGDK_E_INVALID for
+ * other mixes or bad sizes, TGDK_E_NOMEM when the arrays do not fit. */
+int tgdk_stream_probe(tgdk_ctx ctx, int pattern, int nreads, int nwrites, const int* dims, int blocks, int reps,
+                      double* ms_per_launch);
 
 /* ---------------------------------------------------------------- operators
  * The discretised operator of Sec. 1 / Sec. 3 Example 1: centred finite

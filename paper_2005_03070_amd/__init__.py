@@ -6,10 +6,12 @@ include/tgdk.h) with a thin Python binding.
 """
 from . import _lib
 from .api import (DeflationSpace, Multigrid, Operator, Report, SetupReport, coarse_setup, context, defl_from_basis,
-                  defl_prolongate, grad_k, prolongate, restrict, solve, solve_idr, solve_instances, solve_noalloc)
+                  defl_prolongate, grad_k, prolongate, restrict, solve, solve_idr, solve_instances, solve_noalloc,
+                  stream_probe)
 from .autograd import DeflatedSolve, TwoGridSolver
 
 __all__ = ["Operator", "DeflationSpace", "Multigrid", "Report", "SetupReport", "coarse_setup", "context", "defl_from_basis",
            "defl_prolongate", "grad_k", "prolongate", "restrict", "solve", "solve_idr", "solve_instances", "solve_noalloc",
+           "stream_probe",
            "DeflatedSolve",
            "TwoGridSolver"]

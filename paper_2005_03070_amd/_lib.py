@@ -91,6 +91,7 @@ SIGNATURES = [
     ("tgdk_ctx_num_cus", I, [P]),
     ("tgdk_ctx_time_kernel", I, [P, I]),
     ("tgdk_ctx_kernel_time", I, [P, I, DP, C.POINTER(C.c_longlong)]),
+    ("tgdk_stream_probe", I, [P, I, I, I, C.POINTER(C.c_int), I, I, DP]),
     ("tgdk_op_create", I, [P, C.POINTER(OpDesc), PP]),
     ("tgdk_op_coarsen", I, [P, PP]),
     ("tgdk_op_apply", I, [P, I, I, P, P, I]),

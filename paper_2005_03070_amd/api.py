@@ -448,3 +448,17 @@ def grad_k(op, lam, u):
     check(lib().tgdk_adjoint_grad_k(op.h, C.c_void_p(lam.data_ptr()), C.c_void_p(u.data_ptr()),
                                     C.c_void_p(g.data_ptr())))
     return g
+
+
+def stream_probe(pattern, nreads, nwrites, dims, blocks=768, reps=10, device=None):
+    """Streaming ceiling for a mix of float64 streams (include/tgdk.h,
+    tgdk_stream_probe): pattern "contiguous" or "march"; returns
+    (ms per launch, bytes moved per launch)."""
+    ctx, _ = context(device)
+    d = (C.c_int * 3)(*[int(v) for v in dims])
+    ms = C.c_double()
+    check(lib().tgdk_stream_probe(ctx, {"contiguous": 0, "march": 1}[pattern], int(nreads), int(nwrites), d,
+                                  int(blocks), int(reps), C.byref(ms)))
+    nx, ny, nz = (int(v) for v in dims)
+    pts = ((nx + 63) // 64 * 64 if pattern == "contiguous" else nx) * ny * nz
+    return ms.value, (nreads + nwrites) * pts * 8
