@@ -106,38 +106,30 @@ def act_bytes(dim, w, wv, k, sep):
     """Algorithmic HBM bytes per grid point of each step-kernel action: what
     the action must read and write at least (w: inner word, 8 or 4; wv: word
     of the stored deflation basis; sep: the float32 inner residual is a
-    vector of its own).  x, b and r are float64.  On 3-D grids phase B stores
-    t but not s, and s = r_i - alpha v_i is formed again where needed (phase
-    A, the pending update of the boundary actions), so those read r_i and v_i
-    in place of s."""
+    vector of its own).  x, b and r are float64.  Phase B stores t but not
+    s; s = r_i - alpha v_i is formed again where needed (phase A, the pending
+    update of the boundary actions), which read r_i and v_i in its place."""
     rin = w if sep else 0
-    if dim == 3:
-        upd = 4 * w                                    # e, p, r_i, v_i
-        return {
-            "NONE": 0,
-            "A": 10 * w,                               # reads r_i t p v e r^; writes r e p v
-            "A0": 6 * w,                               # reads r r^; writes p v e and r into r_i's buffer
-            "B": 4 * w,                                # reads r v r^; writes t
-            # reads x b and the pending update (and V when c = V^T r is fused: float32 V); writes r
-            "RES": 24 + upd + (k * wv if wv == 4 else 0) + (0 if k else w + rin),
-            "CDOT": 8 + k * wv,                        # float64 V: reads r, V
-            "REDUCE": 0,
-            "APPLY": 24 + w + rin,                     # reads w r; writes r r^ (r_in)
-            "APPLYW": 24 + upd + k * wv,               # reads x, the update, V; writes x w
-            "FIN": 16 + upd,
-            "FIN_A0": 16 + upd + 6 * w,
-        }
-    return {
+    upd = 4 * w                                        # the pending update: e, p, r_i, v_i
+    out = {
         "NONE": 0,
-        "A": 10 * w,                                   # reads s t p v e r^; writes r e p v
-        "A0": 5 * w,                                   # reads r r^; writes p v e
-        "B": 5 * w,                                    # reads r v r^; writes s t
-        "RES": 24 + 3 * w + k * wv + (0 if k else w + rin),  # reads x e p s b V; writes r (k = 0: r^, r_in)
+        "A": 10 * w,                                   # reads r_i t p v e r^; writes r e p v
+        "A0": 6 * w,                                   # reads r r^; writes p v e and r into r_i's buffer
+        "B": 4 * w,                                    # reads r v r^; writes t
         "REDUCE": 0,
-        "APPLY": 32 + 3 * w + k * wv + w + rin,
-        "FIN": 16 + 3 * w,
-        "FIN_A0": 16 + 3 * w + 5 * w,
+        "FIN": 16 + upd,
+        "FIN_A0": 16 + upd + 6 * w,
     }
+    if dim == 3:
+        # reads x b and the update (and V for the fused c = V^T r: float32 V); writes r
+        out["RES"] = 24 + upd + (k * wv if wv == 4 else 0) + (0 if k else w + rin)
+        out["CDOT"] = 8 + k * wv                       # float64 V: reads r, V
+        out["APPLY"] = 24 + w + rin                    # reads w r; writes r r^ (r_in)
+        out["APPLYW"] = 24 + upd + k * wv              # reads x, the update, V; writes x w
+    else:
+        out["RES"] = 24 + upd + k * wv + (0 if k else w + rin)  # reads x b, the update, V; writes r
+        out["APPLY"] = 32 + upd + k * wv + w + rin     # reads x r, the update, V; writes x r r^ (r_in)
+    return out
 
 
 def cpu_model():

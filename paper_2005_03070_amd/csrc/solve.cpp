@@ -269,8 +269,7 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
         off_vec[j] = off;
         const size_t n = nstore[j];
         off += align256(n * 8);                            // r (float64)
-        off += (g.inner_f32 ? 9 : 8) * align256(n * ies);  // inner vectors
-        if (g.dim == 3) off += align256(n * ies);           // 3-D: r_i double-buffered instead of s
+        off += (g.inner_f32 ? 10 : 9) * align256(n * ies);  // inner vectors
         if (g.dim == 3 && P.k > 0) off += align256(n * 8);  // w = V d (3-D boundary)
         off_part[j] = off;
         // tile kernels: ntiles rows; step kernel: two launch-parity slots
@@ -322,7 +321,7 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
         P.r = (double*)v;
         v += align256(n * 8);
         void* vecs[10];
-        const int nv = (g.inner_f32 ? 9 : 8) + (g.dim == 3 ? 1 : 0);
+        const int nv = g.inner_f32 ? 10 : 9;
         for (int i = 0; i < nv; ++i) {
             vecs[i] = v;
             v += align256(n * ies);
@@ -334,12 +333,8 @@ static int build_group(tgdk_ctx ctx, const std::vector<ProbSpec>& ps, const tgdk
         P.p[1] = vecs[i++];
         P.v[0] = vecs[i++];
         P.v[1] = vecs[i++];
-        if (g.dim == 3) {  // the marching phases keep r_i in two buffers of their own and store no s
-            P.r2[0] = vecs[i++];
-            P.r2[1] = vecs[i++];
-        } else {
-            P.s = vecs[i++];
-        }
+        P.r2[0] = vecs[i++];  // r_i, alternating with p and v (no s is stored)
+        P.r2[1] = vecs[i++];
         P.t = vecs[i++];
         P.e = vecs[i++];
         if (g.dim == 3 && P.k > 0) P.w = (double*)v;

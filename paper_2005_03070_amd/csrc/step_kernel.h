@@ -53,6 +53,14 @@ struct Upd {
     int any, pbuf;
 };
 
+// Element i (0 or 1) of a two-buffer field of the descriptor, by a select:
+// a run-time index into the descriptor that k_step1 receives by value made
+// the compiler copy the whole descriptor to scratch memory.
+template <class T>
+__device__ __forceinline__ T pick2(const T (&a)[2], int i) {
+    return i ? a[1] : a[0];
+}
+
 // Start of an inner cycle from a residual of norm nu: its tolerance
 // (Sec. 4.1 step 3 b, cycle_tolerance) and fresh BiCGStab scalars; returns
 // the criterion taken (1, 2 or 3).
@@ -272,16 +280,14 @@ __device__ __forceinline__ double vload(const DevProb& P, long long i) {
 }
 
 // s = r_i - alpha v_i of the iteration whose update is pending, at index g:
-// stored by phase B on 2-D grids; on 3-D grids formed from r_i and v_i with
-// phase B's own expression (a = alpha whenever w != 0), so the same bits.
+// phase B does not store s, so it is formed from r_i and v_i with phase B's
+// own expression (a = alpha whenever w != 0), which gives the same bits.
 template <int DIM, class TI>
 __device__ __forceinline__ TI s_at(const DevProb& P, const Upd& U, long long g) {
-    if constexpr (DIM == 3) {
-        const TI a = (TI)U.a;
-        return vp<const TI>(P.r2[U.pbuf])[g] - a * vp<const TI>(P.v[U.pbuf])[g];
-    } else {
-        return vp<const TI>(P.s)[g];
-    }
+    const TI a = (TI)U.a;
+    const TI* r = vp<const TI>(pick2(P.r2, U.pbuf));
+    const TI* v = vp<const TI>(pick2(P.v, U.pbuf));
+    return r[g] - a * v[g];
 }
 
 // e + a p + w s at index g of the step kernel's own vectors (padded pitch
@@ -289,7 +295,7 @@ __device__ __forceinline__ TI s_at(const DevProb& P, const Upd& U, long long g) 
 template <int DIM, class TI>
 __device__ __forceinline__ double upd_at(const DevProb& P, const Upd& U, long long g) {
     double u = (double)vp<const TI>(P.e)[g];
-    if (U.a != 0.0) u += U.a * (double)vp<const TI>(P.p[U.pbuf])[g];
+    if (U.a != 0.0) u += U.a * (double)vp<const TI>(pick2(P.p, U.pbuf))[g];
     if (U.w != 0.0) u += U.w * (double)s_at<DIM, TI>(P, U, g);
     return u;
 }
@@ -314,13 +320,14 @@ __device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, boo
     using HL = Halo<Cfg, DIM>;
     const DevOp& op = P.op;
     const int pb = (gslot >> 1) & 1;
-    const gptr<TI> __restrict__ pnew = gp<TI>(P.p[pb]);
-    const gptr<const TI> __restrict__ pold = gp<const TI>(P.p[pb ^ 1]);
-    const gptr<TI> __restrict__ vnew = gp<TI>(P.v[pb]);
-    const gptr<const TI> __restrict__ vold = gp<const TI>(P.v[pb ^ 1]);
-    const gptr<TI> rin = gp<TI>(P.rin);
+    const gptr<TI> __restrict__ pnew = gp<TI>(pick2(P.p, pb));
+    const gptr<const TI> __restrict__ pold = gp<const TI>(pick2(P.p, pb ^ 1));
+    const gptr<TI> __restrict__ vnew = gp<TI>(pick2(P.v, pb));
+    const gptr<const TI> __restrict__ vold = gp<const TI>(pick2(P.v, pb ^ 1));
+    const gptr<const TI> rin = gp<const TI>(P.rin);
+    const gptr<TI> __restrict__ rnew = gp<TI>(pick2(P.r2, pb));
+    const gptr<const TI> __restrict__ rold = gp<const TI>(pick2(P.r2, pb ^ 1));
     const gptr<const TI> __restrict__ rhat = gp<const TI>(P.rhat);
-    const gptr<const TI> __restrict__ sv_ = gp<const TI>(P.s);
     const gptr<const TI> __restrict__ tv_ = gp<const TI>(P.t);
     const gptr<TI> e = gp<TI>(P.e);
     const gptr<const TI> zero = gp<const TI>(op.zero);
@@ -349,7 +356,7 @@ __device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, boo
             if (FIRST) {
                 a0[q] = *at(rin, gq[q]);
             } else {
-                a0[q] = *at(sv_, gq[q]);
+                a0[q] = *at(rold, gq[q]);
                 a1[q] = *at(tv_, gq[q]);
                 a2[q] = *at(pold, gq[q]);
                 a3[q] = *at(vold, gq[q]);
@@ -360,7 +367,7 @@ __device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, boo
             if (FIRST) {
                 h0[h] = *at(rin, gh[h]);
             } else {
-                h0[h] = *at(sv_, gh[h]);
+                h0[h] = *at(rold, gh[h]);
                 h1[h] = *at(tv_, gh[h]);
                 h2[h] = *at(pold, gh[h]);
                 h3[h] = *at(vold, gh[h]);
@@ -371,7 +378,8 @@ __device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, boo
             for (int q = 0; q < Cfg::PPT; ++q)
                 if (gq[q] >= 0) P.x[gq[q]] += upd_at<DIM, TI>(P, U, gq[q]);
         }
-        // stencil input p_i on the tile and its halo
+        // stencil input p_i on the tile and its halo (s = r - alpha v of the
+        // last phase B formed again: it is not stored)
         TI rq[Cfg::PPT];
 #pragma unroll
         for (int q = 0; q < Cfg::PPT; ++q) {
@@ -380,7 +388,8 @@ __device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, boo
                 rq[q] = a0[q];
                 pv = rq[q];
             } else {
-                rq[q] = a0[q] - omega * a1[q];
+                const TI sv = a0[q] - alpha * a3[q];
+                rq[q] = sv - omega * a1[q];
                 pv = rq[q] + beta * (a2[q] - omega * a3[q]);
             }
             L[cq[q]] = pv;
@@ -391,7 +400,8 @@ __device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, boo
             if (FIRST) {
                 L[ch[h]] = h0[h];
             } else {
-                const TI rv = h0[h] - omega * h1[h];
+                const TI sv = h0[h] - alpha * h3[h];
+                const TI rv = sv - omega * h1[h];
                 L[ch[h]] = rv + beta * (h2[h] - omega * h3[h]);
             }
         }
@@ -403,12 +413,11 @@ __device__ __forceinline__ void phase_a(const DevProb& P, int lw, int gslot, boo
             const TI vv = stencil_row_t<Cfg, DIM, VAR, TI>(op, L, cq[q], g);
             st_stream<DIM>(&pnew[g], L[cq[q]]);
             st_stream<DIM>(&vnew[g], vv);
-            if (FIRST) {
+            st_stream<DIM>(&rnew[g], rq[q]);
+            if (FIRST)
                 st_stream<DIM>(&e[g], TI(0));
-            } else {
-                st_stream<DIM>(&rin[g], rq[q]);
-                st_stream<DIM>(&e[g], e[g] + alpha * a2[q] + omega * a0[q]);
-            }
+            else
+                st_stream<DIM>(&e[g], e[g] + alpha * a2[q] + omega * (a0[q] - alpha * a3[q]));
             acc[0] += (double)rhat[g] * (double)vv;
             acc[1] += (double)rq[q] * (double)rq[q];
         }
@@ -425,11 +434,10 @@ template <class Cfg, int DIM, bool VAR, class TI>
 __device__ __forceinline__ void phase_b(const DevProb& P, int lw, int gslot, const StepHot& N, TI* L, double* sh) {
     using HL = Halo<Cfg, DIM>;
     const DevOp& op = P.op;
-    const int pb = ((gslot - 1) >> 1) & 1;  // v of this iteration's phase A
-    const gptr<const TI> __restrict__ v = gp<const TI>(P.v[pb]);
-    const gptr<const TI> __restrict__ rin = gp<const TI>(P.rin);
+    const int pb = ((gslot - 1) >> 1) & 1;  // r and v of this iteration's phase A
+    const gptr<const TI> __restrict__ v = gp<const TI>(pick2(P.v, pb));
+    const gptr<const TI> __restrict__ rin = gp<const TI>(pick2(P.r2, pb));
     const gptr<const TI> __restrict__ rhat = gp<const TI>(P.rhat);
-    const gptr<TI> __restrict__ s = gp<TI>(P.s);
     const gptr<TI> __restrict__ tt_ = gp<TI>(P.t);
     const gptr<const TI> zero = gp<const TI>(op.zero);
     auto at = [&](gptr<const TI> arr, long long g) { return g >= 0 ? arr + g : zero; };
@@ -474,7 +482,6 @@ __device__ __forceinline__ void phase_b(const DevProb& P, int lw, int gslot, con
             const long long g = gq[q];
             const TI sv = L[cq[q]];
             const TI tv = stencil_row_t<Cfg, DIM, VAR, TI>(op, L, cq[q], g);
-            st_stream<DIM>(&s[g], sv);
             st_stream<DIM>(&tt_[g], tv);
             const double rh = (double)hq[q];
             const double sd = (double)sv, td = (double)tv;
@@ -858,15 +865,15 @@ __device__ __forceinline__ void march_a(const DevProb& P, int lw, int gslot, boo
     const int pb = (gslot >> 1) & 1;
     const TI* zero = reinterpret_cast<const TI*>(P.op.zero);
     if (first) {
-        MarchA0<TI> ph{vp<const TI>(P.rin), vp<const TI>(P.rhat), zero, vp<TI>(P.p[pb]), vp<TI>(P.v[pb]),
-                       vp<TI>(P.r2[pb]), vp<TI>(P.e), &P, U, fin};
+        MarchA0<TI> ph{vp<const TI>(P.rin), vp<const TI>(P.rhat), zero, vp<TI>(pick2(P.p, pb)), vp<TI>(pick2(P.v, pb)),
+                       vp<TI>(pick2(P.r2, pb)), vp<TI>(P.e), &P, U, fin};
         march_phase<VAR, TI, MarchA0<TI>, 2>(P, lw, gslot, ph, L, sh);
     } else {
         const TI alpha = (TI)N.alpha, omega = (TI)N.omega;
         const TI beta = (TI)((N.rho / N.rho_old) * (N.alpha / N.omega));
-        MarchA<TI> ph{vp<const TI>(P.r2[pb ^ 1]), vp<const TI>(P.t), vp<const TI>(P.p[pb ^ 1]),
-                      vp<const TI>(P.v[pb ^ 1]), vp<const TI>(P.rhat), zero, vp<TI>(P.p[pb]), vp<TI>(P.v[pb]),
-                      vp<TI>(P.r2[pb]), vp<TI>(P.e), alpha, omega, beta};
+        MarchA<TI> ph{vp<const TI>(pick2(P.r2, pb ^ 1)), vp<const TI>(P.t), vp<const TI>(pick2(P.p, pb ^ 1)),
+                      vp<const TI>(pick2(P.v, pb ^ 1)), vp<const TI>(P.rhat), zero, vp<TI>(pick2(P.p, pb)), vp<TI>(pick2(P.v, pb)),
+                      vp<TI>(pick2(P.r2, pb)), vp<TI>(P.e), alpha, omega, beta};
         march_phase<VAR, TI, MarchA<TI>, 2>(P, lw, gslot, ph, L, sh);
     }
 }
@@ -874,7 +881,7 @@ __device__ __forceinline__ void march_a(const DevProb& P, int lw, int gslot, boo
 template <bool VAR, class TI>
 __device__ __forceinline__ void march_b(const DevProb& P, int lw, int gslot, const StepHot& N, TI* L, double* sh) {
     const int pb = ((gslot - 1) >> 1) & 1;
-    MarchB<TI> ph{vp<const TI>(P.r2[pb]), vp<const TI>(P.v[pb]), vp<const TI>(P.rhat),
+    MarchB<TI> ph{vp<const TI>(pick2(P.r2, pb)), vp<const TI>(pick2(P.v, pb)), vp<const TI>(P.rhat),
                   reinterpret_cast<const TI*>(P.op.zero), vp<TI>(P.t), (TI)N.alpha};
     march_phase<VAR, TI, MarchB<TI>, 5>(P, lw, gslot, ph, L, sh);
 }
@@ -997,8 +1004,8 @@ __device__ __forceinline__ void march_res(const DevProb& P, int lw, int gslot, c
     if (fused_c)
         for (int i = threadIdx.x; i < k; i += NT) csum[i] = 0.0;
     TI* rin = vp<TI>(P.rin);
-    MarchRes<TI> ph{P.x, P.b, vp<const TI>(P.e), vp<const TI>(P.p[U.pbuf]), vp<const TI>(P.r2[U.pbuf]),
-                    vp<const TI>(P.v[U.pbuf]),
+    MarchRes<TI> ph{P.x, P.b, vp<const TI>(P.e), vp<const TI>(pick2(P.p, U.pbuf)),
+                    vp<const TI>(pick2(P.r2, U.pbuf)), vp<const TI>(pick2(P.v, U.pbuf)),
                     reinterpret_cast<const double*>(P.op.zero), reinterpret_cast<const TI*>(P.op.zero), U, P.r,
                     rin, vp<TI>(P.rhat), k == 0, (void*)rin != (void*)P.r};
     if (lw < P.nchunks) {

@@ -129,8 +129,8 @@ struct DevProb {
     void* rhat;
     void* p[2];
     void* v[2];
-    void* s;                 // 2-D: s = r - alpha v (3-D: null, s is formed from r2 and v where needed)
-    void* r2[2];             // 3-D: the inner residual r_i, double-buffered with p and v (2-D: null)
+    void* r2[2];             // the inner residual r_i, double-buffered with p and v (s = r_i - alpha v_i is
+                             // formed where needed, never stored)
     void* t;
     void* e;
     const void* V;           // deflation basis, column-major, leading dim ldv
