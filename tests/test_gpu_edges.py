@@ -1,6 +1,6 @@
 """Edge cases of the solvers on the GPU through the C-ABI: degenerate grids
 (1 x 1, 3 x 1, 1 x 5, 1 x 1 x 1), an exact initial guess, the largest
-deflation space (63 vectors) with the longest GMRES cycle (128), a GMRES
+deflation space (256 vectors) with the longest GMRES cycle (256), a GMRES
 cycle longer than the system, and IDR(s) with a zero or non-finite
 right-hand side."""
 import numpy as np
