@@ -145,8 +145,8 @@ def cpu_model():
 def main():
     a = _args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): this build measures one GPU's share; "
-              "the multi-GPU design is documented but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): the library solves on one GPU; "
+              "how the path would shard over several is described, not implemented", file=sys.stderr)
         sys.exit(2)
     if a.cpu_full:
         return cpu_full(a.cpu_full.split(","))
