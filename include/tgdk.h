@@ -394,7 +394,9 @@ typedef struct {
      * deflation space used (A V for H = V^T A V; paid once per space, not by
      * this call).  vops: length-n vector operations of this call (a dot
      * product, a norm or an update y += a x counts one; formed from the
-     * iteration counts, see DESIGN). */
+     * iteration counts: BiCGStab 12 a full iteration and 7 a half step,
+     * GMRES 2j^2 + 5j + 1 a cycle of j steps, IDR(s) the vector updates of
+     * its rounds, 3 a true residual, 2k + 3 a projection). */
     long long mvp_setup, vops;
 } tgdk_solve_report;
 

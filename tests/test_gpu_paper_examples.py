@@ -11,11 +11,11 @@ level by level.  GMRES-DR(150,100) runs until 80 pairs have converged;
 BiCGStab(ncyc)-Proj(100) solves to rtol 1e-10 for every ncyc of Table 4.1.
 
 The paper's "residual norm below 1e-8" does not say how its matrix is
-scaled; the relative eigen-residual 1e-10 (R13's measure) reproduces its
+scaled; the eigen-residual 1e-10 relative to ||A||_1 reproduces its
 coarse phase: 109 cycles and 5513 products here against the paper's 107 and
 5450 (Sec. 3, Example 1), so that is the setting here.  The paper ran
 MATLAB's BiCGStab, whose exit rules differ from the textbook iteration here,
-and interpolated with splines of unstated degree (linear here, R4), so the
+and interpolated with splines of unstated degree (linear here), so the
 fine counts are a soft band, as for Table 4.2: every ncyc >= 20 within 20 %
 of the printed value, and the table's shape: ncyc = 5 and 10 need more
 products than ncyc = 20, at most twice the printed count."""
