@@ -57,29 +57,33 @@ def uneven_instances():
 
 
 # Workload table.  "C1" is the small case the oracle finishes in seconds;
-# "C2" is the headline single-GPU configuration.  k vectors are kept and moved
-# to the fine grid; GMRES-DR stops once nev = 0.8 k of them have converged (the
-# paper's Example 1 converges 80 of the 100 vectors it keeps).
+# "C3" (255^3) is the largest single-GPU configuration.  k vectors are kept
+# and moved to the fine grid; GMRES-DR stops once nev = 0.8 k of them have
+# converged (the paper's Example 1 converges 80 of the 100 vectors it keeps),
+# a pair counting as converged at an eigen-residual below 1e-10 relative to
+# ||A||_1, the measure with which the paper's "residual norm below 1e-8"
+# gives its own coarse cycle counts (Example 1: 107 cycles, Table 3.1,
+# Example 4: 285 cycles).
 CONFIGS = {
     "C1": dict(dim=2, n=(63, 63), beta=(40.0, 0.0), sigma=0.0, seed=1,
-               m=30, k=10, nev=8, rtolev=1e-8, ncyc=20, rtol=1e-8),
+               m=30, k=10, nev=8, rtolev=1e-10, ncyc=20, rtol=1e-8),
     "C2": dict(dim=2, n=(1023, 1023), beta=(100.0, 0.0), sigma=0.0, seed=2,
-               m=80, k=30, nev=24, rtolev=1e-8, ncyc=20, rtol=1e-8, m3=50),
+               m=80, k=30, nev=24, rtolev=1e-10, ncyc=20, rtol=1e-8, m3=50),
     "C3": dict(dim=3, n=(255, 255, 255), beta=(50.0, 20.0, 10.0), sigma=0.0, seed=3,
-               m=90, k=40, nev=32, rtolev=1e-8, maxcyc=300, ncyc=20, rtol=1e-8, max_extra=40),
+               m=90, k=40, nev=32, rtolev=1e-10, maxcyc=300, ncyc=20, rtol=1e-8, max_extra=40),
     "C4": dict(dim=2, n=(511, 511), beta=(100.0, 0.0), sigma=0.0, seeds=list(range(100, 132)),
-               m=80, k=30, nev=24, rtolev=1e-8, ncyc=20, rtol=1e-8),
+               m=80, k=30, nev=24, rtolev=1e-10, ncyc=20, rtol=1e-8),
     "C5": dict(dim=2, n=(1023, 1023), beta=(60.0, 0.0), sigma=0.0, kseed=5, bstar_seed=6,
-               bseed=7, dir_seed=8, m=80, k=30, nev=24, rtolev=1e-8, ncyc=20, rtol=1e-8),
+               bseed=7, dir_seed=8, m=80, k=30, nev=24, rtolev=1e-10, ncyc=20, rtol=1e-8),
     # The paper's Example 4 as printed: -Lap(u) - 100^2 u on 511^2 with a
     # random normal right-hand side, coarse grid 127^2 (two levels),
     # GMRES-DR(200,150) until 120 pairs converge, then IDR(20)-Proj(150) and
     # GMRES(100)-Proj(150) on the fine grid, rtol 1e-10.
     "H1": dict(dim=2, n=(511, 511), beta=(0.0, 0.0), sigma=-1.0e4, seed=4, levels=2,
-               m=200, k=150, nev=120, rtolev=1e-8, maxcyc=400, ncyc=20, rtol=1e-10, s=20, m3=100),
+               m=200, k=150, nev=120, rtolev=1e-10, maxcyc=400, ncyc=20, rtol=1e-10, s=20, m3=100),
     # The paper's Example 5: the same problem preconditioned on both grids by
     # multigrid on -Lap(u) + 100^2 u; GMRES-DR(150,100) on A_c M_c^{-1} until
     # 80 pairs converge, IDR(5)(5)-Proj(100) on the fine grid.
     "H2": dict(dim=2, n=(511, 511), beta=(0.0, 0.0), sigma=-1.0e4, seed=4, mg_cycles=2, mg_nu=2, levels=2,
-               m=150, k=100, nev=80, rtolev=1e-8, maxcyc=400, ncyc=5, rtol=1e-10, s=5, m3=100),
+               m=150, k=100, nev=80, rtolev=1e-10, maxcyc=400, ncyc=5, rtol=1e-10, s=5, m3=100),
 }
