@@ -82,10 +82,12 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(name):
+def traffic_from_profiles(name, alg_bytes):
     """HBM bytes per launch of the step kernel from a committed counter
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by the factor a plain
-    copy kernel gives), if it was taken on the current kernel sources."""
+    copy kernel gives), if it was taken on the current kernel sources and on
+    the same launch mix (its algorithmic bytes per launch within 1 % of this
+    run's alg_bytes)."""
     p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
@@ -97,8 +99,11 @@ def traffic_from_profiles(name):
     if kv.get("kernel_source_hash") != kernel_hash():
         return None
     try:
+        prof_alg = float(kv["algorithmic_bytes_per_launch"].split()[0])
+        if abs(prof_alg - alg_bytes) > 0.01 * alg_bytes:
+            return None
         return float(kv["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
+    except (KeyError, ValueError, IndexError):
         return None
 
 
@@ -383,7 +388,8 @@ def main():
                    "n": n3, "k": space3.k, "ncyc": c3["ncyc"], "seed": c3["seed"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_from_profiles("k_step_f64_255cube_counters.txt"),
+                     "traffic": traffic_from_profiles("k_step_f64_255cube_counters.txt",
+                                                      st3["algorithmic_bytes_per_launch"]),
                      "kernel": "k_step (3-D BiCGStab(ncyc)-Proj(k) step kernel, float64, every launch of a solve)",
                      "algorithmic_bytes_per_launch": st3["algorithmic_bytes_per_launch"],
                      "avg_launch_us": avg_launch_us, "launches_per_solve": st3["launches"],
