@@ -757,12 +757,16 @@ def stream_ceiling(tg):
     phase B of the 3-D step kernel (3 + 1) and phase A (6 + 4) on 255^3
     arrays, each in copy order (grid-strided; best of 768..8192 workgroups)
     and in the marching phases' order (64 x 8 column chunks walked plane by
-    plane; best of about 768, 1024 and 2048 chunks).  One JSON line."""
+    plane; best of about 768, 1024 and 2048 chunks), the latter also over
+    arrays stored chunk by chunk (each chunk plane one contiguous 4 KB
+    block) and with the loads of 2 or 3 planes in flight.  One JSON line."""
     out = {}
     for tag, nr, nw, dims in (("copy_1r1w_511cube", 1, 1, (511, 511, 511)), ("phaseB_3r1w_255cube", 3, 1, (255, 255, 255)),
                               ("phaseA_6r4w_255cube", 6, 4, (255, 255, 255))):
         row = {}
-        for pattern, blocks_list in (("contiguous", (768, 1024, 2048, 4096, 8192)), ("march", (768, 1024, 2048))):
+        for pattern, blocks_list in (("contiguous", (768, 1024, 2048, 4096, 8192)), ("march", (768, 1024, 2048)),
+                                    ("tiled", (768, 1024, 2048)), ("march_pf2", (768, 1024, 2048)),
+                                    ("march_pf3", (768, 1024, 2048))):
             best = None
             for blocks in blocks_list:
                 ms, nbytes = tg.stream_probe(pattern, nr, nw, dims, blocks=blocks, reps=10)

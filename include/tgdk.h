@@ -120,7 +120,11 @@ int tgdk_ctx_kernel_time(tgdk_ctx ctx, int action, double* total_ms, long long* 
  * the step kernel's own vectors), allocated and freed by the call.
  * pattern 0: each array walked grid-strided by `blocks` workgroups (copy
  * order); pattern 1: one workgroup per 64 x 8 column chunk walking its planes
- * (the marching phases' order, about `blocks` chunks, no LDS or stencil).
+ * (the marching phases' order, about `blocks` chunks, no LDS or stencil);
+ * pattern 2: the same walk over arrays stored chunk by chunk, each chunk's
+ * 64 x 8 plane one contiguous block (y padded to a multiple of 8 as well);
+ * patterns 3 and 4: the march of pattern 1 with the loads of the next one or
+ * two planes issued before a plane is stored (2 or 3 planes in flight).
  * Runs one untimed and `reps` timed launches on the context's stream;
  * *ms_per_launch = their average (HIP events).  Returns TGDK_E_INVALID for
  * other mixes or bad sizes, TGDK_E_NOMEM when the arrays do not fit. */

@@ -452,12 +452,13 @@ def grad_k(op, lam, u):
 
 def stream_probe(pattern, nreads, nwrites, dims, blocks=768, reps=10, device=None):
     """Streaming ceiling for a mix of float64 streams (include/tgdk.h,
-    tgdk_stream_probe): pattern "contiguous" or "march"; returns
+    tgdk_stream_probe): pattern "contiguous", "march", "tiled", "march_pf2" or
+    "march_pf3" (the march with 2 or 3 planes of loads in flight); returns
     (ms per launch, bytes moved per launch)."""
     ctx, _ = context(device)
     d = (C.c_int * 3)(*[int(v) for v in dims])
     ms = C.c_double()
-    check(lib().tgdk_stream_probe(ctx, {"contiguous": 0, "march": 1}[pattern], int(nreads), int(nwrites), d,
+    check(lib().tgdk_stream_probe(ctx, {"contiguous": 0, "march": 1, "tiled": 2, "march_pf2": 3, "march_pf3": 4}[pattern], int(nreads), int(nwrites), d,
                                   int(blocks), int(reps), C.byref(ms)))
     nx, ny, nz = (int(v) for v in dims)
     pts = ((nx + 63) // 64 * 64 if pattern == "contiguous" else nx) * ny * nz
