@@ -125,3 +125,20 @@ def test_every_tile_shape_gives_identical_stencil(tmp_path, monkeypatch):
         # candidate tile heights: 2-D 16, 8, 4, 32; 3-D 4, 8, 4, 2 (timing decides)
         assert ty in ((16, 8, 4, 32) if len(dims) == 2 else (4, 8, 2))
         assert "tile=" in (tmp_path / "fresh.txt").read_text()
+
+
+@pytest.mark.parametrize("pattern", ["contiguous", "march", "tiled", "march_pf2", "march_pf3"])
+def test_stream_probe_runs_every_pattern_and_mix(pattern):
+    """The streaming probe (a measurement utility, not a step of the method)
+    on a ragged grid smaller than one chunk in x and y, more than one in z:
+    every pattern and stream mix completes and reports the bytes of the
+    grid's points; an unknown mix and a bad grid are refused."""
+    dims = (65, 9, 7)
+    for nr, nw in ((1, 1), (3, 1), (6, 4)):
+        ms, nbytes = tg().stream_probe(pattern, nr, nw, dims, blocks=8, reps=2)
+        pts = (128 if pattern == "contiguous" else 65) * 9 * 7
+        assert ms > 0 and nbytes == (nr + nw) * pts * 8
+    with pytest.raises(tg()._lib.TgdkError):
+        tg().stream_probe(pattern, 2, 2, dims)
+    with pytest.raises(tg()._lib.TgdkError):
+        tg().stream_probe(pattern, 1, 1, (0, 9, 7))
