@@ -447,8 +447,8 @@ int tgdk_solve_idr(tgdk_op fine, tgdk_defl defl, const double* b, double* x, int
  * MiB per GPU, held by the library until the process ends; the status
  * mirror and events come from tgdk_ctx_create.  The caller passes inputs and
  * outputs as for tgdk_solve.
- *  - Capacity: about 72 n bytes per right-hand side with TGDK_FP64 inner
- *    cycles, 44 n with TGDK_FP32_IR (8 n more on 3-D grids with a deflation
+ *  - Capacity: about 80 n bytes per right-hand side with TGDK_FP64 inner
+ *    cycles, 48 n with TGDK_FP32_IR (8 n more on 3-D grids with a deflation
  *    space), plus partial sums; at most 64 right-hand sides.  A call that
  *    needs more returns TGDK_E_INVALID (the message gives the bytes needed)
  *    without touching x.  Step-kernel timing (tgdk_ctx_time_kernel) must be

@@ -50,13 +50,13 @@ def test_noalloc_equals_solve_on_two_calls(precision):
 
 def test_noalloc_rejects_a_solve_larger_than_the_scratch():
     from paper_2005_03070_amd._lib import TgdkError, E_INVALID
-    op = tg().Operator.const_cd((1023, 1023), (100.0, 0.0))    # 72 n bytes > 64 MiB in FP64
+    op = tg().Operator.const_cd((1023, 1023), (100.0, 0.0))    # 80 n bytes > 64 MiB in FP64
     b = torch.tensor(W.rhs(op.n, 2), device=DEV)
     out = torch.full_like(b, 7.0)
     with pytest.raises(TgdkError) as ei:
         tg().solve_noalloc(op, b, out=out, rtol=1e-8)
     assert ei.value.code == E_INVALID and "scratch" in str(ei.value)
     assert bool((out == 7.0).all())
-    # float32 inner cycles need 44 n bytes: this one fits and converges
+    # float32 inner cycles need 48 n bytes: this one fits and converges
     x, r = tg().solve_noalloc(op, b, rtol=1e-8, precision="fp32_ir", max_extra=40)
     assert r[0].status == 0 and r[0].relres_true <= 1e-8
