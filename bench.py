@@ -331,6 +331,30 @@ def main():
                                     "status": r64f[0].status_name, **cost(r64f[0], 3)}
         del space3f
         log_timing("255^3 fp32_ir V f32", variants["c3_fp32_ir_Vf32"]["step_kernel"])
+        # deflation against none and the size of the space at 255^3 (FP64
+        # inner cycles, V float64): BiCGStab(20) from zero without a coarse
+        # grid, and GMRES-DR(k + 50, k) spaces of 20 and 80 vectors (0.8 k
+        # pairs converged) beside the headline's 40
+        s0, (xn, rn) = timed(lambda: tg.solve(op3, b3, rtol=c3["rtol"], ncyc=c3["ncyc"], max_extra=80), reps=1)
+        variants["c3_fp64_no_deflation"] = {"seconds": s0, "relres_true": relres(op3, b3, xn),
+                                            "status": rn[0].status_name, **cost(rn[0], 3)}
+        log(f"255^3 fp64 BiCGStab(20), no deflation, from zero: {s0*1e3:.1f} ms, mvps {rn[0].mvp_inner}")
+        for kk in (20, 80):
+            t = time.perf_counter()
+            xck, csk, srk = tg.coarse_setup(cop3, tg.restrict(op3, cop3, b3), kk + 50, kk, int(0.8 * kk),
+                                            c3["rtolev"], 1e-8, c3["maxcyc"])
+            spk = tg.defl_prolongate(csk, op3, store=torch.float64)
+            x0k = tg.prolongate(cop3, op3, xck)
+            sync()
+            setup_k = time.perf_counter() - t
+            sk, (xk, rk) = timed(lambda: tg.solve(op3, b3, x0=x0k, defl=spk, rtol=c3["rtol"], ncyc=c3["ncyc"],
+                                                  max_extra=c3["max_extra"], precision="fp64"), reps=2)
+            variants[f"c3_fp64_k{kk}"] = {"seconds": sk, "setup_seconds": setup_k, "gmresdr_cycles": srk.cycles,
+                                          "k": spk.k, "relres_true": relres(op3, b3, xk),
+                                          "status": rk[0].status_name, **cost(rk[0], 3)}
+            log(f"255^3 fp64 BiCGStab(20)-Proj({spk.k}): {sk*1e3:.1f} ms, mvps {rk[0].mvp_inner}; setup "
+                f"GMRES-DR({kk + 50},{kk}) {srk.cycles} cycles, {setup_k:.2f} s")
+            del spk, csk
         torch.cuda.empty_cache()
         workloads.update(other_workloads(tg, W, dev, timed, relres, cost, step_timing, log_timing, np))
 
