@@ -68,7 +68,57 @@ def _args():
                     help="only measure the streaming ceilings of the step kernel's stream mixes (a copy, phase B's "
                          "3 reads + 1 write, phase A's 6 + 4) in copy order and in the marching phases' order, "
                          "then print one JSON line")
+    ap.add_argument("--action-traffic", nargs=2, default=None, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="only print the step kernel's HBM traffic per action of the 255^3 headline solve from "
+                         "two rocprofv3 per-dispatch counter files (FETCH_SIZE, WRITE_SIZE), then exit")
     return ap.parse_args()
+
+
+def action_traffic(fetch_csv, write_csv, fetch_scale=2.0, write_scale=1.0):
+    """Per-action HBM bytes of k_step over one 255^3 headline solve (float64
+    inner vectors and basis, k = 40) from rocprofv3's per-dispatch counter
+    files of two runs of the same solve: the k_step dispatches of both runs,
+    in dispatch order, are paired; each is assigned to the action whose
+    algorithmic (read, write) bytes per point are nearest (in log scale) to
+    its scaled FETCH_SIZE and WRITE_SIZE; prints a markdown table."""
+    import collections
+    import csv
+    import math
+
+    def per_dispatch(path):
+        vals = collections.OrderedDict()
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if "k_step<" in row.get("Kernel_Name", ""):
+                    d = int(row["Dispatch_Id"])
+                    vals[d] = vals.get(d, 0.0) + float(row.get("Counter_Value") or 0.0)
+        return [v for _, v in sorted(vals.items())]
+
+    n, w, k = 255 ** 3, 8, 40
+    reads = {"A": 6 * w, "A0": 2 * w, "B": 3 * w, "RES": 16 + 4 * w, "CDOT": 8 + 8 * k,
+             "APPLYW": 8 + 4 * w + 8 * k, "APPLY": 16, "FIN": 8 + 4 * w, "NONE/REDUCE": 0}
+    writes = {"A": 4 * w, "A0": 4 * w, "B": w, "RES": 8, "CDOT": 0, "APPLYW": 16, "APPLY": 16, "FIN": 8,
+              "NONE/REDUCE": 0}
+    bpp = act_bytes(3, w, 8, k, False)
+    assert all(reads[a] + writes[a] == bpp[a] for a in ("A", "A0", "B", "RES", "CDOT", "APPLYW", "APPLY", "FIN"))
+    fe, wr = per_dispatch(fetch_csv), per_dispatch(write_csv)
+    if len(fe) != len(wr):
+        raise SystemExit(f"the two runs have {len(fe)} and {len(wr)} k_step dispatches")
+    agg = collections.OrderedDict((a, [0, 0.0, 0.0]) for a in reads)
+    for f, x in zip(fe, wr):
+        r, wv = f * 1024 * fetch_scale, x * 1024 * write_scale
+        a = min(reads, key=lambda a: abs(math.log1p(r / n) - math.log1p(reads[a]))
+                + abs(math.log1p(wv / n) - math.log1p(writes[a])))
+        agg[a][0] += 1
+        agg[a][1] += r
+        agg[a][2] += wv
+    print("| Action | Launches | Read GB (alg.) | Written GB (alg.) | Measured / algorithmic |")
+    print("|---|---:|---:|---:|---:|")
+    for a, (c, r, wv) in agg.items():
+        if c:
+            ar, aw = reads[a] * n, writes[a] * n
+            ratio = f"{(r + wv) / c / (ar + aw):.3f}" if ar + aw else ""
+            print(f"| {a} | {c} | {r / c / 1e9:.3f} ({ar / 1e9:.3f}) | {wv / c / 1e9:.3f} ({aw / 1e9:.3f}) | {ratio} |")
 
 
 def kernel_hash():
@@ -155,6 +205,8 @@ def main():
         sys.exit(2)
     if a.cpu_full:
         return cpu_full(a.cpu_full.split(","))
+    if a.action_traffic:
+        return action_traffic(*a.action_traffic)
     import numpy as np
     import torch
 

@@ -83,3 +83,28 @@ def test_more_than_one_gpu_exits_with_a_message():
                        text=True, timeout=120, env={**os.environ, "HIP_VISIBLE_DEVICES": ""})
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_action_traffic_assigns_exact_counters_to_their_actions(tmp_path, capsys):
+    """Per-dispatch counter files whose values are exactly the algorithmic
+    bytes of a known launch sequence (FETCH_SIZE in KiB at half the bytes
+    read, WRITE_SIZE in KiB at the bytes written, as the copy calibration
+    reads them) are assigned action by action, with ratio 1 everywhere."""
+    n, w, k = 255 ** 3, 8, 40
+    rw = {"A": (48, 32), "A0": (16, 32), "B": (24, 8), "RES": (48, 8), "CDOT": (328, 0), "APPLYW": (360, 16),
+          "APPLY": (16, 16), "FIN": (40, 8), "NONE/REDUCE": (0, 0)}
+    seq = ["A0", "B"] + ["A", "B"] * 5 + ["RES", "CDOT", "NONE/REDUCE", "APPLYW", "APPLY", "FIN"]
+    name = "void tgdk::k_step<tgdk::Tile<3, 4, 4>, 3, false, double>(tgdk::DevProb const*, int const*, int)"
+    for which, col, scale in (("fetch", 0, 2.0), ("write", 1, 1.0)):
+        lines = ["Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value"]
+        lines.append('1,"void tgdk::k_apply<x>(int)",X,123')  # another kernel: ignored
+        for i, a in enumerate(seq):
+            lines.append(f'{i + 2},"{name}",{which.upper()}_SIZE,{rw[a][col] * n / 1024 / scale}')
+        (tmp_path / f"{which}.csv").write_text("\n".join(lines) + "\n")
+    bench.action_traffic(str(tmp_path / "fetch.csv"), str(tmp_path / "write.csv"))
+    out = capsys.readouterr().out
+    rows = {r.split("|")[1].strip(): r.split("|") for r in out.splitlines()[2:]}
+    for a in set(seq):
+        assert int(rows[a][2]) == seq.count(a), a
+        if a != "NONE/REDUCE":
+            assert rows[a][5].strip() == "1.000", (a, rows[a])
